@@ -1,0 +1,26 @@
+"""FP64 CPU oracle of the eRTIS energyscape pipeline.
+
+TEST INFRASTRUCTURE ONLY. This package is the plain, slow, obviously correct
+reference that the HIP library is checked against.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may
+import it.  The product path (``paper_2208_10839_amd``) never imports, calls or
+links anything here, and nothing here imports the product path: the two share
+no code.
+"""
+
+from .sonar_oracle import (  # noqa: F401
+    analytic_weights,
+    band_mask,
+    beam_window_indices,
+    chirp_spectrum_filter,
+    das_fd,
+    das_td,
+    default_lowpass,
+    delays,
+    energyscape,
+    envelope,
+    matched_filter,
+    matched_filter_spectrum,
+    num_range_bins,
+    td_offsets,
+)

@@ -1,0 +1,258 @@
+"""Plain FP64 oracle of the energyscape pipeline (TEST INFRASTRUCTURE ONLY).
+
+The paper (Jansen et al., "In-Air Imaging Sonar Sensor Network With Real-time
+Processing Using GPUs") turns one multi-microphone recording of a broadband FM
+sweep into a range x direction intensity image in three steps (Fig. 3 caption;
+§4.1 Signal Processing): a matched filter against the emitted sweep, delay-and-sum
+beamforming toward every direction of interest, and an envelope detector whose
+output is subsampled (§4.3 GPU Algorithm Implementation).  The paper states
+these steps in prose only; the precise definition implemented here is the one
+written down in DESIGN.md ("Readings of the paper"), which fixes what the paper
+leaves open (circular length-P arithmetic, analytic signal from one-sided
+weights, zero-phase FIR low-pass, linear-interpolation or exact fractional
+delays).
+
+Everything is numpy in float64 (complex128), with ``numpy.fft`` as the only
+library primitive.  Nothing is blocked, fused or reordered beyond what the
+definition states, so each function can be read against the definition.  Only
+``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline`` leg
+may use this module; the HIP library never does.
+
+DFT convention: X[k] = sum_n x[n] exp(-2j*pi*k*n/P);
+IDFT(X)[n] = (1/P) sum_k X[k] exp(+2j*pi*k*n/P).
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+
+# ---------------------------------------------------------------------------
+# Matched filter (§4.1: each channel is matched-filtered against the emitted
+# sweep; §4.3: on the GPU this filter is an FFT convolution whose group delay is
+# removed afterwards).
+# ---------------------------------------------------------------------------
+
+def analytic_weights(P: int) -> np.ndarray:
+    """One-sided weights that turn a real signal's DFT into its analytic signal.
+
+    W[0] = 1, W[k] = 2 for 0 < k < P/2, W[P/2] = 1, W[k] = 0 above P/2 (the
+    discrete analytic signal; the envelope of §4.1 is the magnitude of it).
+    """
+    if P % 2:
+        raise ValueError("P must be even")
+    W = np.zeros(P)
+    W[0] = 1.0
+    W[1:P // 2] = 2.0
+    W[P // 2] = 1.0
+    return W
+
+
+def band_mask(P: int, fs: float, band=None) -> np.ndarray:
+    """beta[k] = 1 where lo <= k*fs/P <= hi, else 0; all ones when band is None."""
+    if band is None or (band[0] == 0 and band[1] == 0):
+        return np.ones(P)
+    lo, hi = band
+    f = np.arange(P) * (fs / P)
+    return ((f >= lo) & (f <= hi)).astype(np.float64)
+
+
+def chirp_spectrum_filter(chirp, P: int, fs: float, band=None) -> np.ndarray:
+    """C[k] = beta[k] * W[k] * conj(S[k]) with S = DFT_P(chirp zero-padded)."""
+    s = np.asarray(chirp, dtype=np.float64)
+    S = np.fft.fft(s, n=P)
+    return band_mask(P, fs, band) * analytic_weights(P) * np.conj(S)
+
+
+def matched_filter_spectrum(x, chirp, P: int, fs: float, band=None) -> np.ndarray:
+    """Yhat_m[k] = X_m[k] * C[k], k in [0, P): the spectrum of the analytic MF output.
+
+    x is [M][N] (zero-padded to P).  Correlation (not convolution) with the
+    emitted chirp, so lag 0 of the output is the echo onset: the filter's group
+    delay is removed by construction.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("x must be [M][N]")
+    if P < x.shape[1] + len(chirp) - 1:
+        raise ValueError("P must be >= N + L - 1")
+    X = np.fft.fft(x, n=P, axis=1)
+    return X * chirp_spectrum_filter(chirp, P, fs, band)[None, :]
+
+
+def matched_filter(x, chirp, P: int, fs: float, band=None) -> np.ndarray:
+    """yhat_m[n] = IDFT_P(Yhat_m)[n] for n in Z_P, complex128 [M][P].
+
+    Without a band mask, Re yhat_m[n] = sum_l chirp[l] * x_m[n + l] (the linear
+    correlation; negative lags sit at P + n) and Im yhat is its discrete Hilbert
+    transform.
+    """
+    return np.fft.ifft(matched_filter_spectrum(x, chirp, P, fs, band), axis=1)
+
+
+# ---------------------------------------------------------------------------
+# Delays (§4.1: for each direction of interest the delay relative to each
+# channel of the array is computed; it depends on direction and channel only,
+# i.e. far-field plane-wave steering).
+# ---------------------------------------------------------------------------
+
+def delays(mic_pos, dirs, fs: float, c: float) -> np.ndarray:
+    """Dl[d][m] = fs * (p_m . u_d) / c in samples (float64).
+
+    A plane wave arriving from unit direction u reaches microphone m earlier by
+    p_m . u / c than it reaches the origin, so beamforming toward u reads
+    channel m Dl[d][m] samples later.
+    """
+    pos = np.asarray(mic_pos, dtype=np.float64)
+    u = np.asarray(dirs, dtype=np.float64)
+    D, M = u.shape[0], pos.shape[0]
+    Dl = np.empty((D, M))
+    for d in range(D):
+        for m in range(M):
+            Dl[d, m] = fs * (pos[m, 0] * u[d, 0] + pos[m, 1] * u[d, 1] + pos[m, 2] * u[d, 2]) / c
+    return Dl
+
+
+def td_offsets(Dl):
+    """Integer offset o = floor(-Dl) and interpolation weight alpha = -Dl - o in [0, 1)."""
+    Dl = np.asarray(Dl, dtype=np.float64)
+    o = np.floor(-Dl)
+    return o.astype(np.int64), (-Dl - o)
+
+
+# ---------------------------------------------------------------------------
+# Delay-and-sum beamforming (§4.1: simple delay-and-sum steering; §4.3: a device
+# kernel on the GPU).
+# ---------------------------------------------------------------------------
+
+def das_td(yhat, Dl, n_idx) -> np.ndarray:
+    """Fractional-delay DAS with linear interpolation, circular in P.
+
+    b_d[n] = (1/M) sum_m [(1 - alpha) yhat_m[(n + o) mod P] + alpha yhat_m[(n + o + 1) mod P]]
+    evaluated at the sample indices n_idx (which may be negative).
+    Returns complex128 [D][len(n_idx)].
+    """
+    yhat = np.asarray(yhat)
+    M, P = yhat.shape
+    o, alpha = td_offsets(Dl)
+    n_idx = np.asarray(n_idx, dtype=np.int64)
+    D = o.shape[0]
+    b = np.zeros((D, n_idx.size), dtype=np.complex128)
+    for d in range(D):
+        acc = np.zeros(n_idx.size, dtype=np.complex128)
+        for m in range(M):
+            i0 = np.mod(n_idx + o[d, m], P)
+            i1 = np.mod(n_idx + o[d, m] + 1, P)
+            acc += (1.0 - alpha[d, m]) * yhat[m, i0] + alpha[d, m] * yhat[m, i1]
+        b[d] = acc / M
+    return b
+
+
+def das_fd(Yspec, Dl, n_idx) -> np.ndarray:
+    """Exact fractional-delay DAS by per-bin phase steering, circular in P.
+
+    B_d[k] = (1/M) sum_m Yhat_m[k] exp(-2j pi k Dl[d][m] / P), b_d = IDFT_P(B_d),
+    evaluated at n_idx.  Yhat vanishes above P/2 (analytic weights), so the
+    sum over k runs over 0..P/2 only; the other bins of B_d are zero.
+    """
+    Y = np.asarray(Yspec)
+    M, P = Y.shape
+    Dl = np.asarray(Dl, dtype=np.float64)
+    n_idx = np.mod(np.asarray(n_idx, dtype=np.int64), P)
+    k = np.arange(P // 2 + 1, dtype=np.float64)
+    D = Dl.shape[0]
+    b = np.zeros((D, n_idx.size), dtype=np.complex128)
+    for d in range(D):
+        B = np.zeros(P, dtype=np.complex128)
+        for m in range(M):
+            B[:P // 2 + 1] += Y[m, :P // 2 + 1] * np.exp(-2j * np.pi * (k * Dl[d, m] / P))
+        B /= M
+        b[d] = np.fft.ifft(B)[n_idx]
+    return b
+
+
+# ---------------------------------------------------------------------------
+# Envelope and subsampling (§4.1: the envelope of each beam is the reflector
+# distribution along range; §4.3: filters run as FFT convolution with their
+# group delay removed, and the envelope is subsampled afterwards).
+# ---------------------------------------------------------------------------
+
+def default_lowpass(R: int) -> np.ndarray:
+    """Default zero-phase low-pass: K = 8R+1 Hamming-windowed sinc, cutoff fs/(2R), sum 1."""
+    if R < 1:
+        raise ValueError("R must be >= 1")
+    K = 8 * R + 1
+    j = np.arange(K, dtype=np.float64)
+    w = 0.54 - 0.46 * np.cos(2.0 * np.pi * j / (K - 1))
+    h = w * np.sinc((j - (K - 1) / 2) / R)
+    return h / h.sum()
+
+
+def num_range_bins(n0: int, n1: int, R: int) -> int:
+    """Q = ceil((n1 - n0) / R)."""
+    return -(-(n1 - n0) // R)
+
+
+def beam_window_indices(n0: int, Q: int, R: int, K: int) -> np.ndarray:
+    """Beam sample indices needed for Q outputs: n0 - (K-1)/2 ... n0 + (Q-1)R + (K-1)/2."""
+    hk = (K - 1) // 2
+    return np.arange(n0 - hk, n0 + (Q - 1) * R + hk + 1, dtype=np.int64)
+
+
+def envelope(b_win, taps, Q: int, R: int) -> np.ndarray:
+    """E[d][q] = sum_j h[j] |b_d[n0 + qR + (K-1)/2 - j]| from the beam window.
+
+    b_win[d][i] holds b_d at sample n0 - (K-1)/2 + i, so the FIR tap j of output
+    q reads window position qR + K - 1 - j.
+    """
+    h = np.asarray(taps, dtype=np.float64)
+    K = h.size
+    e = np.abs(np.asarray(b_win))
+    D = e.shape[0]
+    if e.shape[1] != (Q - 1) * R + K:
+        raise ValueError("beam window has the wrong length")
+    E = np.zeros((D, Q))
+    for q in range(Q):
+        seg = e[:, q * R:q * R + K]          # window positions qR .. qR+K-1
+        E[:, q] = seg @ h[::-1]               # position qR+K-1-j pairs with h[j]
+    return E
+
+
+# ---------------------------------------------------------------------------
+# Whole pipeline (Fig. 3 order: matched filter, beamformer, envelope).
+# ---------------------------------------------------------------------------
+
+def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None = None,
+                gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
+                dir_index=None, return_beam: bool = False):
+    """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation) or 'fd' (exact).
+
+    dir_index selects a subset of directions (rows of the result follow it).
+    With return_beam, also returns the complex beam window b[d][G'].
+    """
+    x = np.asarray(x, dtype=np.float64)
+    M, N = x.shape
+    L = len(chirp)
+    if P is None:
+        P = 1
+        while P < N + L - 1:
+            P *= 2
+    n0, n1 = (0, N) if gate is None else gate
+    h = default_lowpass(R) if taps is None else np.asarray(taps, dtype=np.float64)
+    K = h.size
+    if K % 2 == 0:
+        raise ValueError("FIR length must be odd")
+    Q = num_range_bins(n0, n1, R)
+    u = np.asarray(dirs, dtype=np.float64)
+    if dir_index is not None:
+        u = u[np.asarray(dir_index)]
+    Dl = delays(mic_pos, u, fs, c)
+    n_idx = beam_window_indices(n0, Q, R, K)
+    if mode == "td":
+        b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
+    elif mode == "fd":
+        b = das_fd(matched_filter_spectrum(x, chirp, P, fs, band), Dl, n_idx)
+    else:
+        raise ValueError("mode must be 'td' or 'fd'")
+    E = envelope(b, h, Q, R)
+    return (E, b) if return_beam else E

@@ -1,0 +1,204 @@
+"""Synthetic recordings with the shapes of the paper's workload.
+
+The paper measures on real recordings of a 32-microphone eRTIS sensor sampled
+at 450 kHz (§2 Sonar Synchronisation), processed with 90, 1850 and 3000
+directions of interest (§5 Experimental Validation).  Those recordings, the
+array layout (Fig. 1a) and the sweep parameters are not published, so every
+input here is seeded and synthetic:
+
+* array: microphones uniform in a square planar aperture in the z = 0 plane
+  (the paper only says "known, irregularly positioned");
+* emitted sweep: Hann-windowed linear FM sweep (the paper says "broadband
+  FM-sweep");
+* echoes: point reflectors with 1/r amplitude spreading and exact spherical
+  round-trip travel time from an emitter at the origin, with the continuous
+  sweep evaluated at each sample instant (no interpolation);
+* noise: white Gaussian at a stated SNR, sigma^2 = mean(clean^2) / 10^(SNR/10).
+
+Seeds: numpy SeedSequence([config_id, sensor, frame, stream]) with stream
+0 = geometry, 1 = reflectors, 2 = noise; frames of one sensor share geometry.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+FS_HZ = 450e3      # §2: the eRTIS samples at 450 kHz
+C_MPS = 343.0      # speed of sound in air at 20 C (not stated in the paper)
+N_MICS = 32        # §2: 32 digital microphones
+
+
+def _rng(cfg_id: int, sensor: int, frame: int, stream: int) -> np.random.Generator:
+    return np.random.default_rng(np.random.SeedSequence([cfg_id, sensor, frame, stream]))
+
+
+def linear_chirp(fs: float = FS_HZ, f0: float = 25e3, f1: float = 80e3, T: float = 1e-3) -> np.ndarray:
+    """Samples s[l] = s(l/fs), l < round(T*fs), of the Hann-windowed linear sweep."""
+    L = int(round(T * fs))
+    t = np.arange(L) / fs
+    return _chirp_at(t, f0, f1, T)
+
+
+def _chirp_at(t, f0, f1, T):
+    t = np.asarray(t, dtype=np.float64)
+    inside = (t >= 0.0) & (t < T)
+    w = 0.5 * (1.0 - np.cos(2.0 * np.pi * t / T))
+    s = w * np.sin(2.0 * np.pi * (f0 * t + (f1 - f0) * t * t / (2.0 * T)))
+    return np.where(inside, s, 0.0)
+
+
+def planar_array(M: int, aperture: float, rng: np.random.Generator) -> np.ndarray:
+    """[M][3] positions, uniform in [-a/2, a/2]^2 in the z = 0 plane (metres)."""
+    pos = np.zeros((M, 3))
+    pos[:, :2] = rng.uniform(-aperture / 2, aperture / 2, size=(M, 2))
+    return pos
+
+
+def azimuth_grid(n: int = 91, lo_deg: float = -90.0, step_deg: float = 2.0) -> np.ndarray:
+    """Horizontal-plane directions u = (sin az, 0, cos az) (2D image of §5)."""
+    az = np.deg2rad(lo_deg + step_deg * np.arange(n))
+    return np.stack([np.sin(az), np.zeros(n), np.cos(az)], axis=1)
+
+
+def fibonacci_hemisphere(D: int) -> np.ndarray:
+    """D near-uniform directions on the frontal (z > 0) hemisphere (golden-angle spiral)."""
+    i = np.arange(D, dtype=np.float64)
+    z = (i + 0.5) / D
+    phi = i * np.pi * (3.0 - math.sqrt(5.0))
+    r = np.sqrt(1.0 - z * z)
+    return np.stack([r * np.cos(phi), r * np.sin(phi), z], axis=1)
+
+
+def restricted_grid(D_target: int = 1850, half_deg: float = 45.0) -> np.ndarray:
+    """Fibonacci directions with |azimuth|, |elevation| <= half_deg (the 1850-direction case of §5).
+
+    The spiral density is chosen so that about D_target points survive the cut.
+    """
+    best = None
+    for D in range(D_target, 20 * D_target):
+        u = fibonacci_hemisphere(D)
+        az = np.degrees(np.arctan2(u[:, 0], u[:, 2]))
+        el = np.degrees(np.arcsin(np.clip(u[:, 1], -1, 1)))
+        keep = u[(np.abs(az) <= half_deg) & (np.abs(el) <= half_deg)]
+        if keep.shape[0] >= D_target:
+            best = keep
+            break
+    return best
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    cfg_id: int
+    name: str
+    n_mics: int
+    aperture: float
+    n_samples: int
+    n_reflectors: int
+    r_range: tuple
+    snr_db: float
+    grid: str                 # "az91" or "fib<D>"
+    band: tuple | None        # matched-filter band mask in Hz, or None
+    decim: int = 10
+    planar_reflectors: bool = False   # True: elevation 0, azimuth within +-80 deg
+
+
+CONFIGS = {
+    # plain method, 1 sensor, horizontal plane (small enough for the oracle in seconds)
+    "c1": Config(1, "c1", 32, 0.035, 4096, 3, (0.5, 4.0), 20.0, "az91", None, planar_reflectors=True),
+    # single sensor, full 3D, the throughput workload: 32 mics x 16384 samples x 1500 directions
+    "c2": Config(2, "c2", 32, 0.035, 16384, 20, (0.3, 6.0), 20.0, "fib1500", (20e3, 85e3)),
+    # stress: 64 mics in 7 cm, 65536 samples, 10000 directions
+    "c5": Config(5, "c5", 64, 0.070, 65536, 50, (0.3, 24.0), 10.0, "fib10000", (20e3, 85e3)),
+}
+
+
+@dataclasses.dataclass
+class Workload:
+    cfg: Config
+    x: np.ndarray          # [F][M][N] float32
+    chirp: np.ndarray      # [L] float64
+    mic_pos: np.ndarray    # [M][3] float64
+    dirs: np.ndarray       # [D][3] float64
+    reflectors: list       # per frame: list of (r, u[3], amplitude)
+    fs: float = FS_HZ
+    c: float = C_MPS
+
+
+def make_grid(grid: str) -> np.ndarray:
+    if grid == "az91":
+        return azimuth_grid(91)
+    if grid.startswith("fib"):
+        return fibonacci_hemisphere(int(grid[3:]))
+    raise ValueError(grid)
+
+
+def simulate_frame(mic_pos, chirp_params, reflectors, n_samples, snr_db, rng_noise,
+                   fs: float = FS_HZ, c: float = C_MPS) -> np.ndarray:
+    """x[m][n] = sum_i (a_i/r_i) s(n/fs - tau_im) + noise, tau_im = (r_i + |r_i u_i - p_m|)/c."""
+    f0, f1, T = chirp_params
+    M = mic_pos.shape[0]
+    x = np.zeros((M, n_samples))
+    L = int(round(T * fs))
+    for (r, u, a) in reflectors:
+        pt = r * np.asarray(u)
+        for m in range(M):
+            tau = (r + np.linalg.norm(pt - mic_pos[m])) / c
+            n_first = int(math.floor(tau * fs))
+            lo = max(n_first, 0)
+            hi = min(n_first + L + 2, n_samples)
+            if lo >= hi:
+                continue
+            n = np.arange(lo, hi)
+            x[m, lo:hi] += (a / r) * _chirp_at(n / fs - tau, f0, f1, T)
+    p_sig = float(np.mean(x * x))
+    if snr_db is not None and p_sig > 0:
+        sigma = math.sqrt(p_sig / (10.0 ** (snr_db / 10.0)))
+        x += rng_noise.normal(0.0, sigma, size=x.shape)
+    return x
+
+
+def _draw_reflectors(cfg: Config, rng: np.random.Generator):
+    out = []
+    for _ in range(cfg.n_reflectors):
+        r = rng.uniform(*cfg.r_range)
+        if cfg.planar_reflectors:
+            az = np.deg2rad(rng.uniform(-80.0, 80.0))
+            u = np.array([np.sin(az), 0.0, np.cos(az)])
+        else:
+            z = rng.uniform(0.0, 1.0)
+            ph = rng.uniform(0.0, 2 * np.pi)
+            s = math.sqrt(1.0 - z * z)
+            u = np.array([s * math.cos(ph), s * math.sin(ph), z])
+        a = rng.uniform(0.2, 1.0)
+        out.append((r, u, a))
+    return out
+
+
+def make_workload(name: str, frames: int = 1, sensor: int = 0, n_samples: int | None = None,
+                  n_dirs: int | None = None, n_mics: int | None = None,
+                  chirp_params=(25e3, 80e3, 1e-3)) -> Workload:
+    """Seeded synthetic batch of `frames` recordings of one sensor for a named config.
+
+    n_samples / n_dirs / n_mics override the config's sizes (for reduced test shapes);
+    the seeds stay those of the named config.
+    """
+    cfg = CONFIGS[name]
+    if n_samples is not None or n_mics is not None:
+        cfg = dataclasses.replace(cfg, n_samples=n_samples or cfg.n_samples,
+                                  n_mics=n_mics or cfg.n_mics)
+    mic_pos = planar_array(cfg.n_mics, cfg.aperture, _rng(cfg.cfg_id, sensor, 0, 0))
+    dirs = make_grid(cfg.grid) if n_dirs is None else fibonacci_hemisphere(n_dirs)
+    if n_dirs is not None and cfg.grid == "az91":
+        dirs = azimuth_grid(n_dirs, -90.0, 180.0 / max(n_dirs - 1, 1))
+    chirp = linear_chirp(FS_HZ, *chirp_params)
+    xs, refl = [], []
+    for f in range(frames):
+        rf = _draw_reflectors(cfg, _rng(cfg.cfg_id, sensor, f, 1))
+        x = simulate_frame(mic_pos, chirp_params, rf, cfg.n_samples, cfg.snr_db,
+                           _rng(cfg.cfg_id, sensor, f, 2))
+        xs.append(x.astype(np.float32))
+        refl.append(rf)
+    return Workload(cfg, np.stack(xs), chirp, mic_pos, dirs, refl)
