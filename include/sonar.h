@@ -1,0 +1,193 @@
+/*
+ * sonar.h -- C ABI of the MI355X energyscape library.
+ *
+ * One multi-microphone recording of a broadband FM sweep's echoes becomes one
+ * energyscape E[d][q]: the reflector intensity along range bin q for
+ * direction of interest d.  The pipeline is the one of the paper's processing
+ * chain (Fig. 3 caption; §4.1 Signal Processing; §4.3 GPU Algorithm
+ * Implementation): a matched filter against the emitted sweep, delay-and-sum
+ * beamforming toward every direction, and an envelope detector whose output
+ * is subsampled.  The exact arithmetic each call performs is written next to
+ * it below.
+ *
+ * DFT convention: X[k] = sum_n x[n] exp(-2 pi i k n / P),
+ *                 IDFT(X)[n] = (1/P) sum_k X[k] exp(+2 pi i k n / P).
+ *
+ * Conventions shared by every call
+ *  - Host arrays in the plan descriptor are copied by sonar_plan_create; the
+ *    caller may free them afterwards.
+ *  - Every pointer passed to an execution call is caller-owned DEVICE memory on
+ *    the device that was current when the plan was created, contiguous, 16-byte
+ *    aligned, laid out as stated.  The library never allocates during
+ *    execution: the plan owns all workspace, allocated once at creation (the
+ *    paper preallocates device memory for the same reason, §4.3).
+ *  - Execution calls only enqueue work on the given stream (no implicit
+ *    synchronisation).  One plan serves one stream at a time because its
+ *    workspace is shared between calls.
+ *  - Errors are negative status codes; nothing is thrown or aborted across the
+ *    ABI.  sonar_last_error() returns a thread-local message for the last
+ *    failing call on the calling thread.  Launch failures map to SONAR_E_HIP;
+ *    asynchronous device faults surface at the caller's next synchronisation.
+ *    NaN or Inf in the samples propagate unchecked.
+ */
+#ifndef SONAR_H
+#define SONAR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sonar_plan_s* sonar_plan;
+
+enum sonar_status {
+  SONAR_OK = 0,
+  SONAR_E_INVALID = -1,      /* bad argument (null pointer, size, range)            */
+  SONAR_E_NOMEM = -2,        /* device allocation failed, or above max_workspace    */
+  SONAR_E_HIP = -3,          /* a HIP runtime call or kernel launch failed          */
+  SONAR_E_UNSUPPORTED = -4   /* valid per the definition, not supported by the build */
+};
+
+/* Beamformer (§4.1: delay-and-sum steering toward each direction).
+ *  TD_LINEAR : fractional delay by linear interpolation between samples.
+ *  FD_FP32   : exact fractional delay as a per-frequency-bin phase, FP32.
+ *  FD_BF16   : as FD_FP32 with BF16 operands on MFMA, FP32 accumulation.   */
+enum sonar_bf_mode { SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2 };
+
+/* Element type of the microphone samples x. */
+enum sonar_dtype { SONAR_F32 = 0, SONAR_F16 = 1, SONAR_BF16 = 2 };
+
+typedef struct {
+  int32_t n_mics;            /* M >= 1 (the eRTIS has 32, §2)                               */
+  const double* mic_pos;     /* [M][3] microphone positions, metres                          */
+  int32_t chirp_len;         /* L >= 1                                                       */
+  const double* chirp;       /* [L] emitted sweep sampled at fs (the matched-filter template) */
+  double fs_hz;              /* sample rate (450 kHz on the eRTIS, §2)                       */
+  double c_mps;              /* speed of sound                                               */
+  int32_t n_dirs;            /* D >= 1                                                       */
+  const double* dirs;        /* [D][3] unit vectors, | |u| - 1 | <= 1e-9                      */
+  int32_t n_samples;         /* N samples per channel, N >= L                                */
+  int32_t gate_begin;        /* range gate [n0, n1) in matched-filter samples;              */
+  int32_t gate_end;          /*   0, 0 selects [0, N)                                        */
+  int32_t decim;             /* R >= 1, subsampling factor after the envelope (§4.3)        */
+  int32_t lpf_len;           /* K, odd; 0 selects the default low-pass (K = 8R + 1)          */
+  const double* lpf_taps;    /* [K] envelope low-pass taps, or NULL for the default          */
+  double band_lo_hz;         /* matched-filter band mask [lo, hi] in Hz;                    */
+  double band_hi_hz;         /*   0, 0 disables the mask                                     */
+  int32_t fft_len;           /* P: power of two >= N + L - 1; 0 selects the smallest        */
+  int32_t bf_mode;           /* enum sonar_bf_mode                                            */
+  int32_t sample_dtype;      /* enum sonar_dtype of x                                         */
+  int32_t max_frames;        /* F_max >= 1: the workspace is sized for this batch            */
+} sonar_plan_desc;
+
+/* Keys for sonar_plan_query. */
+enum sonar_query {
+  SONAR_Q_RANGE_BINS = 0,     /* Q = ceil((n1 - n0) / R)                                   */
+  SONAR_Q_BEAM_LEN = 1,       /* G' = (Q - 1) R + K: beam samples per direction            */
+  SONAR_Q_FFT_LEN = 2,        /* P                                                          */
+  SONAR_Q_MF_ROW = 3,         /* complex elements per microphone row of the MF buffer      */
+  SONAR_Q_MF_ORIGIN = 4,      /* TD: sample index n of MF row element 0 (may be negative)  */
+  SONAR_Q_BAND_LO_BIN = 5,    /* FD: first stored frequency bin                            */
+  SONAR_Q_BAND_BINS = 6,      /* FD: number of stored frequency bins Kb                    */
+  SONAR_Q_WORKSPACE_BYTES = 7,/* device bytes owned by the plan                            */
+  SONAR_Q_LPF_LEN = 8,        /* K                                                          */
+  SONAR_Q_MF_FRAME_ELEMS = 9  /* complex elements per frame of the MF buffer               */
+};
+
+/*
+ * sonar_plan_create -- validate the descriptor, copy it, allocate the plan's
+ * whole device workspace for max_frames frames, and build the plan tables on
+ * the device in FP64 (§4.1: the delay of every direction relative to every
+ * channel is computed up front):
+ *   Dl[d][m] = fs * (p_m . u_d) / c  samples;
+ *   TD: o = floor(-Dl), alpha = -Dl - o;
+ *   C[k] = beta[k] W[k] conj(S[k]), S = DFT_P(chirp), W the one-sided analytic
+ *   weights (1, 2, ..., 2, 1, 0, ...), beta the band mask;
+ *   FFT twiddles.
+ * The tables are built with work enqueued on `stream`; the call synchronises
+ * that stream before returning.  Returns SONAR_E_INVALID for a descriptor that
+ * breaks a rule stated above, SONAR_E_UNSUPPORTED for P > 32768, and
+ * SONAR_E_NOMEM when allocation fails.  *out is set only on success.
+ */
+int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_plan* out);
+
+/* Free every device buffer of the plan.  NULL is accepted.  The caller must
+ * make sure no work that uses the plan is still pending. */
+int sonar_plan_destroy(sonar_plan plan);
+
+/* Read one derived size of the plan (enum sonar_query) into *value. */
+int sonar_plan_query(sonar_plan plan, int32_t what, int64_t* value);
+
+/*
+ * sonar_matched_filter -- §4.1 matched filter, realised as an FFT filter with
+ * its group delay removed (§4.3):
+ *   yhat_m[n] = IDFT_P( beta W X_m conj(S) )[n],  X_m = DFT_P(x_m zero-padded),
+ * i.e. the analytic signal of the correlation sum_l s[l] x_m[n + l], circular
+ * in P.
+ *   x      : [F][M][N] samples of sample_dtype.
+ *   mf_out : complex64 (float re, im) buffer, SONAR_Q_MF_FRAME_ELEMS per frame.
+ *            TD mode: [F][M][row] with row = SONAR_Q_MF_ROW, element i holding
+ *            yhat_m[(origin + i) mod P], origin = SONAR_Q_MF_ORIGIN.
+ *            FD modes: [F][Kb][M] (bin-major), element (j, m) holding the
+ *            spectrum Yhat_m[k] = beta W X_m conj(S) at bin k = band_lo_bin + j
+ *            (Kb = SONAR_Q_BAND_BINS; bins outside are zero by definition).
+ *   F      : 1 <= F <= max_frames.
+ */
+int sonar_matched_filter(sonar_plan plan, const void* x, int32_t F, void* mf_out,
+                         hipStream_t stream);
+
+/*
+ * sonar_beamform -- §4.1 delay-and-sum toward every direction, evaluated on the
+ * beam window n = n0 - (K-1)/2 + i, i in [0, G'):
+ *   TD: b_d[n] = (1/M) sum_m (1 - a) yhat_m[n + o] + a yhat_m[n + o + 1],
+ *       (o, a) = (o[d][m], alpha[d][m]), indices mod P;
+ *   FD: b_d = IDFT_P( (1/M) sum_m Yhat_m[k] exp(-2 pi i k Dl[d][m] / P) ).
+ *   mf_in    : a buffer written by sonar_matched_filter with this plan.
+ *   beam_out : complex64 [F][D][G'].
+ */
+int sonar_beamform(sonar_plan plan, const void* mf_in, int32_t F, void* beam_out,
+                   hipStream_t stream);
+
+/*
+ * sonar_envelope -- §4.1 envelope and §4.3 subsampling:
+ *   E[d][q] = sum_{j<K} h[j] |b_d[n0 + q R + (K-1)/2 - j]|,  q in [0, Q),
+ * a zero-phase FIR low-pass of the beam magnitude read at every R-th sample.
+ *   beam_in : complex64 [F][D][G'] as written by sonar_beamform.
+ *   E       : float [F][D][Q].
+ */
+int sonar_envelope(sonar_plan plan, const void* beam_in, int32_t F, float* E,
+                   hipStream_t stream);
+
+/*
+ * sonar_beamform_envelope -- sonar_beamform followed by sonar_envelope with
+ * the beam kept on chip (it is never written to memory):
+ *   E[d][q] = sum_{j<K} h[j] |b_d[n0 + q R + (K-1)/2 - j]|,  b as in sonar_beamform.
+ *   mf_in : a buffer written by sonar_matched_filter with this plan.
+ *   E     : float [F][D][Q].
+ */
+int sonar_beamform_envelope(sonar_plan plan, const void* mf_in, int32_t F, float* E,
+                            hipStream_t stream);
+
+/*
+ * sonar_energyscape_batch -- the whole chain for F recordings that share the
+ * plan (geometry, directions, sweep): the result equals sonar_envelope(
+ * sonar_beamform(sonar_matched_filter(x))) up to floating-point reordering, but
+ * the beam is never written to memory.
+ *   x : [F][M][N] samples of sample_dtype;  E : float [F][D][Q].
+ */
+int sonar_energyscape_batch(sonar_plan plan, const void* x, int32_t F, float* E,
+                            hipStream_t stream);
+
+/* Static text for a status code. */
+const char* sonar_status_string(int status);
+
+/* Thread-local detail message of the last failing call on this thread ("" if none). */
+const char* sonar_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SONAR_H */

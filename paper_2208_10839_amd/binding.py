@@ -1,0 +1,265 @@
+"""Thin ctypes binding of the C ABI in include/sonar.h.
+
+Argument marshalling only: every step of the pipeline runs in the HIP
+library.  PyTorch supplies device memory (tensors) and the stream handle; the
+library never sees a torch type.  Loading fails loudly when the library has
+not been built: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "lib", "libsonar.so")
+
+SONAR_OK = 0
+SONAR_E_INVALID = -1
+SONAR_E_NOMEM = -2
+SONAR_E_HIP = -3
+SONAR_E_UNSUPPORTED = -4
+
+BF_MODES = {"td": 0, "fd_fp32": 1, "fd_bf16": 2}
+DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
+
+Q_RANGE_BINS, Q_BEAM_LEN, Q_FFT_LEN, Q_MF_ROW, Q_MF_ORIGIN = 0, 1, 2, 3, 4
+Q_BAND_LO_BIN, Q_BAND_BINS, Q_WORKSPACE_BYTES, Q_LPF_LEN, Q_MF_FRAME_ELEMS = 5, 6, 7, 8, 9
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class PlanDesc(ctypes.Structure):
+    """Mirror of sonar_plan_desc (field order and types as in include/sonar.h)."""
+    _fields_ = [
+        ("n_mics", ctypes.c_int32), ("mic_pos", _dp),
+        ("chirp_len", ctypes.c_int32), ("chirp", _dp),
+        ("fs_hz", ctypes.c_double), ("c_mps", ctypes.c_double),
+        ("n_dirs", ctypes.c_int32), ("dirs", _dp),
+        ("n_samples", ctypes.c_int32),
+        ("gate_begin", ctypes.c_int32), ("gate_end", ctypes.c_int32),
+        ("decim", ctypes.c_int32),
+        ("lpf_len", ctypes.c_int32), ("lpf_taps", _dp),
+        ("band_lo_hz", ctypes.c_double), ("band_hi_hz", ctypes.c_double),
+        ("fft_len", ctypes.c_int32),
+        ("bf_mode", ctypes.c_int32), ("sample_dtype", ctypes.c_int32), ("max_frames", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every function declared in include/sonar.h
+_SIGNATURES = {
+    "sonar_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sonar_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sonar_plan_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "sonar_matched_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_beamform": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_beamform_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_energyscape_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "sonar_last_error": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libsonar.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class SonarError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        lib = load()
+        msg = lib.sonar_last_error().decode()
+        super().__init__(f"{what}: {lib.sonar_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(status: int, what: str):
+    if status != SONAR_OK:
+        raise SonarError(status, what)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Plan:
+    """A plan: array geometry, sweep, directions and range gate, with its device workspace."""
+
+    def __init__(self, mic_pos, chirp, dirs, n_samples: int, *, fs: float, c: float,
+                 gate=None, decim: int = 10, taps=None, band=None, fft_len: int = 0,
+                 mode: str = "td", sample_dtype: str = "f32", max_frames: int = 1, stream=None):
+        lib = load()
+        self._keep = []
+        pos = _f64(mic_pos)
+        u = _f64(dirs)
+        s = _f64(chirp).reshape(-1)
+        h = None if taps is None else _f64(taps).reshape(-1)
+        self._keep += [pos, u, s, h]
+        d = PlanDesc()
+        d.n_mics = pos.shape[0]
+        d.mic_pos = _ptr(pos)
+        d.chirp_len = s.size
+        d.chirp = _ptr(s)
+        d.fs_hz = fs
+        d.c_mps = c
+        d.n_dirs = u.shape[0]
+        d.dirs = _ptr(u)
+        d.n_samples = int(n_samples)
+        d.gate_begin, d.gate_end = (0, 0) if gate is None else (int(gate[0]), int(gate[1]))
+        d.decim = int(decim)
+        d.lpf_len = 0 if h is None else h.size
+        d.lpf_taps = _ptr(h)
+        d.band_lo_hz, d.band_hi_hz = (0.0, 0.0) if band is None else (float(band[0]), float(band[1]))
+        d.fft_len = int(fft_len)
+        d.bf_mode = BF_MODES[mode]
+        d.sample_dtype = DTYPES[sample_dtype]
+        d.max_frames = int(max_frames)
+        self.mode = mode
+        self.sample_dtype = sample_dtype
+        self.M, self.D, self.N = d.n_mics, d.n_dirs, d.n_samples
+        self.max_frames = d.max_frames
+        handle = ctypes.c_void_p()
+        _check(lib.sonar_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(handle)),
+               "sonar_plan_create")
+        self._h = handle
+        self.Q = self.query(Q_RANGE_BINS)
+        self.G = self.query(Q_BEAM_LEN)
+        self.P = self.query(Q_FFT_LEN)
+        self.K = self.query(Q_LPF_LEN)
+        self.mf_row = self.query(Q_MF_ROW)
+        self.mf_origin = self.query(Q_MF_ORIGIN)
+        self.mf_frame_elems = self.query(Q_MF_FRAME_ELEMS)
+        self.band_lo_bin = self.query(Q_BAND_LO_BIN)
+        self.band_bins = self.query(Q_BAND_BINS)
+
+    # -- plumbing -------------------------------------------------------------
+    def query(self, what: int) -> int:
+        v = ctypes.c_int64()
+        _check(load().sonar_plan_query(self._h, what, ctypes.byref(v)), "sonar_plan_query")
+        return int(v.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().sonar_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _frames(self, t, per_frame_shape, what):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{what} must be a CUDA tensor")
+        if not t.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if tuple(t.shape[1:]) != tuple(per_frame_shape):
+            raise ValueError(f"{what} must have shape [F]{list(per_frame_shape)}, got {list(t.shape)}")
+        return t.shape[0]
+
+    def _samples(self, x):
+        import torch
+        want = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}[self.sample_dtype]
+        if x.dtype != want:
+            raise TypeError(f"x must be {want}, got {x.dtype}")
+        return self._frames(x, (self.M, self.N), "x")
+
+    def _out(self, out, shape, dtype, device):
+        import torch
+        if out is None:
+            return torch.empty(shape, dtype=dtype, device=device)
+        if tuple(out.shape) != tuple(shape) or out.dtype != dtype or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous {dtype} tensor of shape {list(shape)}")
+        return out
+
+    # -- pipeline -------------------------------------------------------------
+    def energyscape(self, x, out=None, stream=None):
+        """E[F][D][Q] (float32) for samples x[F][M][N]."""
+        import torch
+        F = self._samples(x)
+        E = self._out(out, (F, self.D, self.Q), torch.float32, x.device)
+        _check(load().sonar_energyscape_batch(self._h, ctypes.c_void_p(x.data_ptr()), F,
+                                              ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
+               "sonar_energyscape_batch")
+        return E
+
+    def matched_filter(self, x, out=None, stream=None):
+        """Matched-filter buffer, complex64 [F][mf_frame_elems] (layout per mode, see sonar.h)."""
+        import torch
+        F = self._samples(x)
+        mf = self._out(out, (F, self.mf_frame_elems), torch.complex64, x.device)
+        _check(load().sonar_matched_filter(self._h, ctypes.c_void_p(x.data_ptr()), F,
+                                           ctypes.c_void_p(mf.data_ptr()), _stream_handle(stream)),
+               "sonar_matched_filter")
+        return mf
+
+    def beamform(self, mf, out=None, stream=None):
+        """Beam window b[F][D][G'] (complex64) from a matched-filter buffer."""
+        import torch
+        F = self._frames(mf, (self.mf_frame_elems,), "mf")
+        b = self._out(out, (F, self.D, self.G), torch.complex64, mf.device)
+        _check(load().sonar_beamform(self._h, ctypes.c_void_p(mf.data_ptr()), F,
+                                     ctypes.c_void_p(b.data_ptr()), _stream_handle(stream)),
+               "sonar_beamform")
+        return b
+
+    def envelope(self, beam, out=None, stream=None):
+        """E[F][D][Q] from a beam window b[F][D][G']."""
+        import torch
+        F = self._frames(beam, (self.D, self.G), "beam")
+        E = self._out(out, (F, self.D, self.Q), torch.float32, beam.device)
+        _check(load().sonar_envelope(self._h, ctypes.c_void_p(beam.data_ptr()), F,
+                                     ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
+               "sonar_envelope")
+        return E
+
+    def beamform_envelope(self, mf, out=None, stream=None):
+        """E[F][D][Q] from a matched-filter buffer, beam kept on chip."""
+        import torch
+        F = self._frames(mf, (self.mf_frame_elems,), "mf")
+        E = self._out(out, (F, self.D, self.Q), torch.float32, mf.device)
+        _check(load().sonar_beamform_envelope(self._h, ctypes.c_void_p(mf.data_ptr()), F,
+                                              ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
+               "sonar_beamform_envelope")
+        return E
+
+
+def header_functions(header_path=None):
+    """Names of the functions declared in include/sonar.h."""
+    import re
+    if header_path is None:
+        header_path = os.path.join(os.path.dirname(PKG), "include", "sonar.h")
+    with open(header_path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sonar_[a-z_]+)\s*\(", text)))

@@ -1,0 +1,201 @@
+// Matched-filter kernels (§4.1 matched filter; §4.3 FFT-convolution filters
+// with the group delay removed).
+//
+// Per channel (frame f, microphone m) one workgroup computes
+//   Yhat[k] = X[k] C[k],  X = DFT_P(x zero-padded),  C = beta W conj(S),
+// for k in [0, P/2] (C vanishes above P/2), and, for the time-domain
+// beamformer, the analytic matched-filter output
+//   yhat[n] = IDFT_P(Yhat)[n].
+// The real input is packed as z[n] = x[2n] + i x[2n+1] into an NF = P/2 point
+// complex FFT and split afterwards (X[k] = E[k] + exp(-2 pi i k/P) O[k]).
+// Because Yhat vanishes above NF, the inverse splits by output parity:
+//   yhat[2a + r] = (1/P) ( sum_{k<NF} Yhat[k] exp(2 pi i k r/P) exp(2 pi i k a/NF)
+//                          + Yhat[NF] (-1)^r ),
+// two NF-point inverse FFTs, one workgroup each, reading the spectrum that the
+// forward kernel left in the plan's workspace (L2/MALL resident at these sizes).
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include "fft_lds.hpp"
+#include "plan.hpp"
+
+using namespace fftk;
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ float to_f32(T v);
+template <>
+__device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <>
+__device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+template <>
+__device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
+
+// Loads the twiddle tables of the plan into LDS.
+template <int LOGNF>
+__device__ __forceinline__ void load_tw(float2* tw, const float2* __restrict__ tw_g, int tid, int nthreads) {
+  constexpr int NF = 1 << LOGNF;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int LEN = NHI + 64 + (NF / 64 + 1) + 64;
+  for (int i = tid; i < LEN; i += nthreads) tw[i] = tw_g[i];
+}
+
+// Forward transform of one channel and the matched-filter product.  On return
+// lds holds Yhat[0..NF) (padded layout), *nyq holds Yhat[NF].
+template <int LOGNF, typename TIn>
+__device__ __forceinline__ void forward_mf(const TIn* __restrict__ x, int N,
+                                           const float2* __restrict__ cspec, float2* lds,
+                                           const float2* tw, float2* nyq, int tid) {
+  using S = FftShape<LOGNF>;
+  constexpr int NF = S::NF;
+  constexpr int T = S::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  const float2* tw_hi = tw;
+  const float2* tw_lo = tw + NHI;
+  const float2* twp_hi = tw + NHI + 64;                 // exp(-2 pi i 64 t / P)
+  const float2* twp_lo = tw + NHI + 64 + (NF / 64 + 1);   // exp(-2 pi i t / P)
+
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int n = tid + r * (NF / 16);
+    const int i0 = 2 * n;
+    const float a = i0 < N ? to_f32<TIn>(x[i0]) : 0.0f;
+    const float b = i0 + 1 < N ? to_f32<TIn>(x[i0 + 1]) : 0.0f;
+    v[r] = make_float2(a, b);
+  }
+  fft_lds<LOGNF, false>(v, lds, tw_hi, tw_lo, tid);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lds[padi(S::out_index(tid, i))] = v[i];
+  __syncthreads();
+  // split the packed transform into the real signal's spectrum and apply C
+  for (int k = tid; k <= NF / 2; k += T) {
+    const float2 A = lds[padi(k)];
+    const float2 B = lds[padi((NF - k) & (NF - 1))];
+    const float2 Ek = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));      // (A + conj B)/2
+    const float2 Ok = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));     // (A - conj B)/(2i)
+    const float2 wk = cmul(twp_hi[k >> 6], twp_lo[k & 63]);                     // exp(-2 pi i k / P)
+    const float2 wo = cmul(wk, Ok);
+    const float2 Xk = cadd(Ek, wo);
+    const float2 Xm = cconj(csub(Ek, wo));                                      // X[NF - k]
+    lds[padi(k)] = cmul(Xk, cspec[k]);
+    if (k == 0) {
+      *nyq = cmul(Xm, cspec[NF]);
+    } else if (k != NF / 2) {
+      lds[padi(NF - k)] = cmul(Xm, cspec[NF - k]);
+    }
+  }
+  __syncthreads();
+}
+
+// Forward transform and matched-filter product of one channel per workgroup;
+// writes the one-sided spectrum Yhat[0..NF] to spec[ch][0..NF].
+template <int LOGNF, typename TIn>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
+    const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
+    const float2* __restrict__ tw_g, float2* __restrict__ spec) {
+  using S = FftShape<LOGNF>;
+  constexpr int NF = S::NF;
+  constexpr int T = S::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  __shared__ float2 nyq;
+  const int tid = threadIdx.x;
+  const long long ch = blockIdx.x;                       // f * M + m
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
+  float2* out = spec + ch * (NF + 1);
+  for (int k = tid; k < NF; k += T) out[k] = lds[padi(k)];
+  if (tid == 0) out[NF] = nyq;
+}
+
+// Inverse transform of one output parity of one channel per workgroup:
+//   yhat[2a + par] = (1/P) (IDFT'_NF(Yhat[k] exp(2 pi i k par / P))[a] + Yhat[NF] (-1)^par)
+// written to the MF rows: element j of a row holds yhat[(origin + j) mod P].
+template <int LOGNF>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
+    const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
+    int row, int origin, int P) {
+  using S = FftShape<LOGNF>;
+  constexpr int NF = S::NF;
+  constexpr int T = S::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  const int tid = threadIdx.x;
+  const int par = blockIdx.x & 1;
+  const long long ch = blockIdx.x >> 1;
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  const float2* tw_hi = tw;
+  const float2* tw_lo = tw + NHI;
+  const float2* twp_hi = tw + NHI + 64;
+  const float2* twp_lo = tw + NHI + 64 + (NF / 64 + 1);
+  const float2* in = spec + ch * (NF + 1);
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k = tid + r * (NF / 16);
+    v[r] = in[k];
+    if (par) v[r] = cmul(v[r], cconj(cmul(twp_hi[k >> 6], twp_lo[k & 63])));   // exp(+2 pi i k / P)
+  }
+  const float2 ny = in[NF];
+  fft_lds<LOGNF, true>(v, lds, tw_hi, tw_lo, tid);
+  const float inv_p = 1.0f / static_cast<float>(P);
+  const float sgn = par ? -1.0f : 1.0f;
+  float2* out = yext + ch * row;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int n = 2 * S::out_index(tid, i) + par;
+    const float2 y = make_float2((v[i].x + sgn * ny.x) * inv_p, (v[i].y + sgn * ny.y) * inv_p);
+    for (int j = (n - origin) & (P - 1); j < row; j += P) out[j] = y;
+  }
+}
+
+template <int LOGNF, typename TIn>
+hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+  constexpr int T = (1 << LOGNF) / 16;
+  hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
+                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
+                     p->d_spec, p->d_tw, yext, p->row, static_cast<int>(p->origin), p->P);
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t launch_mf_td_dt(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+  switch (p->logNF) {
+    case 4: return launch_mf_td_t<4, TIn>(p, x, F, yext, s);
+    case 5: return launch_mf_td_t<5, TIn>(p, x, F, yext, s);
+    case 6: return launch_mf_td_t<6, TIn>(p, x, F, yext, s);
+    case 7: return launch_mf_td_t<7, TIn>(p, x, F, yext, s);
+    case 8: return launch_mf_td_t<8, TIn>(p, x, F, yext, s);
+    case 9: return launch_mf_td_t<9, TIn>(p, x, F, yext, s);
+    case 10: return launch_mf_td_t<10, TIn>(p, x, F, yext, s);
+    case 11: return launch_mf_td_t<11, TIn>(p, x, F, yext, s);
+    case 12: return launch_mf_td_t<12, TIn>(p, x, F, yext, s);
+    case 13: return launch_mf_td_t<13, TIn>(p, x, F, yext, s);
+    case 14: return launch_mf_td_t<14, TIn>(p, x, F, yext, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+  switch (p->dtype) {
+    case SONAR_F32: return launch_mf_td_dt<float>(p, x, F, yext, s);
+    case SONAR_F16: return launch_mf_td_dt<__half>(p, x, F, yext, s);
+    case SONAR_BF16: return launch_mf_td_dt<__hip_bfloat16>(p, x, F, yext, s);
+    default: return hipErrorInvalidValue;
+  }
+}

@@ -1,0 +1,76 @@
+// Internal plan object and kernel launchers of the energyscape library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+#include "sonar.h"
+
+// Tile shape of the time-domain beamformer: one wavefront per direction,
+// TD_NW directions per workgroup, TD_NB blocks of 64 consecutive beam samples
+// per wavefront (one sample per lane).
+constexpr int TD_NB = 16;
+constexpr int TD_NW = 16;
+constexpr int TD_LDS_BYTES = 160 * 1024 - 4096;   // staging budget per workgroup
+
+struct sonar_plan_s {
+  // descriptor (copied)
+  int M = 0, L = 0, D = 0, N = 0;
+  int n0 = 0, n1 = 0, R = 1, K = 0;
+  int P = 0, NF = 0, logNF = 0;
+  int bf_mode = 0, dtype = 0, max_frames = 1;
+  double fs = 0, c = 0, band_lo = 0, band_hi = 0;
+  bool band_on = false;
+
+  // derived sizes
+  int Q = 0;            // range bins
+  int G = 0;            // beam window length G' = (Q-1)R + K
+  int hk = 0;           // (K-1)/2
+  int omin = 0, omax = 0, spread = 0;   // bounds of o = floor(-Dl) over all (d, m)
+  int64_t origin = 0;   // sample index of MF row element 0 (TD)
+  int row = 0;          // complex elements per MF row (TD)
+
+  // time-domain beamformer tiling
+  int td_ws = 0;        // staged samples per microphone
+  int td_mc = 0;        // microphones staged per pass
+  int td_tn = 0;        // valid beam samples per wavefront tile (64*NB - 1)
+  int td_qc = 0;        // range bins per tile
+  int td_nqc = 0;       // range-bin tiles
+  int td_nbc = 0;       // beam-sample tiles (beamform-only kernel)
+
+  // frequency-domain layout
+  int k_lo = 0, kb = 0;
+
+  int device = 0;
+  size_t ws_bytes = 0;
+
+  // device buffers (owned)
+  int4* d_dtab = nullptr;      // [D][M] {o - omin, bits((1-a)/M), bits(a/M), 0}
+  double* d_dl = nullptr;      // [D][M] delays in samples (FP64)
+  double* d_pos = nullptr;     // [M][3]
+  double* d_dirs = nullptr;    // [D][3]
+  double* d_chirp = nullptr;   // [L]
+  float* d_taps = nullptr;     // [K]
+  float2* d_cspec = nullptr;   // [NF+1] beta W conj(S)
+  float2* d_tw = nullptr;      // FFT twiddle tables (see fft layout)
+  float2* d_mf = nullptr;      // MF workspace, [max_frames][M][row]
+  float2* d_spec = nullptr;    // one-sided MF spectra, [max_frames][M][NF+1]
+  void* d_aux = nullptr;       // plan-build scratch
+};
+
+// FFT twiddle table layout inside d_tw (all FP32 values built from FP64):
+//   [0, nhi)              : exp(-2 pi i * 64 * t / NF)   t < nhi = max(NF/64, 1)
+//   [nhi, nhi+64)         : exp(-2 pi i * t / NF)        t < 64
+//   [nhi+64, +nhp)        : exp(-2 pi i * 64 * t / P)    t < nhp = NF/64 + 1
+//   [.., +64)             : exp(-2 pi i * t / P)         t < 64
+__host__ __device__ inline int fft_nhi(int NF) { return NF / 64 > 0 ? NF / 64 : 1; }
+__host__ __device__ inline int fft_nhp(int NF) { return NF / 64 + 1; }
+__host__ __device__ inline int fft_tw_len(int NF) { return fft_nhi(NF) + 64 + fft_nhp(NF) + 64; }
+
+hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
+hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
+hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, float2* beam, hipStream_t s);
+hipError_t launch_envelope(const sonar_plan_s* p, const float2* beam, int F, float* E, hipStream_t s);
+hipError_t init_td_kernel_attributes();

@@ -1,0 +1,363 @@
+// C ABI of the energyscape library: plan creation (validation, derived sizes,
+// one-time allocation of all device memory, FP64 table build) and the
+// execution entry points, which only enqueue kernels.
+//
+// The paper preallocates every device buffer once when the processing node
+// starts and frees it at shutdown, because per-measurement allocation cost
+// performance (§4.3); the plan object is that preallocation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+#include "sonar.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SONAR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int ilog2(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Default envelope low-pass: K = 8R + 1 Hamming-windowed sinc with cutoff
+// fs/(2R), normalised to unit DC gain (zero phase about its centre tap).
+std::vector<double> default_lowpass(int R) {
+  const int K = 8 * R + 1;
+  std::vector<double> h(K);
+  const double pi = 3.14159265358979323846;
+  double sum = 0.0;
+  for (int j = 0; j < K; ++j) {
+    const double w = 0.54 - 0.46 * std::cos(2.0 * pi * j / (K - 1));
+    const double t = (j - (K - 1) / 2.0) / R;
+    const double sinc = t == 0.0 ? 1.0 : std::sin(pi * t) / (pi * t);
+    h[j] = w * sinc;
+    sum += h[j];
+  }
+  for (double& v : h) v /= sum;
+  return h;
+}
+
+void free_plan(sonar_plan_s* p) {
+  if (!p) return;
+  (void)hipFree(p->d_dtab);
+  (void)hipFree(p->d_dl);
+  (void)hipFree(p->d_pos);
+  (void)hipFree(p->d_dirs);
+  (void)hipFree(p->d_chirp);
+  (void)hipFree(p->d_taps);
+  (void)hipFree(p->d_cspec);
+  (void)hipFree(p->d_tw);
+  (void)hipFree(p->d_mf);
+  (void)hipFree(p->d_spec);
+  (void)hipFree(p->d_aux);
+  delete p;
+}
+
+template <typename T>
+hipError_t dev_alloc(T** ptr, size_t count, size_t* total) {
+  const size_t bytes = count * sizeof(T);
+  *total += bytes;
+  return hipMalloc(reinterpret_cast<void**>(ptr), bytes > 0 ? bytes : 16);
+}
+
+bool finite_all(const double* v, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
+  if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
+  if (!a || !b) return fail(SONAR_E_INVALID, "NULL buffer");
+  if (F < 1 || F > p->max_frames)
+    return fail(SONAR_E_INVALID, "F=%d outside [1, max_frames=%d]", F, p->max_frames);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(SONAR_E_INVALID, "current device %d is not the plan's device %d", dev, p->device);
+  return SONAR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sonar_status_string(int status) {
+  switch (status) {
+    case SONAR_OK: return "success";
+    case SONAR_E_INVALID: return "invalid argument";
+    case SONAR_E_NOMEM: return "out of device memory";
+    case SONAR_E_HIP: return "HIP runtime error";
+    case SONAR_E_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+  }
+}
+
+const char* sonar_last_error(void) { return g_last_error.c_str(); }
+
+int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_plan* out) {
+  g_last_error.clear();
+  if (!desc || !out) return fail(SONAR_E_INVALID, "desc or out is NULL");
+  const sonar_plan_desc& d = *desc;
+  if (d.n_mics < 1 || !d.mic_pos) return fail(SONAR_E_INVALID, "n_mics must be >= 1 with mic_pos");
+  if (d.chirp_len < 1 || !d.chirp) return fail(SONAR_E_INVALID, "chirp_len must be >= 1 with chirp");
+  if (d.n_dirs < 1 || !d.dirs) return fail(SONAR_E_INVALID, "n_dirs must be >= 1 with dirs");
+  if (!(d.fs_hz > 0) || !std::isfinite(d.fs_hz)) return fail(SONAR_E_INVALID, "fs_hz must be > 0");
+  if (!(d.c_mps > 0) || !std::isfinite(d.c_mps)) return fail(SONAR_E_INVALID, "c_mps must be > 0");
+  if (d.n_samples < d.chirp_len) return fail(SONAR_E_INVALID, "n_samples must be >= chirp_len");
+  if (d.decim < 1) return fail(SONAR_E_INVALID, "decim must be >= 1");
+  if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
+  if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
+    return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_FD_BF16)
+    return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
+  if (d.bf_mode != SONAR_BF_TD_LINEAR)
+    return fail(SONAR_E_UNSUPPORTED, "frequency-domain beamformer not built in this library version");
+  if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
+      !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
+      !finite_all(d.chirp, static_cast<size_t>(d.chirp_len)))
+    return fail(SONAR_E_INVALID, "non-finite geometry, direction or chirp value");
+  for (int i = 0; i < d.n_dirs; ++i) {
+    const double* u = d.dirs + 3 * i;
+    const double n = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (std::fabs(n - 1.0) > 1e-9) return fail(SONAR_E_INVALID, "direction %d is not a unit vector", i);
+  }
+
+  auto* p = new (std::nothrow) sonar_plan_s();
+  if (!p) return fail(SONAR_E_NOMEM, "host allocation failed");
+  p->M = d.n_mics;
+  p->L = d.chirp_len;
+  p->D = d.n_dirs;
+  p->N = d.n_samples;
+  p->R = d.decim;
+  p->fs = d.fs_hz;
+  p->c = d.c_mps;
+  p->bf_mode = d.bf_mode;
+  p->dtype = d.sample_dtype;
+  p->max_frames = d.max_frames;
+  p->n0 = d.gate_begin;
+  p->n1 = d.gate_end;
+  if (p->n0 == 0 && p->n1 == 0) p->n1 = p->N;
+  if (p->n0 < 0 || p->n0 >= p->n1 || p->n1 > p->N) {
+    delete p;
+    return fail(SONAR_E_INVALID, "gate [%d, %d) outside [0, N=%d)", d.gate_begin, d.gate_end, d.n_samples);
+  }
+  p->band_lo = d.band_lo_hz;
+  p->band_hi = d.band_hi_hz;
+  p->band_on = !(d.band_lo_hz == 0.0 && d.band_hi_hz == 0.0);
+  if (p->band_on && !(d.band_lo_hz >= 0.0 && d.band_hi_hz >= d.band_lo_hz)) {
+    delete p;
+    return fail(SONAR_E_INVALID, "band must satisfy 0 <= lo <= hi");
+  }
+
+  // FFT length
+  const long long need = static_cast<long long>(p->N) + p->L - 1;
+  long long P = d.fft_len;
+  if (P == 0) {
+    P = 32;
+    while (P < need) P *= 2;
+  } else if (!is_pow2(P) || P < need || P < 32) {
+    delete p;
+    return fail(SONAR_E_INVALID, "fft_len %d must be a power of two >= max(N + L - 1, 32)", d.fft_len);
+  }
+  if (P > 32768) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "FFT length %lld above 32768 is not supported", P);
+  }
+  p->P = static_cast<int>(P);
+  p->NF = p->P / 2;
+  p->logNF = ilog2(p->NF);
+
+  // envelope low-pass
+  std::vector<double> taps;
+  if (d.lpf_len == 0) {
+    taps = default_lowpass(p->R);
+  } else {
+    if (d.lpf_len < 1 || (d.lpf_len % 2) == 0 || !d.lpf_taps) {
+      delete p;
+      return fail(SONAR_E_INVALID, "lpf_len must be odd with lpf_taps (or 0 for the default)");
+    }
+    if (!finite_all(d.lpf_taps, static_cast<size_t>(d.lpf_len))) {
+      delete p;
+      return fail(SONAR_E_INVALID, "non-finite low-pass tap");
+    }
+    taps.assign(d.lpf_taps, d.lpf_taps + d.lpf_len);
+  }
+  p->K = static_cast<int>(taps.size());
+  p->hk = (p->K - 1) / 2;
+  p->Q = (p->n1 - p->n0 + p->R - 1) / p->R;
+  p->G = (p->Q - 1) * p->R + p->K;
+
+  // bounds of the integer offset o = floor(-Dl): |Dl| <= fs |p_m| / c (|u| = 1)
+  double bmax = 0.0;
+  for (int m = 0; m < p->M; ++m) {
+    const double* q = d.mic_pos + 3 * m;
+    bmax = std::fmax(bmax, std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * p->fs / p->c);
+  }
+  bmax = bmax * (1.0 + 1e-9) + 1e-9;
+  p->omin = static_cast<int>(std::floor(-bmax)) - 1;
+  p->omax = static_cast<int>(std::floor(bmax)) + 1;
+  p->spread = p->omax - p->omin;
+
+  // time-domain tiling
+  p->td_tn = 64 * TD_NB - 1;
+  if (p->K > p->td_tn) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "low-pass length %d above %d is not supported", p->K, p->td_tn);
+  }
+  if (p->spread > 4096) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "array aperture too large (%d samples of delay spread)", p->spread);
+  }
+  p->td_qc = (p->td_tn - p->K) / p->R + 1;
+  p->td_nqc = (p->Q + p->td_qc - 1) / p->td_qc;
+  p->td_nbc = (p->G + p->td_tn - 1) / p->td_tn;
+  p->td_ws = 64 * TD_NB + p->spread;
+  p->td_ws += p->td_ws & 1;
+  int mc = TD_LDS_BYTES / (p->td_ws * static_cast<int>(sizeof(float2)));
+  p->td_mc = mc < p->M ? mc : p->M;
+  const long long need_env = static_cast<long long>(p->td_nqc - 1) * p->td_qc * p->R + p->td_ws;
+  const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + p->td_ws;
+  long long row = need_env > need_beam ? need_env : need_beam;
+  row = (row + 3) / 4 * 4;
+  p->row = static_cast<int>(row);
+  p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
+
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(SONAR_E_HIP, "hipGetDevice failed");
+  }
+  hipError_t e = init_td_kernel_attributes();
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e, "kernel attributes");
+  }
+
+  // one-time allocation of every device buffer
+  size_t total = 0;
+  const size_t dm = static_cast<size_t>(p->D) * p->M;
+  const size_t mf_elems = static_cast<size_t>(p->max_frames) * p->M * p->row;
+  const size_t aux_bytes = static_cast<size_t>(p->P) * sizeof(double2);
+  bool ok = dev_alloc(&p->d_dtab, dm, &total) == hipSuccess &&
+            dev_alloc(&p->d_dl, dm, &total) == hipSuccess &&
+            dev_alloc(&p->d_pos, 3 * static_cast<size_t>(p->M), &total) == hipSuccess &&
+            dev_alloc(&p->d_dirs, 3 * static_cast<size_t>(p->D), &total) == hipSuccess &&
+            dev_alloc(&p->d_chirp, static_cast<size_t>(p->L), &total) == hipSuccess &&
+            dev_alloc(&p->d_taps, static_cast<size_t>(p->K), &total) == hipSuccess &&
+            dev_alloc(&p->d_cspec, static_cast<size_t>(p->NF) + 1, &total) == hipSuccess &&
+            dev_alloc(&p->d_tw, static_cast<size_t>(fft_tw_len(p->NF)), &total) == hipSuccess &&
+            dev_alloc(&p->d_mf, mf_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_spec, static_cast<size_t>(p->max_frames) * p->M * (p->NF + 1), &total) == hipSuccess &&
+            dev_alloc(reinterpret_cast<char**>(&p->d_aux), aux_bytes, &total) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_plan(p);
+    return fail(SONAR_E_NOMEM, "device allocation of %zu bytes failed", total);
+  }
+  p->ws_bytes = total;
+
+  std::vector<float> taps_f(taps.begin(), taps.end());
+  ok = hipMemcpyAsync(p->d_pos, d.mic_pos, 3 * sizeof(double) * p->M, hipMemcpyHostToDevice, stream) == hipSuccess &&
+       hipMemcpyAsync(p->d_dirs, d.dirs, 3 * sizeof(double) * p->D, hipMemcpyHostToDevice, stream) == hipSuccess &&
+       hipMemcpyAsync(p->d_chirp, d.chirp, sizeof(double) * p->L, hipMemcpyHostToDevice, stream) == hipSuccess &&
+       hipMemcpyAsync(p->d_taps, taps_f.data(), sizeof(float) * p->K, hipMemcpyHostToDevice, stream) == hipSuccess;
+  if (!ok) {
+    e = hipGetLastError();
+    free_plan(p);
+    return hip_fail(e, "plan upload");
+  }
+  e = launch_build_tables(p, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "plan table build");
+  }
+  *out = p;
+  return SONAR_OK;
+}
+
+int sonar_plan_destroy(sonar_plan plan) {
+  free_plan(plan);
+  return SONAR_OK;
+}
+
+int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
+  if (!p || !value) return fail(SONAR_E_INVALID, "plan or value is NULL");
+  switch (what) {
+    case SONAR_Q_RANGE_BINS: *value = p->Q; break;
+    case SONAR_Q_BEAM_LEN: *value = p->G; break;
+    case SONAR_Q_FFT_LEN: *value = p->P; break;
+    case SONAR_Q_MF_ROW: *value = p->row; break;
+    case SONAR_Q_MF_ORIGIN: *value = p->origin; break;
+    case SONAR_Q_BAND_LO_BIN: *value = p->k_lo; break;
+    case SONAR_Q_BAND_BINS: *value = p->kb; break;
+    case SONAR_Q_WORKSPACE_BYTES: *value = static_cast<int64_t>(p->ws_bytes); break;
+    case SONAR_Q_LPF_LEN: *value = p->K; break;
+    case SONAR_Q_MF_FRAME_ELEMS: *value = static_cast<int64_t>(p->M) * p->row; break;
+    default: return fail(SONAR_E_INVALID, "unknown query key %d", what);
+  }
+  return SONAR_OK;
+}
+
+int sonar_matched_filter(sonar_plan p, const void* x, int32_t F, void* mf_out, hipStream_t stream) {
+  int st = check_exec(p, x, mf_out, F);
+  if (st != SONAR_OK) return st;
+  hipError_t e = launch_mf_td(p, x, F, static_cast<float2*>(mf_out), stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "matched filter launch");
+}
+
+int sonar_beamform(sonar_plan p, const void* mf_in, int32_t F, void* beam_out, hipStream_t stream) {
+  int st = check_exec(p, mf_in, beam_out, F);
+  if (st != SONAR_OK) return st;
+  hipError_t e = launch_das_td_beam(p, static_cast<const float2*>(mf_in), F, static_cast<float2*>(beam_out), stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform launch");
+}
+
+int sonar_envelope(sonar_plan p, const void* beam_in, int32_t F, float* E, hipStream_t stream) {
+  int st = check_exec(p, beam_in, E, F);
+  if (st != SONAR_OK) return st;
+  hipError_t e = launch_envelope(p, static_cast<const float2*>(beam_in), F, E, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "envelope launch");
+}
+
+int sonar_beamform_envelope(sonar_plan p, const void* mf_in, int32_t F, float* E, hipStream_t stream) {
+  int st = check_exec(p, mf_in, E, F);
+  if (st != SONAR_OK) return st;
+  hipError_t e = launch_das_td_env(p, static_cast<const float2*>(mf_in), F, E, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform-envelope launch");
+}
+
+int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hipStream_t stream) {
+  int st = check_exec(p, x, E, F);
+  if (st != SONAR_OK) return st;
+  hipError_t e = launch_mf_td(p, x, F, p->d_mf, stream);
+  if (e == hipSuccess) e = launch_das_td_env(p, p->d_mf, F, E, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape launch");
+}
+
+}  // extern "C"
