@@ -31,29 +31,55 @@ __device__ __forceinline__ float from_next_lane(float v, int lane) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(((lane + 1) & 63) << 2, __float_as_int(v)));
 }
 
+// Accumulates A[n] = sum_m w0 yhat_m[n + o] and C[n] = sum_m w1 yhat_m[n + o]
+// for this wavefront's direction over all microphones.  Microphones are
+// consumed in groups of at most NW rows held in LDS; wavefront w copies row w
+// of a group with back-to-back 16-byte loads (one address register plus
+// immediate offsets), then stores them.  The table entries (o - omin, w0, w1)
+// of the wavefront's direction sit one microphone per lane (up to 128 mics)
+// and are broadcast with readlane.
 template <int NB, int NW>
 __device__ __forceinline__ void das_accumulate(const float2* __restrict__ yrow0, long long row,
                                                const int4* __restrict__ dtab_d, int M, int mc, int ws,
-                                               bool active, float2* smem, float2 (&A)[NB],
-                                               float2 (&C)[NB], int lane) {
+                                               bool active, float2 (&A)[NB], float2 (&C)[NB],
+                                               int wv, int lane) {
+  extern __shared__ float2 smem[];
+  constexpr int MAXL = TD_MAX_ROW_PAIRS / 64;   // 16-byte loads per lane for the longest row
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     A[t] = make_float2(0.f, 0.f);
     C[t] = make_float2(0.f, 0.f);
   }
+  int4 ent0 = make_int4(0, 0, 0, 0), ent1 = make_int4(0, 0, 0, 0);
+  if (active) {
+    if (lane < M) ent0 = dtab_d[lane];
+    if (lane + 64 < M) ent1 = dtab_d[lane + 64];
+  }
   for (int m0 = 0; m0 < M; m0 += mc) {
-    const int mcc = M - m0 < mc ? M - m0 : mc;
-    for (int ml = 0; ml < mcc; ++ml) {
-      const float2* src = yrow0 + static_cast<long long>(m0 + ml) * row;
-      float2* dst = smem + ml * ws;
-      for (int t = threadIdx.x; t < ws; t += NW * 64) dst[t] = src[t];
+    const int rows = M - m0 < mc ? M - m0 : mc;
+    if (wv < rows) {
+      // rows are staged whole: 64 * MAXL pairs per row (ws = 128 * MAXL samples);
+      // the matched-filter rows are padded so these loads stay in the allocation
+      const float4* src = reinterpret_cast<const float4*>(yrow0 + static_cast<long long>(m0 + wv) * row) + lane;
+      float4* dst = reinterpret_cast<float4*>(smem + wv * ws) + lane;
+      float4 stage[MAXL];
+#pragma unroll
+      for (int j = 0; j < MAXL; ++j) stage[j] = src[64 * j];
+#pragma unroll
+      for (int j = 0; j < MAXL; ++j) dst[64 * j] = stage[j];
     }
     __syncthreads();
     if (active) {
-      for (int ml = 0; ml < mcc; ++ml) {
-        const int4 e = dtab_d[m0 + ml];
-        const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.z);
-        const float2* p = smem + ml * ws + e.x + lane;
+      const float2* cur = smem + lane;
+#pragma unroll 2
+      for (int ml = 0; ml < rows; ++ml) {
+        const int m = m0 + ml;
+        const int src_lane = m & 63;
+        const int4 e4 = m < 64 ? ent0 : ent1;
+        const int rel = __builtin_amdgcn_readlane(e4.x, src_lane);
+        const float w0 = __int_as_float(__builtin_amdgcn_readlane(e4.y, src_lane));
+        const float w1 = __int_as_float(__builtin_amdgcn_readlane(e4.z, src_lane));
+        const float2* p = cur + ml * ws + rel;
 #pragma unroll
         for (int t = 0; t < NB; ++t) {
           const float2 y = p[64 * t];
@@ -76,7 +102,7 @@ __device__ __forceinline__ float2 beam_sample(const float2 (&A)[NB], const float
 }
 
 template <int NB, int NW>
-__global__ __launch_bounds__(NW * 64) void das_td_env_kernel(
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_env_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, const float* __restrict__ taps,
     float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc, int nqc, int ws, int mc) {
   extern __shared__ float2 smem[];
@@ -95,7 +121,7 @@ __global__ __launch_bounds__(NW * 64) void das_td_env_kernel(
   float2 A[NB], C[NB];
   das_accumulate<NB, NW>(yext + static_cast<long long>(f) * M * row + i0, row,
                          dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
-                         smem, A, C, lane);
+                         A, C, wv, lane);
 
   float* absb = reinterpret_cast<float*>(smem);
 #pragma unroll
@@ -117,7 +143,7 @@ __global__ __launch_bounds__(NW * 64) void das_td_env_kernel(
 }
 
 template <int NB, int NW>
-__global__ __launch_bounds__(NW * 64) void das_td_beam_kernel(
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_beam_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, float2* __restrict__ beam,
     int M, int D, int G, int row, int tc, int nbc, int ws, int mc) {
   extern __shared__ float2 smem[];
@@ -136,7 +162,7 @@ __global__ __launch_bounds__(NW * 64) void das_td_beam_kernel(
   float2 A[NB], C[NB];
   das_accumulate<NB, NW>(yext + static_cast<long long>(f) * M * row + i0, row,
                          dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
-                         smem, A, C, lane);
+                         A, C, wv, lane);
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     const float2 b = beam_sample<NB>(A, C, t, lane);

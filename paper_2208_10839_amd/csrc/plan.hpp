@@ -11,8 +11,11 @@
 // TD_NW directions per workgroup, TD_NB blocks of 64 consecutive beam samples
 // per wavefront (one sample per lane).
 constexpr int TD_NB = 16;
-constexpr int TD_NW = 16;
-constexpr int TD_LDS_BYTES = 160 * 1024 - 4096;   // staging budget per workgroup
+constexpr int TD_NW = 8;
+constexpr int TD_WAVES_PER_EU = 4;   // two workgroups per CU (80 KiB LDS each): 128 VGPRs per lane
+constexpr int TD_LDS_BYTES = 80 * 1024;    // LDS budget of one beamformer workgroup
+constexpr int TD_MAX_MICS = 128;
+constexpr int TD_MAX_ROW_PAIRS = 640;   // staged row = 1280 samples: delay spread <= 1280 - 64 * TD_NB - 1
 
 struct sonar_plan_s {
   // descriptor (copied)

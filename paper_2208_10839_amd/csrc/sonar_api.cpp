@@ -230,19 +230,38 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     delete p;
     return fail(SONAR_E_UNSUPPORTED, "low-pass length %d above %d is not supported", p->K, p->td_tn);
   }
-  if (p->spread > 4096) {
+  if (p->M > TD_MAX_MICS) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "more than %d microphones is not supported", TD_MAX_MICS);
+  }
+  if (64 * TD_NB + p->spread + 1 > 2 * TD_MAX_ROW_PAIRS) {
     delete p;
     return fail(SONAR_E_UNSUPPORTED, "array aperture too large (%d samples of delay spread)", p->spread);
   }
+  // tile starts in the MF rows must be even (16-byte aligned copies into LDS)
   p->td_qc = (p->td_tn - p->K) / p->R + 1;
+  if ((p->td_qc * p->R) & 1) p->td_qc -= 1;
+  if (p->td_qc < 1) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "low-pass length %d too long for decimation %d", p->K, p->R);
+  }
+  p->td_tn -= p->td_tn & 1;
   p->td_nqc = (p->Q + p->td_qc - 1) / p->td_qc;
   p->td_nbc = (p->G + p->td_tn - 1) / p->td_tn;
-  p->td_ws = 64 * TD_NB + p->spread;
-  p->td_ws += p->td_ws & 1;
+  // staged row length (LDS row stride): a fixed 2 * TD_MAX_ROW_PAIRS samples,
+  // enough for 64 * TD_NB beam samples plus the delay spread
+  p->td_ws = 2 * TD_MAX_ROW_PAIRS;
+  // one LDS buffer holds mc microphone rows of ws samples, one row per wavefront
   int mc = TD_LDS_BYTES / (p->td_ws * static_cast<int>(sizeof(float2)));
+  if (mc > TD_NW) mc = TD_NW;
+  if (mc < 1) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "array aperture too large for the beamformer tile");
+  }
   p->td_mc = mc < p->M ? mc : p->M;
-  const long long need_env = static_cast<long long>(p->td_nqc - 1) * p->td_qc * p->R + p->td_ws;
-  const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + p->td_ws;
+  // every staging copy reads 2 * TD_MAX_ROW_PAIRS samples from its tile start
+  const long long need_env = static_cast<long long>(p->td_nqc - 1) * p->td_qc * p->R + 2 * TD_MAX_ROW_PAIRS;
+  const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + 2 * TD_MAX_ROW_PAIRS;
   long long row = need_env > need_beam ? need_env : need_beam;
   row = (row + 3) / 4 * 4;
   p->row = static_cast<int>(row);
