@@ -52,9 +52,16 @@ enum sonar_status {
 
 /* Beamformer (§4.1: delay-and-sum steering toward each direction).
  *  TD_LINEAR : fractional delay by linear interpolation between samples.
- *  FD_FP32   : exact fractional delay as a per-frequency-bin phase, FP32.
- *  FD_BF16   : as FD_FP32 with BF16 operands on MFMA, FP32 accumulation.   */
-enum sonar_bf_mode { SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2 };
+ *  FD_FP32   : exact fractional delay as a per-frequency-bin phase; the
+ *              per-bin complex product over microphones runs in FP32.
+ *  FD_BF16   : as FD_FP32 on BF16 MFMA with FP32 accumulation: the
+ *              steering operand is rounded to one BF16 term, the sample
+ *              operand is carried as two BF16 terms (hi + lo), two products.
+ *  FD_BF16X3 : as FD_BF16 with each operand split into two BF16 terms
+ *              (hi + lo) and three products (hi*hi + hi*lo + lo*hi).         */
+enum sonar_bf_mode {
+  SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3
+};
 
 /* Element type of the microphone samples x. */
 enum sonar_dtype { SONAR_F32 = 0, SONAR_F16 = 1, SONAR_BF16 = 2 };

@@ -71,7 +71,6 @@ __device__ __forceinline__ void das_accumulate(const float2* __restrict__ yrow0,
     __syncthreads();
     if (active) {
       const float2* cur = smem + lane;
-#pragma unroll 2
       for (int ml = 0; ml < rows; ++ml) {
         const int m = m0 + ml;
         const int src_lane = m & 63;

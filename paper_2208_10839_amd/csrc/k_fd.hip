@@ -1,0 +1,420 @@
+// Frequency-domain beamformer (§4.1 delay-and-sum toward every direction of
+// interest, with each channel's delay applied exactly as a per-bin phase) and
+// its envelope (§4.1 envelope; §4.3 subsampling after envelope detection):
+//
+//   B_d[k]  = sum_m (1/M) exp(-2 pi i k Dl[d][m] / P) Yhat_m[k]      (per-bin GEMM)
+//   b_d[n]  = IDFT_P(B_d)[n]                                          (per direction)
+//   E[d][q] = sum_j h[j] |b_d[n0 + qR + (K-1)/2 - j]|
+//
+// Per frequency bin the product over microphones is a small complex GEMM
+// (directions x microphones) x (microphones x frames): it is dense when many
+// frames share one geometry, and runs on MFMA.  The steering matrix is never
+// stored: each lane rebuilds its slice bin by bin from an FP64-anchored phasor
+// and an FP64-derived per-bin rotation.
+//
+// The stored spectra are band-limited to kb bins starting at k_lo, so the
+// inverse transform of one direction runs as R' = P / L polyphase transforms
+// of L points (L >= kb - 1):
+//   b_d[R' a + r] = (1/P) exp(2 pi i k_lo n / P)
+//                   ( IDFT'_L( B'[k'] exp(2 pi i k' r / P) )[a] + B'[L] exp(2 pi i r / R') ),
+// with B'[k'] = B_d[k_lo + k'] and IDFT' unnormalised; the last term exists
+// only when kb = L + 1.  The envelope needs |b| only, so the exp(2 pi i k_lo n/P)
+// factor drops out of the fused kernel.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.hpp"
+#include "plan.hpp"
+
+using namespace fftk;
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int MODE_FP32 = SONAR_BF_FD_FP32;
+constexpr int MODE_BF16 = SONAR_BF_FD_BF16;
+constexpr int MODE_BF16X3 = SONAR_BF_FD_BF16X3;
+
+// ---------------------------------------------------------------------------
+// Per-bin GEMM.  Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS bins,
+// up to 16 frames.  Lane l builds the steering values of direction l % 16 of
+// its wavefront for 8 microphones and supplies the samples of frame l % 16 for
+// the same 8 microphones, matching the MFMA operand layouts:
+//   v_mfma_f32_16x16x32_bf16: lane l holds A[l%16][8(l/16) + j], B[8(l/16) + j][l%16]
+//   v_mfma_f32_16x16x4_f32:   lane l holds A[l%16][l/16],        B[l/16][l%16]
+// (microphone of slot j: 8(l/16) + j for BF16, 4j + l/16 for FP32 MFMA), and
+// receives D[4(l/16) + i][l%16] (direction 4(l/16) + i, frame l%16).
+// Real embedding: Cr = Ar Yr - Ai Yi, Ci = Ai Yr + Ar Yi.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bf16x8 to_bf16x8(const float (&v)[8]) {
+  bf16x8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r[j] = static_cast<__bf16>(v[j]);
+  return r;
+}
+
+// hi = bf16(v), lo = bf16(v - hi)
+__device__ __forceinline__ void split_bf16x8(const float (&v)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const __bf16 h = static_cast<__bf16>(v[j]);
+    hi[j] = h;
+    lo[j] = static_cast<__bf16>(v[j] - static_cast<float>(h));
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fd_gemm_kernel(
+    const float2* __restrict__ band, const double* __restrict__ dl, float2* __restrict__ bspec,
+    int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt) {
+  constexpr int NBIN = FD_GEMM_BINS;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  int bid = blockIdx.x;
+  const int bt = bid % nbt;
+  bid /= nbt;
+  const int dt = bid % ndt;
+  const int ft = bid / ndt;
+  const int k0 = bt * NBIN;                 // first stored bin of the tile
+  const int r16 = lane & 15, grp = lane >> 4;
+  const int d_st = dt * FD_GEMM_DIRS + wv * 16 + r16;    // direction this lane steers
+  const int f_ld = ft * FD_GEMM_FRAMES + r16;           // frame this lane loads
+  const bool d_ok = d_st < D, f_ok = f_ld < F;
+  const double invP = 1.0 / static_cast<double>(P);
+
+  f32x4 cr[NBIN], ci[NBIN];
+#pragma unroll
+  for (int b = 0; b < NBIN; ++b) {
+    cr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+    ci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+
+  for (int mc = 0; mc < M; mc += 32) {
+    // phasors exp(-2 pi i k Dl / P) / M at the tile's first bin, and the per-bin rotation
+    float phr[8], phi[8], str[8], sti[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
+      phr[j] = phi[j] = str[j] = sti[j] = 0.f;
+      if (d_ok && m < M) {
+        const double Dl = dl[static_cast<long long>(d_st) * M + m];
+        const double t = static_cast<double>(k_lo + k0) * Dl * invP;
+        const double fr = t - floor(t);
+        double s, c;
+        sincospi(-2.0 * fr, &s, &c);
+        phr[j] = static_cast<float>(c / M);
+        phi[j] = static_cast<float>(s / M);
+        double s1, c1;
+        sincospi(-2.0 * Dl * invP, &s1, &c1);
+        str[j] = static_cast<float>(c1);
+        sti[j] = static_cast<float>(s1);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NBIN; ++b) {
+      const int kk = k0 + b;
+      if (kk >= kb) break;
+      float ar[8], ai[8], nai[8], yr[8], yi[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        ar[j] = phr[j];
+        ai[j] = phi[j];
+        nai[j] = -phi[j];
+        const float nr = phr[j] * str[j] - phi[j] * sti[j];
+        const float ni = phr[j] * sti[j] + phi[j] * str[j];
+        phr[j] = nr;
+        phi[j] = ni;
+        const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
+        float2 y = make_float2(0.f, 0.f);
+        if (f_ok && m < M) y = band[(static_cast<long long>(f_ld) * kb + kk) * M + m];
+        yr[j] = y.x;
+        yi[j] = y.y;
+      }
+      if constexpr (MODE == MODE_FP32) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yr[j], cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[j], yi[j], cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[j], yr[j], ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yi[j], ci[b], 0, 0, 0);
+        }
+      } else if constexpr (MODE == MODE_BF16) {
+        // steering in one BF16 term, samples in two (hi + lo): two products
+        const bf16x8 Ar = to_bf16x8(ar), Ai = to_bf16x8(ai), nAi = to_bf16x8(nai);
+        bf16x8 Yrh, Yrl, Yih, Yil;
+        split_bf16x8(yr, Yrh, Yrl);
+        split_bf16x8(yi, Yih, Yil);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrh, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrl, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yih, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yil, cr[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrh, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrl, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yih, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yil, ci[b], 0, 0, 0);
+      } else {
+        bf16x8 Arh, Arl, Aih, Ail, nAih, nAil, Yrh, Yrl, Yih, Yil;
+        split_bf16x8(ar, Arh, Arl);
+        split_bf16x8(ai, Aih, Ail);
+        split_bf16x8(nai, nAih, nAil);
+        split_bf16x8(yr, Yrh, Yrl);
+        split_bf16x8(yi, Yih, Yil);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrh, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrl, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yrh, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yih, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yil, cr[b], 0, 0, 0);
+        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAil, Yih, cr[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrh, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrl, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ail, Yrh, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yih, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yil, ci[b], 0, 0, 0);
+        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yih, ci[b], 0, 0, 0);
+      }
+    }
+  }
+
+  // lane holds (direction 4 grp + i, frame r16) for the tile's bins: 16
+  // consecutive bins of one output row, written as 16-byte pairs
+  const int f_out = ft * FD_GEMM_FRAMES + r16;
+  if (f_out < F) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int d_out = dt * FD_GEMM_DIRS + wv * 16 + 4 * grp + i;
+      if (d_out < D) {
+        float4* dst = reinterpret_cast<float4*>(bspec + (static_cast<long long>(f_out) * D + d_out) * kb_pad + k0);
+#pragma unroll
+        for (int b = 0; b < NBIN; b += 2) dst[b / 2] = make_float4(cr[b][i], ci[b][i], cr[b + 1][i], ci[b + 1][i]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Polyphase inverse transforms.
+// ---------------------------------------------------------------------------
+
+template <int LOGL>
+struct FdTw {
+  static constexpr int L = 1 << LOGL;
+  static constexpr int LH = L / 64 > 0 ? L / 64 : 1;
+};
+
+// Loads the phase-r input of one direction: thread t holds B'[k'] exp(2 pi i k' r / P)
+// for k' = t + s L/16; returns the extra-bin term B'[L] exp(2 pi i r / R').
+template <int LOGL>
+__device__ __forceinline__ float2 load_phase(const float2* __restrict__ in, int kb, int r, const float2* twp_hi,
+                                             const float2* twp_lo, float2 (&v)[16], int tid) {
+  constexpr int L = 1 << LOGL;
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = tid + s * (L / 16);
+    float2 x = make_float2(0.f, 0.f);
+    if (k < kb) {
+      x = in[k];
+      if (r != 0) {
+        const int e = k * r;
+        x = cmul(x, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
+      }
+    }
+    v[s] = x;
+  }
+  float2 extra = make_float2(0.f, 0.f);
+  if (kb == L + 1) {
+    extra = in[L];
+    if (r != 0) {
+      const int e = L * r;
+      extra = cmul(extra, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
+    }
+  }
+  return extra;
+}
+
+template <int LOGL>
+__device__ __forceinline__ void load_fd_tw(float2* tw, const float2* __restrict__ tw_g, int P, int tid, int nt) {
+  const int len = FdTw<LOGL>::LH + 64 + P / 64 + 1 + 64;
+  for (int i = tid; i < len; i += nt) tw[i] = tw_g[i];
+}
+
+constexpr int FD_MAX_TW_P = 32768 / 64 + 1 + 64;   // P tables for P <= 32768
+
+template <int LOGL>
+__global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
+    const float2* __restrict__ bspec, const float2* __restrict__ tw_g, const float* __restrict__ taps,
+    float* __restrict__ E, int kb, int kb_pad, int Rp, int P, int n0, int Q, int R, int K) {
+  using S = FftShape<LOGL>;
+  constexpr int L = S::NF;
+  constexpr int T = S::T;
+  constexpr int LH = FdTw<LOGL>::LH;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[LH + 64 + FD_MAX_TW_P];
+  __shared__ float hs[FD_MAX_TAPS];
+  const int tid = threadIdx.x;
+  const long long fd = blockIdx.x;            // f * D + d
+  load_fd_tw<LOGL>(tw, tw_g, P, tid, T);
+  for (int j = tid; j < K; j += T) hs[j] = taps[j];
+  __syncthreads();
+  const float2* tw_hi = tw;
+  const float2* tw_lo = tw + LH;
+  const float2* twp_hi = tw + LH + 64;
+  const float2* twp_lo = tw + LH + 64 + P / 64 + 1;
+  const float2* in = bspec + fd * kb_pad;
+  const float invP = 1.0f / static_cast<float>(P);
+  const int hk = (K - 1) / 2;
+  float* mag = reinterpret_cast<float*>(lds);
+  float acc[FD_QPT];
+#pragma unroll
+  for (int i = 0; i < FD_QPT; ++i) acc[i] = 0.f;
+
+  for (int r = 0; r < Rp; ++r) {
+    float2 v[16];
+    const float2 extra = load_phase<LOGL>(in, kb, r, twp_hi, twp_lo, v, tid);
+    fft_lds<LOGL, true>(v, lds, tw_hi, tw_lo, tid);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const float ux = v[i].x + extra.x, uy = v[i].y + extra.y;
+      mag[S::out_index(tid, i)] = sqrtf(ux * ux + uy * uy) * invP;
+    }
+    __syncthreads();
+    // taps of output q that read samples of this phase: n = n_q + hk - j = R' a + r (mod P)
+#pragma unroll
+    for (int i = 0; i < FD_QPT; ++i) {
+      const int q = tid + i * T;
+      if (q < Q) {
+        const int nq = n0 + q * R + hk;                 // sample read by tap 0
+        int j = (nq - r) % Rp;
+        if (j < 0) j += Rp;
+        int nm = (nq - j) % P;
+        if (nm < 0) nm += P;
+        int a = (nm - r) / Rp;
+        float s = 0.f;
+        for (; j < K; j += Rp) {
+          s = fmaf(hs[j], mag[a], s);
+          a = a == 0 ? L - 1 : a - 1;
+        }
+        acc[i] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < FD_QPT; ++i) {
+    const int q = tid + i * T;
+    if (q < Q) E[fd * Q + q] = acc[i];
+  }
+}
+
+// Beam window of one phase of one direction: b at n = R' a + r, written to
+// beam[f][d][n - (n0 - hk) mod P] for window positions below G.
+template <int LOGL>
+__global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_beam_kernel(
+    const float2* __restrict__ bspec, const float2* __restrict__ tw_g, float2* __restrict__ beam,
+    int kb, int kb_pad, int Rp, int P, int k_lo, int n_start, int G) {
+  using S = FftShape<LOGL>;
+  constexpr int T = S::T;
+  constexpr int LH = FdTw<LOGL>::LH;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[LH + 64 + FD_MAX_TW_P];
+  const int tid = threadIdx.x;
+  const int r = blockIdx.x % Rp;
+  const long long fd = blockIdx.x / Rp;
+  load_fd_tw<LOGL>(tw, tw_g, P, tid, T);
+  __syncthreads();
+  const float2* tw_hi = tw;
+  const float2* tw_lo = tw + LH;
+  const float2* twp_hi = tw + LH + 64;
+  const float2* twp_lo = tw + LH + 64 + P / 64 + 1;
+  float2 v[16];
+  const float2 extra = load_phase<LOGL>(bspec + fd * kb_pad, kb, r, twp_hi, twp_lo, v, tid);
+  fft_lds<LOGL, true>(v, lds, tw_hi, tw_lo, tid);
+  const float invP = 1.0f / static_cast<float>(P);
+  float2* out = beam + fd * G;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const long long n = static_cast<long long>(Rp) * S::out_index(tid, i) + r;
+    const int e = static_cast<int>((static_cast<long long>(k_lo) * n) % P);   // exp(2 pi i k_lo n / P)
+    const float2 rot = cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63]));
+    const float2 y = cmul(make_float2((v[i].x + extra.x) * invP, (v[i].y + extra.y) * invP), rot);
+    for (int j = static_cast<int>((n - n_start) & (P - 1)); j < G; j += P) out[j] = y;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s) {
+  const int nbt = p->kb_pad / FD_GEMM_BINS;
+  const int ndt = (p->D + FD_GEMM_DIRS - 1) / FD_GEMM_DIRS;
+  const int nft = (F + FD_GEMM_FRAMES - 1) / FD_GEMM_FRAMES;
+  const dim3 grid(static_cast<unsigned>(nbt) * ndt * nft);
+  switch (p->bf_mode) {
+    case SONAR_BF_FD_FP32:
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_FP32>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+      break;
+    case SONAR_BF_FD_BF16:
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+      break;
+    case SONAR_BF_FD_BF16X3:
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16X3>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int LOGL>
+hipError_t launch_env_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16), 0, s,
+                     bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, p->P, p->n0, p->Q, p->R, p->K);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  switch (p->fd_logL) {
+    case 4: return launch_env_t<4>(p, bspec, F, E, s);
+    case 5: return launch_env_t<5>(p, bspec, F, E, s);
+    case 6: return launch_env_t<6>(p, bspec, F, E, s);
+    case 7: return launch_env_t<7>(p, bspec, F, E, s);
+    case 8: return launch_env_t<8>(p, bspec, F, E, s);
+    case 9: return launch_env_t<9>(p, bspec, F, E, s);
+    case 10: return launch_env_t<10>(p, bspec, F, E, s);
+    case 11: return launch_env_t<11>(p, bspec, F, E, s);
+    case 12: return launch_env_t<12>(p, bspec, F, E, s);
+    case 13: return launch_env_t<13>(p, bspec, F, E, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int LOGL>
+hipError_t launch_beam_t(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s) {
+  hipLaunchKernelGGL((fd_ifft_beam_kernel<LOGL>), dim3(static_cast<unsigned>(F) * p->D * p->fd_R),
+                     dim3((1 << LOGL) / 16), 0, s, bspec, p->d_fdtw, beam, p->kb, p->kb_pad, p->fd_R, p->P,
+                     p->k_lo, p->n0 - p->hk, p->G);
+  return hipGetLastError();
+}
+
+hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s) {
+  switch (p->fd_logL) {
+    case 4: return launch_beam_t<4>(p, bspec, F, beam, s);
+    case 5: return launch_beam_t<5>(p, bspec, F, beam, s);
+    case 6: return launch_beam_t<6>(p, bspec, F, beam, s);
+    case 7: return launch_beam_t<7>(p, bspec, F, beam, s);
+    case 8: return launch_beam_t<8>(p, bspec, F, beam, s);
+    case 9: return launch_beam_t<9>(p, bspec, F, beam, s);
+    case 10: return launch_beam_t<10>(p, bspec, F, beam, s);
+    case 11: return launch_beam_t<11>(p, bspec, F, beam, s);
+    case 12: return launch_beam_t<12>(p, bspec, F, beam, s);
+    case 13: return launch_beam_t<13>(p, bspec, F, beam, s);
+    case 14: return launch_beam_t<14>(p, bspec, F, beam, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t init_fd_kernel_attributes() { return hipSuccess; }

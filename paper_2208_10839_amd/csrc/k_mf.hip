@@ -159,6 +159,60 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   }
 }
 
+// Forward transform and matched-filter product of one channel per workgroup;
+// writes the band bins [k_lo, k_lo + kb) bin-major: band[f][k'][m].
+template <int LOGNF, typename TIn>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_band_kernel(
+    const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
+    const float2* __restrict__ tw_g, float2* __restrict__ band, int M, int k_lo, int kb) {
+  using S = FftShape<LOGNF>;
+  constexpr int NF = S::NF;
+  constexpr int T = S::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  __shared__ float2 nyq;
+  const int tid = threadIdx.x;
+  const long long ch = blockIdx.x;                       // f * M + m
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
+  const long long f = ch / M;
+  const int m = static_cast<int>(ch - f * M);
+  float2* out = band + f * kb * M + m;
+  for (int j = tid; j < kb; j += T) {
+    const int k = k_lo + j;
+    out[static_cast<long long>(j) * M] = k < NF ? lds[padi(k)] : nyq;
+  }
+}
+
+template <int LOGNF, typename TIn>
+hipError_t launch_mf_band_t(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s) {
+  constexpr int T = (1 << LOGNF) / 16;
+  hipLaunchKernelGGL((mf_fwd_band_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
+                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, band, p->M, p->k_lo, p->kb);
+  return hipGetLastError();
+}
+
+template <typename TIn>
+hipError_t launch_mf_band_dt(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s) {
+  switch (p->logNF) {
+    case 4: return launch_mf_band_t<4, TIn>(p, x, F, band, s);
+    case 5: return launch_mf_band_t<5, TIn>(p, x, F, band, s);
+    case 6: return launch_mf_band_t<6, TIn>(p, x, F, band, s);
+    case 7: return launch_mf_band_t<7, TIn>(p, x, F, band, s);
+    case 8: return launch_mf_band_t<8, TIn>(p, x, F, band, s);
+    case 9: return launch_mf_band_t<9, TIn>(p, x, F, band, s);
+    case 10: return launch_mf_band_t<10, TIn>(p, x, F, band, s);
+    case 11: return launch_mf_band_t<11, TIn>(p, x, F, band, s);
+    case 12: return launch_mf_band_t<12, TIn>(p, x, F, band, s);
+    case 13: return launch_mf_band_t<13, TIn>(p, x, F, band, s);
+    case 14: return launch_mf_band_t<14, TIn>(p, x, F, band, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int LOGNF, typename TIn>
 hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
   constexpr int T = (1 << LOGNF) / 16;
@@ -196,6 +250,15 @@ hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yex
     case SONAR_F32: return launch_mf_td_dt<float>(p, x, F, yext, s);
     case SONAR_F16: return launch_mf_td_dt<__half>(p, x, F, yext, s);
     case SONAR_BF16: return launch_mf_td_dt<__hip_bfloat16>(p, x, F, yext, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s) {
+  switch (p->dtype) {
+    case SONAR_F32: return launch_mf_band_dt<float>(p, x, F, band, s);
+    case SONAR_F16: return launch_mf_band_dt<__half>(p, x, F, band, s);
+    case SONAR_BF16: return launch_mf_band_dt<__hip_bfloat16>(p, x, F, band, s);
     default: return hipErrorInvalidValue;
   }
 }

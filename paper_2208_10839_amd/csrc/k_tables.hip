@@ -79,7 +79,29 @@ __global__ void fft_twiddle_kernel(float2* __restrict__ tw, int NF, int P) {
   tw[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
 }
 
+// FD twiddles (layout: fd_tw_len in plan.hpp)
+__global__ void fd_twiddle_kernel(float2* __restrict__ tw, int L, int P) {
+  const int lh = L / 64 > 0 ? L / 64 : 1;
+  const int ph = P / 64 + 1;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= lh + 64 + ph + 64) return;
+  double num, den;
+  if (i < lh) { num = 64.0 * i; den = L; }
+  else if (i < lh + 64) { num = i - lh; den = L; }
+  else if (i < lh + 64 + ph) { num = 64.0 * (i - lh - 64); den = P; }
+  else { num = i - lh - 64 - ph; den = P; }
+  double s, c;
+  sincospi(-2.0 * num / den, &s, &c);
+  tw[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
+}
+
 }  // namespace
+
+hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s) {
+  const int n = fd_tw_len(p->fd_L, p->P);
+  hipLaunchKernelGGL(fd_twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p->d_fdtw, p->fd_L, p->P);
+  return hipGetLastError();
+}
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;

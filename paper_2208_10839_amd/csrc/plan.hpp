@@ -42,8 +42,14 @@ struct sonar_plan_s {
   int td_nqc = 0;       // range-bin tiles
   int td_nbc = 0;       // beam-sample tiles (beamform-only kernel)
 
-  // frequency-domain layout
+  // frequency-domain layout: stored band bins [k_lo, k_lo + kb); the
+  // per-direction inverse transform runs as fd_R polyphase transforms of
+  // fd_L = P / fd_R points (fd_L >= kb - 1; a bin at k' = fd_L adds a constant
+  // per phase)
   int k_lo = 0, kb = 0;
+  int kb_pad = 0;       // row stride (bins) of the per-direction spectra
+  int fd_L = 0, fd_logL = 0, fd_R = 0;
+  bool fd_fused = false;   // fd_L small enough for the fused inverse + envelope kernel
 
   int device = 0;
   size_t ws_bytes = 0;
@@ -59,6 +65,10 @@ struct sonar_plan_s {
   float2* d_tw = nullptr;      // FFT twiddle tables (see fft layout)
   float2* d_mf = nullptr;      // MF workspace, [max_frames][M][row]
   float2* d_spec = nullptr;    // one-sided MF spectra, [max_frames][M][NF+1]
+  float2* d_fdspec = nullptr;  // FD: band spectra of the MF output, [max_frames][kb][M]
+  float2* d_bspec = nullptr;   // FD: beam spectra, [max_frames][D][kb_pad]
+  float2* d_fdtw = nullptr;    // FD: twiddles for fd_L and P (layout: fd_tw_len)
+  float2* d_beam = nullptr;    // FD fallback: beam window [max_frames][D][G'] (unfused plans only)
   void* d_aux = nullptr;       // plan-build scratch
 };
 
@@ -71,7 +81,27 @@ __host__ __device__ inline int fft_nhi(int NF) { return NF / 64 > 0 ? NF / 64 : 
 __host__ __device__ inline int fft_nhp(int NF) { return NF / 64 + 1; }
 __host__ __device__ inline int fft_tw_len(int NF) { return fft_nhi(NF) + 64 + fft_nhp(NF) + 64; }
 
+// FD twiddle layout inside d_fdtw:
+//   [0, lh)            : exp(-2 pi i * 64 * t / L)   t < lh = max(L/64, 1)
+//   [lh, lh+64)        : exp(-2 pi i * t / L)        t < 64
+//   [lh+64, +P/64+1)   : exp(-2 pi i * 64 * t / P)   t <= P/64
+//   [.., +64)          : exp(-2 pi i * t / P)        t < 64
+__host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L / 64 : 1) + 64 + P / 64 + 1 + 64; }
+
+constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
+constexpr int FD_GEMM_BINS = 16;       // bins per FD GEMM workgroup
+constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
+constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
+constexpr int FD_QPT = 8;              // range bins per thread in the fused FD inverse + envelope kernel
+constexpr int FD_MAX_TAPS = 1024;
+
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
+hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s);
+hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
+hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);
+hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
+hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
+hipError_t init_fd_kernel_attributes();
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
 hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, float2* beam, hipStream_t s);

@@ -75,6 +75,10 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_tw);
   (void)hipFree(p->d_mf);
   (void)hipFree(p->d_spec);
+  (void)hipFree(p->d_fdspec);
+  (void)hipFree(p->d_bspec);
+  (void)hipFree(p->d_beam);
+  (void)hipFree(p->d_fdtw);
   (void)hipFree(p->d_aux);
   delete p;
 }
@@ -134,10 +138,8 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_FD_BF16)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_FD_BF16X3)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
-  if (d.bf_mode != SONAR_BF_TD_LINEAR)
-    return fail(SONAR_E_UNSUPPORTED, "frequency-domain beamformer not built in this library version");
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
       !finite_all(d.chirp, static_cast<size_t>(d.chirp_len)))
@@ -267,6 +269,34 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   p->row = static_cast<int>(row);
   p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
 
+  // frequency-domain layout: the stored bins are exactly those the band mask keeps
+  if (p->band_on) {
+    int lo = -1, hi = -1;
+    for (int k = 0; k <= p->NF; ++k) {
+      const double f = static_cast<double>(k) * (p->fs / static_cast<double>(p->P));
+      if (f >= p->band_lo && f <= p->band_hi) {
+        if (lo < 0) lo = k;
+        hi = k;
+      }
+    }
+    if (lo < 0) {
+      delete p;
+      return fail(SONAR_E_INVALID, "band [%g, %g] Hz holds no frequency bin", p->band_lo, p->band_hi);
+    }
+    p->k_lo = lo;
+    p->kb = hi - lo + 1;
+  } else {
+    p->k_lo = 0;
+    p->kb = p->NF + 1;
+  }
+  p->kb_pad = (p->kb + FD_GEMM_BINS - 1) / FD_GEMM_BINS * FD_GEMM_BINS;
+  p->fd_L = 16;
+  while (p->fd_L < p->kb - 1) p->fd_L *= 2;
+  p->fd_logL = ilog2(p->fd_L);
+  p->fd_R = p->P / p->fd_L;
+  p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->Q <= FD_QPT * (p->fd_L / 16) && p->K <= FD_MAX_TAPS;
+  const bool fd = p->bf_mode != SONAR_BF_TD_LINEAR;
+
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(SONAR_E_HIP, "hipGetDevice failed");
@@ -280,7 +310,12 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   // one-time allocation of every device buffer
   size_t total = 0;
   const size_t dm = static_cast<size_t>(p->D) * p->M;
-  const size_t mf_elems = static_cast<size_t>(p->max_frames) * p->M * p->row;
+  const size_t mf_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->M * p->row;
+  const size_t spec_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->M * (p->NF + 1);
+  const size_t band_elems = fd ? static_cast<size_t>(p->max_frames) * p->kb * p->M : 0;
+  const size_t bspec_elems = fd ? static_cast<size_t>(p->max_frames) * p->D * p->kb_pad : 0;
+  const size_t beam_elems = fd && !p->fd_fused ? static_cast<size_t>(p->max_frames) * p->D * p->G : 0;
+  const size_t fdtw_elems = fd ? static_cast<size_t>(fd_tw_len(p->fd_L, p->P)) : 0;
   const size_t aux_bytes = static_cast<size_t>(p->P) * sizeof(double2);
   bool ok = dev_alloc(&p->d_dtab, dm, &total) == hipSuccess &&
             dev_alloc(&p->d_dl, dm, &total) == hipSuccess &&
@@ -291,7 +326,11 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
             dev_alloc(&p->d_cspec, static_cast<size_t>(p->NF) + 1, &total) == hipSuccess &&
             dev_alloc(&p->d_tw, static_cast<size_t>(fft_tw_len(p->NF)), &total) == hipSuccess &&
             dev_alloc(&p->d_mf, mf_elems, &total) == hipSuccess &&
-            dev_alloc(&p->d_spec, static_cast<size_t>(p->max_frames) * p->M * (p->NF + 1), &total) == hipSuccess &&
+            dev_alloc(&p->d_spec, spec_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_fdspec, band_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_bspec, bspec_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_beam, beam_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_fdtw, fdtw_elems, &total) == hipSuccess &&
             dev_alloc(reinterpret_cast<char**>(&p->d_aux), aux_bytes, &total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -311,6 +350,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     return hip_fail(e, "plan upload");
   }
   e = launch_build_tables(p, stream);
+  if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     free_plan(p);
@@ -337,7 +377,10 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
     case SONAR_Q_BAND_BINS: *value = p->kb; break;
     case SONAR_Q_WORKSPACE_BYTES: *value = static_cast<int64_t>(p->ws_bytes); break;
     case SONAR_Q_LPF_LEN: *value = p->K; break;
-    case SONAR_Q_MF_FRAME_ELEMS: *value = static_cast<int64_t>(p->M) * p->row; break;
+    case SONAR_Q_MF_FRAME_ELEMS:
+      *value = p->bf_mode == SONAR_BF_TD_LINEAR ? static_cast<int64_t>(p->M) * p->row
+                                                : static_cast<int64_t>(p->kb) * p->M;
+      break;
     default: return fail(SONAR_E_INVALID, "unknown query key %d", what);
   }
   return SONAR_OK;
@@ -346,14 +389,21 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
 int sonar_matched_filter(sonar_plan p, const void* x, int32_t F, void* mf_out, hipStream_t stream) {
   int st = check_exec(p, x, mf_out, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = launch_mf_td(p, x, F, static_cast<float2*>(mf_out), stream);
+  hipError_t e = p->bf_mode == SONAR_BF_TD_LINEAR ? launch_mf_td(p, x, F, static_cast<float2*>(mf_out), stream)
+                                                  : launch_mf_fd(p, x, F, static_cast<float2*>(mf_out), stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "matched filter launch");
 }
 
 int sonar_beamform(sonar_plan p, const void* mf_in, int32_t F, void* beam_out, hipStream_t stream) {
   int st = check_exec(p, mf_in, beam_out, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = launch_das_td_beam(p, static_cast<const float2*>(mf_in), F, static_cast<float2*>(beam_out), stream);
+  hipError_t e;
+  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+    e = launch_das_td_beam(p, static_cast<const float2*>(mf_in), F, static_cast<float2*>(beam_out), stream);
+  } else {
+    e = launch_fd_gemm(p, static_cast<const float2*>(mf_in), F, p->d_bspec, stream);
+    if (e == hipSuccess) e = launch_fd_ifft_beam(p, p->d_bspec, F, static_cast<float2*>(beam_out), stream);
+  }
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform launch");
 }
 
@@ -364,18 +414,39 @@ int sonar_envelope(sonar_plan p, const void* beam_in, int32_t F, float* E, hipSt
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "envelope launch");
 }
 
+namespace {
+
+// beamformer + envelope from a matched-filter buffer of this plan's layout
+hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hipStream_t s) {
+  if (p->bf_mode == SONAR_BF_TD_LINEAR) return launch_das_td_env(p, mf, F, E, s);
+  hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
+  if (e != hipSuccess) return e;
+  if (p->fd_fused) return launch_fd_ifft_env(p, p->d_bspec, F, E, s);
+  e = launch_fd_ifft_beam(p, p->d_bspec, F, p->d_beam, s);
+  if (e != hipSuccess) return e;
+  return launch_envelope(p, p->d_beam, F, E, s);
+}
+
+}  // namespace
+
 int sonar_beamform_envelope(sonar_plan p, const void* mf_in, int32_t F, float* E, hipStream_t stream) {
   int st = check_exec(p, mf_in, E, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = launch_das_td_env(p, static_cast<const float2*>(mf_in), F, E, stream);
+  hipError_t e = beam_env(p, static_cast<const float2*>(mf_in), F, E, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform-envelope launch");
 }
 
 int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hipStream_t stream) {
   int st = check_exec(p, x, E, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = launch_mf_td(p, x, F, p->d_mf, stream);
-  if (e == hipSuccess) e = launch_das_td_env(p, p->d_mf, F, E, stream);
+  hipError_t e;
+  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+    e = launch_mf_td(p, x, F, p->d_mf, stream);
+    if (e == hipSuccess) e = beam_env(p, p->d_mf, F, E, stream);
+  } else {
+    e = launch_mf_fd(p, x, F, p->d_fdspec, stream);
+    if (e == hipSuccess) e = beam_env(p, p->d_fdspec, F, E, stream);
+  }
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape launch");
 }
 
