@@ -65,11 +65,20 @@ __device__ __forceinline__ void split_bf16x8(const float (&v)[8], bf16x8& hi, bf
   }
 }
 
+// Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS bins in chunks of 8,
+// 16 frames.  The samples of a chunk (16 frames x 8 bins x 32 microphones)
+// are staged once in LDS and shared by the four wavefronts.  Steering values
+// restart at every chunk from an anchor exp(-2 pi i k Dl / P) whose phase is
+// reduced in FP64, then advance bin by bin with the per-(d, m) rotation
+// exp(-2 pi i Dl / P) taken from the plan table (at most 7 FP32 rotations).
+constexpr int CHB = 8;                  // bins per chunk
+constexpr int YS_FRAME = CHB * 32 + 2;  // float2 per frame row in LDS (padded)
+
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fd_gemm_kernel(
-    const float2* __restrict__ band, const double* __restrict__ dl, float2* __restrict__ bspec,
-    int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt) {
-  constexpr int NBIN = FD_GEMM_BINS;
+    const float2* __restrict__ band, const double* __restrict__ dl, const float2* __restrict__ step,
+    float2* __restrict__ bspec, int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt) {
+  __shared__ float2 ys[FD_GEMM_FRAMES * YS_FRAME];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   int bid = blockIdx.x;
@@ -77,117 +86,135 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   bid /= nbt;
   const int dt = bid % ndt;
   const int ft = bid / ndt;
-  const int k0 = bt * NBIN;                 // first stored bin of the tile
   const int r16 = lane & 15, grp = lane >> 4;
   const int d_st = dt * FD_GEMM_DIRS + wv * 16 + r16;    // direction this lane steers
-  const int f_ld = ft * FD_GEMM_FRAMES + r16;           // frame this lane loads
-  const bool d_ok = d_st < D, f_ok = f_ld < F;
+  const bool d_ok = d_st < D;
   const double invP = 1.0 / static_cast<double>(P);
+  const int f_out = ft * FD_GEMM_FRAMES + r16;
 
-  f32x4 cr[NBIN], ci[NBIN];
+  for (int k0 = bt * FD_GEMM_BINS; k0 < (bt + 1) * FD_GEMM_BINS && k0 < kb; k0 += CHB) {
+    f32x4 cr[CHB], ci[CHB];
 #pragma unroll
-  for (int b = 0; b < NBIN; ++b) {
-    cr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-    ci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
-  }
-
-  for (int mc = 0; mc < M; mc += 32) {
-    // phasors exp(-2 pi i k Dl / P) / M at the tile's first bin, and the per-bin rotation
-    float phr[8], phi[8], str[8], sti[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
-      phr[j] = phi[j] = str[j] = sti[j] = 0.f;
-      if (d_ok && m < M) {
-        const double Dl = dl[static_cast<long long>(d_st) * M + m];
-        const double t = static_cast<double>(k_lo + k0) * Dl * invP;
-        const double fr = t - floor(t);
-        double s, c;
-        sincospi(-2.0 * fr, &s, &c);
-        phr[j] = static_cast<float>(c / M);
-        phi[j] = static_cast<float>(s / M);
-        double s1, c1;
-        sincospi(-2.0 * Dl * invP, &s1, &c1);
-        str[j] = static_cast<float>(c1);
-        sti[j] = static_cast<float>(s1);
-      }
+    for (int b = 0; b < CHB; ++b) {
+      cr[b] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ci[b] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+    for (int mc = 0; mc < M; mc += 32) {
+      // stage samples: ys[f][b][m] = band[frame][k0 + b][mc + m].  Each thread
+      // issues its 16 loads back to back; out-of-range slots read a clamped
+      // (valid) address and are zeroed, so no load sits behind a branch.
+      __syncthreads();
+      {
+        float2 y[16];
 #pragma unroll
-    for (int b = 0; b < NBIN; ++b) {
-      const int kk = k0 + b;
-      if (kk >= kb) break;
-      float ar[8], ai[8], nai[8], yr[8], yi[8];
+        for (int i = 0; i < 16; ++i) {
+          const int e = threadIdx.x + 256 * i;
+          const int f = e / (CHB * 32), b = (e / 32) % CHB, m = e % 32;
+          const int fg = ft * FD_GEMM_FRAMES + f;
+          const int fc = fg < F ? fg : F - 1;
+          const int kc = k0 + b < kb ? k0 + b : kb - 1;
+          const int mcl = mc + m < M ? mc + m : M - 1;
+          y[i] = band[(static_cast<long long>(fc) * kb + kc) * M + mcl];
+          if (!(fg < F && k0 + b < kb && mc + m < M)) y[i] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int e = threadIdx.x + 256 * i;
+          const int f = e / (CHB * 32), b = (e / 32) % CHB, m = e % 32;
+          ys[f * YS_FRAME + b * 32 + m] = y[i];
+        }
+      }
+      __syncthreads();
+      float phr[8], phi[8], str[8], sti[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
-        ar[j] = phr[j];
-        ai[j] = phi[j];
-        nai[j] = -phi[j];
-        const float nr = phr[j] * str[j] - phi[j] * sti[j];
-        const float ni = phr[j] * sti[j] + phi[j] * str[j];
-        phr[j] = nr;
-        phi[j] = ni;
         const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
-        float2 y = make_float2(0.f, 0.f);
-        if (f_ok && m < M) y = band[(static_cast<long long>(f_ld) * kb + kk) * M + m];
-        yr[j] = y.x;
-        yi[j] = y.y;
+        phr[j] = phi[j] = str[j] = sti[j] = 0.f;
+        if (d_ok && m < M) {
+          const double Dl = dl[static_cast<long long>(d_st) * M + m];
+          const double tt = static_cast<double>(k_lo + k0) * Dl * invP;
+          const float fr = static_cast<float>(tt - floor(tt));
+          float s, c;
+          sincospif(-2.0f * fr, &s, &c);
+          phr[j] = c / static_cast<float>(M);
+          phi[j] = s / static_cast<float>(M);
+          const float2 st = step[static_cast<long long>(d_st) * M + m];
+          str[j] = st.x;
+          sti[j] = st.y;
+        }
       }
-      if constexpr (MODE == MODE_FP32) {
+#pragma unroll
+      for (int b = 0; b < CHB; ++b) {
+        float ar[8], ai[8], nai[8], yr[8], yi[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yr[j], cr[b], 0, 0, 0);
-          cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[j], yi[j], cr[b], 0, 0, 0);
-          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[j], yr[j], ci[b], 0, 0, 0);
-          ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yi[j], ci[b], 0, 0, 0);
+          ar[j] = phr[j];
+          ai[j] = phi[j];
+          nai[j] = -phi[j];
+          const float nr = phr[j] * str[j] - phi[j] * sti[j];
+          const float ni = phr[j] * sti[j] + phi[j] * str[j];
+          phr[j] = nr;
+          phi[j] = ni;
+          const int m = MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j;
+          const float2 y = ys[r16 * YS_FRAME + b * 32 + m];
+          yr[j] = y.x;
+          yi[j] = y.y;
         }
-      } else if constexpr (MODE == MODE_BF16) {
-        // steering in one BF16 term, samples in two (hi + lo): two products
-        const bf16x8 Ar = to_bf16x8(ar), Ai = to_bf16x8(ai), nAi = to_bf16x8(nai);
-        bf16x8 Yrh, Yrl, Yih, Yil;
-        split_bf16x8(yr, Yrh, Yrl);
-        split_bf16x8(yi, Yih, Yil);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrh, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrl, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yih, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yil, cr[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrh, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrl, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yih, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yil, ci[b], 0, 0, 0);
-      } else {
-        bf16x8 Arh, Arl, Aih, Ail, nAih, nAil, Yrh, Yrl, Yih, Yil;
-        split_bf16x8(ar, Arh, Arl);
-        split_bf16x8(ai, Aih, Ail);
-        split_bf16x8(nai, nAih, nAil);
-        split_bf16x8(yr, Yrh, Yrl);
-        split_bf16x8(yi, Yih, Yil);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrh, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrl, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yrh, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yih, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yil, cr[b], 0, 0, 0);
-        cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAil, Yih, cr[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrh, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrl, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ail, Yrh, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yih, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yil, ci[b], 0, 0, 0);
-        ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yih, ci[b], 0, 0, 0);
+        if constexpr (MODE == MODE_FP32) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yr[j], cr[b], 0, 0, 0);
+            cr[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(nai[j], yi[j], cr[b], 0, 0, 0);
+            ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[j], yr[j], ci[b], 0, 0, 0);
+            ci[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[j], yi[j], ci[b], 0, 0, 0);
+          }
+        } else if constexpr (MODE == MODE_BF16) {
+          // steering in one BF16 term, samples in two (hi + lo): two products
+          const bf16x8 Ar = to_bf16x8(ar), Ai = to_bf16x8(ai), nAi = to_bf16x8(nai);
+          bf16x8 Yrh, Yrl, Yih, Yil;
+          split_bf16x8(yr, Yrh, Yrl);
+          split_bf16x8(yi, Yih, Yil);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrh, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrl, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yih, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yil, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrh, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ai, Yrl, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yih, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yil, ci[b], 0, 0, 0);
+        } else {
+          bf16x8 Arh, Arl, Aih, Ail, nAih, nAil, Yrh, Yrl, Yih, Yil;
+          split_bf16x8(ar, Arh, Arl);
+          split_bf16x8(ai, Aih, Ail);
+          split_bf16x8(nai, nAih, nAil);
+          split_bf16x8(yr, Yrh, Yrl);
+          split_bf16x8(yi, Yih, Yil);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrh, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrl, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yrh, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yih, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAih, Yil, cr[b], 0, 0, 0);
+          cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAil, Yih, cr[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrh, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Aih, Yrl, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ail, Yrh, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yih, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yil, ci[b], 0, 0, 0);
+          ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yih, ci[b], 0, 0, 0);
+        }
       }
     }
-  }
-
-  // lane holds (direction 4 grp + i, frame r16) for the tile's bins: 16
-  // consecutive bins of one output row, written as 16-byte pairs
-  const int f_out = ft * FD_GEMM_FRAMES + r16;
-  if (f_out < F) {
+    // lane holds (direction 4 grp + i, frame r16) for the chunk's bins: CHB
+    // consecutive bins of one output row, written as 16-byte pairs
+    if (f_out < F) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int d_out = dt * FD_GEMM_DIRS + wv * 16 + 4 * grp + i;
-      if (d_out < D) {
-        float4* dst = reinterpret_cast<float4*>(bspec + (static_cast<long long>(f_out) * D + d_out) * kb_pad + k0);
+      for (int i = 0; i < 4; ++i) {
+        const int d_out = dt * FD_GEMM_DIRS + wv * 16 + 4 * grp + i;
+        if (d_out < D) {
+          float4* dst = reinterpret_cast<float4*>(bspec + (static_cast<long long>(f_out) * D + d_out) * kb_pad + k0);
 #pragma unroll
-        for (int b = 0; b < NBIN; b += 2) dst[b / 2] = make_float4(cr[b][i], ci[b][i], cr[b + 1][i], ci[b + 1][i]);
+          for (int b = 0; b < CHB; b += 2) dst[b / 2] = make_float4(cr[b][i], ci[b][i], cr[b + 1][i], ci[b + 1][i]);
+        }
       }
     }
   }
@@ -241,10 +268,13 @@ __device__ __forceinline__ void load_fd_tw(float2* tw, const float2* __restrict_
 
 constexpr int FD_MAX_TW_P = 32768 / 64 + 1 + 64;   // P tables for P <= 32768
 
+// One direction of one frame per workgroup.  The stored spectrum is read once;
+// each phase's transform lands as |b| in an LDS copy of the beam window (the
+// samples n = R' a + r of phase r), and the FIR runs once over that window.
 template <int LOGL>
 __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
     const float2* __restrict__ bspec, const float2* __restrict__ tw_g, const float* __restrict__ taps,
-    float* __restrict__ E, int kb, int kb_pad, int Rp, int P, int n0, int Q, int R, int K) {
+    float* __restrict__ E, int kb, int kb_pad, int Rp, int P, int n_start, int G, int Q, int R, int K) {
   using S = FftShape<LOGL>;
   constexpr int L = S::NF;
   constexpr int T = S::T;
@@ -252,59 +282,55 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   __shared__ float2 lds[S::LDS_ELEMS];
   __shared__ float2 tw[LH + 64 + FD_MAX_TW_P];
   __shared__ float hs[FD_MAX_TAPS];
+  extern __shared__ float mag[];              // |b| over the beam window, G floats
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
   load_fd_tw<LOGL>(tw, tw_g, P, tid, T);
   for (int j = tid; j < K; j += T) hs[j] = taps[j];
+  const float2* in = bspec + fd * kb_pad;
+  float2 bin[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k = tid + s * (L / 16);
+    bin[s] = k < kb ? in[k] : make_float2(0.f, 0.f);
+  }
+  const float2 top = kb == L + 1 ? in[L] : make_float2(0.f, 0.f);
   __syncthreads();
   const float2* tw_hi = tw;
   const float2* tw_lo = tw + LH;
   const float2* twp_hi = tw + LH + 64;
   const float2* twp_lo = tw + LH + 64 + P / 64 + 1;
-  const float2* in = bspec + fd * kb_pad;
   const float invP = 1.0f / static_cast<float>(P);
-  const int hk = (K - 1) / 2;
-  float* mag = reinterpret_cast<float*>(lds);
-  float acc[FD_QPT];
-#pragma unroll
-  for (int i = 0; i < FD_QPT; ++i) acc[i] = 0.f;
 
   for (int r = 0; r < Rp; ++r) {
     float2 v[16];
-    const float2 extra = load_phase<LOGL>(in, kb, r, twp_hi, twp_lo, v, tid);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int e = (tid + s * (L / 16)) * r;          // < P
+      v[s] = r == 0 ? bin[s] : cmul(bin[s], cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
+    }
+    float2 extra = top;
+    if (r != 0) {
+      const int e = L * r;
+      extra = cmul(top, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
+    }
     fft_lds<LOGL, true>(v, lds, tw_hi, tw_lo, tid);
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const float ux = v[i].x + extra.x, uy = v[i].y + extra.y;
-      mag[S::out_index(tid, i)] = sqrtf(ux * ux + uy * uy) * invP;
-    }
-    __syncthreads();
-    // taps of output q that read samples of this phase: n = n_q + hk - j = R' a + r (mod P)
-#pragma unroll
-    for (int i = 0; i < FD_QPT; ++i) {
-      const int q = tid + i * T;
-      if (q < Q) {
-        const int nq = n0 + q * R + hk;                 // sample read by tap 0
-        int j = (nq - r) % Rp;
-        if (j < 0) j += Rp;
-        int nm = (nq - j) % P;
-        if (nm < 0) nm += P;
-        int a = (nm - r) / Rp;
-        float s = 0.f;
-        for (; j < K; j += Rp) {
-          s = fmaf(hs[j], mag[a], s);
-          a = a == 0 ? L - 1 : a - 1;
-        }
-        acc[i] += s;
+      const int n = Rp * S::out_index(tid, i) + r;
+      const int w = (n - n_start) & (P - 1);             // window position of sample n
+      if (w < G) {
+        const float ux = v[i].x + extra.x, uy = v[i].y + extra.y;
+        mag[w] = sqrtf(ux * ux + uy * uy) * invP;
       }
     }
-    __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < FD_QPT; ++i) {
-    const int q = tid + i * T;
-    if (q < Q) E[fd * Q + q] = acc[i];
+  __syncthreads();
+  for (int q = tid; q < Q; q += T) {
+    const float* a = mag + q * R + K - 1;
+    float acc = 0.f;
+    for (int j = 0; j < K; ++j) acc = fmaf(hs[j], a[-j], acc);
+    E[fd * Q + q] = acc;
   }
 }
 
@@ -346,21 +372,21 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_beam_kernel(
 }  // namespace
 
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s) {
-  const int nbt = p->kb_pad / FD_GEMM_BINS;
+  const int nbt = (p->kb_pad + FD_GEMM_BINS - 1) / FD_GEMM_BINS;
   const int ndt = (p->D + FD_GEMM_DIRS - 1) / FD_GEMM_DIRS;
   const int nft = (F + FD_GEMM_FRAMES - 1) / FD_GEMM_FRAMES;
   const dim3 grid(static_cast<unsigned>(nbt) * ndt * nft);
   switch (p->bf_mode) {
     case SONAR_BF_FD_FP32:
-      hipLaunchKernelGGL(fd_gemm_kernel<MODE_FP32>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_FP32>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
                          p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
       break;
     case SONAR_BF_FD_BF16:
-      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
                          p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
       break;
     case SONAR_BF_FD_BF16X3:
-      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16X3>, grid, dim3(256), 0, s, band, p->d_dl, bspec, F, p->D, p->M,
+      hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16X3>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
                          p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
       break;
     default:
@@ -371,8 +397,13 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
 
 template <int LOGL>
 hipError_t launch_env_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
-  hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16), 0, s,
-                     bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, p->P, p->n0, p->Q, p->R, p->K);
+  const size_t smem = static_cast<size_t>(p->G) * sizeof(float);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fd_ifft_env_kernel<LOGL>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
+                     smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, p->P,
+                     p->n0 - p->hk, p->G, p->Q, p->R, p->K);
   return hipGetLastError();
 }
 
@@ -417,4 +448,12 @@ hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F
   }
 }
 
-hipError_t init_fd_kernel_attributes() { return hipSuccess; }
+// static LDS of the fused kernel for a transform of 2^logL points (the beam
+// window |b| comes on top as dynamic LDS)
+size_t fd_env_static_lds(int logL, int P) {
+  const int L = 1 << logL;
+  const int lh = L / 64 > 0 ? L / 64 : 1;
+  (void)P;
+  return static_cast<size_t>(L + L / 16) * sizeof(float2) +
+         static_cast<size_t>(lh + 64 + FD_MAX_TW_P) * sizeof(float2) + FD_MAX_TAPS * sizeof(float);
+}

@@ -95,11 +95,25 @@ __global__ void fd_twiddle_kernel(float2* __restrict__ tw, int L, int P) {
   tw[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
 }
 
+// FD steering rotation per bin: exp(-2 pi i Dl / P) from the FP64 delays
+__global__ void fd_step_kernel(const double* __restrict__ dl, long long n, int P, float2* __restrict__ step) {
+  const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s, c;
+  sincospi(-2.0 * dl[i] / static_cast<double>(P), &s, &c);
+  step[i] = make_float2(static_cast<float>(c), static_cast<float>(s));
+}
+
 }  // namespace
 
 hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s) {
   const int n = fd_tw_len(p->fd_L, p->P);
   hipLaunchKernelGGL(fd_twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p->d_fdtw, p->fd_L, p->P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long dm = static_cast<long long>(p->D) * p->M;
+  hipLaunchKernelGGL(fd_step_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s, p->d_dl, dm,
+                     p->P, p->d_fdstep);
   return hipGetLastError();
 }
 

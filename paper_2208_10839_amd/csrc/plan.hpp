@@ -68,6 +68,7 @@ struct sonar_plan_s {
   float2* d_fdspec = nullptr;  // FD: band spectra of the MF output, [max_frames][kb][M]
   float2* d_bspec = nullptr;   // FD: beam spectra, [max_frames][D][kb_pad]
   float2* d_fdtw = nullptr;    // FD: twiddles for fd_L and P (layout: fd_tw_len)
+  float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
   float2* d_beam = nullptr;    // FD fallback: beam window [max_frames][D][G'] (unfused plans only)
   void* d_aux = nullptr;       // plan-build scratch
 };
@@ -89,10 +90,9 @@ __host__ __device__ inline int fft_tw_len(int NF) { return fft_nhi(NF) + 64 + ff
 __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L / 64 : 1) + 64 + P / 64 + 1 + 64; }
 
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
-constexpr int FD_GEMM_BINS = 16;       // bins per FD GEMM workgroup
+constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
-constexpr int FD_QPT = 8;              // range bins per thread in the fused FD inverse + envelope kernel
 constexpr int FD_MAX_TAPS = 1024;
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
@@ -101,7 +101,7 @@ hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* ban
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
-hipError_t init_fd_kernel_attributes();
+size_t fd_env_static_lds(int logL, int P);
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
 hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, float2* beam, hipStream_t s);

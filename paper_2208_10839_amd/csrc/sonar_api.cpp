@@ -79,6 +79,7 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_bspec);
   (void)hipFree(p->d_beam);
   (void)hipFree(p->d_fdtw);
+  (void)hipFree(p->d_fdstep);
   (void)hipFree(p->d_aux);
   delete p;
 }
@@ -289,12 +290,13 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     p->k_lo = 0;
     p->kb = p->NF + 1;
   }
-  p->kb_pad = (p->kb + FD_GEMM_BINS - 1) / FD_GEMM_BINS * FD_GEMM_BINS;
+  p->kb_pad = (p->kb + 15) / 16 * 16;
   p->fd_L = 16;
   while (p->fd_L < p->kb - 1) p->fd_L *= 2;
   p->fd_logL = ilog2(p->fd_L);
   p->fd_R = p->P / p->fd_L;
-  p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->Q <= FD_QPT * (p->fd_L / 16) && p->K <= FD_MAX_TAPS;
+  p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->K <= FD_MAX_TAPS &&
+                fd_env_static_lds(p->fd_logL, p->P) + static_cast<size_t>(p->G) * sizeof(float) <= 160 * 1024;
   const bool fd = p->bf_mode != SONAR_BF_TD_LINEAR;
 
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -331,6 +333,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
             dev_alloc(&p->d_bspec, bspec_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_beam, beam_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_fdtw, fdtw_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_fdstep, fd ? dm : 0, &total) == hipSuccess &&
             dev_alloc(reinterpret_cast<char**>(&p->d_aux), aux_bytes, &total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
