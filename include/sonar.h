@@ -58,9 +58,14 @@ enum sonar_status {
  *              steering operand is rounded to one BF16 term, the sample
  *              operand is carried as two BF16 terms (hi + lo), two products.
  *  FD_BF16X3 : as FD_BF16 with each operand split into two BF16 terms
- *              (hi + lo) and three products (hi*hi + hi*lo + lo*hi).         */
+ *              (hi + lo) and three products (hi*hi + hi*lo + lo*hi).
+ *  TD_BF16   : the TD_LINEAR result computed on BF16 MFMA with FP32
+ *              accumulation: interpolation weights in one BF16 term, samples
+ *              in two (hi + lo).  Only the fused beamformer + envelope runs on
+ *              MFMA; sonar_beamform in this mode returns the FP32 beam.        */
 enum sonar_bf_mode {
-  SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3
+  SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
+  SONAR_BF_TD_BF16 = 4
 };
 
 /* Element type of the microphone samples x. */

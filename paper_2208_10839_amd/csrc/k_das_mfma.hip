@@ -1,0 +1,197 @@
+// Time-domain delay-and-sum on BF16 MFMA (§4.1 delay-and-sum toward every
+// direction; §4.3 subsampling after the envelope), fused with the envelope:
+//
+//   b_d[n]  = sum_m w0[d][m] yhat_m[n + o] + w1[d][m] yhat_m[n + o + 1]
+//   E[d][q] = sum_j h[j] |b_d[n0 + qR + (K-1)/2 - j]|
+//
+// The same linear-interpolation result as the FP32 beamformer, computed as a
+// dense product.  Directions are grouped into tiles of 32 neighbours (plan
+// time, along a Hilbert curve of the direction grid), so within a tile the
+// integer offsets o[d][m] of one microphone span only a few samples.  For
+// each microphone the tile covers that span with groups of 8 consecutive
+// taps; the tap weights form a sparse 32 x K matrix W (two nonzeros per
+// direction and microphone) and the samples a Hankel matrix
+//   Y[(m, toff + j)][n] = yhat_m[n + toff + j],
+// so b = W Y runs on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  A
+// B-operand fragment (8 consecutive taps of one sample) is 8 consecutive
+// samples of one row.  The 32 columns of an output tile are samples
+// 4c + rho of one residue rho, and the tap groups used for residue rho start
+// at t0 with t0 + rho = 0 mod 4, so every fragment read starts on an 8-byte
+// boundary.
+//
+// Precision: weights and samples are each carried as two BF16 terms
+// (hi = bf16(v), lo = bf16(v - hi)); the product keeps hi*hi + hi*lo + lo*hi
+// (the dropped lo*lo term is below 2^-16 relative), real and imaginary parts
+// separately, so each K-chunk costs six MFMAs per 32 x 32 output tile.
+#include <hip/hip_runtime.h>
+
+#include "plan.hpp"
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+
+__device__ __forceinline__ unsigned short bf16_bits(float v) {
+  const __bf16 h = static_cast<__bf16>(v);
+  return __builtin_bit_cast(unsigned short, h);
+}
+
+__device__ __forceinline__ float bf16_val(unsigned short b) {
+  return __builtin_bit_cast(float, static_cast<unsigned int>(b) << 16);
+}
+
+// 8 BF16 values at an 8-byte aligned LDS address
+__device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
+  const uint2 a = *reinterpret_cast<const uint2*>(p);
+  const uint2 b = *reinterpret_cast<const uint2*>(p + 4);
+  return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
+}
+
+// Workgroup: one tile of 32 directions x NWAVE * 128 beam samples of one frame.
+// Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
+// wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
+template <int NWAVE>
+__global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
+    const float2* __restrict__ yext, const int2* __restrict__ gtab, const uint4* __restrict__ wtab,
+    const int2* __restrict__ kcr, const int* __restrict__ perm, const float* __restrict__ taps,
+    float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc, int nqt, int ntiles,
+    int gmax, int kcmax, int nmc, int wrow) {
+  extern __shared__ unsigned short sm[];    // 4 planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo)
+  constexpr int NS = NWAVE * 128;            // beam samples per workgroup
+  static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int rho = wv % MT_RES;
+  const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;   // first sample of the wavefront
+  int bid = blockIdx.x;
+  const int tile = bid % ntiles;
+  bid /= ntiles;
+  const int qt = bid % nqt;
+  const int f = bid / nqt;
+  const long long s0 = static_cast<long long>(qt) * qc * R;   // first window sample of the tile
+  const int plane = MT_MICS * wrow;
+
+  f32x16 cre[4], cim[4];
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    cre[nt] = f32x16{};
+    cim[nt] = f32x16{};
+  }
+
+  for (int mc = 0; mc < nmc; ++mc) {
+    const int m0 = mc * MT_MICS;
+    const int rows = M - m0 < MT_MICS ? M - m0 : MT_MICS;
+    // stage rows m0.. of this frame, samples [s0, s0 + wrow), as four BF16 planes;
+    // pairs of samples per thread, loads issued in batches of 6
+    {
+      const int half = wrow >> 1;
+      const int total = rows * half;
+      for (int base = threadIdx.x; base < total; base += NWAVE * 64 * 6) {
+        float4 v[6];
+        int idx[6];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const int e0 = base + i * NWAVE * 64;
+          idx[i] = e0 < total ? e0 : total - 1;
+          const int ml = idx[i] / half, t2 = idx[i] - ml * half;
+          v[i] = *reinterpret_cast<const float4*>(yext + (static_cast<long long>(f) * M + m0 + ml) * row + s0 + 2 * t2);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+          const int ml = idx[i] / half, t2 = idx[i] - ml * half;
+          const int o = ml * wrow + 2 * t2;
+          const unsigned short rh0 = bf16_bits(v[i].x), rh1 = bf16_bits(v[i].z);
+          const unsigned short ih0 = bf16_bits(v[i].y), ih1 = bf16_bits(v[i].w);
+          const unsigned short rl0 = bf16_bits(v[i].x - bf16_val(rh0)), rl1 = bf16_bits(v[i].z - bf16_val(rh1));
+          const unsigned short il0 = bf16_bits(v[i].y - bf16_val(ih0)), il1 = bf16_bits(v[i].w - bf16_val(ih1));
+          *reinterpret_cast<unsigned int*>(sm + o) = rh0 | (static_cast<unsigned int>(rh1) << 16);
+          *reinterpret_cast<unsigned int*>(sm + plane + o) = rl0 | (static_cast<unsigned int>(rl1) << 16);
+          *reinterpret_cast<unsigned int*>(sm + 2 * plane + o) = ih0 | (static_cast<unsigned int>(ih1) << 16);
+          *reinterpret_cast<unsigned int*>(sm + 3 * plane + o) = il0 | (static_cast<unsigned int>(il1) << 16);
+        }
+      }
+    }
+    __syncthreads();
+    const int li = tile * MT_RES + rho;
+    const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
+    if (kr.x < kr.y) {
+      const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
+      const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
+      uint4 ah_next = wt[kr.x * 128], al_next = wt[kr.x * 128 + 64];
+      int2 g_next = gt[2 * kr.x];
+      for (int kc = kr.x; kc < kr.y; ++kc) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, ah_next);
+        const bf16x8 al = __builtin_bit_cast(bf16x8, al_next);
+        const int2 g = g_next;
+        if (kc + 1 < kr.y) {
+          ah_next = wt[(kc + 1) * 128];
+          al_next = wt[(kc + 1) * 128 + 64];
+          g_next = gt[2 * (kc + 1)];
+        }
+        const unsigned short* p = sm + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const bf16x8 brh = lds_frag(p + 128 * nt);
+          const bf16x8 brl = lds_frag(p + plane + 128 * nt);
+          const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
+          const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
+          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
+          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
+          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
+          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
+          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
+          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // |b| of the tile into LDS: lane holds rows 8(v/4) + 4(lane/32) + v%4 (directions)
+  // of column lane%32 (sample sb + 128 nt + 4 column) for each output tile
+  float* absb = reinterpret_cast<float*>(sm);
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int s = sb + 128 * nt + 4 * (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+      absb[dl * NS + s] = sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
+    }
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < 32 * qc; idx += NWAVE * 64) {
+    const int dl = idx / qc, q = idx - dl * qc;
+    const int d = perm[tile * 32 + dl];
+    const int qq = qt * qc + q;
+    if (d >= 0 && qq < Q) {
+      const float* a = absb + dl * NS + q * R + K - 1;
+      float acc = 0.f;
+      for (int j = 0; j < K; ++j) acc = fmaf(taps[j], a[-j], acc);
+      E[(static_cast<long long>(f) * D + d) * Q + qq] = acc;
+    }
+  }
+}
+
+}  // namespace
+
+size_t mt_smem_bytes(const sonar_plan_s* p) {
+  const size_t planes = 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
+  const size_t absb = 32 * static_cast<size_t>(MT_NWAVE * 128) * sizeof(float);
+  return planes > absb ? planes : absb;
+}
+
+hipError_t init_mt_kernel_attributes() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
+  const long long nblk = static_cast<long long>(F) * p->mt_nqt * p->mt_ntiles;
+  hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
+                     mt_smem_bytes(p), s, yext, p->d_mt_g, reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
+                     p->d_mt_perm, p->d_taps, E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
+                     p->mt_ntiles, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow);
+  return hipGetLastError();
+}

@@ -51,6 +51,9 @@ struct sonar_plan_s {
   int fd_L = 0, fd_logL = 0, fd_R = 0;
   bool fd_fused = false;   // fd_L small enough for the fused inverse + envelope kernel
 
+  // time-domain BF16-MFMA beamformer tiling (see k_das_mfma.hip)
+  int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
+
   int device = 0;
   size_t ws_bytes = 0;
 
@@ -70,6 +73,10 @@ struct sonar_plan_s {
   float2* d_fdtw = nullptr;    // FD: twiddles for fd_L and P (layout: fd_tw_len)
   float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
   float2* d_beam = nullptr;    // FD fallback: beam window [max_frames][D][G'] (unfused plans only)
+  int2* d_mt_g = nullptr;      // TD BF16: tap groups {mic, first tap offset}, [tiles][MT_RES][gmax]
+  unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][MT_RES][kcmax][hi, lo][64 lanes][8] BF16
+  int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][MT_RES]
+  int* d_mt_perm = nullptr;    // TD BF16: tile slot -> direction (-1: empty), [tiles][32]
   void* d_aux = nullptr;       // plan-build scratch
 };
 
@@ -89,6 +96,13 @@ __host__ __device__ inline int fft_tw_len(int NF) { return fft_nhi(NF) + 64 + ff
 //   [.., +64)          : exp(-2 pi i * t / P)        t < 64
 __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L / 64 : 1) + 64 + P / 64 + 1 + 64; }
 
+// time-domain beamformer on BF16 MFMA: tiles of 32 directions x MT_NWAVE * 128
+// beam samples per workgroup; wavefront w computes the samples of residue
+// w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time
+constexpr int MT_NWAVE = 8;
+constexpr int MT_MICS = 16;
+constexpr int MT_RES = 4;
+
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
@@ -96,6 +110,9 @@ constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
 constexpr int FD_MAX_TAPS = 1024;
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
+hipError_t init_mt_kernel_attributes();
+size_t mt_smem_bytes(const sonar_plan_s* p);
+hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);

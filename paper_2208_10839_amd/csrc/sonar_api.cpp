@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,6 +81,10 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_beam);
   (void)hipFree(p->d_fdtw);
   (void)hipFree(p->d_fdstep);
+  (void)hipFree(p->d_mt_g);
+  (void)hipFree(p->d_mt_w);
+  (void)hipFree(p->d_mt_kcr);
+  (void)hipFree(p->d_mt_perm);
   (void)hipFree(p->d_aux);
   delete p;
 }
@@ -95,6 +100,150 @@ bool finite_all(const double* v, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(v[i])) return false;
   return true;
+}
+
+bool is_td(const sonar_plan_s* p) {
+  return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16;
+}
+
+// Position of (x, y) in [0, 2^16)^2 along a Hilbert curve (iterative quadrant walk).
+uint64_t hilbert_index(uint32_t x, uint32_t y) {
+  uint64_t d = 0;
+  for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
+    const uint32_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
+    d += static_cast<uint64_t>(s) * s * ((3 * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - (x & (s - 1)) + (x & ~(s - 1));
+        y = s - 1 - (y & (s - 1)) + (y & ~(s - 1));
+        x &= 0xFFFF;
+        y &= 0xFFFF;
+      }
+      const uint32_t tmp = x;
+      x = y;
+      y = tmp;
+    }
+  }
+  return d;
+}
+
+uint16_t to_bf16_bits(float v) {
+  uint32_t u;
+  std::memcpy(&u, &v, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even (finite values)
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// Tiles of the BF16-MFMA time-domain beamformer, built from the device's FP64
+// delay table: directions ordered along a Hilbert curve of (u_x, u_y) (front
+// and back hemispheres apart) and cut into tiles of 32.  Beam samples are
+// split by residue mod MT_RES; for residue rho, per tile and microphone the
+// span of integer offsets is covered by groups of 8 taps whose first tap t0
+// has t0 + rho = 0 mod MT_RES, so every sample fragment read by the kernel
+// starts on an 8-byte boundary.  A group pair is one K-chunk of
+// v_mfma_f32_32x32x16_bf16, whose A fragments (tap weights as BF16 hi and lo
+// terms) are stored in lane order.
+int build_mt_tables(sonar_plan_s* p, const double* dirs, hipStream_t stream, size_t* total) {
+  const int D = p->D, M = p->M;
+  std::vector<int4> dtab(static_cast<size_t>(D) * M);
+  hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "delay table read-back");
+  std::vector<std::pair<uint64_t, int>> key(D);
+  for (int d = 0; d < D; ++d) {
+    const double* u = dirs + 3 * d;
+    const uint32_t xi = static_cast<uint32_t>(std::lround((u[0] + 1.0) * 0.5 * 65535.0));
+    const uint32_t yi = static_cast<uint32_t>(std::lround((u[1] + 1.0) * 0.5 * 65535.0));
+    key[d] = {(static_cast<uint64_t>(u[2] < 0 ? 1 : 0) << 40) | hilbert_index(xi, yi), d};
+  }
+  std::stable_sort(key.begin(), key.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  const int nt = (D + 31) / 32, nmc = (M + MT_MICS - 1) / MT_MICS;
+  std::vector<int> perm(static_cast<size_t>(nt) * 32, -1);
+  for (int i = 0; i < D; ++i) perm[i] = key[i].second;
+  const int nlist = nt * MT_RES;   // group list per (tile, residue)
+  std::vector<std::vector<int2>> groups(nlist);
+  std::vector<std::vector<char>> pad(nlist);   // zero-weight group completing a K-chunk
+  std::vector<int2> kcr(static_cast<size_t>(nt) * nmc * MT_RES);
+  int gmax = 2;
+  for (int t = 0; t < nt; ++t) {
+    for (int rho = 0; rho < MT_RES; ++rho) {
+      std::vector<int2>& gl = groups[t * MT_RES + rho];
+      std::vector<char>& pl = pad[t * MT_RES + rho];
+      for (int mc = 0; mc < nmc; ++mc) {
+        const int m0 = mc * MT_MICS, m1 = std::min(M, m0 + MT_MICS);
+        const int g0 = static_cast<int>(gl.size());
+        for (int m = m0; m < m1; ++m) {
+          int rmin = 1 << 30, rmax = -(1 << 30);
+          for (int s = 0; s < 32; ++s) {
+            const int d = perm[t * 32 + s];
+            if (d < 0) continue;
+            rmin = std::min(rmin, dtab[static_cast<size_t>(d) * M + m].x);
+            rmax = std::max(rmax, dtab[static_cast<size_t>(d) * M + m].x);
+          }
+          const int t0 = rmin - (rmin + rho) % MT_RES;   // rmin >= 0, so t0 + rho >= 0
+          const int ng = (rmax + 2 - t0 + 7) / 8;          // taps t0 .. rmax + 1
+          for (int g = 0; g < ng; ++g) {
+            gl.push_back(make_int2(m, t0 + 8 * g));
+            pl.push_back(0);
+          }
+        }
+        if ((gl.size() - g0) & 1) {
+          gl.push_back(make_int2(m0, (MT_RES - rho) % MT_RES));
+          pl.push_back(1);
+        }
+        kcr[(static_cast<size_t>(t) * nmc + mc) * MT_RES + rho] = make_int2(g0 / 2, static_cast<int>(gl.size()) / 2);
+      }
+      gmax = std::max(gmax, static_cast<int>(gl.size()));
+    }
+  }
+  const int kcmax = gmax / 2;
+  std::vector<int2> gtab(static_cast<size_t>(nlist) * gmax, make_int2(0, 0));
+  std::vector<uint16_t> wtab(static_cast<size_t>(nlist) * kcmax * 2 * 64 * 8, 0);
+  for (int li = 0; li < nlist; ++li) {
+    const int t = li / MT_RES;
+    for (size_t g = 0; g < groups[li].size(); ++g) gtab[static_cast<size_t>(li) * gmax + g] = groups[li][g];
+    for (int kc = 0; kc < static_cast<int>(groups[li].size()) / 2; ++kc) {
+      for (int l = 0; l < 64; ++l) {
+        const int d = perm[t * 32 + (l & 31)];
+        const int gi = 2 * kc + (l >> 5);
+        const int2 g = groups[li][gi];
+        const bool zero = d < 0 || pad[li][gi];
+        for (int j = 0; j < 8; ++j) {
+          float w = 0.f;
+          if (!zero) {
+            const int4 en = dtab[static_cast<size_t>(d) * M + g.x];
+            float w0, w1;
+            std::memcpy(&w0, &en.y, 4);
+            std::memcpy(&w1, &en.z, 4);
+            if (g.y + j == en.x) w = w0;
+            else if (g.y + j == en.x + 1) w = w1;
+          }
+          const uint16_t hi = to_bf16_bits(w);
+          const uint32_t hb = static_cast<uint32_t>(hi) << 16;
+          float hv;
+          std::memcpy(&hv, &hb, 4);
+          const size_t at = ((static_cast<size_t>(li) * kcmax + kc) * 128 + l) * 8 + j;
+          wtab[at] = hi;
+          wtab[at + 64 * 8] = to_bf16_bits(w - hv);
+        }
+      }
+    }
+  }
+  p->mt_gmax = gmax;
+  p->mt_kcmax = kcmax;
+  bool ok = dev_alloc(&p->d_mt_g, gtab.size(), total) == hipSuccess &&
+            dev_alloc(&p->d_mt_w, wtab.size(), total) == hipSuccess &&
+            dev_alloc(&p->d_mt_kcr, kcr.size(), total) == hipSuccess &&
+            dev_alloc(&p->d_mt_perm, perm.size(), total) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    return fail(SONAR_E_NOMEM, "device allocation of the MFMA beamformer tables failed");
+  }
+  e = hipMemcpy(p->d_mt_g, gtab.data(), gtab.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_mt_w, wtab.data(), wtab.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_mt_kcr, kcr.data(), kcr.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_mt_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "MFMA beamformer table upload");
 }
 
 int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
@@ -139,7 +288,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_FD_BF16X3)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_BF16)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -266,6 +415,26 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   const long long need_env = static_cast<long long>(p->td_nqc - 1) * p->td_qc * p->R + 2 * TD_MAX_ROW_PAIRS;
   const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + 2 * TD_MAX_ROW_PAIRS;
   long long row = need_env > need_beam ? need_env : need_beam;
+  if (p->bf_mode == SONAR_BF_TD_BF16) {
+    // MFMA tiles: MT_NWAVE * 128 beam samples, rows staged over the tile plus the delay span
+    const int ns = MT_NWAVE * 128;
+    p->mt_qc = (ns - p->K) / p->R + 1;
+    if ((p->mt_qc * p->R) & 1) p->mt_qc -= 1;
+    if (p->mt_qc < 1) {
+      delete p;
+      return fail(SONAR_E_UNSUPPORTED, "low-pass length %d too long for the BF16 time-domain beamformer", p->K);
+    }
+    p->mt_nqt = (p->Q + p->mt_qc - 1) / p->mt_qc;
+    p->mt_wrow = (ns + p->spread + 16 + 7) / 8 * 8;
+    p->mt_ntiles = (p->D + 31) / 32;
+    p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
+    if (4 * static_cast<long long>(MT_MICS) * p->mt_wrow * 2 > 160 * 1024) {
+      delete p;
+      return fail(SONAR_E_UNSUPPORTED, "array aperture too large for the BF16 time-domain beamformer");
+    }
+    const long long need_mt = static_cast<long long>(p->mt_nqt - 1) * p->mt_qc * p->R + p->mt_wrow;
+    if (need_mt > row) row = need_mt;
+  }
   row = (row + 3) / 4 * 4;
   p->row = static_cast<int>(row);
   p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
@@ -297,13 +466,14 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   p->fd_R = p->P / p->fd_L;
   p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->K <= FD_MAX_TAPS &&
                 fd_env_static_lds(p->fd_logL, p->P) + static_cast<size_t>(p->G) * sizeof(float) <= 160 * 1024;
-  const bool fd = p->bf_mode != SONAR_BF_TD_LINEAR;
+  const bool fd = !is_td(p);
 
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(SONAR_E_HIP, "hipGetDevice failed");
   }
   hipError_t e = init_td_kernel_attributes();
+  if (e == hipSuccess) e = init_mt_kernel_attributes();
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e, "kernel attributes");
@@ -354,6 +524,14 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   }
   e = launch_build_tables(p, stream);
   if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
+  if (e == hipSuccess && p->bf_mode == SONAR_BF_TD_BF16) {
+    const int st = build_mt_tables(p, d.dirs, stream, &total);
+    if (st != SONAR_OK) {
+      free_plan(p);
+      return st;
+    }
+    p->ws_bytes = total;
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
     free_plan(p);
@@ -381,7 +559,7 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
     case SONAR_Q_WORKSPACE_BYTES: *value = static_cast<int64_t>(p->ws_bytes); break;
     case SONAR_Q_LPF_LEN: *value = p->K; break;
     case SONAR_Q_MF_FRAME_ELEMS:
-      *value = p->bf_mode == SONAR_BF_TD_LINEAR ? static_cast<int64_t>(p->M) * p->row
+      *value = is_td(p) ? static_cast<int64_t>(p->M) * p->row
                                                 : static_cast<int64_t>(p->kb) * p->M;
       break;
     default: return fail(SONAR_E_INVALID, "unknown query key %d", what);
@@ -392,7 +570,7 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
 int sonar_matched_filter(sonar_plan p, const void* x, int32_t F, void* mf_out, hipStream_t stream) {
   int st = check_exec(p, x, mf_out, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = p->bf_mode == SONAR_BF_TD_LINEAR ? launch_mf_td(p, x, F, static_cast<float2*>(mf_out), stream)
+  hipError_t e = is_td(p) ? launch_mf_td(p, x, F, static_cast<float2*>(mf_out), stream)
                                                   : launch_mf_fd(p, x, F, static_cast<float2*>(mf_out), stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "matched filter launch");
 }
@@ -401,7 +579,7 @@ int sonar_beamform(sonar_plan p, const void* mf_in, int32_t F, void* beam_out, h
   int st = check_exec(p, mf_in, beam_out, F);
   if (st != SONAR_OK) return st;
   hipError_t e;
-  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+  if (is_td(p)) {
     e = launch_das_td_beam(p, static_cast<const float2*>(mf_in), F, static_cast<float2*>(beam_out), stream);
   } else {
     e = launch_fd_gemm(p, static_cast<const float2*>(mf_in), F, p->d_bspec, stream);
@@ -422,6 +600,7 @@ namespace {
 // beamformer + envelope from a matched-filter buffer of this plan's layout
 hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hipStream_t s) {
   if (p->bf_mode == SONAR_BF_TD_LINEAR) return launch_das_td_env(p, mf, F, E, s);
+  if (p->bf_mode == SONAR_BF_TD_BF16) return launch_das_mfma_env(p, mf, F, E, s);
   hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
   if (e != hipSuccess) return e;
   if (p->fd_fused) return launch_fd_ifft_env(p, p->d_bspec, F, E, s);
@@ -443,7 +622,7 @@ int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hi
   int st = check_exec(p, x, E, F);
   if (st != SONAR_OK) return st;
   hipError_t e;
-  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+  if (is_td(p)) {
     e = launch_mf_td(p, x, F, p->d_mf, stream);
     if (e == hipSuccess) e = beam_env(p, p->d_mf, F, E, stream);
   } else {
