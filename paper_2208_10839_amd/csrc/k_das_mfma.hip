@@ -32,6 +32,8 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
+constexpr int MT_FIR_DIRS = 4;   // directions per thread in the low-pass stage
+
 __device__ __forceinline__ unsigned short bf16_bits(float v) {
   const __bf16 h = static_cast<__bf16>(v);
   return __builtin_bit_cast(unsigned short, h);
@@ -157,19 +159,30 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      absb[dl * NS + s] = sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
+      absb[dl * NS + s] = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
     }
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < 32 * qc; idx += NWAVE * 64) {
-    const int dl = idx / qc, q = idx - dl * qc;
-    const int d = perm[tile * 32 + dl];
+  // low-pass + decimation: lanes run over range bins (coalesced stores), each
+  // thread accumulates MT_FIR_DIRS directions dl = g + 8 i at once
+  constexpr int NG = 32 / MT_FIR_DIRS;
+  for (int it = threadIdx.x; it < NG * qc; it += NWAVE * 64) {
+    const int g = it / qc, q = it - g * qc;
     const int qq = qt * qc + q;
-    if (d >= 0 && qq < Q) {
-      const float* a = absb + dl * NS + q * R + K - 1;
-      float acc = 0.f;
-      for (int j = 0; j < K; ++j) acc = fmaf(taps[j], a[-j], acc);
-      E[(static_cast<long long>(f) * D + d) * Q + qq] = acc;
+    if (qq >= Q) continue;
+    const float* a = absb + g * NS + q * R + K - 1;
+    float acc[MT_FIR_DIRS];
+#pragma unroll
+    for (int i = 0; i < MT_FIR_DIRS; ++i) acc[i] = 0.f;
+    for (int j = 0; j < K; ++j) {
+      const float h = taps[j];
+#pragma unroll
+      for (int i = 0; i < MT_FIR_DIRS; ++i) acc[i] = fmaf(h, a[i * NG * NS - j], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < MT_FIR_DIRS; ++i) {
+      const int d = perm[tile * 32 + g + NG * i];
+      if (d >= 0) E[(static_cast<long long>(f) * D + d) * Q + qq] = acc[i];
     }
   }
 }

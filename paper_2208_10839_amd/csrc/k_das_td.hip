@@ -126,17 +126,28 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
     const float2 b = beam_sample<NB>(A, C, t, lane);
-    absb[wv * 64 * NB + 64 * t + lane] = sqrtf(b.x * b.x + b.y * b.y);
+    absb[wv * 64 * NB + 64 * t + lane] = __builtin_amdgcn_sqrtf(b.x * b.x + b.y * b.y);
   }
   __syncthreads();
-  for (int idx = threadIdx.x; idx < NW * qc; idx += NW * 64) {
-    const int dl = idx / qc, q = idx - dl * qc;
-    const int dd = dt * NW + dl, qq = qi * qc + q;
-    if (dd < D && qq < Q) {
-      const float* a = absb + dl * 64 * NB + q * R + K - 1;
-      float acc = 0.f;
-      for (int j = 0; j < K; ++j) acc = fmaf(taps[j], a[-j], acc);
-      E[(static_cast<long long>(f) * D + dd) * Q + qq] = acc;
+  // low-pass + decimation: lanes over range bins, TD_FIR_DIRS directions per thread
+  constexpr int NG = NW / TD_FIR_DIRS;
+  for (int idx = threadIdx.x; idx < NG * qc; idx += NW * 64) {
+    const int g = idx / qc, q = idx - g * qc;
+    const int qq = qi * qc + q;
+    if (qq >= Q) continue;
+    const float* a = absb + g * 64 * NB + q * R + K - 1;
+    float acc[TD_FIR_DIRS];
+#pragma unroll
+    for (int i = 0; i < TD_FIR_DIRS; ++i) acc[i] = 0.f;
+    for (int j = 0; j < K; ++j) {
+      const float h = taps[j];
+#pragma unroll
+      for (int i = 0; i < TD_FIR_DIRS; ++i) acc[i] = fmaf(h, a[i * NG * 64 * NB - j], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < TD_FIR_DIRS; ++i) {
+      const int dd = dt * NW + g + NG * i;
+      if (dd < D) E[(static_cast<long long>(f) * D + dd) * Q + qq] = acc[i];
     }
   }
 }
@@ -189,7 +200,7 @@ __global__ __launch_bounds__(256) void envelope_kernel(const float2* __restrict_
   const float2* b = beam + fd * G + w0;
   for (int i = threadIdx.x; i < wl; i += blockDim.x) {
     const float2 v = b[i];
-    ebuf[i] = sqrtf(v.x * v.x + v.y * v.y);
+    ebuf[i] = __builtin_amdgcn_sqrtf(v.x * v.x + v.y * v.y);
   }
   __syncthreads();
   for (int q = threadIdx.x; q < nq; q += blockDim.x) {

@@ -321,7 +321,7 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
       const int w = (n - n_start) & (P - 1);             // window position of sample n
       if (w < G) {
         const float ux = v[i].x + extra.x, uy = v[i].y + extra.y;
-        mag[w] = sqrtf(ux * ux + uy * uy) * invP;
+        mag[w] = __builtin_amdgcn_sqrtf(ux * ux + uy * uy) * invP;
       }
     }
   }

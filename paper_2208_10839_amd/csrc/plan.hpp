@@ -12,6 +12,7 @@
 // per wavefront (one sample per lane).
 constexpr int TD_NB = 16;
 constexpr int TD_NW = 8;
+constexpr int TD_FIR_DIRS = 2;   // directions per thread in the fused low-pass stage
 constexpr int TD_WAVES_PER_EU = 4;   // two workgroups per CU (80 KiB LDS each): 128 VGPRs per lane
 constexpr int TD_LDS_BYTES = 80 * 1024;    // LDS budget of one beamformer workgroup
 constexpr int TD_MAX_MICS = 128;
