@@ -186,6 +186,10 @@ def run_path(name, w, x, args, stream):
             "frac_of_plain_fma_peak": round(achieved / PEAK_FP32_NOPACK_TFLOPS, 4),
             "traffic": traffic_record(kernel, khash),
             "flop_per_launch": flops, "launch_ms": round(ms_be, 4), "kernel_sources_sha256_16": khash}
+    mflop = plan.query(binding.Q_MATRIX_FLOP_PER_FRAME) * F
+    if mflop:
+        roof["matrix_flop_per_launch"] = mflop
+        roof["matrix_pipe_frac"] = round(mflop / (ms_be / 1e3) / 1e12 / PEAK_BF16_MFMA_TFLOPS, 4)
     out = {"value": round(F / (ms_step / 1e3), 2), "unit": "energyscapes/s", "ms_per_step": round(ms_step, 4),
            "dtype": dtype, "mode": mode, "oracle_mode": omode, "bar": bar,
            "rel_err_sampled_max": max(errs), "rel_err_sampled_per_frame": [float(f"{e:.3e}") for e in errs],

@@ -60,9 +60,12 @@ enum sonar_status {
  *  FD_BF16X3 : as FD_BF16 with each operand split into two BF16 terms
  *              (hi + lo) and three products (hi*hi + hi*lo + lo*hi).
  *  TD_BF16   : the TD_LINEAR result computed on BF16 MFMA with FP32
- *              accumulation: interpolation weights in one BF16 term, samples
- *              in two (hi + lo).  Only the fused beamformer + envelope runs on
- *              MFMA; sonar_beamform in this mode returns the FP32 beam.        */
+ *              accumulation: directions are tiled 32 at a time and the
+ *              interpolation becomes a dense product of a tap-weight matrix
+ *              with a Hankel matrix of samples; weights and samples are each
+ *              split into two BF16 terms (hi + lo), three products.  Only the
+ *              fused beamformer + envelope runs on MFMA; sonar_beamform in
+ *              this mode returns the FP32 beam.                                 */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
   SONAR_BF_TD_BF16 = 4
@@ -105,7 +108,9 @@ enum sonar_query {
   SONAR_Q_BAND_BINS = 6,      /* FD: number of stored frequency bins Kb                    */
   SONAR_Q_WORKSPACE_BYTES = 7,/* device bytes owned by the plan                            */
   SONAR_Q_LPF_LEN = 8,        /* K                                                          */
-  SONAR_Q_MF_FRAME_ELEMS = 9  /* complex elements per frame of the MF buffer               */
+  SONAR_Q_MF_FRAME_ELEMS = 9, /* complex elements per frame of the MF buffer               */
+  SONAR_Q_MATRIX_FLOP_PER_FRAME = 10  /* TD_BF16: matrix-core flops issued per frame by the
+                                         fused beamformer (padding included); 0 otherwise  */
 };
 
 /*
@@ -140,8 +145,12 @@ int sonar_plan_query(sonar_plan plan, int32_t what, int64_t* value);
  * in P.
  *   x      : [F][M][N] samples of sample_dtype.
  *   mf_out : complex64 (float re, im) buffer, SONAR_Q_MF_FRAME_ELEMS per frame.
- *            TD mode: [F][M][row] with row = SONAR_Q_MF_ROW, element i holding
- *            yhat_m[(origin + i) mod P], origin = SONAR_Q_MF_ORIGIN.
+ *            TD modes: [F][M][row] with row = SONAR_Q_MF_ROW, element i holding
+ *            yhat_m[(origin + i) mod P], origin = SONAR_Q_MF_ORIGIN.  TD_BF16
+ *            appends to each frame the same samples as BF16 planes
+ *            [M][4][row] (re hi, re lo, im hi, im lo; hi = bf16(v),
+ *            lo = bf16(v - hi), round to nearest even), so a frame holds
+ *            2*M*row complex64 elements.
  *            FD modes: [F][Kb][M] (bin-major), element (j, m) holding the
  *            spectrum Yhat_m[k] = beta W X_m conj(S) at bin k = band_lo_bin + j
  *            (Kb = SONAR_Q_BAND_BINS; bins outside are zero by definition).

@@ -22,7 +22,9 @@
 // Precision: weights and samples are each carried as two BF16 terms
 // (hi = bf16(v), lo = bf16(v - hi)); the product keeps hi*hi + hi*lo + lo*hi
 // (the dropped lo*lo term is below 2^-16 relative), real and imaginary parts
-// separately, so each K-chunk costs six MFMAs per 32 x 32 output tile.
+// separately, so each K-chunk costs six MFMAs per 32 x 32 output tile.  The
+// matched filter writes the samples already split, as four BF16 planes per
+// microphone (re hi, re lo, im hi, im lo), so staging a tile is a plain copy.
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -33,15 +35,6 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
 constexpr int MT_FIR_DIRS = 4;   // directions per thread in the low-pass stage
-
-__device__ __forceinline__ unsigned short bf16_bits(float v) {
-  const __bf16 h = static_cast<__bf16>(v);
-  return __builtin_bit_cast(unsigned short, h);
-}
-
-__device__ __forceinline__ float bf16_val(unsigned short b) {
-  return __builtin_bit_cast(float, static_cast<unsigned int>(b) << 16);
-}
 
 // 8 BF16 values at an 8-byte aligned LDS address
 __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
@@ -55,24 +48,33 @@ __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
 // wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
 template <int NWAVE>
 __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
-    const float2* __restrict__ yext, const int2* __restrict__ gtab, const uint4* __restrict__ wtab,
-    const int2* __restrict__ kcr, const int* __restrict__ perm, const float* __restrict__ taps,
-    float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc, int nqt, int ntiles,
-    int gmax, int kcmax, int nmc, int wrow) {
+    const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
+    const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
+    const float* __restrict__ taps, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
+    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow) {
   extern __shared__ unsigned short sm[];    // 4 planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
+  constexpr int NT = NWAVE * 64;
   static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int rho = wv % MT_RES;
-  const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;   // first sample of the wavefront
-  int bid = blockIdx.x;
-  const int tile = bid % ntiles;
-  bid /= ntiles;
+  // Workgroups are handed to the XCDs round-robin by index: XCD x = index % nx
+  // keeps the weights of its own tpx direction tiles in its L2 and runs them
+  // back to back on each staged window (frame f, range tile qt).
+  const int bx = blockIdx.x % nx;
+  int bid = blockIdx.x / nx;
+  const int tile = bx * tpx + bid % tpx;
+  if (tile >= ntiles) return;
+  bid /= tpx;
   const int qt = bid % nqt;
   const int f = bid / nqt;
-  const long long s0 = static_cast<long long>(qt) * qc * R;   // first window sample of the tile
+  const int s0 = qt * qc * R;                // first window sample of the tile (a multiple of 4)
+  const int s0a = s0 & ~7;                   // staged from here: 16-byte aligned rows
+  // first sample of the wavefront, as an index into the staged rows
+  const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
   const int plane = MT_MICS * wrow;
+  const unsigned short* src = planes + f * fstride + s0a;
 
   f32x16 cre[4], cim[4];
 #pragma unroll
@@ -84,34 +86,34 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   for (int mc = 0; mc < nmc; ++mc) {
     const int m0 = mc * MT_MICS;
     const int rows = M - m0 < MT_MICS ? M - m0 : MT_MICS;
-    // stage rows m0.. of this frame, samples [s0, s0 + wrow), as four BF16 planes;
-    // pairs of samples per thread, loads issued in batches of 6
+    // stage rows m0.. of this frame, samples [s0a, s0a + wrow) of each BF16 plane:
+    // segment sg = 4 ml + c is plane c of microphone m0 + ml, copied in 16-byte chunks
     {
-      const int half = wrow >> 1;
-      const int total = rows * half;
-      for (int base = threadIdx.x; base < total; base += NWAVE * 64 * 6) {
-        float4 v[6];
-        int idx[6];
+      constexpr int B = 8;
+      const int cw = wrow >> 3;
+      const int nseg = 4 * rows;
+      const int total = nseg * cw;
+      const int dq = NT / cw, dr = NT % cw;
+      int sg = threadIdx.x / cw, k = threadIdx.x - sg * cw;
+      for (int base = threadIdx.x; base < total; base += NT * B) {
+        uint4 v[B];
+        int dst[B];
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          const int e0 = base + i * NWAVE * 64;
-          idx[i] = e0 < total ? e0 : total - 1;
-          const int ml = idx[i] / half, t2 = idx[i] - ml * half;
-          v[i] = *reinterpret_cast<const float4*>(yext + (static_cast<long long>(f) * M + m0 + ml) * row + s0 + 2 * t2);
+        for (int i = 0; i < B; ++i) {
+          const bool ok = base + i * NT < total;
+          const int sgc = ok ? sg : nseg - 1, kc = ok ? k : cw - 1;
+          v[i] = *reinterpret_cast<const uint4*>(src + static_cast<long long>(m0 * 4 + sgc) * row + 8 * kc);
+          dst[i] = ok ? (sgc & 3) * plane + (sgc >> 2) * wrow + 8 * kc : -1;
+          k += dr;
+          sg += dq;
+          if (k >= cw) {
+            k -= cw;
+            sg += 1;
+          }
         }
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-          const int ml = idx[i] / half, t2 = idx[i] - ml * half;
-          const int o = ml * wrow + 2 * t2;
-          const unsigned short rh0 = bf16_bits(v[i].x), rh1 = bf16_bits(v[i].z);
-          const unsigned short ih0 = bf16_bits(v[i].y), ih1 = bf16_bits(v[i].w);
-          const unsigned short rl0 = bf16_bits(v[i].x - bf16_val(rh0)), rl1 = bf16_bits(v[i].z - bf16_val(rh1));
-          const unsigned short il0 = bf16_bits(v[i].y - bf16_val(ih0)), il1 = bf16_bits(v[i].w - bf16_val(ih1));
-          *reinterpret_cast<unsigned int*>(sm + o) = rh0 | (static_cast<unsigned int>(rh1) << 16);
-          *reinterpret_cast<unsigned int*>(sm + plane + o) = rl0 | (static_cast<unsigned int>(rl1) << 16);
-          *reinterpret_cast<unsigned int*>(sm + 2 * plane + o) = ih0 | (static_cast<unsigned int>(ih1) << 16);
-          *reinterpret_cast<unsigned int*>(sm + 3 * plane + o) = il0 | (static_cast<unsigned int>(il1) << 16);
-        }
+        for (int i = 0; i < B; ++i)
+          if (dst[i] >= 0) *reinterpret_cast<uint4*>(sm + dst[i]) = v[i];
       }
     }
     __syncthreads();
@@ -151,11 +153,12 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   }
 
   // |b| of the tile into LDS: lane holds rows 8(v/4) + 4(lane/32) + v%4 (directions)
-  // of column lane%32 (sample sb + 128 nt + 4 column) for each output tile
+  // of column lane%32 (window sample sw + 128 nt + 4 column) for each output tile
   float* absb = reinterpret_cast<float*>(sm);
+  const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
-    const int s = sb + 128 * nt + 4 * (lane & 31);
+    const int s = sw + 128 * nt + 4 * (lane & 31);
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -201,10 +204,15 @@ hipError_t init_mt_kernel_attributes() {
 }
 
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
-  const long long nblk = static_cast<long long>(F) * p->mt_nqt * p->mt_ntiles;
+  const int nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
+  const int tpx = (p->mt_ntiles + nx - 1) / nx;
+  const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
+  // the BF16 planes of frame f follow its M complex rows
+  const unsigned short* planes = reinterpret_cast<const unsigned short*>(yext + static_cast<long long>(p->M) * p->row);
   hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
-                     mt_smem_bytes(p), s, yext, p->d_mt_g, reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
+                     mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
+                     reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, p->d_taps, E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
-                     p->mt_ntiles, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow);
+                     p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow);
   return hipGetLastError();
 }

@@ -103,22 +103,28 @@ __device__ __forceinline__ float2 beam_sample(const float2 (&A)[NB], const float
 template <int NB, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_env_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, const float* __restrict__ taps,
-    float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc, int nqc, int ws, int mc) {
+    float* __restrict__ E, long long fstride, int M, int D, int Q, int row, int R, int K, int qc, int nqc, int ws,
+    int mc, int nwin) {
   extern __shared__ float2 smem[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int ndt = (D + NW - 1) / NW;
-  int bid = blockIdx.x;
+  // Workgroups are handed to the XCDs round-robin by index: XCD x runs every
+  // direction tile of windows (frame, range tile) x, x + TD_XCDS, ... so each
+  // staged window is fetched into one L2 only.
+  const int bx = blockIdx.x % TD_XCDS;
+  int bid = blockIdx.x / TD_XCDS;
   const int dt = bid % ndt;
-  bid /= ndt;
-  const int qi = bid % nqc;
-  const int f = bid / nqc;
+  const int win = bx + TD_XCDS * (bid / ndt);
+  if (win >= nwin) return;
+  const int qi = win % nqc;
+  const int f = win / nqc;
   const int d = dt * NW + wv;
   const bool active = d < D;
   const long long i0 = static_cast<long long>(qi) * qc * R;
 
   float2 A[NB], C[NB];
-  das_accumulate<NB, NW>(yext + static_cast<long long>(f) * M * row + i0, row,
+  das_accumulate<NB, NW>(yext + f * fstride + i0, row,
                          dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
                          A, C, wv, lane);
 
@@ -155,7 +161,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
 template <int NB, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_beam_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, float2* __restrict__ beam,
-    int M, int D, int G, int row, int tc, int nbc, int ws, int mc) {
+    long long fstride, int M, int D, int G, int row, int tc, int nbc, int ws, int mc) {
   extern __shared__ float2 smem[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
   const long long i0 = static_cast<long long>(ci) * tc;
 
   float2 A[NB], C[NB];
-  das_accumulate<NB, NW>(yext + static_cast<long long>(f) * M * row + i0, row,
+  das_accumulate<NB, NW>(yext + f * fstride + i0, row,
                          dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
                          A, C, wv, lane);
 #pragma unroll
@@ -233,10 +239,11 @@ hipError_t init_td_kernel_attributes() {
 hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
   const int ndt = (p->D + TD_NW - 1) / TD_NW;
   const size_t smem = td_smem_bytes(p);
-  const long long nblk = static_cast<long long>(F) * p->td_nqc * ndt;
+  const int nwin = F * p->td_nqc;
+  const long long nblk = static_cast<long long>((nwin + TD_XCDS - 1) / TD_XCDS) * TD_XCDS * ndt;
   hipLaunchKernelGGL((das_td_env_kernel<TD_NB, TD_NW>), dim3(static_cast<unsigned>(nblk)), dim3(TD_NW * 64),
-                     smem, s, yext, p->d_dtab, p->d_taps, E, p->M, p->D, p->Q, p->row, p->R, p->K,
-                     p->td_qc, p->td_nqc, p->td_ws, p->td_mc);
+                     smem, s, yext, p->d_dtab, p->d_taps, E, p->mf_fstride, p->M, p->D, p->Q, p->row, p->R, p->K,
+                     p->td_qc, p->td_nqc, p->td_ws, p->td_mc, nwin);
   return hipGetLastError();
 }
 
@@ -245,7 +252,7 @@ hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, 
   const size_t smem = td_smem_bytes(p);
   const long long nblk = static_cast<long long>(F) * p->td_nbc * ndt;
   hipLaunchKernelGGL((das_td_beam_kernel<TD_NB, TD_NW>), dim3(static_cast<unsigned>(nblk)), dim3(TD_NW * 64),
-                     smem, s, yext, p->d_dtab, beam, p->M, p->D, p->G, p->row, p->td_tn, p->td_nbc,
+                     smem, s, yext, p->d_dtab, beam, p->mf_fstride, p->M, p->D, p->G, p->row, p->td_tn, p->td_nbc,
                      p->td_ws, p->td_mc);
   return hipGetLastError();
 }

@@ -34,6 +34,11 @@ template <>
 __device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) { return __bfloat162float(v); }
 
 // Loads the twiddle tables of the plan into LDS.
+// round-to-nearest-even BF16 bits of a finite float
+__device__ __forceinline__ unsigned short bf16_rne(float v) {
+  return __builtin_bit_cast(unsigned short, static_cast<__bf16>(v));
+}
+
 template <int LOGNF>
 __device__ __forceinline__ void load_tw(float2* tw, const float2* __restrict__ tw_g, int tid, int nthreads) {
   constexpr int NF = 1 << LOGNF;
@@ -121,7 +126,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
 template <int LOGNF>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
-    int row, int origin, int P) {
+    long long fstride, int M, int row, int origin, int P, int planes) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -150,12 +155,33 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   fft_lds<LOGNF, true>(v, lds, tw_hi, tw_lo, tid);
   const float inv_p = 1.0f / static_cast<float>(P);
   const float sgn = par ? -1.0f : 1.0f;
-  float2* out = yext + ch * row;
+  const long long f = ch / M;
+  const int m = static_cast<int>(ch - f * M);
+  float2* out = yext + f * fstride + static_cast<long long>(m) * row;
+  // BF16 planes (re hi, re lo, im hi, im lo) of the same samples after the
+  // complex rows of the frame: [M][4][row]
+  unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
+                       static_cast<long long>(m) * 4 * row;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int n = 2 * S::out_index(tid, i) + par;
     const float2 y = make_float2((v[i].x + sgn * ny.x) * inv_p, (v[i].y + sgn * ny.y) * inv_p);
-    for (int j = (n - origin) & (P - 1); j < row; j += P) out[j] = y;
+    unsigned short rh = 0, rl = 0, ih = 0, il = 0;
+    if (planes) {
+      rh = bf16_rne(y.x);
+      rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
+      ih = bf16_rne(y.y);
+      il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+    }
+    for (int j = (n - origin) & (P - 1); j < row; j += P) {
+      out[j] = y;
+      if (planes) {
+        pl[j] = rh;
+        pl[row + j] = rl;
+        pl[2 * row + j] = ih;
+        pl[3 * row + j] = il;
+      }
+    }
   }
 }
 
@@ -221,7 +247,8 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
-                     p->d_spec, p->d_tw, yext, p->row, static_cast<int>(p->origin), p->P);
+                     p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
+                     p->bf_mode == SONAR_BF_TD_BF16 ? 1 : 0);
   return hipGetLastError();
 }
 

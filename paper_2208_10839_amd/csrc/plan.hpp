@@ -12,6 +12,7 @@
 // per wavefront (one sample per lane).
 constexpr int TD_NB = 16;
 constexpr int TD_NW = 8;
+constexpr int TD_XCDS = 8;       // accelerator dies (each with its own L2) that workgroups are spread over
 constexpr int TD_FIR_DIRS = 2;   // directions per thread in the fused low-pass stage
 constexpr int TD_WAVES_PER_EU = 4;   // two workgroups per CU (80 KiB LDS each): 128 VGPRs per lane
 constexpr int TD_LDS_BYTES = 80 * 1024;    // LDS budget of one beamformer workgroup
@@ -33,7 +34,9 @@ struct sonar_plan_s {
   int hk = 0;           // (K-1)/2
   int omin = 0, omax = 0, spread = 0;   // bounds of o = floor(-Dl) over all (d, m)
   int64_t origin = 0;   // sample index of MF row element 0 (TD)
-  int row = 0;          // complex elements per MF row (TD)
+  int row = 0;          // complex elements per MF row (TD), a multiple of 8
+  long long mf_fstride = 0;   // complex64 elements per frame of the TD MF buffer: M*row, or 2*M*row
+                              // when the BF16 planes [M][4][row] follow the complex rows (TD BF16)
 
   // time-domain beamformer tiling
   int td_ws = 0;        // staged samples per microphone
@@ -54,6 +57,7 @@ struct sonar_plan_s {
 
   // time-domain BF16-MFMA beamformer tiling (see k_das_mfma.hip)
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
+  long long mt_flop_per_frame = 0;   // matrix-core flops issued per frame
 
   int device = 0;
   size_t ws_bytes = 0;
@@ -103,6 +107,7 @@ __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L 
 constexpr int MT_NWAVE = 8;
 constexpr int MT_MICS = 16;
 constexpr int MT_RES = 4;
+constexpr int MT_XCDS = 8;   // accelerator dies (each with its own L2) that workgroups are spread over
 
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)

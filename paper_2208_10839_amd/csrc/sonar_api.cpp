@@ -231,6 +231,10 @@ int build_mt_tables(sonar_plan_s* p, const double* dirs, hipStream_t stream, siz
   }
   p->mt_gmax = gmax;
   p->mt_kcmax = kcmax;
+  // every (tile, residue) K-chunk runs on MT_NWAVE / MT_RES wavefronts x 4 output tiles x 6 MFMAs
+  long long chunks = 0;
+  for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / 2;
+  p->mt_flop_per_frame = chunks * (MT_NWAVE / MT_RES) * 4 * 6 * (2LL * 32 * 32 * 16) * p->mt_nqt;
   bool ok = dev_alloc(&p->d_mt_g, gtab.size(), total) == hipSuccess &&
             dev_alloc(&p->d_mt_w, wtab.size(), total) == hipSuccess &&
             dev_alloc(&p->d_mt_kcr, kcr.size(), total) == hipSuccess &&
@@ -419,13 +423,13 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     // MFMA tiles: MT_NWAVE * 128 beam samples, rows staged over the tile plus the delay span
     const int ns = MT_NWAVE * 128;
     p->mt_qc = (ns - p->K) / p->R + 1;
-    if ((p->mt_qc * p->R) & 1) p->mt_qc -= 1;
+    while (p->mt_qc > 0 && (p->mt_qc * p->R) % 4 != 0) p->mt_qc -= 1;
     if (p->mt_qc < 1) {
       delete p;
       return fail(SONAR_E_UNSUPPORTED, "low-pass length %d too long for the BF16 time-domain beamformer", p->K);
     }
     p->mt_nqt = (p->Q + p->mt_qc - 1) / p->mt_qc;
-    p->mt_wrow = (ns + p->spread + 16 + 7) / 8 * 8;
+    p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
     p->mt_ntiles = (p->D + 31) / 32;
     p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
     if (4 * static_cast<long long>(MT_MICS) * p->mt_wrow * 2 > 160 * 1024) {
@@ -435,8 +439,9 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     const long long need_mt = static_cast<long long>(p->mt_nqt - 1) * p->mt_qc * p->R + p->mt_wrow;
     if (need_mt > row) row = need_mt;
   }
-  row = (row + 3) / 4 * 4;
+  row = (row + 7) / 8 * 8;
   p->row = static_cast<int>(row);
+  p->mf_fstride = static_cast<long long>(p->bf_mode == SONAR_BF_TD_BF16 ? 2 : 1) * p->M * p->row;
   p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
 
   // frequency-domain layout: the stored bins are exactly those the band mask keeps
@@ -482,7 +487,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   // one-time allocation of every device buffer
   size_t total = 0;
   const size_t dm = static_cast<size_t>(p->D) * p->M;
-  const size_t mf_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->M * p->row;
+  const size_t mf_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->mf_fstride;
   const size_t spec_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->M * (p->NF + 1);
   const size_t band_elems = fd ? static_cast<size_t>(p->max_frames) * p->kb * p->M : 0;
   const size_t bspec_elems = fd ? static_cast<size_t>(p->max_frames) * p->D * p->kb_pad : 0;
@@ -558,8 +563,9 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
     case SONAR_Q_BAND_BINS: *value = p->kb; break;
     case SONAR_Q_WORKSPACE_BYTES: *value = static_cast<int64_t>(p->ws_bytes); break;
     case SONAR_Q_LPF_LEN: *value = p->K; break;
+    case SONAR_Q_MATRIX_FLOP_PER_FRAME: *value = p->mt_flop_per_frame; break;
     case SONAR_Q_MF_FRAME_ELEMS:
-      *value = is_td(p) ? static_cast<int64_t>(p->M) * p->row
+      *value = is_td(p) ? static_cast<int64_t>(p->mf_fstride)
                                                 : static_cast<int64_t>(p->kb) * p->M;
       break;
     default: return fail(SONAR_E_INVALID, "unknown query key %d", what);

@@ -60,15 +60,16 @@ def test_td_bf16_stages(gpu, torch_mod):
     plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 3000, mode="td_bf16", **kw)
     ref = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 3000, mode="td", **kw)
     assert plan.mf_row == ref.mf_row and plan.mf_origin == ref.mf_origin
-    assert plan.mf_frame_elems == plan.M * plan.mf_row
+    assert plan.mf_frame_elems == 2 * plan.M * plan.mf_row
     x = torch.from_numpy(w.x).cuda()
     mf = plan.matched_filter(x)
+    check_planes(mf, plan)
     beam = plan.beamform(mf)
     E = plan.envelope(beam)
     E2 = plan.beamform_envelope(mf)
     E3 = plan.energyscape(x)
     torch.cuda.synchronize()
-    assert torch.equal(mf, ref.matched_filter(x))
+    assert torch.equal(mf[:, :plan.M * plan.mf_row], ref.matched_filter(x))
     xf = w.x[0].astype(np.float64)
     yhat = O.matched_filter(xf, w.chirp, plan.P, w.fs, w.cfg.band)
     Dl = O.delays(w.mic_pos, w.dirs, w.fs, w.c)
@@ -85,6 +86,26 @@ def test_td_bf16_stages(gpu, torch_mod):
         _say(f"  {name} rel L2 = {e:.3e}")
         assert e <= BAR
     assert torch.equal(E2, E3)
+
+
+def _bf16_rne(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def check_planes(mf, plan):
+    """The BF16 planes after the complex rows: bit-exact hi/lo split of the same samples."""
+    import torch
+    M, row = plan.M, plan.mf_row
+    fr = mf[0].cpu()
+    y = fr[:M * row].numpy().reshape(M, row)
+    pl = fr[M * row:].view(torch.int16).numpy().view(np.uint16).reshape(M, 4, row)
+    for c, part in enumerate((y.real, y.imag)):
+        hi = _bf16_rne(part)
+        hv = (hi.astype(np.uint32) << 16).view(np.float32)
+        lo = _bf16_rne(part.astype(np.float32) - hv)
+        assert np.array_equal(pl[:, 2 * c], hi)
+        assert np.array_equal(pl[:, 2 * c + 1], lo)
 
 
 def _sphere(n, seed):
