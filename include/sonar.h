@@ -125,7 +125,9 @@ enum sonar_query {
  *   FFT twiddles.
  * The tables are built with work enqueued on `stream`; the call synchronises
  * that stream before returning.  Returns SONAR_E_INVALID for a descriptor that
- * breaks a rule stated above, SONAR_E_UNSUPPORTED for P > 32768, and
+ * breaks a rule stated above; SONAR_E_UNSUPPORTED for P > 524288, for the
+ * frequency-domain modes when P > 65536 or more than 16385 bins are stored,
+ * and for array apertures whose delay spread exceeds the beamformer tiles;
  * SONAR_E_NOMEM when allocation fails.  *out is set only on success.
  */
 int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_plan* out);

@@ -266,7 +266,7 @@ __device__ __forceinline__ void load_fd_tw(float2* tw, const float2* __restrict_
   for (int i = tid; i < len; i += nt) tw[i] = tw_g[i];
 }
 
-constexpr int FD_MAX_TW_P = 32768 / 64 + 1 + 64;   // P tables for P <= 32768
+constexpr int FD_MAX_TW_P = FD_MAX_P / 64 + 1 + 64;   // P tables for P <= FD_MAX_P
 
 // One direction of one frame per workgroup.  The stored spectrum is read once;
 // each phase's transform lands as |b| in an LDS copy of the beam window (the

@@ -273,6 +273,7 @@ hipError_t launch_mf_td_dt(const sonar_plan_s* p, const void* x, int F, float2* 
 }  // namespace
 
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+  if (p->NF > (1 << MB_LOGN2)) return launch_mf_big_td(p, x, F, yext, s);
   switch (p->dtype) {
     case SONAR_F32: return launch_mf_td_dt<float>(p, x, F, yext, s);
     case SONAR_F16: return launch_mf_td_dt<__half>(p, x, F, yext, s);
@@ -282,6 +283,7 @@ hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yex
 }
 
 hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s) {
+  if (p->NF > (1 << MB_LOGN2)) return launch_mf_big_fd(p, x, F, band, s);
   switch (p->dtype) {
     case SONAR_F32: return launch_mf_band_dt<float>(p, x, F, band, s);
     case SONAR_F16: return launch_mf_band_dt<__half>(p, x, F, band, s);

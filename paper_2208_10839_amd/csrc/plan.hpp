@@ -76,6 +76,8 @@ struct sonar_plan_s {
   float2* d_fdspec = nullptr;  // FD: band spectra of the MF output, [max_frames][kb][M]
   float2* d_bspec = nullptr;   // FD: beam spectra, [max_frames][D][kb_pad]
   float2* d_fdtw = nullptr;    // FD: twiddles for fd_L and P (layout: fd_tw_len)
+  float2* d_big = nullptr;     // NF > 2^MB_LOGN2: matched-filter scratch, [max_frames][M][2 NF]
+  float2* d_tw2 = nullptr;     // NF > 2^MB_LOGN2: twiddles of the 2^MB_LOGN2-point row transforms
   float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
   float2* d_beam = nullptr;    // FD fallback: beam window [max_frames][D][G'] (unfused plans only)
   int2* d_mt_g = nullptr;      // TD BF16: tap groups {mic, first tap offset}, [tiles][MT_RES][gmax]
@@ -105,6 +107,10 @@ __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L 
 // beam samples per workgroup; wavefront w computes the samples of residue
 // w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time
 constexpr int MT_NWAVE = 8;
+// matched filters with NF > 2^MB_LOGN2 run as a radix-(NF / 2^MB_LOGN2) pass over
+// global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
+constexpr int MB_LOGN2 = 14;
+constexpr int MB_MAX_R = 16;
 constexpr int MT_MICS = 16;
 constexpr int MT_RES = 4;
 constexpr int MT_XCDS = 8;   // accelerator dies (each with its own L2) that workgroups are spread over
@@ -114,9 +120,12 @@ constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple o
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
 constexpr int FD_MAX_TAPS = 1024;
+constexpr int FD_MAX_P = 65536;   // FFT length limit of the frequency-domain inverse (LDS twiddle tables)
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t init_mt_kernel_attributes();
+hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+hipError_t launch_mf_big_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 size_t mt_smem_bytes(const sonar_plan_s* p);
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s);

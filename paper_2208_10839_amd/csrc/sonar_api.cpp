@@ -81,6 +81,8 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_beam);
   (void)hipFree(p->d_fdtw);
   (void)hipFree(p->d_fdstep);
+  (void)hipFree(p->d_big);
+  (void)hipFree(p->d_tw2);
   (void)hipFree(p->d_mt_g);
   (void)hipFree(p->d_mt_w);
   (void)hipFree(p->d_mt_kcr);
@@ -341,9 +343,9 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     delete p;
     return fail(SONAR_E_INVALID, "fft_len %d must be a power of two >= max(N + L - 1, 32)", d.fft_len);
   }
-  if (P > 32768) {
+  if (P > 2LL * MB_MAX_R * (1 << MB_LOGN2)) {
     delete p;
-    return fail(SONAR_E_UNSUPPORTED, "FFT length %lld above 32768 is not supported", P);
+    return fail(SONAR_E_UNSUPPORTED, "FFT length %lld above %d is not supported", P, 2 * MB_MAX_R * (1 << MB_LOGN2));
   }
   p->P = static_cast<int>(P);
   p->NF = p->P / 2;
@@ -472,6 +474,16 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->K <= FD_MAX_TAPS &&
                 fd_env_static_lds(p->fd_logL, p->P) + static_cast<size_t>(p->G) * sizeof(float) <= 160 * 1024;
   const bool fd = !is_td(p);
+  if (fd && p->P > FD_MAX_P) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "frequency-domain beamformer: FFT length %d above %d", p->P, FD_MAX_P);
+  }
+  if (fd && p->fd_L > (1 << 14)) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED,
+                "frequency-domain beamformer: %d stored bins need a %d-point inverse transform (at most 16384)", p->kb,
+                p->fd_L);
+  }
 
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
@@ -494,6 +506,9 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   const size_t beam_elems = fd && !p->fd_fused ? static_cast<size_t>(p->max_frames) * p->D * p->G : 0;
   const size_t fdtw_elems = fd ? static_cast<size_t>(fd_tw_len(p->fd_L, p->P)) : 0;
   const size_t aux_bytes = static_cast<size_t>(p->P) * sizeof(double2);
+  const bool big = p->NF > (1 << MB_LOGN2);
+  const size_t big_elems = big ? static_cast<size_t>(p->max_frames) * p->M * 2 * p->NF : 0;
+  const size_t tw2_elems = big ? static_cast<size_t>(fft_tw_len(1 << MB_LOGN2)) : 0;
   bool ok = dev_alloc(&p->d_dtab, dm, &total) == hipSuccess &&
             dev_alloc(&p->d_dl, dm, &total) == hipSuccess &&
             dev_alloc(&p->d_pos, 3 * static_cast<size_t>(p->M), &total) == hipSuccess &&
@@ -509,6 +524,8 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
             dev_alloc(&p->d_beam, beam_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_fdtw, fdtw_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_fdstep, fd ? dm : 0, &total) == hipSuccess &&
+            dev_alloc(&p->d_big, big_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_tw2, tw2_elems, &total) == hipSuccess &&
             dev_alloc(reinterpret_cast<char**>(&p->d_aux), aux_bytes, &total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();

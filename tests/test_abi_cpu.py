@@ -71,7 +71,7 @@ def _desc(**over):
     ("fs_hz", -1.0, binding.SONAR_E_INVALID),
     ("fft_len", 100, binding.SONAR_E_INVALID),        # not a power of two
     ("fft_len", 64, binding.SONAR_E_INVALID),         # below N + L - 1
-    ("fft_len", 65536, binding.SONAR_E_UNSUPPORTED),
+    ("fft_len", 1048576, binding.SONAR_E_UNSUPPORTED),  # above 2 x 16 x 16384
     ("gate_begin", 50, binding.SONAR_E_INVALID),      # gate_end 0 -> n0 >= n1
     ("lpf_len", 4, binding.SONAR_E_INVALID),          # even, and no taps
     ("bf_mode", 7, binding.SONAR_E_INVALID),
@@ -84,6 +84,18 @@ def test_bad_descriptor_rejected_on_host(field, value, status):
     assert lib.sonar_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == status
     assert h.value is None
     assert len(lib.sonar_last_error()) > 0
+
+
+@pytest.mark.parametrize("fft_len,band,what", [
+    (131072, (0.0, 0.0), b"FFT length"),             # above the FD inverse's twiddle tables
+    (65536, (0.0, 0.0), b"inverse transform"),       # 32769 stored bins need a 32768-point inverse
+])
+def test_frequency_domain_size_limits(fft_len, band, what):
+    lib = binding.load()
+    d, keep = _desc(fft_len=fft_len, bf_mode=binding.BF_MODES["fd_fp32"], band_lo_hz=band[0], band_hi_hz=band[1])
+    h = ctypes.c_void_p()
+    assert lib.sonar_plan_create(ctypes.byref(d), None, ctypes.byref(h)) == binding.SONAR_E_UNSUPPORTED
+    assert what in lib.sonar_last_error()
 
 
 def test_non_unit_direction_rejected():

@@ -221,5 +221,5 @@ def test_exec_errors(gpu, torch_mod):
     with pytest.raises(TypeError):
         plan.energyscape(torch.zeros((1, 32, 4096), device="cuda", dtype=torch.float16))
     with pytest.raises(gpu.SonarError) as ei:
-        gpu.Plan(w.mic_pos, w.chirp, w.dirs, 4096, fs=w.fs, c=w.c, fft_len=131072)
+        gpu.Plan(w.mic_pos, w.chirp, w.dirs, 4096, fs=w.fs, c=w.c, fft_len=1 << 20)
     assert ei.value.status == gpu.SONAR_E_UNSUPPORTED
