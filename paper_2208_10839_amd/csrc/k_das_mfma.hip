@@ -34,7 +34,6 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 
-constexpr int MT_FIR_DIRS = 4;   // directions per thread in the low-pass stage
 
 // 8 BF16 values at an 8-byte aligned LDS address
 __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
@@ -50,7 +49,7 @@ template <int NWAVE>
 __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
-    const float* __restrict__ taps, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
+    const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
     int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow) {
   extern __shared__ unsigned short sm[];    // 4 planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
@@ -74,6 +73,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   // first sample of the wavefront, as an index into the staged rows
   const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
   const int plane = MT_MICS * wrow;
+  const int bufsz = 4 * plane;               // one staging buffer: 4 planes x MT_MICS rows
   const unsigned short* src = planes + f * fstride + s0a;
 
   f32x16 cre[4], cim[4];
@@ -83,78 +83,117 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     cim[nt] = f32x16{};
   }
 
-  for (int mc = 0; mc < nmc; ++mc) {
-    const int m0 = mc * MT_MICS;
-    const int rows = M - m0 < MT_MICS ? M - m0 : MT_MICS;
-    // stage rows m0.. of this frame, samples [s0a, s0a + wrow) of each BF16 plane:
-    // segment sg = 4 ml + c is plane c of microphone m0 + ml, copied in 16-byte chunks
-    {
-      constexpr int B = 8;
-      const int cw = wrow >> 3;
-      const int nseg = 4 * rows;
-      const int total = nseg * cw;
-      const int dq = NT / cw, dr = NT % cw;
-      int sg = threadIdx.x / cw, k = threadIdx.x - sg * cw;
-      for (int base = threadIdx.x; base < total; base += NT * B) {
-        uint4 v[B];
-        int dst[B];
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-          const bool ok = base + i * NT < total;
-          const int sgc = ok ? sg : nseg - 1, kc = ok ? k : cw - 1;
-          v[i] = *reinterpret_cast<const uint4*>(src + static_cast<long long>(m0 * 4 + sgc) * row + 8 * kc);
-          dst[i] = ok ? (sgc & 3) * plane + (sgc >> 2) * wrow + 8 * kc : -1;
-          k += dr;
-          sg += dq;
-          if (k >= cw) {
-            k -= cw;
-            sg += 1;
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-          if (dst[i] >= 0) *reinterpret_cast<uint4*>(sm + dst[i]) = v[i];
-      }
-    }
-    __syncthreads();
-    const int li = tile * MT_RES + rho;
-    const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
-    if (kr.x < kr.y) {
-      const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-      const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
-      uint4 ah_next = wt[kr.x * 128], al_next = wt[kr.x * 128 + 64];
-      int2 g_next = gt[2 * kr.x];
-      for (int kc = kr.x; kc < kr.y; ++kc) {
-        const bf16x8 ah = __builtin_bit_cast(bf16x8, ah_next);
-        const bf16x8 al = __builtin_bit_cast(bf16x8, al_next);
-        const int2 g = g_next;
-        if (kc + 1 < kr.y) {
-          ah_next = wt[(kc + 1) * 128];
-          al_next = wt[(kc + 1) * 128 + 64];
-          g_next = gt[2 * (kc + 1)];
-        }
-        const unsigned short* p = sm + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-          const bf16x8 brh = lds_frag(p + 128 * nt);
-          const bf16x8 brl = lds_frag(p + plane + 128 * nt);
-          const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
-          const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
-          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
-          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
-          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
-          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
-          cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
-          cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
+  // Staging: rows m0.. of this frame, samples [s0a, s0a + wrow) of each BF16 plane,
+  // copied in 16-byte chunks; chunk i of a microphone group is segment sg = 4 ml + c
+  // (plane c of microphone m0 + ml), column k.  Thread t owns chunks t + NT j, j < MT_SPT.
+  // Two LDS buffers: the loads for group mc + 1 are in flight while group mc runs.
+  const int cw = wrow >> 3;
+  const int dq = NT / cw, dr = NT % cw;
+  const int sg0 = threadIdx.x / cw, k0 = threadIdx.x - sg0 * cw;
+  static_assert(MT_SPT == 10, "the staging registers below are written out for 5 chunks per half");
+  uint4 st0, st1, st2, st3, st4;
+  int sgh = sg0, kh = k0;                    // chunk position of st0 within the group
+  // one half (5 chunks per thread) of the staging of a microphone group
+#define MT_ADV                                                                                         \
+  k += dr;                                                                                             \
+  sg += dq;                                                                                            \
+  if (k >= cw) {                                                                                       \
+    k -= cw;                                                                                           \
+    sg += 1;                                                                                           \
+  }
+#define MT_LD(R_)                                                                                      \
+  R_ = *reinterpret_cast<const uint4*>(src + static_cast<long long>(m0n * 4 + (sg < nseg ? sg : 0)) * row + \
+                                        8 * (sg < nseg ? k : 0));                                       \
+  MT_ADV
+#define MT_ST(R_)                                                                                      \
+  if (sg < nseg) *reinterpret_cast<uint4*>(dstb + (sg & 3) * plane + (sg >> 2) * wrow + 8 * k) = R_;   \
+  MT_ADV
+#define MT_STAGE_LOAD(MC)                                                                              \
+  {                                                                                                    \
+    const int m0n = (MC) * MT_MICS;                                                                    \
+    const int nseg = 4 * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                      \
+    int sg = sgh, k = kh;                                                                              \
+    MT_LD(st0) MT_LD(st1) MT_LD(st2) MT_LD(st3) MT_LD(st4)                                             \
+  }
+#define MT_STAGE_STORE(MC, BUF)                                                                        \
+  {                                                                                                    \
+    const int m0n = (MC) * MT_MICS;                                                                    \
+    const int nseg = 4 * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                      \
+    unsigned short* dstb = (BUF);                                                                      \
+    int sg = sgh, k = kh;                                                                              \
+    MT_ST(st0) MT_ST(st1) MT_ST(st2) MT_ST(st3) MT_ST(st4)                                             \
+    sgh = sg;                                                                                          \
+    kh = k;                                                                                            \
   }
 
-  // |b| of the tile into LDS: lane holds rows 8(v/4) + 4(lane/32) + v%4 (directions)
-  // of column lane%32 (window sample sw + 128 nt + 4 column) for each output tile
-  float* absb = reinterpret_cast<float*>(sm);
+  MT_STAGE_LOAD(0)
+  MT_STAGE_STORE(0, sm)
+  MT_STAGE_LOAD(0)
+  MT_STAGE_STORE(0, sm)
+  for (int mc = 0; mc < nmc; ++mc) {
+    const int m0 = mc * MT_MICS;
+    unsigned short* buf = sm + (mc & 1) * bufsz;
+    unsigned short* nbuf = sm + ((mc + 1) & 1) * bufsz;
+    const bool next = mc + 1 < nmc;
+    __syncthreads();                         // group mc staged; group mc - 1 no longer read
+    sgh = sg0;
+    kh = k0;
+    const int li = tile * MT_RES + rho;
+    const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
+    const int kmid = (kr.x + kr.y) >> 1;
+    const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
+    const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
+    // the next group is staged in two halves, each loaded during one half of the K-chunks
+    for (int hk = 0; hk < 2; ++hk) {
+      if (next) {
+        if (hk == 1) MT_STAGE_STORE(mc + 1, nbuf)
+        MT_STAGE_LOAD(mc + 1)
+      }
+      const int ka = hk ? kmid : kr.x, kb = hk ? kr.y : kmid;
+      if (ka < kb) {
+        uint4 ah_next = wt[ka * 128], al_next = wt[ka * 128 + 64];
+        int2 g_next = gt[2 * ka];
+        for (int kc = ka; kc < kb; ++kc) {
+          const bf16x8 ah = __builtin_bit_cast(bf16x8, ah_next);
+          const bf16x8 al = __builtin_bit_cast(bf16x8, al_next);
+          const int2 g = g_next;
+          if (kc + 1 < kb) {
+            ah_next = wt[(kc + 1) * 128];
+            al_next = wt[(kc + 1) * 128 + 64];
+            g_next = gt[2 * (kc + 1)];
+          }
+          const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+#pragma unroll
+          for (int nt = 0; nt < 4; ++nt) {
+            const bf16x8 brh = lds_frag(p + 128 * nt);
+            const bf16x8 brl = lds_frag(p + plane + 128 * nt);
+            const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
+            const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
+            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
+            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
+            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
+            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
+            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
+            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (next) MT_STAGE_STORE(mc + 1, nbuf)
+  }
+#undef MT_STAGE_LOAD
+#undef MT_STAGE_STORE
+#undef MT_LD
+#undef MT_ST
+#undef MT_ADV
+  __syncthreads();
+
+  // |b| of the tile into LDS as BF16 hi/lo planes [32][MT_NSP]: lane holds rows
+  // 8(v/4) + 4(lane/32) + v%4 (directions) of column lane%32 (window sample
+  // sw + 128 nt + 4 column) for each output tile
+  constexpr int NSP = MT_NSP;
+  unsigned short* bh = sm;
+  unsigned short* bl = sm + 32 * NSP;
   const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -162,39 +201,82 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      absb[dl * NS + s] = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
+      const float a = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
+      const unsigned short hi = __builtin_bit_cast(unsigned short, static_cast<__bf16>(a));
+      const float lo = a - __builtin_bit_cast(float, static_cast<unsigned int>(hi) << 16);
+      bh[dl * NSP + s] = hi;
+      bl[dl * NSP + s] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(lo));
     }
   }
+  // the last K-step of a column block reads up to 15 samples past the window: those
+  // of each row's tail, the next row's first ones, and after the last row 16 zeros
+  for (int i = threadIdx.x; i < 2 * 32 * (NSP - NS) + 16; i += NT) {
+    const int r = i / (NSP - NS), c = i - r * (NSP - NS);
+    sm[r * NSP + NS + c] = 0;
+  }
   __syncthreads();
-  // low-pass + decimation: lanes run over range bins (coalesced stores), each
-  // thread accumulates MT_FIR_DIRS directions dl = g + 8 i at once
-  constexpr int NG = 32 / MT_FIR_DIRS;
-  for (int it = threadIdx.x; it < NG * qc; it += NWAVE * 64) {
-    const int g = it / qc, q = it - g * qc;
-    const int qq = qt * qc + q;
-    if (qq >= Q) continue;
-    const float* a = absb + g * NS + q * R + K - 1;
-    float acc[MT_FIR_DIRS];
+  // low-pass + decimation on MFMA: E[d][q] = sum_s |b|[d][s] H[s][q], H[s][q] = h[qR + K-1 - s],
+  // a banded Toeplitz operand.  A column block of 32 range bins q0.. needs samples
+  // q0 R .. (q0 + 31) R + K - 1; with s = q0 R + 16 ks + k the B fragments
+  // h[nR + K-1 - 16 ks - k] do not depend on q0 and come from the plan (hi, lo terms).
+  const int nqb = (qc + 31) / 32;
+  // partial sums of the second K-half of each column block: [MT_NWAVE / 2][64 lanes][16]
+  float* part = reinterpret_cast<float*>(sm + 2 * 32 * NSP + 16);
+  const int half = wv & 1;
+  for (int cbr = 0; cbr < nqb; cbr += NWAVE / 2) {
+    const int cb = cbr + (wv >> 1);
+    f32x16 acc = f32x16{};
+    if (cb < nqb) {
+      const int q0 = 32 * cb;
+      const int nval = qc - q0 < 32 ? qc - q0 : 32;
+      const int nks = ((nval - 1) * R + K + 15) / 16;
+      const int kmid = (nks + 1) >> 1;
+      const int ks0 = half ? kmid : 0, ks1 = half ? nks : kmid;
+      const unsigned short* ah = bh + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
+      if (ks0 < ks1) {
+        uint4 hh = ftab[(2 * ks0) * 64 + lane], hl = ftab[(2 * ks0 + 1) * 64 + lane];
+        for (int ks = ks0; ks < ks1; ++ks) {
+          const bf16x8 h_hi = __builtin_bit_cast(bf16x8, hh);
+          const bf16x8 h_lo = __builtin_bit_cast(bf16x8, hl);
+          if (ks + 1 < ks1) {
+            hh = ftab[(2 * ks + 2) * 64 + lane];
+            hl = ftab[(2 * ks + 3) * 64 + lane];
+          }
+          const bf16x8 a_hi = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ah + 16 * ks));
+          const bf16x8 a_lo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ah + 32 * NSP + 16 * ks));
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, h_hi, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, h_lo, acc, 0, 0, 0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo, h_hi, acc, 0, 0, 0);
+        }
+      }
+      if (half) {
 #pragma unroll
-    for (int i = 0; i < MT_FIR_DIRS; ++i) acc[i] = 0.f;
-    for (int j = 0; j < K; ++j) {
-      const float h = taps[j];
-#pragma unroll
-      for (int i = 0; i < MT_FIR_DIRS; ++i) acc[i] = fmaf(h, a[i * NG * NS - j], acc[i]);
+        for (int v = 0; v < 16; ++v) part[((wv >> 1) * 64 + lane) * 16 + v] = acc[v];
+      }
     }
+    __syncthreads();
+    if (cb < nqb && !half) {
+      const int q = 32 * cb + (lane & 31);
+      const int qq = qt * qc + q;
+      if (q < qc && qq < Q) {
 #pragma unroll
-    for (int i = 0; i < MT_FIR_DIRS; ++i) {
-      const int d = perm[tile * 32 + g + NG * i];
-      if (d >= 0) E[(static_cast<long long>(f) * D + d) * Q + qq] = acc[i];
+        for (int v = 0; v < 16; ++v) {
+          const int d = perm[tile * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
+          if (d >= 0)
+            E[(static_cast<long long>(f) * D + d) * Q + qq] = acc[v] + part[((wv >> 1) * 64 + lane) * 16 + v];
+        }
+      }
     }
+    __syncthreads();
   }
 }
 
 }  // namespace
 
 size_t mt_smem_bytes(const sonar_plan_s* p) {
-  const size_t planes = 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
-  const size_t absb = 32 * static_cast<size_t>(MT_NWAVE * 128) * sizeof(float);
+  const size_t planes = 2 * 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
+  const size_t absb = (2 * 32 * static_cast<size_t>(MT_NSP) + 16) * sizeof(unsigned short) +
+                      static_cast<size_t>(MT_NWAVE / 2) * 64 * 16 * sizeof(float);
   return planes > absb ? planes : absb;
 }
 
@@ -212,7 +294,7 @@ hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F,
   hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
                      mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
-                     p->d_mt_perm, p->d_taps, E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
+                     p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
                      p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow);
   return hipGetLastError();
 }

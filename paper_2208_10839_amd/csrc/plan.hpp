@@ -84,6 +84,7 @@ struct sonar_plan_s {
   unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][MT_RES][kcmax][hi, lo][64 lanes][8] BF16
   int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][MT_RES]
   int* d_mt_perm = nullptr;    // TD BF16: tile slot -> direction (-1: empty), [tiles][32]
+  unsigned short* d_mt_fir = nullptr;   // TD BF16: low-pass B fragments, [K-steps][hi, lo][64 lanes][8] BF16
   void* d_aux = nullptr;       // plan-build scratch
 };
 
@@ -111,9 +112,13 @@ constexpr int MT_NWAVE = 8;
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
 constexpr int MB_LOGN2 = 14;
 constexpr int MB_MAX_R = 16;
-constexpr int MT_MICS = 16;
+constexpr int MT_MICS = 8;
+constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: 4 planes x MT_MICS rows x wrow / 8 <= MT_SPT x 512
 constexpr int MT_RES = 4;
-constexpr int MT_XCDS = 8;   // accelerator dies (each with its own L2) that workgroups are spread over
+constexpr int MT_XCDS = 8;
+// |b| rows in LDS for the matrix-core low-pass: MT_NWAVE * 128 samples + a zeroed tail,
+// padded so that a row is 16 bytes past a multiple of 256 (bank spread)
+constexpr int MT_NSP = MT_NWAVE * 128 + 8;   // accelerator dies (each with its own L2) that workgroups are spread over
 
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)

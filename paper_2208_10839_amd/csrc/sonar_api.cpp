@@ -87,6 +87,7 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_mt_w);
   (void)hipFree(p->d_mt_kcr);
   (void)hipFree(p->d_mt_perm);
+  (void)hipFree(p->d_mt_fir);
   (void)hipFree(p->d_aux);
   delete p;
 }
@@ -145,7 +146,8 @@ uint16_t to_bf16_bits(float v) {
 // starts on an 8-byte boundary.  A group pair is one K-chunk of
 // v_mfma_f32_32x32x16_bf16, whose A fragments (tap weights as BF16 hi and lo
 // terms) are stored in lane order.
-int build_mt_tables(sonar_plan_s* p, const double* dirs, hipStream_t stream, size_t* total) {
+int build_mt_tables(sonar_plan_s* p, const double* dirs, const std::vector<double>& taps, hipStream_t stream,
+                    size_t* total) {
   const int D = p->D, M = p->M;
   std::vector<int4> dtab(static_cast<size_t>(D) * M);
   hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
@@ -231,16 +233,40 @@ int build_mt_tables(sonar_plan_s* p, const double* dirs, hipStream_t stream, siz
       }
     }
   }
+  // low-pass B fragments: K-step ks, lane l holds H[16 ks + 8 (l / 32) + j][l % 32],
+  // H[k][n] = h[n R + K - 1 - k], as BF16 hi and lo terms
+  const int nks = (31 * p->R + p->K + 15) / 16;
+  std::vector<uint16_t> ftab(static_cast<size_t>(nks) * 2 * 64 * 8, 0);
+  for (int ks = 0; ks < nks; ++ks) {
+    for (int l = 0; l < 64; ++l) {
+      for (int j = 0; j < 8; ++j) {
+        const int idx = (l & 31) * p->R + p->K - 1 - (16 * ks + 8 * (l >> 5) + j);
+        const float h = idx >= 0 && idx < p->K ? static_cast<float>(taps[idx]) : 0.f;
+        const uint16_t hi = to_bf16_bits(h);
+        const uint32_t hb = static_cast<uint32_t>(hi) << 16;
+        float hv;
+        std::memcpy(&hv, &hb, 4);
+        ftab[((static_cast<size_t>(2 * ks) * 64) + l) * 8 + j] = hi;
+        ftab[((static_cast<size_t>(2 * ks + 1) * 64) + l) * 8 + j] = to_bf16_bits(h - hv);
+      }
+    }
+  }
   p->mt_gmax = gmax;
   p->mt_kcmax = kcmax;
   // every (tile, residue) K-chunk runs on MT_NWAVE / MT_RES wavefronts x 4 output tiles x 6 MFMAs
   long long chunks = 0;
   for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / 2;
   p->mt_flop_per_frame = chunks * (MT_NWAVE / MT_RES) * 4 * 6 * (2LL * 32 * 32 * 16) * p->mt_nqt;
+  for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {   // low-pass: 3 MFMAs per K-step and column block
+    const int nval = std::min(32, p->mt_qc - q0);
+    p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * 3 * (2LL * 32 * 32 * 16) *
+                            nt * p->mt_nqt;
+  }
   bool ok = dev_alloc(&p->d_mt_g, gtab.size(), total) == hipSuccess &&
             dev_alloc(&p->d_mt_w, wtab.size(), total) == hipSuccess &&
             dev_alloc(&p->d_mt_kcr, kcr.size(), total) == hipSuccess &&
-            dev_alloc(&p->d_mt_perm, perm.size(), total) == hipSuccess;
+            dev_alloc(&p->d_mt_perm, perm.size(), total) == hipSuccess &&
+            dev_alloc(&p->d_mt_fir, ftab.size(), total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     return fail(SONAR_E_NOMEM, "device allocation of the MFMA beamformer tables failed");
@@ -249,6 +275,7 @@ int build_mt_tables(sonar_plan_s* p, const double* dirs, hipStream_t stream, siz
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_w, wtab.data(), wtab.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_kcr, kcr.data(), kcr.size() * sizeof(int2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(p->d_mt_fir, ftab.data(), ftab.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "MFMA beamformer table upload");
 }
 
@@ -434,7 +461,8 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
     p->mt_ntiles = (p->D + 31) / 32;
     p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
-    if (4 * static_cast<long long>(MT_MICS) * p->mt_wrow * 2 > 160 * 1024) {
+    if (4LL * MT_MICS * (p->mt_wrow / 8) > static_cast<long long>(MT_SPT) * MT_NWAVE * 64 ||
+        mt_smem_bytes(p) > 160 * 1024) {
       delete p;
       return fail(SONAR_E_UNSUPPORTED, "array aperture too large for the BF16 time-domain beamformer");
     }
@@ -547,7 +575,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   e = launch_build_tables(p, stream);
   if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
   if (e == hipSuccess && p->bf_mode == SONAR_BF_TD_BF16) {
-    const int st = build_mt_tables(p, d.dirs, stream, &total);
+    const int st = build_mt_tables(p, d.dirs, taps, stream, &total);
     if (st != SONAR_OK) {
       free_plan(p);
       return st;
