@@ -50,7 +50,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow) {
+    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off) {
   extern __shared__ unsigned short sm[];    // 4 planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
   constexpr int NT = NWAVE * 64;
@@ -75,6 +75,9 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   const int plane = MT_MICS * wrow;
   const int bufsz = 4 * plane;               // one staging buffer: 4 planes x MT_MICS rows
   const unsigned short* src = planes + f * fstride + s0a;
+  // slot -> direction of this tile, kept in LDS past every other region (read by the stores)
+  int* permL = reinterpret_cast<int*>(reinterpret_cast<char*>(sm) + perm_off);
+  if (threadIdx.x < 32) permL[threadIdx.x] = perm[tile * 32 + threadIdx.x];
 
   f32x16 cre[4], cim[4];
 #pragma unroll
@@ -188,12 +191,11 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
 #undef MT_ADV
   __syncthreads();
 
-  // |b| of the tile into LDS as BF16 hi/lo planes [32][MT_NSP]: lane holds rows
+  // |b| of the tile into LDS as [32][MT_NSP] words {bf16 hi, bf16 lo}: lane holds rows
   // 8(v/4) + 4(lane/32) + v%4 (directions) of column lane%32 (window sample
   // sw + 128 nt + 4 column) for each output tile
   constexpr int NSP = MT_NSP;
-  unsigned short* bh = sm;
-  unsigned short* bl = sm + 32 * NSP;
+  unsigned int* bw = reinterpret_cast<unsigned int*>(sm);
   const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
@@ -202,53 +204,86 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     for (int v = 0; v < 16; ++v) {
       const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
       const float a = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
-      const unsigned short hi = __builtin_bit_cast(unsigned short, static_cast<__bf16>(a));
-      const float lo = a - __builtin_bit_cast(float, static_cast<unsigned int>(hi) << 16);
-      bh[dl * NSP + s] = hi;
-      bl[dl * NSP + s] = __builtin_bit_cast(unsigned short, static_cast<__bf16>(lo));
+      const unsigned int hi = __builtin_bit_cast(unsigned short, static_cast<__bf16>(a));
+      const float lo = a - __builtin_bit_cast(float, hi << 16);
+      bw[dl * NSP + s] = hi | (static_cast<unsigned int>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(lo))) << 16);
     }
   }
   // the last K-step of a column block reads up to 15 samples past the window: those
   // of each row's tail, the next row's first ones, and after the last row 16 zeros
-  for (int i = threadIdx.x; i < 2 * 32 * (NSP - NS) + 16; i += NT) {
+  for (int i = threadIdx.x; i < 32 * (NSP - NS) + 16; i += NT) {
     const int r = i / (NSP - NS), c = i - r * (NSP - NS);
-    sm[r * NSP + NS + c] = 0;
+    bw[r < 32 ? r * NSP + NS + c : 32 * NSP + (i - 32 * (NSP - NS))] = 0;
   }
   __syncthreads();
   // low-pass + decimation on MFMA: E[d][q] = sum_s |b|[d][s] H[s][q], H[s][q] = h[qR + K-1 - s],
   // a banded Toeplitz operand.  A column block of 32 range bins q0.. needs samples
   // q0 R .. (q0 + 31) R + K - 1; with s = q0 R + 16 ks + k the B fragments
-  // h[nR + K-1 - 16 ks - k] do not depend on q0 and come from the plan (hi, lo terms).
+  // h[nR + K-1 - 16 ks - k] do not depend on q0 and come from the plan (hi, lo terms),
+  // loaded four K-steps at a time, one batch ahead.
   const int nqb = (qc + 31) / 32;
   // partial sums of the second K-half of each column block: [MT_NWAVE / 2][64 lanes][16]
-  float* part = reinterpret_cast<float*>(sm + 2 * 32 * NSP + 16);
+  float* part = reinterpret_cast<float*>(bw + 32 * NSP + 16);
   const int half = wv & 1;
+#define MT_FIR_LOAD(H0, L0, H1, L1, H2, L2, H3, L3, KB)                                               \
+  {                                                                                                    \
+    const int k0_ = (KB) < ks1 - 1 ? (KB) : ks1 - 1;                                                   \
+    const int k1_ = (KB) + 1 < ks1 - 1 ? (KB) + 1 : ks1 - 1;                                           \
+    const int k2_ = (KB) + 2 < ks1 - 1 ? (KB) + 2 : ks1 - 1;                                           \
+    const int k3_ = (KB) + 3 < ks1 - 1 ? (KB) + 3 : ks1 - 1;                                           \
+    H0 = ftab[2 * k0_ * 64 + lane];                                                                    \
+    L0 = ftab[(2 * k0_ + 1) * 64 + lane];                                                              \
+    H1 = ftab[2 * k1_ * 64 + lane];                                                                    \
+    L1 = ftab[(2 * k1_ + 1) * 64 + lane];                                                              \
+    H2 = ftab[2 * k2_ * 64 + lane];                                                                    \
+    L2 = ftab[(2 * k2_ + 1) * 64 + lane];                                                              \
+    H3 = ftab[2 * k3_ * 64 + lane];                                                                    \
+    L3 = ftab[(2 * k3_ + 1) * 64 + lane];                                                              \
+  }
+#define MT_FIR_STEP(H, L, KS, ACC)                                                                        \
+  if ((KS) < ks1) {                                                                                    \
+    const uint4 w0 = *reinterpret_cast<const uint4*>(ah + 16 * (KS));                                  \
+    const uint4 w1 = *reinterpret_cast<const uint4*>(ah + 16 * (KS) + 4);                              \
+    const uint4 ahi = make_uint4(__builtin_amdgcn_perm(w0.y, w0.x, 0x05040100u),                       \
+                                 __builtin_amdgcn_perm(w0.w, w0.z, 0x05040100u),                       \
+                                 __builtin_amdgcn_perm(w1.y, w1.x, 0x05040100u),                       \
+                                 __builtin_amdgcn_perm(w1.w, w1.z, 0x05040100u));                      \
+    const uint4 alo = make_uint4(__builtin_amdgcn_perm(w0.y, w0.x, 0x07060302u),                       \
+                                 __builtin_amdgcn_perm(w0.w, w0.z, 0x07060302u),                       \
+                                 __builtin_amdgcn_perm(w1.y, w1.x, 0x07060302u),                       \
+                                 __builtin_amdgcn_perm(w1.w, w1.z, 0x07060302u));                      \
+    const bf16x8 h_hi = __builtin_bit_cast(bf16x8, H);                                                 \
+    const bf16x8 h_lo = __builtin_bit_cast(bf16x8, L);                                                 \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ahi), h_hi, ACC, 0, 0, 0); \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ahi), h_lo, ACC, 0, 0, 0); \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, alo), h_hi, ACC, 0, 0, 0); \
+  }
   for (int cbr = 0; cbr < nqb; cbr += NWAVE / 2) {
     const int cb = cbr + (wv >> 1);
-    f32x16 acc = f32x16{};
+    f32x16 acc = f32x16{}, acc2 = f32x16{};   // even and odd K-steps (independent MFMA chains)
     if (cb < nqb) {
       const int q0 = 32 * cb;
       const int nval = qc - q0 < 32 ? qc - q0 : 32;
       const int nks = ((nval - 1) * R + K + 15) / 16;
       const int kmid = (nks + 1) >> 1;
       const int ks0 = half ? kmid : 0, ks1 = half ? nks : kmid;
-      const unsigned short* ah = bh + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
+      const unsigned int* ah = bw + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
       if (ks0 < ks1) {
-        uint4 hh = ftab[(2 * ks0) * 64 + lane], hl = ftab[(2 * ks0 + 1) * 64 + lane];
-        for (int ks = ks0; ks < ks1; ++ks) {
-          const bf16x8 h_hi = __builtin_bit_cast(bf16x8, hh);
-          const bf16x8 h_lo = __builtin_bit_cast(bf16x8, hl);
-          if (ks + 1 < ks1) {
-            hh = ftab[(2 * ks + 2) * 64 + lane];
-            hl = ftab[(2 * ks + 3) * 64 + lane];
-          }
-          const bf16x8 a_hi = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ah + 16 * ks));
-          const bf16x8 a_lo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ah + 32 * NSP + 16 * ks));
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, h_hi, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_hi, h_lo, acc, 0, 0, 0);
-          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a_lo, h_hi, acc, 0, 0, 0);
+        uint4 ch0, cl0, ch1, cl1, ch2, cl2, ch3, cl3;   // current batch
+        uint4 nh0, nl0, nh1, nl1, nh2, nl2, nh3, nl3;   // next batch
+        MT_FIR_LOAD(ch0, cl0, ch1, cl1, ch2, cl2, ch3, cl3, ks0)
+        for (int kb = ks0; kb < ks1; kb += 4) {
+          if (kb + 4 < ks1) MT_FIR_LOAD(nh0, nl0, nh1, nl1, nh2, nl2, nh3, nl3, kb + 4)
+          MT_FIR_STEP(ch0, cl0, kb, acc)
+          MT_FIR_STEP(ch1, cl1, kb + 1, acc2)
+          MT_FIR_STEP(ch2, cl2, kb + 2, acc)
+          MT_FIR_STEP(ch3, cl3, kb + 3, acc2)
+          ch0 = nh0; cl0 = nl0; ch1 = nh1; cl1 = nl1;
+          ch2 = nh2; cl2 = nl2; ch3 = nh3; cl3 = nl3;
         }
       }
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
       if (half) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) part[((wv >> 1) * 64 + lane) * 16 + v] = acc[v];
@@ -261,7 +296,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
       if (q < qc && qq < Q) {
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-          const int d = perm[tile * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
+          const int d = permL[8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
           if (d >= 0)
             E[(static_cast<long long>(f) * D + d) * Q + qq] = acc[v] + part[((wv >> 1) * 64 + lane) * 16 + v];
         }
@@ -269,16 +304,21 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     }
     __syncthreads();
   }
+#undef MT_FIR_LOAD
+#undef MT_FIR_STEP
 }
 
 }  // namespace
 
-size_t mt_smem_bytes(const sonar_plan_s* p) {
+// byte offset of the tile's slot -> direction table, after the staging and low-pass regions
+static size_t mt_perm_offset(const sonar_plan_s* p) {
   const size_t planes = 2 * 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
-  const size_t absb = (2 * 32 * static_cast<size_t>(MT_NSP) + 16) * sizeof(unsigned short) +
+  const size_t absb = (32 * static_cast<size_t>(MT_NSP) + 16) * sizeof(unsigned int) +
                       static_cast<size_t>(MT_NWAVE / 2) * 64 * 16 * sizeof(float);
-  return planes > absb ? planes : absb;
+  return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
+
+size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * sizeof(int); }
 
 hipError_t init_mt_kernel_attributes() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE>),
@@ -295,6 +335,7 @@ hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F,
                      mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
-                     p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow);
+                     p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                     static_cast<int>(mt_perm_offset(p)));
   return hipGetLastError();
 }
