@@ -33,6 +33,8 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 
 // 8 BF16 values at an 8-byte aligned LDS address
@@ -201,17 +203,21 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   for (int nt = 0; nt < 4; ++nt) {
     const int s = sw + 128 * nt + 4 * (lane & 31);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-      const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-      const float a = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
-      const unsigned int hi = __builtin_bit_cast(unsigned short, static_cast<__bf16>(a));
-      const float lo = a - __builtin_bit_cast(float, hi << 16);
-      bw[dl * NSP + s] = hi | (static_cast<unsigned int>(__builtin_bit_cast(unsigned short, static_cast<__bf16>(lo))) << 16);
+    for (int v = 0; v < 16; v += 2) {
+      const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);   // dl + 1 for v + 1
+      const f32x2 a = {__builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]),
+                       __builtin_amdgcn_sqrtf(cre[nt][v + 1] * cre[nt][v + 1] + cim[nt][v + 1] * cim[nt][v + 1])};
+      const unsigned int hp = __builtin_bit_cast(unsigned int, __builtin_convertvector(a, bf16x2));
+      const f32x2 l = {a.x - __builtin_bit_cast(float, hp << 16), a.y - __builtin_bit_cast(float, hp & 0xFFFF0000u)};
+      const unsigned int lp = __builtin_bit_cast(unsigned int, __builtin_convertvector(l, bf16x2));
+      bw[dl * NSP + s] = __builtin_amdgcn_perm(lp, hp, 0x05040100u);         // {hi, lo} of a.x
+      bw[(dl + 1) * NSP + s] = __builtin_amdgcn_perm(lp, hp, 0x07060302u);   // {hi, lo} of a.y
     }
   }
-  // the last K-step of a column block reads up to 15 samples past the window: those
-  // of each row's tail, the next row's first ones, and after the last row 16 zeros
-  for (int i = threadIdx.x; i < 32 * (NSP - NS) + 16; i += NT) {
+  // the K-steps of a column block (rounded up to a multiple of 4) read up to 63 samples past
+  // the window: those of each row's tail, the next row's first ones, and after the last
+  // row MT_FIR_TAIL zeros; their tap fragments are zero
+  for (int i = threadIdx.x; i < 32 * (NSP - NS) + MT_FIR_TAIL; i += NT) {
     const int r = i / (NSP - NS), c = i - r * (NSP - NS);
     bw[r < 32 ? r * NSP + NS + c : 32 * NSP + (i - 32 * (NSP - NS))] = 0;
   }
@@ -222,26 +228,23 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   // h[nR + K-1 - 16 ks - k] do not depend on q0 and come from the plan (hi, lo terms),
   // loaded four K-steps at a time, one batch ahead.
   const int nqb = (qc + 31) / 32;
-  // partial sums of the second K-half of each column block: [MT_NWAVE / 2][64 lanes][16]
-  float* part = reinterpret_cast<float*>(bw + 32 * NSP + 16);
-  const int half = wv & 1;
+  // The product is taken as E^T = H^T |b|^T: the same fragments with the operands swapped,
+  // so lane l receives range bins 8 g + 4 (l / 32) + 0..3 (g = v / 4) of direction l % 32
+  // and writes them with one 16-byte store per g.
 #define MT_FIR_LOAD(H0, L0, H1, L1, H2, L2, H3, L3, KB)                                               \
   {                                                                                                    \
-    const int k0_ = (KB) < ks1 - 1 ? (KB) : ks1 - 1;                                                   \
-    const int k1_ = (KB) + 1 < ks1 - 1 ? (KB) + 1 : ks1 - 1;                                           \
-    const int k2_ = (KB) + 2 < ks1 - 1 ? (KB) + 2 : ks1 - 1;                                           \
-    const int k3_ = (KB) + 3 < ks1 - 1 ? (KB) + 3 : ks1 - 1;                                           \
-    H0 = ftab[2 * k0_ * 64 + lane];                                                                    \
-    L0 = ftab[(2 * k0_ + 1) * 64 + lane];                                                              \
-    H1 = ftab[2 * k1_ * 64 + lane];                                                                    \
-    L1 = ftab[(2 * k1_ + 1) * 64 + lane];                                                              \
-    H2 = ftab[2 * k2_ * 64 + lane];                                                                    \
-    L2 = ftab[(2 * k2_ + 1) * 64 + lane];                                                              \
-    H3 = ftab[2 * k3_ * 64 + lane];                                                                    \
-    L3 = ftab[(2 * k3_ + 1) * 64 + lane];                                                              \
+    const uint4* fp = ftab + 2 * (KB) * 64 + lane;                                                     \
+    H0 = fp[0];                                                                                        \
+    L0 = fp[64];                                                                                       \
+    H1 = fp[128];                                                                                      \
+    L1 = fp[192];                                                                                      \
+    H2 = fp[256];                                                                                      \
+    L2 = fp[320];                                                                                      \
+    H3 = fp[384];                                                                                      \
+    L3 = fp[448];                                                                                      \
   }
-#define MT_FIR_STEP(H, L, KS, ACC)                                                                        \
-  if ((KS) < ks1) {                                                                                    \
+#define MT_FIR_STEP(H, L, KS, ACC)                                                                     \
+  {                                                                                                    \
     const uint4 w0 = *reinterpret_cast<const uint4*>(ah + 16 * (KS));                                  \
     const uint4 w1 = *reinterpret_cast<const uint4*>(ah + 16 * (KS) + 4);                              \
     const uint4 ahi = make_uint4(__builtin_amdgcn_perm(w0.y, w0.x, 0x05040100u),                       \
@@ -254,55 +257,54 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
                                  __builtin_amdgcn_perm(w1.w, w1.z, 0x07060302u));                      \
     const bf16x8 h_hi = __builtin_bit_cast(bf16x8, H);                                                 \
     const bf16x8 h_lo = __builtin_bit_cast(bf16x8, L);                                                 \
-    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ahi), h_hi, ACC, 0, 0, 0); \
-    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ahi), h_lo, ACC, 0, 0, 0); \
-    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, alo), h_hi, ACC, 0, 0, 0); \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h_hi, __builtin_bit_cast(bf16x8, ahi), ACC, 0, 0, 0); \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h_lo, __builtin_bit_cast(bf16x8, ahi), ACC, 0, 0, 0); \
+    ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h_hi, __builtin_bit_cast(bf16x8, alo), ACC, 0, 0, 0); \
   }
-  for (int cbr = 0; cbr < nqb; cbr += NWAVE / 2) {
-    const int cb = cbr + (wv >> 1);
+  for (int cb = wv; cb < nqb; cb += NWAVE) {
     f32x16 acc = f32x16{}, acc2 = f32x16{};   // even and odd K-steps (independent MFMA chains)
-    if (cb < nqb) {
-      const int q0 = 32 * cb;
-      const int nval = qc - q0 < 32 ? qc - q0 : 32;
-      const int nks = ((nval - 1) * R + K + 15) / 16;
-      const int kmid = (nks + 1) >> 1;
-      const int ks0 = half ? kmid : 0, ks1 = half ? nks : kmid;
-      const unsigned int* ah = bw + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
-      if (ks0 < ks1) {
-        uint4 ch0, cl0, ch1, cl1, ch2, cl2, ch3, cl3;   // current batch
-        uint4 nh0, nl0, nh1, nl1, nh2, nl2, nh3, nl3;   // next batch
-        MT_FIR_LOAD(ch0, cl0, ch1, cl1, ch2, cl2, ch3, cl3, ks0)
-        for (int kb = ks0; kb < ks1; kb += 4) {
-          if (kb + 4 < ks1) MT_FIR_LOAD(nh0, nl0, nh1, nl1, nh2, nl2, nh3, nl3, kb + 4)
-          MT_FIR_STEP(ch0, cl0, kb, acc)
-          MT_FIR_STEP(ch1, cl1, kb + 1, acc2)
-          MT_FIR_STEP(ch2, cl2, kb + 2, acc)
-          MT_FIR_STEP(ch3, cl3, kb + 3, acc2)
-          ch0 = nh0; cl0 = nl0; ch1 = nh1; cl1 = nl1;
-          ch2 = nh2; cl2 = nl2; ch3 = nh3; cl3 = nl3;
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
-      if (half) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) part[((wv >> 1) * 64 + lane) * 16 + v] = acc[v];
-      }
-    }
-    __syncthreads();
-    if (cb < nqb && !half) {
-      const int q = 32 * cb + (lane & 31);
-      const int qq = qt * qc + q;
-      if (q < qc && qq < Q) {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int d = permL[8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
-          if (d >= 0)
-            E[(static_cast<long long>(f) * D + d) * Q + qq] = acc[v] + part[((wv >> 1) * 64 + lane) * 16 + v];
+    const int q0 = 32 * cb;
+    const int nval = qc - q0 < 32 ? qc - q0 : 32;
+    const int nks4 = (((nval - 1) * R + K + 15) / 16 + 3) & ~3;   // K-steps, in batches of 4
+    const unsigned int* ah = bw + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
+    {
+      uint4 ah0, al0, ah1, al1, ah2, al2, ah3, al3;   // tap fragments, batch A
+      uint4 bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3;   // batch B
+      MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, 0)
+      for (int kb = 0; kb < nks4; kb += 8) {
+        const bool more = kb + 4 < nks4;
+        if (more) MT_FIR_LOAD(bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3, kb + 4)
+        MT_FIR_STEP(ah0, al0, kb, acc)
+        MT_FIR_STEP(ah1, al1, kb + 1, acc2)
+        MT_FIR_STEP(ah2, al2, kb + 2, acc)
+        MT_FIR_STEP(ah3, al3, kb + 3, acc2)
+        if (more) {
+          if (kb + 8 < nks4) MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, kb + 8)
+          MT_FIR_STEP(bh0, bl0, kb + 4, acc)
+          MT_FIR_STEP(bh1, bl1, kb + 5, acc2)
+          MT_FIR_STEP(bh2, bl2, kb + 6, acc)
+          MT_FIR_STEP(bh3, bl3, kb + 7, acc2)
         }
       }
     }
-    __syncthreads();
+    const int d = permL[lane & 31];
+    if (d >= 0) {
+      float* erow = E + (static_cast<long long>(f) * D + d) * Q + static_cast<long long>(qt) * qc;
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int q = q0 + 8 * g + 4 * (lane >> 5);
+        const float4 o = make_float4(acc[4 * g] + acc2[4 * g], acc[4 * g + 1] + acc2[4 * g + 1],
+                                     acc[4 * g + 2] + acc2[4 * g + 2], acc[4 * g + 3] + acc2[4 * g + 3]);
+        const int lim = (qc < Q - qt * qc ? qc : Q - qt * qc) - q;   // valid bins from q on
+        if (lim >= 4) {
+          __builtin_memcpy(erow + q, &o, 16);
+        } else {
+          if (lim > 0) erow[q] = o.x;
+          if (lim > 1) erow[q + 1] = o.y;
+          if (lim > 2) erow[q + 2] = o.z;
+        }
+      }
+    }
   }
 #undef MT_FIR_LOAD
 #undef MT_FIR_STEP
@@ -313,8 +315,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
 static size_t mt_perm_offset(const sonar_plan_s* p) {
   const size_t planes = 2 * 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
-  const size_t absb = (32 * static_cast<size_t>(MT_NSP) + 16) * sizeof(unsigned int) +
-                      static_cast<size_t>(MT_NWAVE / 2) * 64 * 16 * sizeof(float);
+  const size_t absb = (32 * static_cast<size_t>(MT_NSP) + MT_FIR_TAIL) * sizeof(unsigned int);
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
 

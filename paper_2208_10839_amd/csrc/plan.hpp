@@ -118,7 +118,8 @@ constexpr int MT_RES = 4;
 constexpr int MT_XCDS = 8;
 // |b| rows in LDS for the matrix-core low-pass (one 32-bit word per sample): MT_NWAVE * 128
 // samples + a zeroed tail, padded so that a row is 16 bytes past a multiple of 256 (bank spread)
-constexpr int MT_NSP = MT_NWAVE * 128 + 4;   // accelerator dies (each with its own L2) that workgroups are spread over
+constexpr int MT_NSP = MT_NWAVE * 128 + 4;
+constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row   // accelerator dies (each with its own L2) that workgroups are spread over
 
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)

@@ -236,7 +236,8 @@ int build_mt_tables(sonar_plan_s* p, const double* dirs, const std::vector<doubl
   // low-pass B fragments: K-step ks, lane l holds H[16 ks + 8 (l / 32) + j][l % 32],
   // H[k][n] = h[n R + K - 1 - k], as BF16 hi and lo terms
   const int nks = (31 * p->R + p->K + 15) / 16;
-  std::vector<uint16_t> ftab(static_cast<size_t>(nks) * 2 * 64 * 8, 0);
+  // rounded up to whole batches of 4 K-steps; the extra K-steps have zero taps
+  std::vector<uint16_t> ftab(static_cast<size_t>((nks + 3) & ~3) * 2 * 64 * 8, 0);
   for (int ks = 0; ks < nks; ++ks) {
     for (int l = 0; l < 64; ++l) {
       for (int j = 0; j < 8; ++j) {
