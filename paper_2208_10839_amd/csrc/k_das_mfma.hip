@@ -135,6 +135,16 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   MT_STAGE_STORE(0, sm)
   MT_STAGE_LOAD(0)
   MT_STAGE_STORE(0, sm)
+  // The wavefront's K-chunks of all microphone groups are consecutive in the tables, so
+  // the one-ahead prefetch of weight fragments runs across group and half boundaries.
+  const int li = tile * MT_RES + rho;
+  const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
+  const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
+  const int kend = kcr[(tile * nmc + nmc - 1) * MT_RES + rho].y;
+  int kfirst = kcr[tile * nmc * MT_RES + rho].x;
+  if (kfirst >= kend) kfirst = 0;            // no chunks at all: harmless in-table prefetch
+  uint4 ah_next = wt[kfirst * 128], al_next = wt[kfirst * 128 + 64];
+  int2 g_next = gt[2 * kfirst];
   for (int mc = 0; mc < nmc; ++mc) {
     const int m0 = mc * MT_MICS;
     unsigned short* buf = sm + (mc & 1) * bufsz;
@@ -143,11 +153,8 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     __syncthreads();                         // group mc staged; group mc - 1 no longer read
     sgh = sg0;
     kh = k0;
-    const int li = tile * MT_RES + rho;
     const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
     const int kmid = (kr.x + kr.y) >> 1;
-    const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-    const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
     // the next group is staged in two halves, each loaded during one half of the K-chunks
     for (int hk = 0; hk < 2; ++hk) {
       if (next) {
@@ -155,14 +162,12 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
         MT_STAGE_LOAD(mc + 1)
       }
       const int ka = hk ? kmid : kr.x, kb = hk ? kr.y : kmid;
-      if (ka < kb) {
-        uint4 ah_next = wt[ka * 128], al_next = wt[ka * 128 + 64];
-        int2 g_next = gt[2 * ka];
+      {
         for (int kc = ka; kc < kb; ++kc) {
           const bf16x8 ah = __builtin_bit_cast(bf16x8, ah_next);
           const bf16x8 al = __builtin_bit_cast(bf16x8, al_next);
           const int2 g = g_next;
-          if (kc + 1 < kb) {
+          if (kc + 1 < kend) {
             ah_next = wt[(kc + 1) * 128];
             al_next = wt[(kc + 1) * 128 + 64];
             g_next = gt[2 * (kc + 1)];
