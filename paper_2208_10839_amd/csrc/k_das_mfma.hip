@@ -6,7 +6,7 @@
 //
 // The same linear-interpolation result as the FP32 beamformer, computed as a
 // dense product.  Directions are grouped into tiles of 32 neighbours (plan
-// time, along a Hilbert curve of the direction grid), so within a tile the
+// time, compact in delay space), so within a tile the
 // integer offsets o[d][m] of one microphone span only a few samples.  For
 // each microphone the tile covers that span with groups of 8 consecutive
 // taps; the tap weights form a sparse 32 x K matrix W (two nonzeros per

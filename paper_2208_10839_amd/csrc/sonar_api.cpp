@@ -109,25 +109,68 @@ bool is_td(const sonar_plan_s* p) {
   return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16;
 }
 
-// Position of (x, y) in [0, 2^16)^2 along a Hilbert curve (iterative quadrant walk).
-uint64_t hilbert_index(uint32_t x, uint32_t y) {
-  uint64_t d = 0;
-  for (uint32_t s = 1u << 15; s > 0; s >>= 1) {
-    const uint32_t rx = (x & s) ? 1 : 0, ry = (y & s) ? 1 : 0;
-    d += static_cast<uint64_t>(s) * s * ((3 * rx) ^ ry);
-    if (ry == 0) {
-      if (rx == 1) {
-        x = s - 1 - (x & (s - 1)) + (x & ~(s - 1));
-        y = s - 1 - (y & (s - 1)) + (y & ~(s - 1));
-        x &= 0xFFFF;
-        y &= 0xFFFF;
+// Coordinates z_d in which distances between directions equal distances between their
+// delay vectors: |z_d - z_e| = |P (u_d - u_e)| for the microphone position matrix P
+// (rows p_m).  With G = P^T P = V diag(l) V^T, z_d = diag(sqrt(l)) V^T u_d.  The 3 x 3
+// eigenproblem is solved by cyclic Jacobi rotations.
+void delay_space_coords(const double* pos, int M, const double* dirs, int D, std::vector<double>& z) {
+  double G[3][3] = {};
+  for (int m = 0; m < M; ++m)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) G[i][j] += pos[3 * m + i] * pos[3 * m + j];
+  double V[3][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}};
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = std::fabs(G[0][1]) + std::fabs(G[0][2]) + std::fabs(G[1][2]);
+    if (off < 1e-300) break;
+    for (int pq = 0; pq < 3; ++pq) {
+      const int a = pq == 2 ? 1 : 0, b = pq == 0 ? 1 : 2;
+      if (std::fabs(G[a][b]) < 1e-300) continue;
+      const double th = 0.5 * std::atan2(2.0 * G[a][b], G[b][b] - G[a][a]);
+      const double c = std::cos(th), s = std::sin(th);
+      for (int k = 0; k < 3; ++k) {   // G <- G J
+        const double gka = G[k][a], gkb = G[k][b];
+        G[k][a] = c * gka - s * gkb;
+        G[k][b] = s * gka + c * gkb;
       }
-      const uint32_t tmp = x;
-      x = y;
-      y = tmp;
+      for (int k = 0; k < 3; ++k) {   // G <- J^T G
+        const double gak = G[a][k], gbk = G[b][k];
+        G[a][k] = c * gak - s * gbk;
+        G[b][k] = s * gak + c * gbk;
+      }
+      for (int k = 0; k < 3; ++k) {   // V <- V J
+        const double vka = V[k][a], vkb = V[k][b];
+        V[k][a] = c * vka - s * vkb;
+        V[k][b] = s * vka + c * vkb;
+      }
     }
   }
-  return d;
+  z.assign(static_cast<size_t>(D) * 3, 0.0);
+  for (int d = 0; d < D; ++d)
+    for (int i = 0; i < 3; ++i) {
+      const double sl = std::sqrt(std::max(G[i][i], 0.0));
+      z[3 * d + i] = sl * (V[0][i] * dirs[3 * d] + V[1][i] * dirs[3 * d + 1] + V[2][i] * dirs[3 * d + 2]);
+    }
+}
+
+// Orders idx[lo, hi) into runs of 32 that are compact in z: split along the widest axis of the
+// set at a multiple of 32 near the middle, recursively.
+void kd_tiles(std::vector<int>& idx, int lo, int hi, const std::vector<double>& z) {
+  if (hi - lo <= 32) return;
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (int i = lo; i < hi; ++i)
+    for (int k = 0; k < 3; ++k) {
+      mn[k] = std::min(mn[k], z[3 * idx[i] + k]);
+      mx[k] = std::max(mx[k], z[3 * idx[i] + k]);
+    }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (mx[k] - mn[k] > mx[ax] - mn[ax]) ax = k;
+  std::stable_sort(idx.begin() + lo, idx.begin() + hi,
+                   [&](int a, int b) { return z[3 * a + ax] < z[3 * b + ax]; });
+  const int n = hi - lo;
+  const int half = ((n / 32 + 1) / 2) * 32;
+  kd_tiles(idx, lo, lo + half, z);
+  kd_tiles(idx, lo + half, hi, z);
 }
 
 uint16_t to_bf16_bits(float v) {
@@ -138,32 +181,29 @@ uint16_t to_bf16_bits(float v) {
 }
 
 // Tiles of the BF16-MFMA time-domain beamformer, built from the device's FP64
-// delay table: directions ordered along a Hilbert curve of (u_x, u_y) (front
-// and back hemispheres apart) and cut into tiles of 32.  Beam samples are
+// delay table: directions cut into tiles of 32 that are compact in delay space
+// (a k-d split of the coordinates of delay_space_coords).  Beam samples are
 // split by residue mod MT_RES; for residue rho, per tile and microphone the
 // span of integer offsets is covered by groups of 8 taps whose first tap t0
 // has t0 + rho = 0 mod MT_RES, so every sample fragment read by the kernel
 // starts on an 8-byte boundary.  A group pair is one K-chunk of
 // v_mfma_f32_32x32x16_bf16, whose A fragments (tap weights as BF16 hi and lo
 // terms) are stored in lane order.
-int build_mt_tables(sonar_plan_s* p, const double* dirs, const std::vector<double>& taps, hipStream_t stream,
-                    size_t* total) {
+int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, const std::vector<double>& taps,
+                    hipStream_t stream, size_t* total) {
   const int D = p->D, M = p->M;
   std::vector<int4> dtab(static_cast<size_t>(D) * M);
   hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "delay table read-back");
-  std::vector<std::pair<uint64_t, int>> key(D);
-  for (int d = 0; d < D; ++d) {
-    const double* u = dirs + 3 * d;
-    const uint32_t xi = static_cast<uint32_t>(std::lround((u[0] + 1.0) * 0.5 * 65535.0));
-    const uint32_t yi = static_cast<uint32_t>(std::lround((u[1] + 1.0) * 0.5 * 65535.0));
-    key[d] = {(static_cast<uint64_t>(u[2] < 0 ? 1 : 0) << 40) | hilbert_index(xi, yi), d};
-  }
-  std::stable_sort(key.begin(), key.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  std::vector<double> z;
+  delay_space_coords(pos, M, dirs, D, z);
+  std::vector<int> order(D);
+  for (int d = 0; d < D; ++d) order[d] = d;
+  kd_tiles(order, 0, D, z);
   const int nt = (D + 31) / 32, nmc = (M + MT_MICS - 1) / MT_MICS;
   std::vector<int> perm(static_cast<size_t>(nt) * 32, -1);
-  for (int i = 0; i < D; ++i) perm[i] = key[i].second;
+  for (int i = 0; i < D; ++i) perm[i] = order[i];
   const int nlist = nt * MT_RES;   // group list per (tile, residue)
   std::vector<std::vector<int2>> groups(nlist);
   std::vector<std::vector<char>> pad(nlist);   // zero-weight group completing a K-chunk
@@ -576,7 +616,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   e = launch_build_tables(p, stream);
   if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
   if (e == hipSuccess && p->bf_mode == SONAR_BF_TD_BF16) {
-    const int st = build_mt_tables(p, d.dirs, taps, stream, &total);
+    const int st = build_mt_tables(p, d.mic_pos, d.dirs, taps, stream, &total);
     if (st != SONAR_OK) {
       free_plan(p);
       return st;
