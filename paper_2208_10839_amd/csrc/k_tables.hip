@@ -132,7 +132,9 @@ hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int twl = fft_tw_len(p->NF);
   hipLaunchKernelGGL(fft_twiddle_kernel, dim3((twl + 255) / 256), dim3(256), 0, s, p->d_tw, p->NF, p->P);
-  if ((e = hipGetLastError()) != hipSuccess || !p->d_tw2) return e;
+  // row-transform twiddles only for the four-step matched filter (d_tw2 is a 16-byte
+  // placeholder allocation otherwise)
+  if ((e = hipGetLastError()) != hipSuccess || p->NF <= (1 << MB_LOGN2)) return e;
   const int tw2l = fft_tw_len(1 << MB_LOGN2);
   hipLaunchKernelGGL(fft_twiddle_kernel, dim3((tw2l + 255) / 256), dim3(256), 0, s, p->d_tw2, 1 << MB_LOGN2, p->P);
   return hipGetLastError();

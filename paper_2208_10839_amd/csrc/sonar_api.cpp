@@ -92,6 +92,8 @@ void free_plan(sonar_plan_s* p) {
   delete p;
 }
 
+// count == 0 still allocates a 16-byte placeholder: never test a plan buffer pointer to
+// decide whether a feature is enabled
 template <typename T>
 hipError_t dev_alloc(T** ptr, size_t count, size_t* total) {
   const size_t bytes = count * sizeof(T);
@@ -722,6 +724,97 @@ int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hi
     if (e == hipSuccess) e = beam_env(p, p->d_fdspec, F, E, stream);
   }
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape launch");
+}
+
+int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const int32_t* frames,
+                            float* const* E, int32_t n, hipStream_t stream) {
+  if (n < 0 || (n > 0 && (!plans || !x || !frames || !E)))
+    return fail(SONAR_E_INVALID, "multi: NULL item arrays or n < 0");
+  for (int i = 0; i < n; ++i) {
+    const int st = check_exec(plans[i], x[i], E[i], frames[i]);
+    if (st != SONAR_OK) {
+      const std::string why = sonar_last_error();
+      return fail(st, "multi item %d: %s", i, why.c_str());
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    const int st = sonar_energyscape_batch(plans[i], x[i], frames[i], E[i], stream);
+    if (st != SONAR_OK) return st;
+  }
+  return SONAR_OK;
+}
+
+int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
+                            sonar_plan* out, int32_t* chosen_mode) {
+  if (!desc || !out) return fail(SONAR_E_INVALID, "desc and out must not be NULL");
+  if (precision != SONAR_PREC_FP32 && precision != SONAR_PREC_BF16)
+    return fail(SONAR_E_INVALID, "precision %d is not a sonar_precision", precision);
+  std::vector<int> modes = {SONAR_BF_TD_LINEAR, SONAR_BF_FD_FP32, SONAR_BF_FD_BF16X3};
+  if (precision == SONAR_PREC_BF16) {
+    modes.push_back(SONAR_BF_TD_BF16);
+    if (desc->n_mics >= 32) modes.push_back(SONAR_BF_FD_BF16);
+  }
+  const int F = desc->max_frames > 0 ? desc->max_frames : 1;
+  const size_t in_bytes = static_cast<size_t>(F) * (desc->n_mics > 0 ? desc->n_mics : 1) *
+                          (desc->n_samples > 0 ? desc->n_samples : 1) *
+                          (desc->sample_dtype == SONAR_F32 ? 4 : 2);
+  void* xin = nullptr;
+  float* eout = nullptr;
+  sonar_plan best = nullptr;
+  int best_mode = -1, last_status = SONAR_E_UNSUPPORTED;
+  float best_ms = 0.f;
+  std::string last_msg = "no beamformer mode could be planned";
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he == hipSuccess) he = hipMalloc(&xin, in_bytes);
+  if (he == hipSuccess) he = hipMemsetAsync(xin, 0, in_bytes, stream);
+  for (size_t i = 0; he == hipSuccess && i < modes.size(); ++i) {
+    sonar_plan_desc d = *desc;
+    d.bf_mode = modes[i];
+    sonar_plan p = nullptr;
+    const int st = sonar_plan_create(&d, stream, &p);
+    if (st != SONAR_OK) {
+      last_status = st;
+      last_msg = sonar_last_error();
+      if (st == SONAR_E_INVALID) break;   // the descriptor itself is bad
+      continue;
+    }
+    if (!eout) he = hipMalloc(reinterpret_cast<void**>(&eout), static_cast<size_t>(F) * p->D * p->Q * sizeof(float));
+    float ms = 0.f;
+    int rs = he == hipSuccess ? sonar_energyscape_batch(p, xin, F, eout, stream) : SONAR_E_HIP;   // warm-up
+    if (rs == SONAR_OK) he = hipEventRecord(e0, stream);
+    for (int r = 0; rs == SONAR_OK && he == hipSuccess && r < 3; ++r) rs = sonar_energyscape_batch(p, xin, F, eout, stream);
+    if (rs == SONAR_OK && he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (rs == SONAR_OK && he == hipSuccess) he = hipEventSynchronize(e1);
+    if (rs == SONAR_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    if (rs != SONAR_OK || he != hipSuccess) {
+      sonar_plan_destroy(p);
+      last_status = rs != SONAR_OK ? rs : SONAR_E_HIP;
+      break;
+    }
+    if (!best || ms < best_ms) {
+      if (best) sonar_plan_destroy(best);
+      best = p;
+      best_ms = ms;
+      best_mode = modes[i];
+    } else {
+      sonar_plan_destroy(p);
+    }
+  }
+  if (he == hipSuccess) he = hipStreamSynchronize(stream);
+  (void)hipFree(xin);
+  (void)hipFree(eout);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (he != hipSuccess) {
+    if (best) sonar_plan_destroy(best);
+    return hip_fail(he, "mode tuning");
+  }
+  if (!best) return fail(last_status, "%s", last_msg.c_str());
+  *out = best;
+  if (chosen_mode) *chosen_mode = best_mode;
+  return SONAR_OK;
 }
 
 }  // extern "C"
