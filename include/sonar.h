@@ -203,6 +203,43 @@ int sonar_beamform_envelope(sonar_plan plan, const void* mf_in, int32_t F, float
 int sonar_energyscape_batch(sonar_plan plan, const void* x, int32_t F, float* E,
                             hipStream_t stream);
 
+/*
+ * sonar_energyscape_multi -- the whole chain for n independent items, each
+ * with its own plan (its own sensor geometry, recording length, direction
+ * grid and mode): E_i = sonar_energyscape_batch(plans[i], x[i], frames[i]).
+ * This is the sensor network's batch (§3: many sensors' measurements are
+ * processed by the same GPU service; §5).  All items are validated before any
+ * work is enqueued; the items then run in order on `stream`.  The call enqueues
+ * kernels only (no allocation, no synchronisation, no memset), so a caller may
+ * capture it in a HIP graph and replay it; replays reuse the plans' workspaces,
+ * so replays of graphs that share a plan must not overlap.
+ *   plans  : n plan handles (a plan may appear more than once).
+ *   x      : n device pointers, x[i] = [frames[i]][M_i][N_i] samples.
+ *   frames : n frame counts, 1 <= frames[i] <= max_frames of plans[i].
+ *   E      : n device pointers, E[i] = float [frames[i]][D_i][Q_i].
+ * Returns SONAR_E_INVALID (nothing enqueued) when any item is invalid.
+ */
+int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const int32_t* frames,
+                            float* const* E, int32_t n, hipStream_t stream);
+
+/* Precision classes for sonar_plan_create_tuned. */
+enum sonar_precision {
+  SONAR_PREC_FP32 = 0,   /* modes within 1e-5 of the definition: TD_LINEAR, FD_FP32, FD_BF16X3  */
+  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, and FD_BF16 for >= 32 mics   */
+};
+
+/*
+ * sonar_plan_create_tuned -- picks the beamformer mode for a descriptor by
+ * measurement: every mode of the precision class that the build supports for
+ * the descriptor is planned and timed on max_frames frames of zero samples
+ * (the kernels' time does not depend on the sample values), and the fastest
+ * plan is returned; desc->bf_mode is ignored.  The call synchronises `stream`.
+ *   *chosen_mode (may be NULL) receives the selected enum sonar_bf_mode.
+ * Returns the status of sonar_plan_create when no mode can be planned.
+ */
+int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
+                            sonar_plan* out, int32_t* chosen_mode);
+
 /* Static text for a status code. */
 const char* sonar_status_string(int status);
 

@@ -22,6 +22,7 @@ SONAR_E_NOMEM = -2
 SONAR_E_HIP = -3
 SONAR_E_UNSUPPORTED = -4
 
+PRECISIONS = {"fp32": 0, "bf16": 1}
 BF_MODES = {"td": 0, "fd_fp32": 1, "fd_bf16": 2, "fd_bf16x3": 3, "td_bf16": 4}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 
@@ -61,6 +62,11 @@ _SIGNATURES = {
     "sonar_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_beamform_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_energyscape_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_energyscape_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
+                                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
+                                                ctypes.c_int32, ctypes.c_void_p]),
+    "sonar_plan_create_tuned": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32)]),
     "sonar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sonar_last_error": (ctypes.c_char_p, []),
 }
@@ -116,7 +122,10 @@ class Plan:
 
     def __init__(self, mic_pos, chirp, dirs, n_samples: int, *, fs: float, c: float,
                  gate=None, decim: int = 10, taps=None, band=None, fft_len: int = 0,
-                 mode: str = "td", sample_dtype: str = "f32", max_frames: int = 1, stream=None):
+                 mode: str = "td", sample_dtype: str = "f32", max_frames: int = 1, stream=None,
+                 tune: str | None = None):
+        """tune = "fp32" or "bf16" lets sonar_plan_create_tuned pick the fastest mode of that
+        precision class (mode is then ignored; the choice is in self.mode)."""
         lib = load()
         self._keep = []
         pos = _f64(mic_pos)
@@ -148,8 +157,15 @@ class Plan:
         self.M, self.D, self.N = d.n_mics, d.n_dirs, d.n_samples
         self.max_frames = d.max_frames
         handle = ctypes.c_void_p()
-        _check(lib.sonar_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(handle)),
-               "sonar_plan_create")
+        if tune is None:
+            _check(lib.sonar_plan_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(handle)),
+                   "sonar_plan_create")
+        else:
+            chosen = ctypes.c_int32(-1)
+            _check(lib.sonar_plan_create_tuned(ctypes.byref(d), PRECISIONS[tune], _stream_handle(stream),
+                                               ctypes.byref(handle), ctypes.byref(chosen)),
+                   "sonar_plan_create_tuned")
+            self.mode = {v: k for k, v in BF_MODES.items()}[chosen.value]
         self._h = handle
         self.Q = self.query(Q_RANGE_BINS)
         self.G = self.query(Q_BEAM_LEN)
@@ -253,6 +269,25 @@ class Plan:
                                               ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
                "sonar_beamform_envelope")
         return E
+
+
+def energyscape_multi(plans, xs, outs=None, stream=None):
+    """sonar_energyscape_multi: E_i for each (plan_i, x_i[F_i][M_i][N_i]); returns the list of E_i."""
+    import torch
+    n = len(plans)
+    if len(xs) != n or (outs is not None and len(outs) != n):
+        raise ValueError("plans, xs (and outs) must have the same length")
+    Es = []
+    for i, (pl, x) in enumerate(zip(plans, xs)):
+        F = pl._samples(x)
+        Es.append(pl._out(None if outs is None else outs[i], (F, pl.D, pl.Q), torch.float32, x.device))
+    arr_p = (ctypes.c_void_p * n)(*[pl._h.value for pl in plans])
+    arr_x = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+    arr_f = (ctypes.c_int32 * n)(*[x.shape[0] for x in xs])
+    arr_e = (ctypes.c_void_p * n)(*[E.data_ptr() for E in Es])
+    _check(load().sonar_energyscape_multi(arr_p, arr_x, arr_f, arr_e, n, _stream_handle(stream)),
+           "sonar_energyscape_multi")
+    return Es
 
 
 def header_functions(header_path=None):

@@ -98,6 +98,19 @@ def test_frequency_domain_size_limits(fft_len, band, what):
     assert what in lib.sonar_last_error()
 
 
+def test_multi_and_tuned_reject_bad_arguments_on_host():
+    lib = binding.load()
+    assert lib.sonar_energyscape_multi(None, None, None, None, 0, None) == binding.SONAR_OK   # nothing to do
+    assert lib.sonar_energyscape_multi(None, None, None, None, 2, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_energyscape_multi(None, None, None, None, -1, None) == binding.SONAR_E_INVALID
+    d, keep = _desc()
+    h = ctypes.c_void_p()
+    m = ctypes.c_int32()
+    assert lib.sonar_plan_create_tuned(ctypes.byref(d), 7, None, ctypes.byref(h), ctypes.byref(m)) == \
+        binding.SONAR_E_INVALID
+    assert lib.sonar_plan_create_tuned(None, 0, None, ctypes.byref(h), None) == binding.SONAR_E_INVALID
+
+
 def test_non_unit_direction_rejected():
     lib = binding.load()
     d, keep = _desc()

@@ -1,0 +1,117 @@
+"""Heterogeneous sensor network in one call (GPU): 8 sensors x 4 frames, each sensor with its
+own array geometry, recording length (8192 / 16384 / 32768) and direction grid (91-azimuth 2D
+or 1500-direction 3D), through sonar_energyscape_multi; replayed from a HIP graph; and the
+mode chosen by sonar_plan_create_tuned.  Every energyscape is compared with the FP64 oracle
+(all directions of the 2D grids, 12 sampled directions of the 3D grids)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+BARS = {"td": 1e-5, "td_bf16": 1e-3, "fd_fp32": 1e-5, "fd_bf16x3": 1e-5, "fd_bf16": 1e-3}
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def network():
+    return synth.make_network()
+
+
+def _plan(gpu, w, **kw):
+    return gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
+                    max_frames=w.x.shape[0], **kw)
+
+
+def _sample(w):
+    D = w.dirs.shape[0]
+    if D <= 128:
+        return np.arange(D)
+    return np.sort(np.random.default_rng(D).choice(D, 12, replace=False))
+
+
+def _check_against_oracle(w, E, P, mode, label):
+    idx = _sample(w)
+    omode = "fd" if mode.startswith("fd") else "td"
+    errs = []
+    for f in range(w.x.shape[0]):
+        Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=P,
+                           R=w.cfg.decim, band=w.cfg.band, mode=omode, dir_index=idx)
+        errs.append(rel_l2(E[f][idx], Eo))
+    _say(f"  {label}: N={w.x.shape[2]} D={w.dirs.shape[0]} {mode}: max rel L2 over frames = {max(errs):.3e}")
+    assert max(errs) <= BARS[mode]
+
+
+@pytest.mark.parametrize("mode", ["td", "td_bf16"])
+def test_network_multi(gpu, torch_mod, network, mode):
+    torch = torch_mod
+    _say(f"case network multi {mode}: 8 sensors x 4 frames")
+    plans = [_plan(gpu, w, mode=mode) for w in network]
+    xs = [torch.from_numpy(w.x).cuda() for w in network]
+    Es = gpu.energyscape_multi(plans, xs)
+    singles = [pl.energyscape(x) for pl, x in zip(plans, xs)]
+    torch.cuda.synchronize()
+    for s, (w, pl, E, E1) in enumerate(zip(network, plans, Es, singles)):
+        assert torch.equal(E, E1)          # same kernels, same order: bit-identical
+        _check_against_oracle(w, E.cpu().numpy(), pl.P, mode, f"sensor {s}")
+
+
+def test_network_graph_replay(gpu, torch_mod, network):
+    """The multi call captured once in a graph, replayed on new inputs: every replay equals the
+    eager result for the same inputs."""
+    torch = torch_mod
+    _say("case network graph replay: td_bf16")
+    plans = [_plan(gpu, w, mode="td_bf16") for w in network]
+    xs = [torch.from_numpy(w.x).cuda() for w in network]
+    outs = [torch.empty((w.x.shape[0], w.dirs.shape[0], pl.Q), dtype=torch.float32, device="cuda")
+            for w, pl in zip(network, plans)]
+    gpu.energyscape_multi(plans, xs, outs)           # warm-up outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu.energyscape_multi(plans, xs, outs)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    for rep in range(3):
+        for x in xs:                                   # eager work between replays: new inputs
+            x.copy_(torch.from_numpy((rng.standard_normal(tuple(x.shape)) * 0.1).astype(np.float32)))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [o.clone() for o in outs]
+        ref = gpu.energyscape_multi(plans, xs)
+        torch.cuda.synchronize()
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b)
+        _say(f"  replay {rep}: {len(got)} items equal to the eager call")
+
+
+@pytest.mark.parametrize("tune", ["fp32", "bf16"])
+def test_tuned_plan(gpu, torch_mod, network, tune):
+    torch = torch_mod
+    w = network[3]                                     # 16384 samples, 1500 directions
+    pl = _plan(gpu, w, tune=tune)
+    allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16"}}
+    _say(f"case tuned {tune}: chose {pl.mode}")
+    assert pl.mode in allowed[tune]
+    E = pl.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
+    _check_against_oracle(w, E, pl.P, pl.mode, f"tuned {tune}")

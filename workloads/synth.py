@@ -110,6 +110,8 @@ CONFIGS = {
     "c1": Config(1, "c1", 32, 0.035, 4096, 3, (0.5, 4.0), 20.0, "az91", None, planar_reflectors=True),
     # single sensor, full 3D, the throughput workload: 32 mics x 16384 samples x 1500 directions
     "c2": Config(2, "c2", 32, 0.035, 16384, 20, (0.3, 6.0), 20.0, "fib1500", (20e3, 85e3)),
+    # sensor network (one entry per sensor; sizes per sensor come from network_sensor_shape)
+    "c3": Config(3, "c3", 32, 0.035, 16384, 20, (0.3, 6.0), 20.0, "fib1500", (20e3, 85e3)),
     # stress: 64 mics in 7 cm, 65536 samples, 10000 directions
     "c5": Config(5, "c5", 64, 0.070, 65536, 50, (0.3, 24.0), 10.0, "fib10000", (20e3, 85e3)),
 }
@@ -202,3 +204,39 @@ def make_workload(name: str, frames: int = 1, sensor: int = 0, n_samples: int | 
         xs.append(x.astype(np.float32))
         refl.append(rf)
     return Workload(cfg, np.stack(xs), chirp, mic_pos, dirs, refl)
+
+
+NETWORK_LENGTHS = (8192, 16384, 32768)
+
+
+def network_sensor_shape(sensor: int) -> tuple:
+    """(N, grid) of one sensor of the heterogeneous network: N cycles through NETWORK_LENGTHS
+    from a seeded offset, the grid alternates between the 91-azimuth 2D image and the
+    1500-direction hemisphere."""
+    off = int(_rng(3, 0, 0, 3).integers(len(NETWORK_LENGTHS)))
+    n = NETWORK_LENGTHS[(sensor * 2 + off) % len(NETWORK_LENGTHS)]
+    grid = "az91" if sensor % 2 == 0 else "fib1500"
+    return n, grid
+
+
+def make_network(sensors: int = 8, frames: int = 4, n_dirs: int | None = None) -> list:
+    """Seeded sensor network: one Workload per sensor, each with its own array geometry,
+    recording length and direction grid (n_dirs overrides the 3D grid's size for tests)."""
+    out = []
+    for s in range(sensors):
+        n, grid = network_sensor_shape(s)
+        cfg = dataclasses.replace(CONFIGS["c3"], n_samples=n, grid=grid,
+                                  planar_reflectors=(grid == "az91"))
+        mic_pos = planar_array(cfg.n_mics, cfg.aperture, _rng(3, s, 0, 0))
+        dirs = make_grid(grid)
+        if n_dirs is not None and grid != "az91":
+            dirs = fibonacci_hemisphere(n_dirs)
+        chirp_params = (25e3, 80e3, 1e-3)
+        chirp = linear_chirp(FS_HZ, *chirp_params)
+        xs, refl = [], []
+        for f in range(frames):
+            rf = _draw_reflectors(cfg, _rng(3, s, f, 1))
+            xs.append(simulate_frame(mic_pos, chirp_params, rf, n, cfg.snr_db, _rng(3, s, f, 2)).astype(np.float32))
+            refl.append(rf)
+        out.append(Workload(cfg, np.stack(xs), chirp, mic_pos, dirs, refl))
+    return out
