@@ -220,6 +220,37 @@ def plain_path(w, x, args, stream):
             "what": "F=1, matched filter -> beam in HBM -> envelope, FP32 time-domain path"}
 
 
+def network_path(args, stream):
+    """The heterogeneous sensor network (8 sensors x 4 frames, own geometry, N in {8192, 16384, 32768},
+    91-azimuth or 1500-direction grids) through sonar_energyscape_multi, eager and replayed from a graph."""
+    import torch
+
+    from paper_2208_10839_amd import binding
+    from workloads import synth
+    net = synth.make_network()
+    plans = [binding.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
+                          max_frames=w.x.shape[0], mode="td_bf16") for w in net]
+    xs = [torch.from_numpy(w.x).cuda() for w in net]
+    outs = [torch.empty((w.x.shape[0], w.dirs.shape[0], pl.Q), dtype=torch.float32, device="cuda")
+            for w, pl in zip(net, plans)]
+    n_es = sum(w.x.shape[0] for w in net)
+    for _ in range(3):
+        binding.energyscape_multi(plans, xs, outs)
+    ms_eager = time_calls(lambda: binding.energyscape_multi(plans, xs, outs), args.steps, stream)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        binding.energyscape_multi(plans, xs, outs)
+    torch.cuda.synchronize()
+    ms_graph = time_calls(g.replay, args.steps, torch.cuda.current_stream())
+    for pl in plans:
+        pl.close()
+    return {"energyscapes_per_call": n_es, "mode": "td_bf16",
+            "eager": {"value": round(n_es / (ms_eager / 1e3), 2), "unit": "energyscapes/s", "ms_per_call": round(ms_eager, 4)},
+            "graph_replay": {"value": round(n_es / (ms_graph / 1e3), 2), "unit": "energyscapes/s",
+                             "ms_per_call": round(ms_graph, 4)},
+            "shapes": [[int(w.x.shape[2]), int(w.dirs.shape[0])] for w in net]}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -245,6 +276,8 @@ def main():
               file=sys.stderr, flush=True)
         results[name] = run_path(name, w, x, args, stream)
     plain = plain_path(w, x, args, stream)
+    print("[bench] sensor network batch", file=sys.stderr, flush=True)
+    network = network_path(args, stream)
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 1024 * 1024 // 4
@@ -276,6 +309,7 @@ def main():
                             "dirs_per_frame": args.check_dirs},
         "paths": results,
         "plain_single_sensor_gpu_path": plain,
+        "sensor_network_batch": network,
     }
     print(json.dumps(out), flush=True)
 
