@@ -15,12 +15,17 @@ from .sonar_oracle import (  # noqa: F401
     chirp_spectrum_filter,
     das_fd,
     das_td,
+    das_td_vjp,
     default_lowpass,
     delays,
+    delays_vjp,
     energyscape,
+    energyscape_vjp_td,
     envelope,
+    envelope_vjp,
     matched_filter,
     matched_filter_spectrum,
+    matched_filter_vjp,
     num_range_bins,
     td_offsets,
 )

@@ -256,3 +256,94 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
         raise ValueError("mode must be 'td' or 'fd'")
     E = envelope(b, h, Q, R)
     return (E, b) if return_beam else E
+
+
+# ---------------------------------------------------------------------------
+# Reverse-mode derivatives of the time-domain pipeline (the adjoint used for
+# array self-calibration).  For a real loss L of the energyscape, dE = dL/dE.
+# Complex quantities z carry the gradient G_z = dL/dRe z + i dL/dIm z, so that
+# dL = sum Re(conj(G_z) dz).  Each step is the chain rule of the forward step
+# above, written out term by term.
+# ---------------------------------------------------------------------------
+
+def envelope_vjp(b_win, taps, dE, Q: int, R: int) -> np.ndarray:
+    """G_b[d][i] for E = envelope(b_win): dL/d|b| at window position i is
+    sum over the outputs q that read it (i = qR + K-1-j) of dE[d][q] h[j]; then
+    G_b = dL/d|b| * b/|b| (zero where b = 0)."""
+    h = np.asarray(taps, dtype=np.float64)
+    K = h.size
+    b = np.asarray(b_win)
+    dE = np.asarray(dE, dtype=np.float64)
+    g_abs = np.zeros(b.shape)
+    for q in range(Q):
+        for j in range(K):
+            g_abs[:, q * R + K - 1 - j] += dE[:, q] * h[j]
+    mag = np.abs(b)
+    unit = np.where(mag > 0, b / np.where(mag > 0, mag, 1.0), 0.0)
+    return g_abs * unit
+
+
+def das_td_vjp(yhat, Dl, n_idx, G_b):
+    """Gradients of b = das_td(yhat, Dl, n_idx) given G_b [D][len(n_idx)].
+
+    Returns (G_y [M][P] complex, dDl [D][M] real):
+      G_y[m][(n+o) mod P]   += (1-alpha)/M * G_b[d][n],  G_y[m][(n+o+1) mod P] += alpha/M * G_b[d][n]
+      dDl[d][m] = (1/M) sum_n Re(conj(G_b[d][n]) (yhat_m[n+o] - yhat_m[n+o+1]))
+    (alpha = -Dl - o depends on Dl with slope -1 inside a sample cell; o is
+    piecewise constant, so this is the derivative almost everywhere.)"""
+    yhat = np.asarray(yhat)
+    M, P = yhat.shape
+    o, alpha = td_offsets(Dl)
+    n_idx = np.asarray(n_idx, dtype=np.int64)
+    G_b = np.asarray(G_b)
+    D = o.shape[0]
+    G_y = np.zeros((M, P), dtype=np.complex128)
+    dDl = np.zeros((D, M))
+    for d in range(D):
+        for m in range(M):
+            i0 = np.mod(n_idx + o[d, m], P)
+            i1 = np.mod(n_idx + o[d, m] + 1, P)
+            np.add.at(G_y[m], i0, (1.0 - alpha[d, m]) / M * G_b[d])
+            np.add.at(G_y[m], i1, alpha[d, m] / M * G_b[d])
+            dDl[d, m] = np.sum(np.real(np.conj(G_b[d]) * (yhat[m, i0] - yhat[m, i1]))) / M
+    return G_y, dDl
+
+
+def matched_filter_vjp(G_y, chirp, P: int, N: int, fs: float, band=None) -> np.ndarray:
+    """dx [M][N] for yhat = matched_filter(x) (x real, zero-padded to P): the filter is
+    yhat = IDFT(C . DFT(x)), so its adjoint is dx = Re IDFT(conj(C) . DFT(G_y)), cut to N."""
+    C = chirp_spectrum_filter(chirp, P, fs, band)
+    G_hat = np.fft.fft(np.asarray(G_y), axis=1)
+    return np.real(np.fft.ifft(np.conj(C)[None, :] * G_hat, axis=1))[:, :N]
+
+
+def delays_vjp(dDl, dirs, fs: float, c: float) -> np.ndarray:
+    """dpos [M][3] for Dl = delays(pos, dirs): dDl[d][m] * fs/c * u_d summed over d."""
+    u = np.asarray(dirs, dtype=np.float64)
+    return (fs / c) * (np.asarray(dDl, dtype=np.float64).T @ u)
+
+
+def energyscape_vjp_td(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: int | None = None,
+                       gate=None, R: int = 10, taps=None, band=None):
+    """(dx [M][N], dpos [M][3]) of L = sum(dE * energyscape(..., mode='td')) by the chain rule:
+    envelope -> delay-and-sum -> matched filter and delays."""
+    x = np.asarray(x, dtype=np.float64)
+    M, N = x.shape
+    L = len(chirp)
+    if P is None:
+        P = 1
+        while P < N + L - 1:
+            P *= 2
+    n0, n1 = (0, N) if gate is None else gate
+    h = default_lowpass(R) if taps is None else np.asarray(taps, dtype=np.float64)
+    K = h.size
+    Q = num_range_bins(n0, n1, R)
+    Dl = delays(mic_pos, dirs, fs, c)
+    n_idx = beam_window_indices(n0, Q, R, K)
+    yhat = matched_filter(x, chirp, P, fs, band)
+    b = das_td(yhat, Dl, n_idx)
+    G_b = envelope_vjp(b, h, dE, Q, R)
+    G_y, dDl = das_td_vjp(yhat, Dl, n_idx, G_b)
+    dx = matched_filter_vjp(G_y, chirp, P, N, fs, band)
+    dpos = delays_vjp(dDl, dirs, fs, c)
+    return dx, dpos
