@@ -14,17 +14,20 @@ from .sonar_oracle import (  # noqa: F401
     beam_window_indices,
     chirp_spectrum_filter,
     das_fd,
+    das_fd_vjp,
     das_td,
     das_td_vjp,
     default_lowpass,
     delays,
     delays_vjp,
     energyscape,
+    energyscape_vjp_fd,
     energyscape_vjp_td,
     envelope,
     envelope_vjp,
     matched_filter,
     matched_filter_spectrum,
+    matched_filter_spectrum_vjp,
     matched_filter_vjp,
     num_range_bins,
     td_offsets,

@@ -6,11 +6,10 @@ sweep into a range x direction intensity image in three steps (Fig. 3 caption;
 §4.1 Signal Processing): a matched filter against the emitted sweep, delay-and-sum
 beamforming toward every direction of interest, and an envelope detector whose
 output is subsampled (§4.3 GPU Algorithm Implementation).  The paper states
-these steps in prose only; the precise definition implemented here is the one
-written down in DESIGN.md ("Readings of the paper"), which fixes what the paper
-leaves open (circular length-P arithmetic, analytic signal from one-sided
-weights, zero-phase FIR low-pass, linear-interpolation or exact fractional
-delays).
+these steps in prose only; the precise definition implemented here fixes what
+the paper leaves open (circular length-P arithmetic, analytic signal from
+one-sided weights, zero-phase FIR low-pass, linear-interpolation or exact
+fractional delays), and each function states the reading it takes.
 
 Everything is numpy in float64 (complex128), with ``numpy.fft`` as the only
 library primitive.  Nothing is blocked, fused or reordered beyond what the
@@ -321,6 +320,69 @@ def delays_vjp(dDl, dirs, fs: float, c: float) -> np.ndarray:
     """dpos [M][3] for Dl = delays(pos, dirs): dDl[d][m] * fs/c * u_d summed over d."""
     u = np.asarray(dirs, dtype=np.float64)
     return (fs / c) * (np.asarray(dDl, dtype=np.float64).T @ u)
+
+
+def das_fd_vjp(Yspec, Dl, n_idx, G_b):
+    """Gradients of b = das_fd(Yspec, Dl, n_idx) given G_b [D][len(n_idx)].
+
+    b_d = IDFT_P(B_d) on the window, B_d[k] = (1/M) sum_m Yhat_m[k] exp(-2j pi k Dl[d][m] / P)
+    for k <= P/2.  The window read-out is linear, so G_B_d = DFT_P(G_b scattered onto Z_P) / P;
+    then, bin by bin,
+      G_Y[m][k] = (1/M) sum_d exp(+2j pi k Dl[d][m] / P) G_B_d[k]              (k <= P/2, else 0)
+      dDl[d][m] = (1/M) sum_k Re(conj(G_B_d[k]) Yhat_m[k] (-2j pi k / P) exp(-2j pi k Dl[d][m] / P)).
+    The steering phase is smooth in Dl, so these are exact derivatives everywhere.
+    Returns (G_Y [M][P] complex, dDl [D][M] real)."""
+    Y = np.asarray(Yspec)
+    M, P = Y.shape
+    Dl = np.asarray(Dl, dtype=np.float64)
+    n_idx = np.mod(np.asarray(n_idx, dtype=np.int64), P)
+    G_b = np.asarray(G_b)
+    D = Dl.shape[0]
+    k = np.arange(P // 2 + 1, dtype=np.float64)
+    G_Y = np.zeros((M, P), dtype=np.complex128)
+    dDl = np.zeros((D, M))
+    for d in range(D):
+        g = np.zeros(P, dtype=np.complex128)
+        np.add.at(g, n_idx, G_b[d])
+        GB = np.fft.fft(g)[:P // 2 + 1] / P
+        for m in range(M):
+            ph = np.exp(-2j * np.pi * (k * Dl[d, m] / P))
+            G_Y[m, :P // 2 + 1] += np.conj(ph) * GB / M
+            dDl[d, m] = np.sum(np.real(np.conj(GB) * Y[m, :P // 2 + 1] * (-2j * np.pi * k / P) * ph)) / M
+    return G_Y, dDl
+
+
+def matched_filter_spectrum_vjp(G_Y, chirp, P: int, N: int, fs: float, band=None) -> np.ndarray:
+    """dx [M][N] for Yhat = matched_filter_spectrum(x) = C . DFT_P(x) (x real, zero-padded):
+    G_X = conj(C) G_Y and dL/dx[n] = Re sum_k G_X[k] exp(+2j pi k n / P), cut to N."""
+    C = chirp_spectrum_filter(chirp, P, fs, band)
+    return np.real(P * np.fft.ifft(np.conj(C)[None, :] * np.asarray(G_Y), axis=1))[:, :N]
+
+
+def energyscape_vjp_fd(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: int | None = None,
+                       gate=None, R: int = 10, taps=None, band=None):
+    """(dx [M][N], dpos [M][3]) of L = sum(dE * energyscape(..., mode='fd')) by the chain rule:
+    envelope -> exact-phase delay-and-sum -> matched-filter spectrum and delays."""
+    x = np.asarray(x, dtype=np.float64)
+    M, N = x.shape
+    L = len(chirp)
+    if P is None:
+        P = 1
+        while P < N + L - 1:
+            P *= 2
+    n0, n1 = (0, N) if gate is None else gate
+    h = default_lowpass(R) if taps is None else np.asarray(taps, dtype=np.float64)
+    K = h.size
+    Q = num_range_bins(n0, n1, R)
+    Dl = delays(mic_pos, dirs, fs, c)
+    n_idx = beam_window_indices(n0, Q, R, K)
+    Y = matched_filter_spectrum(x, chirp, P, fs, band)
+    b = das_fd(Y, Dl, n_idx)
+    G_b = envelope_vjp(b, h, dE, Q, R)
+    G_Y, dDl = das_fd_vjp(Y, Dl, n_idx, G_b)
+    dx = matched_filter_spectrum_vjp(G_Y, chirp, P, N, fs, band)
+    dpos = delays_vjp(dDl, dirs, fs, c)
+    return dx, dpos
 
 
 def energyscape_vjp_td(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: int | None = None,

@@ -77,3 +77,76 @@ def test_envelope_vjp_of_positive_real_beam_is_the_fir_transpose():
     # the envelope is linear here: <E(b), dE> = <b, G>
     assert np.allclose(np.sum(O.envelope(b, h, Q, R) * dE), np.sum(b * G.real), rtol=1e-12)
     assert np.all(G.imag == 0)
+
+
+def _loss_fd(x, w, P, dE, band, pos=None):
+    E = O.energyscape(x, w.chirp, w.mic_pos if pos is None else pos, w.dirs, fs=FS, c=C, P=P, R=5,
+                      band=band, mode="fd")
+    return float(np.sum(dE * E))
+
+
+def test_fd_vjp_samples_match_finite_differences():
+    w, x, P, dE, band = _tiny(seed=5)
+    dx, _ = O.energyscape_vjp_fd(x, w.chirp, w.mic_pos, w.dirs, dE, fs=FS, c=C, P=P, R=5, band=band)
+    rng = np.random.default_rng(6)
+    h = 1e-5
+    for _ in range(12):
+        m, t = int(rng.integers(x.shape[0])), int(rng.integers(x.shape[1]))
+        xp, xm = x.copy(), x.copy()
+        xp[m, t] += h
+        xm[m, t] -= h
+        fd = (_loss_fd(xp, w, P, dE, band) - _loss_fd(xm, w, P, dE, band)) / (2 * h)
+        assert abs(fd - dx[m, t]) <= 1e-6 * max(1.0, abs(fd)), (m, t, fd, dx[m, t])
+
+
+def test_fd_vjp_positions_match_finite_differences():
+    """The exact-phase beamformer is smooth in the delays: central differences with
+    h = 1e-6 m agree with the adjoint to the O(h^2) truncation error."""
+    w, x, P, dE, band = _tiny(seed=7)
+    _, dpos = O.energyscape_vjp_fd(x, w.chirp, w.mic_pos, w.dirs, dE, fs=FS, c=C, P=P, R=5, band=band)
+    h = 1e-6
+    for m in range(w.mic_pos.shape[0]):
+        for k in range(3):
+            pp, pm = w.mic_pos.copy(), w.mic_pos.copy()
+            pp[m, k] += h
+            pm[m, k] -= h
+            fd = (_loss_fd(x, w, P, dE, band, pp) - _loss_fd(x, w, P, dE, band, pm)) / (2 * h)
+            assert abs(fd - dpos[m, k]) <= 1e-6 * max(1.0, np.abs(dpos).max()), (m, k, fd, dpos[m, k])
+
+
+def test_fd_beamformer_adjoint_identity():
+    """b is linear in the spectra: Re<das_fd(V), G> = Re<V, G_Y> for random V, G (so G_Y is the
+    true adjoint, including the one-sided bin range and the 1/P of the window read-out)."""
+    rng = np.random.default_rng(8)
+    M, P, D = 3, 256, 4
+    V = np.zeros((M, P), dtype=np.complex128)
+    V[:, :P // 2 + 1] = rng.standard_normal((M, P // 2 + 1)) + 1j * rng.standard_normal((M, P // 2 + 1))
+    Dl = rng.uniform(-5, 5, size=(D, M))
+    n_idx = np.arange(-20, 100)
+    G = rng.standard_normal((D, n_idx.size)) + 1j * rng.standard_normal((D, n_idx.size))
+    G_Y, _ = O.das_fd_vjp(V, Dl, n_idx, G)
+    lhs = np.sum(np.real(np.conj(G) * O.das_fd(V, Dl, n_idx)))
+    rhs = np.sum(np.real(np.conj(G_Y) * V))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_fd_matched_filter_spectrum_adjoint_identity():
+    rng = np.random.default_rng(9)
+    M, N, P = 3, 200, 512
+    chirp = synth.linear_chirp(FS, 25e3, 80e3, 2e-4)
+    x = rng.standard_normal((M, N))
+    G = rng.standard_normal((M, P)) + 1j * rng.standard_normal((M, P))
+    lhs = np.sum(np.real(np.conj(G) * O.matched_filter_spectrum(x, chirp, P, FS, (20e3, 85e3))))
+    rhs = np.sum(x * O.matched_filter_spectrum_vjp(G, chirp, P, N, FS, (20e3, 85e3)))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs)
+
+
+def test_td_and_fd_position_gradients_agree_at_integer_delays():
+    """With every delay an integer both beamformers read the matched-filter samples exactly,
+    so the forward pass that the FD adjoint differentiates equals the TD one there."""
+    w, x, P, dE, band = _tiny(seed=10, D=2)
+    pos = np.round(w.mic_pos / (C / FS)) * (C / FS)           # positions on the sample lattice
+    dirs = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, 0.0]])         # axes: every p . u is a lattice point
+    Et = O.energyscape(x, w.chirp, pos, dirs, fs=FS, c=C, P=P, R=5, band=band, mode="td")
+    Ef = O.energyscape(x, w.chirp, pos, dirs, fs=FS, c=C, P=P, R=5, band=band, mode="fd")
+    assert np.allclose(Et, Ef, rtol=1e-9, atol=1e-12 * np.abs(Ef).max())

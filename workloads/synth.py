@@ -240,3 +240,63 @@ def make_network(sensors: int = 8, frames: int = 4, n_dirs: int | None = None) -
             refl.append(rf)
         out.append(Workload(cfg, np.stack(xs), chirp, mic_pos, dirs, refl))
     return out
+
+
+@dataclasses.dataclass
+class CalibrationWorkload:
+    x: np.ndarray          # [F][M][N] float32, recorded with true_pos
+    chirp: np.ndarray      # [L] float64
+    true_pos: np.ndarray   # [M][3] float64
+    start_pos: np.ndarray  # [M][3] float64: true_pos plus the seeded perturbation
+    dirs: np.ndarray       # [D][3] float64
+    cells: list            # per frame: list of (d, q) energyscape cells of the reflectors
+    band: tuple
+    decim: int
+    fs: float = FS_HZ
+    c: float = C_MPS
+
+
+def make_calibration(frames: int = 10, reflectors: int = 5, sigma: float = 0.5e-3, n_samples: int = 16384,
+                     n_dirs: int = 1500, n_mics: int = N_MICS, snr_db: float = 20.0,
+                     chirp_params=(25e3, 80e3, 1e-3)) -> CalibrationWorkload:
+    """Seeded array self-calibration workload (cfg_id 4).
+
+    Reflectors sit in the far field of the 3.5 cm array, so the echo at microphone m
+    arrives after tau = (2 r - p_m . u) / c (the plane-wave model of the §4.1 delays),
+    with a common amplitude per reflector (no spreading loss).  Each reflector is placed
+    exactly on a grid direction d and at a range r = q R c / (2 fs) that puts its beam
+    peak on the centre of range cell q, so the energyscape cells (d, q) are known and
+    the ideal geometry maximises E there.  Ranges of one frame are distinct multiples of
+    25 cells, so the compressed echoes of one frame do not overlap in range.
+    Seeds: SeedSequence([4, 0, frame, stream]), stream 0 = geometry, 1 = reflectors,
+    2 = noise, 4 = position perturbation (Gaussian, sigma metres per coordinate).
+    """
+    R = 10
+    fs, c = FS_HZ, C_MPS
+    true_pos = planar_array(n_mics, 0.035, _rng(4, 0, 0, 0))
+    start_pos = true_pos + _rng(4, 0, 0, 4).normal(0.0, sigma, size=true_pos.shape)
+    dirs = fibonacci_hemisphere(n_dirs)
+    f0, f1, T = chirp_params
+    chirp = linear_chirp(fs, f0, f1, T)
+    L = chirp.size
+    q_hi = (n_samples - L - 8) // R
+    slots = np.arange(50, q_hi, 25)
+    xs, cells = [], []
+    for f in range(frames):
+        rng = _rng(4, 0, f, 1)
+        ds = rng.choice(n_dirs, size=reflectors, replace=False)
+        qs = rng.choice(slots, size=reflectors, replace=False)
+        amps = rng.uniform(0.5, 1.0, size=reflectors)
+        x = np.zeros((n_mics, n_samples))
+        n = np.arange(n_samples)
+        for d, q, a in zip(ds, qs, amps):
+            r = q * R * c / (2.0 * fs)
+            for m in range(n_mics):
+                tau = (2.0 * r - true_pos[m] @ dirs[d]) / c
+                x[m] += a * _chirp_at(n / fs - tau, f0, f1, T)
+        p_sig = float(np.mean(x * x))
+        sig = math.sqrt(p_sig / (10.0 ** (snr_db / 10.0)))
+        x += _rng(4, 0, f, 2).normal(0.0, sig, size=x.shape)
+        xs.append(x.astype(np.float32))
+        cells.append([(int(d), int(q)) for d, q in zip(ds, qs)])
+    return CalibrationWorkload(np.stack(xs), chirp, true_pos, start_pos, dirs, cells, (20e3, 85e3), R)
