@@ -240,6 +240,63 @@ enum sonar_precision {
 int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
                             sonar_plan* out, int32_t* chosen_mode);
 
+/*
+ * Reverse-mode derivatives of the pipeline (the adjoint used to self-calibrate
+ * the array: the delays of §4.1 depend on the microphone positions).  For a
+ * real loss L with dE = dL/dE [F][D][Q], complex quantities z carry gradients
+ * G_z = dL/dRe z + i dL/dIm z:
+ *   envelope        G_b = (FIR^T dE) * b / |b|            (0 where b = 0)
+ *   TD delay-and-sum
+ *                   dL/dDl[d][m] = (1/M) sum_n Re(conj(G_b[n]) (yhat_m[n+o] - yhat_m[n+o+1]))
+ *                   G_yhat_m  = the transposed interpolation of G_b
+ *                   (o = floor(-Dl) is piecewise constant: derivatives almost everywhere)
+ *   FD delay-and-sum
+ *                   G_B[d][k] = DFT_P(G_b[d] on its window)[k] / P
+ *                   dL/dDl[d][m] = (1/M) sum_k Re(conj(G_B[d][k]) Yhat_m[k] (-2 pi i k/P) e^{-2 pi i k Dl/P})
+ *                   G_Yhat_m[k] = (1/M) sum_d e^{+2 pi i k Dl[d][m]/P} G_B[d][k]
+ *                   (smooth in the delays: exact derivatives)
+ *   delays          dL/dp_m = fs/c sum_{f,d} dL/dDl[f][d][m] u_d
+ *   matched filter  dL/dx = Re sum_k conj(C[k]) G_Yhat[k] e^{2 pi i k n/P}, cut to N
+ *                   (TD: G_Yhat = DFT_P(G_yhat) / P)
+ * All gradient arithmetic is FP32 (dL/dp accumulated in FP64) on the buffers of
+ * the forward pass given.
+ *
+ * sonar_plan_enable_gradients -- allocates the gradient workspace of the plan
+ * (once; the bytes are added to SONAR_Q_WORKSPACE_BYTES).  Frequency-domain
+ * plans need P <= 32768 (SONAR_E_UNSUPPORTED otherwise).
+ */
+int sonar_plan_enable_gradients(sonar_plan plan);
+
+/*
+ * sonar_energyscape_vjp -- the derivatives above for F frames, ordered on
+ * `stream`.
+ *   mf_in      : the matched-filter buffer of the forward pass (sonar_matched_filter).
+ *   beam_inout : the beam window of the forward pass (sonar_beamform),
+ *                complex64 [F][D][G']; overwritten with G_b.
+ *   dE         : float [F][D][Q].
+ *   dyhat_out  : gradient of the matched-filter output, or NULL.  TD modes:
+ *                complex64 [F][M][P] G_yhat over Z_P (sample n at index n).
+ *                FD modes: complex64 [F][Kb][M], G_Yhat on the band bins in
+ *                the layout of the FD matched-filter buffer.
+ *   dx_out     : float [F][M][N], or NULL (needs dyhat_out; P <= 32768).
+ *   dpos_out   : double [M][3] dL/dp_m summed over the F frames, or NULL.
+ * SONAR_E_INVALID before sonar_plan_enable_gradients.
+ */
+int sonar_energyscape_vjp(sonar_plan plan, const void* mf_in, void* beam_inout, const float* dE,
+                          int32_t F, void* dyhat_out, float* dx_out, double* dpos_out,
+                          hipStream_t stream);
+
+/*
+ * sonar_plan_set_positions -- new microphone positions [M][3] (metres): the
+ * delay tables (§4.1 delays) are rebuilt on `stream` without reallocating,
+ * ordered after the work already queued there.  TD_LINEAR and FD modes;
+ * SONAR_E_UNSUPPORTED for TD_BF16 (its tiles are built for one geometry) and for
+ * a TD_LINEAR plan whose new geometry needs delays outside the plan's range
+ * (the plan keeps 3 samples of slack on each side of the geometry it was
+ * created with).
+ */
+int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
+
 /* Static text for a status code. */
 const char* sonar_status_string(int status);
 

@@ -67,6 +67,11 @@ _SIGNATURES = {
                                                 ctypes.c_int32, ctypes.c_void_p]),
     "sonar_plan_create_tuned": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.c_int32, ctypes.c_void_p,
                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32)]),
+    "sonar_plan_enable_gradients": (ctypes.c_int, [ctypes.c_void_p]),
+    "sonar_energyscape_vjp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "sonar_plan_set_positions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sonar_last_error": (ctypes.c_char_p, []),
 }
@@ -260,6 +265,43 @@ class Plan:
                "sonar_envelope")
         return E
 
+    def enable_gradients(self):
+        _check(load().sonar_plan_enable_gradients(self._h), "sonar_plan_enable_gradients")
+
+    def set_positions(self, mic_pos, stream=None):
+        """New microphone positions [M][3] (TD_LINEAR plans): rebuilds the delay table."""
+        pos = _f64(mic_pos, (self.M, 3))
+        _check(load().sonar_plan_set_positions(self._h, _ptr(pos), _stream_handle(stream)), "sonar_plan_set_positions")
+
+    def vjp(self, mf, beam, dE, want_dx=True, want_dpos=True, stream=None):
+        """sonar_energyscape_vjp.  Returns (G_mf, dx, dpos): G_mf is the gradient of the
+        matched-filter output (TD modes: complex64 [F][M][P] over Z_P; FD modes: complex64
+        [F][Kb][M] on the band bins), dx float32 [F][M][N] or None, dpos float64 numpy [M][3]
+        or None.  beam (the forward beam window) is overwritten with G_b."""
+        import torch
+        self.enable_gradients()
+        F = self._frames(mf, (self.mf_frame_elems,), "mf")
+        self._frames(beam, (self.D, self.G), "beam")
+        self._frames(dE, (self.D, self.Q), "dE")
+        if dE.dtype != torch.float32 or beam.dtype != torch.complex64:
+            raise TypeError("dE must be float32 and beam complex64")
+        if beam.shape[0] != F or dE.shape[0] != F:
+            raise ValueError("mf, beam and dE must hold the same number of frames")
+        dy = dx = dpos = None
+        if want_dx:
+            shape = (F, self.M, self.P) if self.mode.startswith("td") else (F, self.band_bins, self.M)
+            dy = torch.empty(shape, dtype=torch.complex64, device=mf.device)
+            dx = torch.empty((F, self.M, self.N), dtype=torch.float32, device=mf.device)
+        if want_dpos:
+            dpos = torch.empty((self.M, 3), dtype=torch.float64, device=mf.device)
+        _check(load().sonar_energyscape_vjp(self._h, ctypes.c_void_p(mf.data_ptr()), ctypes.c_void_p(beam.data_ptr()),
+                                            ctypes.c_void_p(dE.data_ptr()), F,
+                                            ctypes.c_void_p(dy.data_ptr() if dy is not None else 0),
+                                            ctypes.c_void_p(dx.data_ptr() if dx is not None else 0),
+                                            ctypes.c_void_p(dpos.data_ptr() if dpos is not None else 0),
+                                            _stream_handle(stream)), "sonar_energyscape_vjp")
+        return dy, dx, (dpos.cpu().numpy() if dpos is not None else None)
+
     def beamform_envelope(self, mf, out=None, stream=None):
         """E[F][D][Q] from a matched-filter buffer, beam kept on chip."""
         import torch
@@ -269,6 +311,46 @@ class Plan:
                                               ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
                "sonar_beamform_envelope")
         return E
+
+
+class Energyscape:
+    """Differentiable energyscape of one TD_LINEAR or FD plan: E = f(x, positions).
+
+    Energyscape.apply(x, pos, plan): x [F][M][N] float32 CUDA tensor, pos [M][3] float64
+    CPU tensor (written into the plan with sonar_plan_set_positions), returns E [F][D][Q].
+    The backward pass is sonar_energyscape_vjp: dL/dx on the device, dL/dpos on the host."""
+
+    _fn = None
+
+    @staticmethod
+    def _make():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, x, pos, plan):
+                plan.set_positions(pos.detach().cpu().numpy())
+                mf = plan.matched_filter(x)
+                beam = plan.beamform(mf)
+                E = plan.envelope(beam)
+                ctx.plan = plan
+                ctx.save_for_backward(mf, beam)
+                return E
+
+            @staticmethod
+            def backward(ctx, dE):
+                mf, beam = ctx.saved_tensors
+                want_dx, want_dpos = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+                _, dx, dpos = ctx.plan.vjp(mf, beam.clone(), dE.contiguous(), want_dx=want_dx, want_dpos=want_dpos)
+                return dx, (torch.from_numpy(dpos) if dpos is not None else None), None
+
+        return _Fn
+
+    @classmethod
+    def apply(cls, x, pos, plan):
+        if cls._fn is None:
+            cls._fn = cls._make()
+        return cls._fn.apply(x, pos, plan)
 
 
 def energyscape_multi(plans, xs, outs=None, stream=None):

@@ -1,0 +1,480 @@
+// Reverse-mode derivatives of the time-domain pipeline (the adjoint used to
+// self-calibrate the array geometry; the forward steps are §4.1 matched
+// filter, delay-and-sum and envelope, §4.3 subsampling).  For a real loss L of
+// the energyscape with dE = dL/dE, complex quantities z carry
+// G_z = dL/dRe z + i dL/dIm z:
+//
+//   envelope      G_b[w]   = (sum_{q, j: qR + K-1-j = w} dE[q] h[j]) * b[w] / |b[w]|
+//   delay-and-sum dDl[d][m] = sum_w Re(conj(G_b[w]) (y_m[w+rel] - y_m[w+rel+1])) / M
+//                 G_y[m][r] = sum_d w0[d][m] G_b[d][r-rel] + w1[d][m] G_b[d][r-rel-1]
+//   delays        dpos[m]   = fs/c * sum_{f,d} dDl[f][d][m] u_d
+//   matched filter dx       = Re IDFT_P(conj(C) . DFT_P(G_yhat)), cut to N
+//
+// (w is the beam-window position, r the position in a matched-filter row, rel
+// the row offset of tap 0; the row layout and weights are those of the forward
+// kernels.)  The complex P-point DFT of G_yhat runs as two NF-point transforms
+// of its even and odd samples; the inverse is the forward matched filter's
+// two-parity inverse.
+//
+// The exact-phase (frequency-domain) beamformer b_d = IDFT_P(B_d) on the window,
+// B_d[k] = (1/M) sum_m Y_m[k] exp(-2 pi i k Dl[d][m] / P) over the band bins, has
+//   G_B[d][k]  = DFT_P(G_b[d] placed on its window positions)[k] / P
+//   dDl[d][m]  = (1/M) sum_k Re(conj(G_B[d][k]) Y_m[k] (-2 pi i k / P) exp(-2 pi i k Dl / P))
+//   G_Y[m][k]  = (1/M) sum_d exp(+2 pi i k Dl[d][m] / P) G_B[d][k]
+//   dx         = Re sum_k conj(C[k]) G_Y[k] exp(2 pi i k n / P), cut to N.
+#include <hip/hip_runtime.h>
+
+#include "fft_lds.hpp"
+#include "plan.hpp"
+
+using namespace fftk;
+
+namespace {
+
+// G_b over the beam window, in place: beam[f][d][w] -> G_b[f][d][w]
+__global__ void env_vjp_kernel(float2* __restrict__ beam, const float* __restrict__ dE,
+                               const float* __restrict__ taps, long long rows, int G, int Q, int R, int K) {
+  const int w = blockIdx.y * blockDim.x + threadIdx.x;
+  const long long fd = blockIdx.x;
+  if (w >= G || fd >= rows) return;
+  // outputs q reading position w: 0 <= qR + K-1-w < K
+  int qlo = w - K + 1 > 0 ? (w - K + 1 + R - 1) / R : 0;
+  int qhi = w / R;
+  if (qhi > Q - 1) qhi = Q - 1;
+  const float* e = dE + fd * Q;
+  float g = 0.f;
+  for (int q = qlo; q <= qhi; ++q) g = fmaf(e[q], taps[q * R + K - 1 - w], g);
+  const float2 b = beam[fd * G + w];
+  const float mag = sqrtf(b.x * b.x + b.y * b.y);
+  const float s = mag > 0.f ? g / mag : 0.f;
+  beam[fd * G + w] = make_float2(s * b.x, s * b.y);
+}
+
+// dDl[f][d][m]: one workgroup per (frame, direction), a block reduction per microphone
+__global__ __launch_bounds__(256) void dl_vjp_kernel(const float2* __restrict__ gb, const float2* __restrict__ yext,
+                                                     const int4* __restrict__ dtab, float* __restrict__ ddl,
+                                                     long long fstride, int M, int D, int G, int row) {
+  __shared__ float red[256 / 64];
+  const int d = blockIdx.x % D;
+  const long long f = blockIdx.x / D;
+  const float2* g = gb + (f * D + d) * G;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int m = 0; m < M; ++m) {
+    const int rel = dtab[static_cast<long long>(d) * M + m].x;
+    const float2* y = yext + f * fstride + static_cast<long long>(m) * row + rel;
+    float acc = 0.f;
+    for (int w = threadIdx.x; w < G; w += 256) {
+      const float2 gw = g[w], a = y[w], b = y[w + 1];
+      acc = fmaf(gw.x, a.x - b.x, acc);
+      acc = fmaf(gw.y, a.y - b.y, acc);
+    }
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      ddl[(f * D + d) * M + m] = (red[0] + red[1] + red[2] + red[3]) / static_cast<float>(M);
+    __syncthreads();
+  }
+}
+
+// dpos[m][k] = fs/c * sum_{f,d} dDl[f][d][m] u_d[k] (FP64 accumulation), one workgroup per microphone
+__global__ __launch_bounds__(256) void pos_vjp_kernel(const float* __restrict__ ddl, const double* __restrict__ dirs,
+                                                      double* __restrict__ dpos, int F, int M, int D, double scale) {
+  __shared__ double red[3][256];
+  const int m = blockIdx.x;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+  for (long long i = threadIdx.x; i < static_cast<long long>(F) * D; i += 256) {
+    const int d = static_cast<int>(i % D);
+    const double v = ddl[i * M + m];
+    a0 += v * dirs[3 * d];
+    a1 += v * dirs[3 * d + 1];
+    a2 += v * dirs[3 * d + 2];
+  }
+  red[0][threadIdx.x] = a0;
+  red[1][threadIdx.x] = a1;
+  red[2][threadIdx.x] = a2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s)
+      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3) dpos[3 * m + threadIdx.x] = scale * red[threadIdx.x][0];
+}
+
+// G_yhat[f][m][n], n in Z_P: every row position r = (n - origin) mod P, r + P, ... below row
+// collects the taps that read it
+__global__ __launch_bounds__(256) void yhat_vjp_kernel(const float2* __restrict__ gb, const int4* __restrict__ dtab,
+                                                       float2* __restrict__ gy, int M, int D, int G, int row, int P,
+                                                       int origin) {
+  const int n = blockIdx.y * 256 + threadIdx.x;
+  const long long fm = blockIdx.x;
+  if (n >= P) return;
+  const long long f = fm / M;
+  const int m = static_cast<int>(fm - f * M);
+  const float2* g = gb + f * D * G;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int r = (n - origin) & (P - 1); r < row; r += P) {
+    for (int d = 0; d < D; ++d) {
+      const int4 e = dtab[static_cast<long long>(d) * M + m];
+      const int w = r - e.x;
+      const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.z);
+      if (w >= 0 && w < G) {
+        const float2 v = g[static_cast<long long>(d) * G + w];
+        acc.x = fmaf(w0, v.x, acc.x);
+        acc.y = fmaf(w0, v.y, acc.y);
+      }
+      if (w >= 1 && w <= G) {
+        const float2 v = g[static_cast<long long>(d) * G + w - 1];
+        acc.x = fmaf(w1, v.x, acc.x);
+        acc.y = fmaf(w1, v.y, acc.y);
+      }
+    }
+  }
+  gy[fm * P + n] = acc;
+}
+
+// Two-level twiddle tables of the plan in LDS (layout in plan.hpp)
+template <int LOGNF>
+__device__ __forceinline__ void load_tw(float2* tw, const float2* __restrict__ tw_g, int tid, int nthreads) {
+  constexpr int NF = 1 << LOGNF;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int LEN = NHI + 64 + (NF / 64 + 1) + 64;
+  for (int i = tid; i < LEN; i += nthreads) tw[i] = tw_g[i];
+}
+
+// S[ch][par][k] = DFT_NF(g[2n + par])[k]
+template <int LOGNF>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void mfadj_fft_kernel(const float2* __restrict__ gy,
+                                                                      const float2* __restrict__ tw_g,
+                                                                      float2* __restrict__ S) {
+  using Sh = FftShape<LOGNF>;
+  constexpr int NF = Sh::NF;
+  constexpr int T = Sh::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[Sh::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  const int tid = threadIdx.x;
+  const int par = blockIdx.x & 1;
+  const long long ch = blockIdx.x >> 1;
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  const float2* in = gy + ch * 2 * NF;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = in[2 * (tid + r * (NF / 16)) + par];
+  fft_lds<LOGNF, false>(v, lds, tw, tw + NHI, tid);
+  float2* out = S + (ch * 2 + par) * NF;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[Sh::out_index(tid, i)] = v[i];
+}
+
+// V[ch][k] = conj(C[k]) (E[k mod NF] + exp(-2 pi i k / P) O[k mod NF]), k in [0, NF]
+__global__ void mfadj_mul_kernel(const float2* __restrict__ S, const float2* __restrict__ cspec,
+                                 const float2* __restrict__ tw_g, float2* __restrict__ V, int NF) {
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  const long long ch = blockIdx.x;
+  if (k > NF) return;
+  const float2* twp_hi = tw_g + fft_nhi(NF) + 64;                   // exp(-2 pi i 64 t / P)
+  const float2* twp_lo = tw_g + fft_nhi(NF) + 64 + fft_nhp(NF);     // exp(-2 pi i t / P)
+  const int km = k & (NF - 1);
+  const float2 e = S[ch * 2 * NF + km], o = S[(ch * 2 + 1) * NF + km];
+  const float2 gk = cadd(e, cmul(cmul(twp_hi[k >> 6], twp_lo[k & 63]), o));
+  V[ch * (NF + 1) + k] = cmul(cconj(cspec[k]), gk);
+}
+
+// dx[ch][2a + par] = Re (1/P) (sum_{k<NF} V[k] exp(2 pi i k par / P) exp(2 pi i k a / NF) + V[NF] (-1)^par)
+template <int LOGNF>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void mfadj_inv_kernel(const float2* __restrict__ V,
+                                                                      const float2* __restrict__ tw_g,
+                                                                      float* __restrict__ dx, int N, int P) {
+  using Sh = FftShape<LOGNF>;
+  constexpr int NF = Sh::NF;
+  constexpr int T = Sh::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[Sh::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  const int tid = threadIdx.x;
+  const int par = blockIdx.x & 1;
+  const long long ch = blockIdx.x >> 1;
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  const float2* twp_hi = tw + NHI + 64;
+  const float2* twp_lo = tw + NHI + 64 + (NF / 64 + 1);
+  const float2* in = V + ch * (NF + 1);
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k = tid + r * (NF / 16);
+    v[r] = in[k];
+    if (par) v[r] = cmul(v[r], cconj(cmul(twp_hi[k >> 6], twp_lo[k & 63])));
+  }
+  const float2 ny = in[NF];
+  fft_lds<LOGNF, true>(v, lds, tw, tw + NHI, tid);
+  const float inv_p = 1.0f / static_cast<float>(P);
+  const float sgn = par ? -1.0f : 1.0f;
+  float* out = dx + ch * N;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int n = 2 * Sh::out_index(tid, i) + par;
+    if (n < N) out[n] = (v[i].x + sgn * ny.x) * inv_p;
+  }
+}
+
+// exp(-2 pi i k Dl / P) with the phase k Dl / P reduced to [-1/2, 1/2] in FP64
+__device__ __forceinline__ float2 steer(int k, double dl_over_p) {
+  const double a = static_cast<double>(k) * dl_over_p;
+  const float r = static_cast<float>(a - rint(a));
+  float s, c;
+  sincospif(-2.0f * r, &s, &c);
+  return make_float2(c, s);
+}
+
+// S[ch][par][k] = DFT_NF(g[2n + par])[k], g = G_b of channel ch = f * D + d placed on Z_P:
+// window position i sits at sample (wstart + i) mod P
+template <int LOGNF>
+__global__ __launch_bounds__((1 << LOGNF) / 16) void gfd_fft_kernel(const float2* __restrict__ gb,
+                                                                     const float2* __restrict__ tw_g,
+                                                                     float2* __restrict__ S, int G, int P,
+                                                                     int wstart) {
+  using Sh = FftShape<LOGNF>;
+  constexpr int NF = Sh::NF;
+  constexpr int T = Sh::T;
+  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
+  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  __shared__ float2 lds[Sh::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  const int tid = threadIdx.x;
+  const int par = blockIdx.x & 1;
+  const long long ch = blockIdx.x >> 1;
+  load_tw<LOGNF>(tw, tw_g, tid, T);
+  __syncthreads();
+  const float2* in = gb + ch * G;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int n = 2 * (tid + r * (NF / 16)) + par;
+    const int i = (n - wstart) & (P - 1);
+    v[r] = i < G ? in[i] : make_float2(0.f, 0.f);
+  }
+  fft_lds<LOGNF, false>(v, lds, tw, tw + NHI, tid);
+  float2* out = S + (ch * 2 + par) * NF;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) out[Sh::out_index(tid, i)] = v[i];
+}
+
+// G_B[ch][j] = (E[k mod NF] + exp(-2 pi i k / P) O[k mod NF]) / P, k = k_lo + j
+__global__ void gfd_band_kernel(const float2* __restrict__ S, const float2* __restrict__ tw_g,
+                                float2* __restrict__ GB, int NF, int P, int k_lo, int kb) {
+  const int j = blockIdx.y * blockDim.x + threadIdx.x;
+  const long long ch = blockIdx.x;
+  if (j >= kb) return;
+  const int k = k_lo + j;
+  const float2* twp_hi = tw_g + fft_nhi(NF) + 64;
+  const float2* twp_lo = tw_g + fft_nhi(NF) + 64 + fft_nhp(NF);
+  const int km = k & (NF - 1);
+  const float2 e = S[ch * 2 * NF + km], o = S[(ch * 2 + 1) * NF + km];
+  const float2 g = cadd(e, cmul(cmul(twp_hi[k >> 6], twp_lo[k & 63]), o));
+  const float inv_p = 1.0f / static_cast<float>(P);
+  GB[ch * kb + j] = make_float2(g.x * inv_p, g.y * inv_p);
+}
+
+// dDl[f][d][m], one workgroup per (frame, direction): lane l of a wavefront takes microphone
+// m0 + l % ms and bins j = jsub + (4 waves x 64/ms) t, where ms = min(64, next pow2 >= M)
+__global__ __launch_bounds__(256) void gfd_dl_kernel(const float2* __restrict__ GB, const float2* __restrict__ Y,
+                                                     const double* __restrict__ dl, float* __restrict__ ddl,
+                                                     int M, int D, int kb, int k_lo, int P, int ms) {
+  __shared__ float red[256];
+  const int d = blockIdx.x % D;
+  const long long f = blockIdx.x / D;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int per_wave = 64 / ms;
+  const int jsub = wv * per_wave + lane / ms;
+  const int jstep = 4 * per_wave;
+  const float2* gb = GB + (f * D + d) * kb;
+  const float2* y = Y + f * static_cast<long long>(kb) * M;
+  const float two_pi_over_p = 6.283185307179586f / static_cast<float>(P);
+  for (int m0 = 0; m0 < M; m0 += ms) {
+    const int m = m0 + lane % ms;
+    float acc = 0.f;
+    if (m < M) {
+      const double dlp = dl[static_cast<long long>(d) * M + m] / static_cast<double>(P);
+      for (int j = jsub; j < kb; j += jstep) {
+        const int k = k_lo + j;
+        const float2 g = gb[j];
+        const float2 yv = y[static_cast<long long>(j) * M + m];
+        const float2 ph = steer(k, dlp);
+        // Re(conj(g) * yv * ph * (-i w)) = w Im(conj(g) * yv * ph), w = 2 pi k / P
+        const float2 t = cmul(cconj(g), cmul(yv, ph));
+        acc = fmaf(two_pi_over_p * static_cast<float>(k), t.y, acc);
+      }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < ms && m0 + static_cast<int>(threadIdx.x) < M) {
+      float s = 0.f;
+      for (int i = threadIdx.x; i < 256; i += ms) s += red[i];
+      ddl[(f * D + d) * M + m0 + threadIdx.x] = s / static_cast<float>(M);
+    }
+    __syncthreads();
+  }
+}
+
+// G_Y[f][j][m] = (1/M) sum_d exp(+2 pi i k Dl[d][m] / P) G_B[f][d][j], one thread per (j, m)
+__global__ __launch_bounds__(256) void gfd_gy_kernel(const float2* __restrict__ GB, const double* __restrict__ dl,
+                                                     float2* __restrict__ GY, int M, int D, int kb, int k_lo, int P) {
+  const long long t = static_cast<long long>(blockIdx.y) * 256 + threadIdx.x;
+  const long long f = blockIdx.x;
+  if (t >= static_cast<long long>(kb) * M) return;
+  const int j = static_cast<int>(t / M), m = static_cast<int>(t - static_cast<long long>(j) * M);
+  const int k = k_lo + j;
+  const float2* gb = GB + f * D * static_cast<long long>(kb) + j;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int d = 0; d < D; ++d) {
+    const float2 ph = steer(k, dl[static_cast<long long>(d) * M + m] / static_cast<double>(P));
+    acc = cadd(acc, cmul(cconj(ph), gb[static_cast<long long>(d) * kb]));
+  }
+  const float inv_m = 1.0f / static_cast<float>(M);
+  GY[f * static_cast<long long>(kb) * M + t] = make_float2(acc.x * inv_m, acc.y * inv_m);
+}
+
+// V[f][m][k] = P conj(C[k]) G_Y[f][k - k_lo][m] on the band bins, 0 elsewhere, k in [0, NF]
+__global__ void gfd_spec_kernel(const float2* __restrict__ GY, const float2* __restrict__ cspec,
+                                float2* __restrict__ V, int M, int NF, int P, int k_lo, int kb) {
+  const int k = blockIdx.y * blockDim.x + threadIdx.x;
+  const long long ch = blockIdx.x;   // f * M + m
+  if (k > NF) return;
+  const long long f = ch / M;
+  const int m = static_cast<int>(ch - f * M);
+  const int j = k - k_lo;
+  float2 v = make_float2(0.f, 0.f);
+  if (j >= 0 && j < kb) {
+    const float2 g = GY[(f * kb + j) * M + m];
+    v = cmul(cconj(cspec[k]), g);
+    v.x *= static_cast<float>(P);
+    v.y *= static_cast<float>(P);
+  }
+  V[ch * (NF + 1) + k] = v;
+}
+
+template <int LOGNF>
+hipError_t launch_gfd_fft_t(const sonar_plan_s* p, const float2* gb, int F, hipStream_t s) {
+  constexpr int T = (1 << LOGNF) / 16;
+  hipLaunchKernelGGL((gfd_fft_kernel<LOGNF>), dim3(2 * F * p->D), dim3(T), 0, s, gb, p->d_tw, p->d_gscr, p->G,
+                     p->P, p->n0 - p->hk);
+  return hipGetLastError();
+}
+
+template <int LOGNF>
+hipError_t launch_mfinv_t(const sonar_plan_s* p, const float2* V, int F, float* dx, hipStream_t s);
+
+template <int LOGNF>
+hipError_t launch_mfadj_t(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
+  constexpr int T = (1 << LOGNF) / 16;
+  const int chans = F * p->M;
+  hipLaunchKernelGGL((mfadj_fft_kernel<LOGNF>), dim3(2 * chans), dim3(T), 0, s, gy, p->d_tw, p->d_gscr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mfadj_mul_kernel, dim3(chans, (p->NF + 1 + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_cspec,
+                     p->d_tw, p->d_spec, p->NF);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return launch_mfinv_t<LOGNF>(p, p->d_spec, F, dx, s);
+}
+
+template <int LOGNF>
+hipError_t launch_mfinv_t(const sonar_plan_s* p, const float2* V, int F, float* dx, hipStream_t s) {
+  constexpr int T = (1 << LOGNF) / 16;
+  hipLaunchKernelGGL((mfadj_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s, V, p->d_tw, dx, p->N, p->P);
+  return hipGetLastError();
+}
+
+#define SONAR_LOGNF_DISPATCH(NAME, ...)          \
+  switch (p->logNF) {                             \
+    case 4: return NAME<4>(__VA_ARGS__);          \
+    case 5: return NAME<5>(__VA_ARGS__);          \
+    case 6: return NAME<6>(__VA_ARGS__);          \
+    case 7: return NAME<7>(__VA_ARGS__);          \
+    case 8: return NAME<8>(__VA_ARGS__);          \
+    case 9: return NAME<9>(__VA_ARGS__);          \
+    case 10: return NAME<10>(__VA_ARGS__);        \
+    case 11: return NAME<11>(__VA_ARGS__);        \
+    case 12: return NAME<12>(__VA_ARGS__);        \
+    case 13: return NAME<13>(__VA_ARGS__);        \
+    case 14: return NAME<14>(__VA_ARGS__);        \
+    default: return hipErrorInvalidValue;         \
+  }
+
+hipError_t gfd_fft(const sonar_plan_s* p, const float2* gb, int F, hipStream_t s) {
+  SONAR_LOGNF_DISPATCH(launch_gfd_fft_t, p, gb, F, s)
+}
+
+hipError_t mfadj(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
+  SONAR_LOGNF_DISPATCH(launch_mfadj_t, p, gy, F, dx, s)
+}
+
+hipError_t mfinv(const sonar_plan_s* p, const float2* V, int F, float* dx, hipStream_t s) {
+  SONAR_LOGNF_DISPATCH(launch_mfinv_t, p, V, F, dx, s)
+}
+
+// exact-phase beamformer: G_B, then dDl / dpos and G_Y / dx
+hipError_t vjp_fd(const sonar_plan_s* p, const float2* mf, const float2* gb, int F, float2* dyhat, float* dx,
+                  double* dpos, hipStream_t s) {
+  hipError_t e = gfd_fft(p, gb, F, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(gfd_band_kernel, dim3(F * p->D, (p->kb + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_tw,
+                     p->d_gband, p->NF, p->P, p->k_lo, p->kb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (dpos) {
+    int ms = 1;
+    while (ms < p->M && ms < 64) ms *= 2;
+    hipLaunchKernelGGL(gfd_dl_kernel, dim3(F * p->D), dim3(256), 0, s, p->d_gband, mf, p->d_dl, p->d_gdl, p->M,
+                       p->D, p->kb, p->k_lo, p->P, ms);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pos_vjp_kernel, dim3(p->M), dim3(256), 0, s, p->d_gdl, p->d_dirs, dpos, F, p->M, p->D,
+                       p->fs / p->c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (dyhat) {
+    const long long items = static_cast<long long>(p->kb) * p->M;
+    hipLaunchKernelGGL(gfd_gy_kernel, dim3(F, static_cast<unsigned>((items + 255) / 256)), dim3(256), 0, s,
+                       p->d_gband, p->d_dl, dyhat, p->M, p->D, p->kb, p->k_lo, p->P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (dx) {
+      hipLaunchKernelGGL(gfd_spec_kernel, dim3(F * p->M, (p->NF + 1 + 255) / 256), dim3(256), 0, s, dyhat,
+                         p->d_cspec, p->d_gspec, p->M, p->NF, p->P, p->k_lo, p->kb);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      return mfinv(p, p->d_gspec, F, dx, s);
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float2* beam_grad, const float* dE, int F,
+                                  float2* dyhat, float* dx, double* dpos, hipStream_t s) {
+  const long long rows = static_cast<long long>(F) * p->D;
+  hipLaunchKernelGGL(env_vjp_kernel, dim3(static_cast<unsigned>(rows), (p->G + 255) / 256), dim3(256), 0, s,
+                     beam_grad, dE, p->d_taps, rows, p->G, p->Q, p->R, p->K);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (p->bf_mode != SONAR_BF_TD_LINEAR && p->bf_mode != SONAR_BF_TD_BF16)
+    return vjp_fd(p, mf, beam_grad, F, dyhat, dx, dpos, s);
+  if (dpos) {
+    hipLaunchKernelGGL(dl_vjp_kernel, dim3(static_cast<unsigned>(rows)), dim3(256), 0, s, beam_grad, mf, p->d_dtab,
+                       p->d_gdl, p->mf_fstride, p->M, p->D, p->G, p->row);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(pos_vjp_kernel, dim3(p->M), dim3(256), 0, s, p->d_gdl, p->d_dirs, dpos, F, p->M, p->D,
+                       p->fs / p->c);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (dyhat) {
+    hipLaunchKernelGGL(yhat_vjp_kernel, dim3(F * p->M, (p->P + 255) / 256), dim3(256), 0, s, beam_grad, p->d_dtab,
+                       dyhat, p->M, p->D, p->G, p->row, p->P, static_cast<int>(p->origin));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (dx) return mfadj(p, dyhat, F, dx, s);
+  }
+  return hipSuccess;
+}

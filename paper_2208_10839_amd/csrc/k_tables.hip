@@ -106,22 +106,30 @@ __global__ void fd_step_kernel(const double* __restrict__ dl, long long n, int P
 
 }  // namespace
 
-hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s) {
-  const int n = fd_tw_len(p->fd_L, p->P);
-  hipLaunchKernelGGL(fd_twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p->d_fdtw, p->fd_L, p->P);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+hipError_t launch_fd_step_table(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;
   hipLaunchKernelGGL(fd_step_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s, p->d_dl, dm,
                      p->P, p->d_fdstep);
   return hipGetLastError();
 }
 
-hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s) {
+hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s) {
+  const int n = fd_tw_len(p->fd_L, p->P);
+  hipLaunchKernelGGL(fd_twiddle_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p->d_fdtw, p->fd_L, p->P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_fd_step_table(p, s);
+}
+
+hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;
   hipLaunchKernelGGL(delay_table_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s,
                      p->d_pos, p->d_dirs, p->M, p->D, p->fs, p->c, p->omin, p->spread, p->d_dtab, p->d_dl);
-  hipError_t e = hipGetLastError();
+  return hipGetLastError();
+}
+
+hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s) {
+  hipError_t e = launch_delay_tables(p, s);
   if (e != hipSuccess) return e;
   double2* roots = static_cast<double2*>(p->d_aux);
   hipLaunchKernelGGL(roots_kernel, dim3((p->P + 255) / 256), dim3(256), 0, s, roots, p->P);

@@ -86,6 +86,12 @@ struct sonar_plan_s {
   int* d_mt_perm = nullptr;    // TD BF16: tile slot -> direction (-1: empty), [tiles][32]
   unsigned short* d_mt_fir = nullptr;   // TD BF16: low-pass B fragments, [K-steps][hi, lo][64 lanes][8] BF16
   void* d_aux = nullptr;       // plan-build scratch
+  float* d_gdl = nullptr;      // gradients (TD): dL/dDl, [max_frames][D][M]
+  float2* d_gscr = nullptr;    // gradients: even/odd spectra of G_yhat [max_frames][M][2][NF] (TD),
+                               // of G_b [max_frames][D][2][NF] (FD)
+  float2* d_gband = nullptr;   // gradients (FD): beam-spectrum gradient G_B, [max_frames][D][kb]
+  float2* d_gspec = nullptr;   // gradients (FD): conj(C) G_Y on [0, NF], [max_frames][M][NF + 1]
+  bool grad_on = false;
 };
 
 // FFT twiddle table layout inside d_tw (all FP32 values built from FP64):
@@ -107,6 +113,7 @@ __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L 
 // time-domain beamformer on BF16 MFMA: tiles of 32 directions x MT_NWAVE * 128
 // beam samples per workgroup; wavefront w computes the samples of residue
 // w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time
+constexpr int DELAY_MARGIN = 3;   // samples of delay range kept beyond the geometry's bound
 constexpr int MT_NWAVE = 8;
 // matched filters with NF > 2^MB_LOGN2 run as a radix-(NF / 2^MB_LOGN2) pass over
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
@@ -141,6 +148,10 @@ hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F,
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
 size_t fd_env_static_lds(int logL, int P);
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s);
+hipError_t launch_fd_step_table(sonar_plan_s* p, hipStream_t s);
+hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float2* beam_grad, const float* dE, int F,
+                                  float2* dyhat, float* dx, double* dpos, hipStream_t s);
 hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, float2* beam, hipStream_t s);
 hipError_t launch_envelope(const sonar_plan_s* p, const float2* beam, int F, float* E, hipStream_t s);

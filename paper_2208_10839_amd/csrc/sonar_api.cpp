@@ -82,6 +82,10 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_fdtw);
   (void)hipFree(p->d_fdstep);
   (void)hipFree(p->d_big);
+  (void)hipFree(p->d_gdl);
+  (void)hipFree(p->d_gscr);
+  (void)hipFree(p->d_gband);
+  (void)hipFree(p->d_gspec);
   (void)hipFree(p->d_tw2);
   (void)hipFree(p->d_mt_g);
   (void)hipFree(p->d_mt_w);
@@ -322,6 +326,16 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "MFMA beamformer table upload");
 }
 
+// largest |p_m| fs / c over the microphones: the delay bound over all directions
+double delay_bound(const double* pos, int M, double fs, double c) {
+  double bmax = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const double* q = pos + 3 * m;
+    bmax = std::fmax(bmax, std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * fs / c);
+  }
+  return bmax * (1.0 + 1e-9) + 1e-9;
+}
+
 int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
   if (!a || !b) return fail(SONAR_E_INVALID, "NULL buffer");
@@ -442,14 +456,10 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   p->G = (p->Q - 1) * p->R + p->K;
 
   // bounds of the integer offset o = floor(-Dl): |Dl| <= fs |p_m| / c (|u| = 1)
-  double bmax = 0.0;
-  for (int m = 0; m < p->M; ++m) {
-    const double* q = d.mic_pos + 3 * m;
-    bmax = std::fmax(bmax, std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * p->fs / p->c);
-  }
-  bmax = bmax * (1.0 + 1e-9) + 1e-9;
-  p->omin = static_cast<int>(std::floor(-bmax)) - 1;
-  p->omax = static_cast<int>(std::floor(bmax)) + 1;
+  const double bmax = delay_bound(d.mic_pos, p->M, p->fs, p->c);
+  // DELAY_MARGIN extra samples on each side let sonar_plan_set_positions move the microphones
+  p->omin = static_cast<int>(std::floor(-bmax)) - DELAY_MARGIN;
+  p->omax = static_cast<int>(std::floor(bmax)) + DELAY_MARGIN;
   p->spread = p->omax - p->omin;
 
   // time-domain tiling
@@ -815,6 +825,69 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   *out = best;
   if (chosen_mode) *chosen_mode = best_mode;
   return SONAR_OK;
+}
+
+
+int sonar_plan_enable_gradients(sonar_plan p) {
+  if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
+  const bool td = is_td(p);
+  if (!td && p->NF > (1 << 14))
+    return fail(SONAR_E_UNSUPPORTED, "frequency-domain gradients: FFT length %d above 32768 is not supported", p->P);
+  if (p->grad_on) return SONAR_OK;
+  const size_t mf = static_cast<size_t>(p->max_frames);
+  size_t total = 0;
+  bool ok = dev_alloc(&p->d_gdl, mf * p->D * p->M, &total) == hipSuccess &&
+            dev_alloc(&p->d_gscr, mf * (td ? p->M : p->D) * 2 * static_cast<size_t>(p->NF), &total) == hipSuccess;
+  if (ok && !td)
+    ok = dev_alloc(&p->d_gband, mf * p->D * p->kb, &total) == hipSuccess &&
+         dev_alloc(&p->d_gspec, mf * p->M * (static_cast<size_t>(p->NF) + 1), &total) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    (void)hipFree(p->d_gdl);
+    (void)hipFree(p->d_gscr);
+    (void)hipFree(p->d_gband);
+    (void)hipFree(p->d_gspec);
+    p->d_gdl = nullptr;
+    p->d_gscr = nullptr;
+    p->d_gband = nullptr;
+    p->d_gspec = nullptr;
+    return fail(SONAR_E_NOMEM, "gradient workspace allocation (%zu bytes) failed", total);
+  }
+  p->ws_bytes += total;
+  p->grad_on = true;
+  return SONAR_OK;
+}
+
+int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, const float* dE, int32_t F,
+                          void* dyhat_out, float* dx_out, double* dpos_out, hipStream_t stream) {
+  int st = check_exec(p, mf_in, dE, F);
+  if (st != SONAR_OK) return st;
+  if (!beam_inout) return fail(SONAR_E_INVALID, "beam_inout is NULL");
+  if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
+  if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
+  if (dx_out && p->NF > (1 << 14))
+    return fail(SONAR_E_UNSUPPORTED, "dx_out: FFT length %d above 32768 is not supported for gradients", p->P);
+  const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),
+                                              dE, F, static_cast<float2*>(dyhat_out), dx_out, dpos_out, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "gradient launch");
+}
+
+int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t stream) {
+  if (!p || !mic_pos) return fail(SONAR_E_INVALID, "plan and mic_pos must not be NULL");
+  if (p->bf_mode == SONAR_BF_TD_BF16)
+    return fail(SONAR_E_UNSUPPORTED, "TD_BF16 tiles are built for one geometry: create a new plan");
+  for (int i = 0; i < 3 * p->M; ++i)
+    if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
+  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+    const double bmax = delay_bound(mic_pos, p->M, p->fs, p->c);
+    if (static_cast<int>(std::floor(-bmax)) < p->omin || static_cast<int>(std::floor(bmax)) + 1 > p->omax)
+      return fail(SONAR_E_UNSUPPORTED, "new positions need delays beyond the plan's range [%d, %d]: create a new plan",
+                  p->omin, p->omax);
+  }
+  hipError_t e = hipMemcpyAsync(p->d_pos, mic_pos, 3 * sizeof(double) * p->M, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = launch_delay_tables(p, stream);
+  if (e == hipSuccess && !is_td(p)) e = launch_fd_step_table(p, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "position update");
 }
 
 }  // extern "C"

@@ -130,6 +130,9 @@ def test_null_arguments_rejected():
     assert lib.sonar_plan_query(None, 0, ctypes.byref(v)) == binding.SONAR_E_INVALID
     assert lib.sonar_energyscape_batch(None, None, 1, None, None) == binding.SONAR_E_INVALID
     assert lib.sonar_plan_destroy(None) == 0
+    assert lib.sonar_plan_enable_gradients(None) == binding.SONAR_E_INVALID
+    assert lib.sonar_energyscape_vjp(None, None, None, None, 1, None, None, None, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_plan_set_positions(None, None, None) == binding.SONAR_E_INVALID
 
 
 def test_product_path_does_not_import_the_oracle():
