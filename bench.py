@@ -22,6 +22,7 @@ itself on the host.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -251,6 +252,46 @@ def network_path(args, stream):
             "shapes": [[int(w.x.shape[2]), int(w.dirs.shape[0])] for w in net]}
 
 
+def adjoint_path(args, stream):
+    """One self-calibration step on the 32 mic x 16384 sample x 1500 direction x 10 frame workload
+    (exact-phase plan): new positions, beamform + envelope, and dL/dp through sonar_energyscape_vjp."""
+    import torch
+
+    from paper_2208_10839_amd import binding
+    from workloads import synth
+    w = synth.make_calibration()
+    F = w.x.shape[0]
+    plan = binding.Plan(w.start_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.band,
+                        decim=w.decim, mode="fd_fp32", max_frames=F)
+    x = torch.from_numpy(w.x).cuda()
+    mf = plan.matched_filter(x)
+    beam = plan.beamform(mf)
+    E = plan.envelope(beam)
+    dE = torch.zeros_like(E)
+    for f, fc in enumerate(w.cells):
+        for d, q in fc:
+            dE[f, d, q] = -1.0
+    dpos = torch.empty((plan.M, 3), dtype=torch.float64, device="cuda")
+    lib = binding.load()
+    sh = binding._stream_handle(stream)
+    pos = np.ascontiguousarray(w.start_pos)
+    plan.enable_gradients()
+
+    def step():
+        binding._check(lib.sonar_plan_set_positions(plan._h, binding._ptr(pos), sh), "set_positions")
+        plan.beamform(mf, out=beam)
+        plan.envelope(beam, out=E)
+        binding._check(lib.sonar_energyscape_vjp(plan._h, ctypes.c_void_p(mf.data_ptr()),
+                                                 ctypes.c_void_p(beam.data_ptr()), ctypes.c_void_p(dE.data_ptr()),
+                                                 F, None, None, ctypes.c_void_p(dpos.data_ptr()), sh), "vjp")
+    for _ in range(2):
+        step()
+    ms = time_calls(step, args.steps, stream)
+    plan.close()
+    return {"what": "set_positions + beamform + envelope + dL/dp (FD exact-phase, FP32), 10 frames",
+            "value": round(F / (ms / 1e3), 2), "unit": "frames/s", "ms_per_step": round(ms, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +319,8 @@ def main():
     plain = plain_path(w, x, args, stream)
     print("[bench] sensor network batch", file=sys.stderr, flush=True)
     network = network_path(args, stream)
+    print("[bench] self-calibration step (adjoint)", file=sys.stderr, flush=True)
+    adjoint = adjoint_path(args, stream)
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 1024 * 1024 // 4
@@ -310,6 +353,7 @@ def main():
         "paths": results,
         "plain_single_sensor_gpu_path": plain,
         "sensor_network_batch": network,
+        "self_calibration_step": adjoint,
     }
     print(json.dumps(out), flush=True)
 

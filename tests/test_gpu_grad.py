@@ -165,6 +165,26 @@ def test_set_positions_matches_a_new_plan(gpu, torch_mod, mode):
         plan.set_positions(w.mic_pos * 4.0)       # exact phases: any geometry
 
 
+def test_autograd_function_matches_vjp(gpu, torch_mod):
+    """Energyscape.apply: backward gives the sonar_energyscape_vjp results for x and positions."""
+    torch = torch_mod
+    w = synth.make_workload("c1", n_dirs=23)
+    _say("case autograd: c1 D=23, fd_fp32")
+    plan = _plan(gpu, w, "fd")
+    x = torch.from_numpy(w.x).cuda().requires_grad_(True)
+    pos = torch.from_numpy(w.mic_pos.copy()).requires_grad_(True)
+    wts = torch.from_numpy(np.random.default_rng(np.random.SeedSequence([4, 0, 0, 8]))
+                           .standard_normal((1, plan.D, plan.Q)).astype(np.float32)).cuda()
+    E = gpu.Energyscape.apply(x, pos, plan)
+    (E * wts).sum().backward()
+    mf = plan.matched_filter(x.detach())
+    beam = plan.beamform(mf)
+    _, dx, dpos = plan.vjp(mf, beam, wts)
+    torch.cuda.synchronize()
+    assert torch.equal(x.grad, dx)
+    assert np.array_equal(pos.grad.numpy(), dpos)
+
+
 def _cal_loss_grad(plan, mf, cells, torch):
     """L = -sum of E at the reflector cells, and dL/dp from sonar_energyscape_vjp."""
     beam = plan.beamform(mf)
