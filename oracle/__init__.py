@@ -30,5 +30,8 @@ from .sonar_oracle import (  # noqa: F401
     matched_filter_spectrum_vjp,
     matched_filter_vjp,
     num_range_bins,
+    pdm_default_taps,
+    pdm_demodulate,
+    pdm_unpack,
     td_offsets,
 )

@@ -258,6 +258,57 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
 
 
 # ---------------------------------------------------------------------------
+# PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density
+# modulation; §4.3: on the GPU the binary data are unpacked, demodulated with a
+# low-pass filter and subsampled before the matched filter).  The paper gives
+# neither the PDM clock, the bit packing nor the filter; the readings taken:
+# ceil(M/32) 32-bit words per PDM tick, microphone m in bit m % 32 of word
+# m // 32 (set = +1, clear = -1); a zero-phase FIR low-pass at the PDM rate
+# evaluated at every decim-th tick.
+# ---------------------------------------------------------------------------
+
+def pdm_default_taps(decim: int, K: int | None = None) -> np.ndarray:
+    """Hamming-windowed sinc, K = 32 decim + 1 taps, cutoff a quarter of the output rate
+    (1/(4 decim) of the PDM rate), normalised to unit DC gain."""
+    K = 32 * decim + 1 if K is None else int(K)
+    j = np.arange(K, dtype=np.float64)
+    hk = (K - 1) / 2.0
+    w = 0.54 - 0.46 * np.cos(2.0 * np.pi * j / (K - 1))
+    h = w * np.sinc((j - hk) / (2.0 * decim))
+    return h / np.sum(h)
+
+
+def pdm_unpack(words, M: int) -> np.ndarray:
+    """s[m][t] in {-1, +1} from words [T][ceil(M/32)] uint32."""
+    words = np.asarray(words, dtype=np.uint32)
+    s = np.empty((M, words.shape[0]))
+    for m in range(M):
+        bit = (words[:, m // 32] >> np.uint32(m % 32)) & np.uint32(1)
+        s[m] = np.where(bit == 1, 1.0, -1.0)
+    return s
+
+
+def pdm_demodulate(words, M: int, N: int, decim: int, taps) -> np.ndarray:
+    """x[m][n] = sum_{j<K} h[j] s_m[n decim + (K-1)/2 - j] with s = 0 outside the T recorded
+    ticks: the zero-phase low-pass (group delay removed) evaluated only where the
+    subsampler keeps it.  Returns float64 [M][N]."""
+    s = pdm_unpack(words, M)
+    T = s.shape[1]
+    h = np.asarray(taps, dtype=np.float64)
+    K = h.size
+    if K % 2 == 0:
+        raise ValueError("PDM filter length must be odd")
+    hk = (K - 1) // 2
+    x = np.zeros((M, N))
+    n = np.arange(N)
+    for j in range(K):
+        t = n * decim + hk - j
+        ok = (t >= 0) & (t < T)
+        x[:, ok] += h[j] * s[:, t[ok]]
+    return x
+
+
+# ---------------------------------------------------------------------------
 # Reverse-mode derivatives of the time-domain pipeline (the adjoint used for
 # array self-calibration).  For a real loss L of the energyscape, dE = dL/dE.
 # Complex quantities z carry the gradient G_z = dL/dRe z + i dL/dIm z, so that
