@@ -292,6 +292,42 @@ def adjoint_path(args, stream):
             "value": round(F / (ms / 1e3), 2), "unit": "frames/s", "ms_per_step": round(ms, 4)}
 
 
+def pdm_path(args, stream, x_shape):
+    """The PDM front end on the headline batch: 16 frames x 32 mics x 16384 samples x 10 ticks of packed
+    1-bit words -> FP32 samples (sonar_pdm_demodulate), alone and followed by the headline energyscape."""
+    import torch
+
+    from paper_2208_10839_amd import binding
+    from workloads import synth
+    F, M, N = x_shape
+    D = 10
+    rng = np.random.default_rng(np.random.SeedSequence([7, 9, 9, 9]))
+    words = torch.from_numpy(rng.integers(0, 2**32, size=(F, N * D, 1), dtype=np.uint64)
+                             .astype(np.uint32).view(np.int32)).cuda()
+    dem = binding.Pdm(M, N, D, max_frames=F)
+    x = dem.demodulate(words)
+    ms = time_calls(lambda: dem.demodulate(words, out=x), args.steps, stream)
+    w = synth.make_workload("c2", frames=1)
+    plan = binding.Plan(w.mic_pos, w.chirp, w.dirs, N, fs=w.fs, c=w.c, band=w.cfg.band, decim=w.cfg.decim,
+                        mode="td_bf16", max_frames=F)
+    E = torch.empty((F, w.dirs.shape[0], plan.Q), dtype=torch.float32, device="cuda")
+
+    def step():
+        dem.demodulate(words, out=x)
+        plan.energyscape(x, out=E)
+    for _ in range(2):
+        step()
+    ms_e2e = time_calls(step, args.steps, stream)
+    algo_bytes = F * N * D * 4 + F * M * N * 4
+    dem.close()
+    plan.close()
+    return {"what": "sonar_pdm_demodulate: 16 frames x 32 mics x 16384 samples x 10 PDM ticks, 321-tap FIR",
+            "ms_per_call": round(ms, 4), "achieved_GBps": round(algo_bytes / (ms / 1e3) / 1e9, 1),
+            "algorithmic_bytes": algo_bytes,
+            "end_to_end_from_pdm": {"value": round(F / (ms_e2e / 1e3), 2), "unit": "energyscapes/s",
+                                    "ms_per_step": round(ms_e2e, 4), "mode": "td_bf16"}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -321,6 +357,8 @@ def main():
     network = network_path(args, stream)
     print("[bench] self-calibration step (adjoint)", file=sys.stderr, flush=True)
     adjoint = adjoint_path(args, stream)
+    print("[bench] PDM front end", file=sys.stderr, flush=True)
+    pdm_fe = pdm_path(args, stream, tuple(x.shape))
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 1024 * 1024 // 4
@@ -354,6 +392,7 @@ def main():
         "plain_single_sensor_gpu_path": plain,
         "sensor_network_batch": network,
         "self_calibration_step": adjoint,
+        "pdm_front_end": pdm_fe,
     }
     print(json.dumps(out), flush=True)
 

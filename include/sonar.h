@@ -297,6 +297,42 @@ int sonar_energyscape_vjp(sonar_plan plan, const void* mf_in, void* beam_inout, 
  */
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
 
+/*
+ * PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density
+ * modulation; §4.3: the binary data are unpacked, demodulated by a low-pass
+ * filter and subsampled before the matched filter):
+ *   x[m][n] = sum_{j<K} h[j] s_m[n D + (K-1)/2 - j],  n < N,
+ * with s_m[t] = +1 (bit set) or -1 (bit clear) for the T = N D recorded ticks and
+ * 0 outside them: a zero-phase FIR low-pass at the PDM rate evaluated at every
+ * D-th tick.  Packing: each tick is W = ceil(M/32) little-endian 32-bit words,
+ * microphone m in bit m % 32 of word m / 32.
+ */
+typedef struct sonar_pdm_s* sonar_pdm;
+
+typedef struct {
+  int32_t n_mics;          /* M, 1 <= M <= 128                                            */
+  int32_t n_out;           /* N >= 1 output samples per microphone                        */
+  int32_t decim;           /* D >= 1 PDM ticks per output sample (10: 4.5 MHz -> 450 kHz)  */
+  int32_t n_taps;          /* K, odd, <= 513; 0 selects the default                       */
+  const double* taps;      /* [K] host taps h, or NULL for the default: Hamming-windowed   */
+                           /* sinc, K = 32 D + 1, cutoff 1/(4 D) of the PDM rate, unit DC  */
+                           /* gain (passband flat to 0.05 dB below 85 kHz at D = 10)       */
+  int32_t max_frames;      /* F per call, >= 1                                             */
+} sonar_pdm_desc;
+
+/* sonar_pdm_create -- builds the filter's tables on the current device (on
+ * `stream`, synchronised before returning).  SONAR_E_UNSUPPORTED when the
+ * staging of one workgroup would not fit in LDS (very large D or K). */
+int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* out);
+int sonar_pdm_destroy(sonar_pdm pdm);
+
+/*
+ * sonar_pdm_demodulate -- F frames: words [F][N D][W] uint32 (device) ->
+ * x [F][M][N] float (device), the sample layout sonar_matched_filter and
+ * sonar_energyscape_batch take with SONAR_DTYPE_F32.  Enqueues one kernel.
+ */
+int sonar_pdm_demodulate(sonar_pdm pdm, const uint32_t* words, int32_t F, float* x, hipStream_t stream);
+
 /* Static text for a status code. */
 const char* sonar_status_string(int status);
 

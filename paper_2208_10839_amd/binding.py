@@ -50,6 +50,14 @@ class PlanDesc(ctypes.Structure):
     ]
 
 
+class PdmDesc(ctypes.Structure):
+    """Mirror of sonar_pdm_desc."""
+    _fields_ = [
+        ("n_mics", ctypes.c_int32), ("n_out", ctypes.c_int32), ("decim", ctypes.c_int32),
+        ("n_taps", ctypes.c_int32), ("taps", _dp), ("max_frames", ctypes.c_int32),
+    ]
+
+
 _lib = None
 
 # name -> (restype, argtypes); every function declared in include/sonar.h
@@ -72,6 +80,10 @@ _SIGNATURES = {
                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
     "sonar_plan_set_positions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_pdm_create": (ctypes.c_int, [ctypes.POINTER(PdmDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "sonar_pdm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "sonar_pdm_demodulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "sonar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sonar_last_error": (ctypes.c_char_p, []),
 }
@@ -311,6 +323,53 @@ class Plan:
                                               ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
                "sonar_beamform_envelope")
         return E
+
+
+class Pdm:
+    """PDM front end: packed 1-bit words [F][N*decim][ceil(M/32)] (uint32 viewed as int32 in torch)
+    -> samples [F][M][N] float32 on the device (sonar_pdm_demodulate)."""
+
+    def __init__(self, n_mics: int, n_out: int, decim: int = 10, taps=None, max_frames: int = 1, stream=None):
+        d = PdmDesc()
+        d.n_mics, d.n_out, d.decim, d.max_frames = int(n_mics), int(n_out), int(decim), int(max_frames)
+        self._keep = None
+        if taps is None:
+            d.n_taps, d.taps = 0, None
+        else:
+            self._keep = _f64(taps)
+            d.n_taps, d.taps = self._keep.size, _ptr(self._keep)
+        h = ctypes.c_void_p()
+        _check(load().sonar_pdm_create(ctypes.byref(d), _stream_handle(stream), ctypes.byref(h)), "sonar_pdm_create")
+        self._h = h
+        self.M, self.N, self.decim, self.max_frames = d.n_mics, d.n_out, d.decim, d.max_frames
+        self.W = (self.M + 31) // 32
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().sonar_pdm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def demodulate(self, words, out=None, stream=None):
+        import torch
+        if not isinstance(words, torch.Tensor) or not words.is_cuda or not words.is_contiguous():
+            raise TypeError("words must be a contiguous CUDA tensor")
+        if words.dtype not in (torch.int32, torch.uint32):
+            raise TypeError("words must hold 32-bit words (int32 or uint32)")
+        if tuple(words.shape[1:]) != (self.N * self.decim, self.W):
+            raise ValueError(f"words must have shape [F][{self.N * self.decim}][{self.W}], got {list(words.shape)}")
+        F = words.shape[0]
+        x = torch.empty((F, self.M, self.N), dtype=torch.float32, device=words.device) if out is None else out
+        if tuple(x.shape) != (F, self.M, self.N) or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("out must be a contiguous float32 tensor [F][M][N]")
+        _check(load().sonar_pdm_demodulate(self._h, ctypes.c_void_p(words.data_ptr()), F, ctypes.c_void_p(x.data_ptr()),
+                                           _stream_handle(stream)), "sonar_pdm_demodulate")
+        return x
 
 
 class Energyscape:

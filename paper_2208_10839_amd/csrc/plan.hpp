@@ -94,6 +94,26 @@ struct sonar_plan_s {
   bool grad_on = false;
 };
 
+// PDM front end (k_pdm.hip): PDM_THREADS threads per workgroup, each workgroup makes
+// NB outputs of every microphone of one frame
+constexpr int PDM_THREADS = 256;
+constexpr int PDM_MAX_MICS = 128;
+constexpr int PDM_MAX_TAPS = 513;
+constexpr size_t PDM_LDS_LIMIT = 150 * 1024;
+
+struct sonar_pdm_s {
+  int M = 0, N = 0, D = 1, K = 0, C = 0, W = 1, max_frames = 1, device = 0;
+  int NB = 0, SW = 0;          // outputs per workgroup, staged words per microphone
+  float* d_lut = nullptr;      // [C][256] byte tables of the reversed taps
+  float* d_grev = nullptr;     // [K] reversed taps, FP32 (windows at the recording's edges)
+};
+
+int pdm_span_words(int NB, int D, int K);
+size_t pdm_lds_bytes(int M, int SW, int C);
+hipError_t launch_pdm_tables(sonar_pdm_s* p, const double* d_taps64, hipStream_t s);
+hipError_t init_pdm_kernel_attributes(size_t lds);
+hipError_t launch_pdm_demod(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s);
+
 // FFT twiddle table layout inside d_tw (all FP32 values built from FP64):
 //   [0, nhi)              : exp(-2 pi i * 64 * t / NF)   t < nhi = max(NF/64, 1)
 //   [nhi, nhi+64)         : exp(-2 pi i * t / NF)        t < 64

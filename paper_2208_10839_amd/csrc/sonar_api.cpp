@@ -890,4 +890,99 @@ int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t st
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "position update");
 }
 
+int sonar_pdm_destroy(sonar_pdm p) {
+  if (!p) return SONAR_OK;
+  (void)hipFree(p->d_lut);
+  (void)hipFree(p->d_grev);
+  delete p;
+  return SONAR_OK;
+}
+
+int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* out) {
+  if (!desc || !out) return fail(SONAR_E_INVALID, "desc and out must not be NULL");
+  *out = nullptr;
+  const sonar_pdm_desc& d = *desc;
+  if (d.n_mics < 1 || d.n_mics > PDM_MAX_MICS) return fail(SONAR_E_INVALID, "n_mics=%d outside [1, %d]", d.n_mics, PDM_MAX_MICS);
+  if (d.n_out < 1 || d.decim < 1 || d.max_frames < 1) return fail(SONAR_E_INVALID, "n_out, decim and max_frames must be >= 1");
+  if (static_cast<long long>(d.n_out) * d.decim > (1LL << 31) / 4)
+    return fail(SONAR_E_UNSUPPORTED, "n_out * decim = %lld ticks is above the supported 2^29", static_cast<long long>(d.n_out) * d.decim);
+  std::vector<double> taps;
+  if (d.n_taps == 0 && !d.taps) {
+    const int K = 32 * d.decim + 1;
+    taps.resize(K);
+    const double hk = 0.5 * (K - 1);
+    double sum = 0.0;
+    for (int j = 0; j < K; ++j) {
+      const double w = 0.54 - 0.46 * std::cos(2.0 * M_PI * j / (K - 1));
+      const double arg = (j - hk) / (2.0 * d.decim);
+      const double sinc = arg == 0.0 ? 1.0 : std::sin(M_PI * arg) / (M_PI * arg);
+      taps[j] = w * sinc;
+      sum += taps[j];
+    }
+    for (double& v : taps) v /= sum;
+  } else {
+    if (!d.taps || d.n_taps < 1) return fail(SONAR_E_INVALID, "n_taps > 0 needs taps (or n_taps = 0 and taps = NULL)");
+    taps.assign(d.taps, d.taps + d.n_taps);
+  }
+  const int K = static_cast<int>(taps.size());
+  if (K % 2 == 0) return fail(SONAR_E_INVALID, "the PDM filter length must be odd (zero phase), got %d", K);
+  if (K > PDM_MAX_TAPS) return fail(SONAR_E_UNSUPPORTED, "PDM filter length %d above %d", K, PDM_MAX_TAPS);
+  for (double v : taps)
+    if (!std::isfinite(v)) return fail(SONAR_E_INVALID, "PDM taps must be finite");
+
+  auto* p = new sonar_pdm_s();
+  p->M = d.n_mics;
+  p->N = d.n_out;
+  p->D = d.decim;
+  p->K = K;
+  p->C = (K + 7) / 8;
+  p->W = (d.n_mics + 31) / 32;
+  p->max_frames = d.max_frames;
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(SONAR_E_HIP, "hipGetDevice failed");
+  }
+  for (int nb = 256; nb >= 64; nb /= 2) {
+    const int sw = pdm_span_words(nb, p->D, K);
+    if (pdm_lds_bytes(p->M, sw, p->C) <= PDM_LDS_LIMIT) {
+      p->NB = nb;
+      p->SW = sw;
+      break;
+    }
+  }
+  if (p->NB == 0) {
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "decim=%d with %d taps needs more LDS than a workgroup has", d.decim, K);
+  }
+  size_t total = 0;
+  double* d_taps64 = nullptr;
+  bool ok = dev_alloc(&p->d_lut, static_cast<size_t>(p->C) * 256, &total) == hipSuccess &&
+            dev_alloc(&p->d_grev, static_cast<size_t>(K), &total) == hipSuccess &&
+            hipMalloc(&d_taps64, sizeof(double) * K) == hipSuccess;
+  hipError_t e = ok ? hipMemcpyAsync(d_taps64, taps.data(), sizeof(double) * K, hipMemcpyHostToDevice, stream)
+                    : hipErrorOutOfMemory;
+  if (e == hipSuccess) e = launch_pdm_tables(p, d_taps64, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess) e = init_pdm_kernel_attributes(pdm_lds_bytes(p->M, p->SW, p->C));
+  (void)hipFree(d_taps64);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    sonar_pdm_destroy(p);
+    return e == hipErrorOutOfMemory ? fail(SONAR_E_NOMEM, "PDM tables allocation failed") : hip_fail(e, "PDM tables");
+  }
+  *out = p;
+  return SONAR_OK;
+}
+
+int sonar_pdm_demodulate(sonar_pdm p, const uint32_t* words, int32_t F, float* x, hipStream_t stream) {
+  if (!p) return fail(SONAR_E_INVALID, "pdm is NULL");
+  if (!words || !x) return fail(SONAR_E_INVALID, "NULL buffer");
+  if (F < 1 || F > p->max_frames) return fail(SONAR_E_INVALID, "F=%d outside [1, max_frames=%d]", F, p->max_frames);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+    return fail(SONAR_E_INVALID, "current device %d is not the device %d the PDM filter was created on", dev, p->device);
+  const hipError_t e = launch_pdm_demod(p, words, F, x, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "PDM demodulation launch");
+}
+
 }  // extern "C"

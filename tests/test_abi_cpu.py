@@ -133,6 +133,28 @@ def test_null_arguments_rejected():
     assert lib.sonar_plan_enable_gradients(None) == binding.SONAR_E_INVALID
     assert lib.sonar_energyscape_vjp(None, None, None, None, 1, None, None, None, None) == binding.SONAR_E_INVALID
     assert lib.sonar_plan_set_positions(None, None, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_pdm_create(None, None, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_pdm_demodulate(None, None, 1, None, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_pdm_destroy(None) == binding.SONAR_OK
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("n_mics", 0, -1), ("n_mics", 129, -1), ("n_out", 0, -1), ("decim", 0, -1), ("max_frames", 0, -1),
+    ("n_taps", 4, -1),            # even length: not zero-phase
+    ("n_taps", 515, -4),          # above the supported length
+])
+def test_bad_pdm_descriptor_rejected_on_host(field, value, status):
+    lib = binding.load()
+    d = binding.PdmDesc(n_mics=32, n_out=1024, decim=10, n_taps=0, taps=None, max_frames=1)
+    keep = None
+    if field == "n_taps":
+        keep = np.ones(value)
+        d.n_taps, d.taps = value, keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    else:
+        setattr(d, field, value)
+    h = ctypes.c_void_p()
+    assert lib.sonar_pdm_create(ctypes.byref(d), None, ctypes.byref(h)) == status
+    assert h.value is None
 
 
 def test_product_path_does_not_import_the_oracle():
