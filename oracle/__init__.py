@@ -16,6 +16,7 @@ from .sonar_oracle import (  # noqa: F401
     das_fd,
     das_fd_vjp,
     das_td,
+    das_td_nearest,
     das_td_vjp,
     default_lowpass,
     delays,
@@ -29,6 +30,7 @@ from .sonar_oracle import (  # noqa: F401
     matched_filter_spectrum,
     matched_filter_spectrum_vjp,
     matched_filter_vjp,
+    nearest_offsets,
     num_range_bins,
     pdm_default_taps,
     pdm_demodulate,

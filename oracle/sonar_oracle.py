@@ -147,6 +147,27 @@ def das_td(yhat, Dl, n_idx) -> np.ndarray:
     return b
 
 
+def nearest_offsets(Dl):
+    """Integer delay: the delay rounded to the nearest sample, ties toward the later sample
+    (o = floor(-Dl + 1/2))."""
+    return np.floor(-np.asarray(Dl, dtype=np.float64) + 0.5).astype(np.int64)
+
+
+def das_td_nearest(yhat, Dl, n_idx) -> np.ndarray:
+    """Integer-delay DAS (the plainest reading of "simple delay-and-sum"), circular in P:
+    b_d[n] = (1/M) sum_m yhat_m[(n + o) mod P], o = nearest_offsets(Dl).  Complex128 [D][len(n_idx)]."""
+    yhat = np.asarray(yhat)
+    M, P = yhat.shape
+    o = nearest_offsets(Dl)
+    n_idx = np.asarray(n_idx, dtype=np.int64)
+    b = np.zeros((o.shape[0], n_idx.size), dtype=np.complex128)
+    for d in range(o.shape[0]):
+        for m in range(M):
+            b[d] += yhat[m, np.mod(n_idx + o[d, m], P)]
+        b[d] /= M
+    return b
+
+
 def das_fd(Yspec, Dl, n_idx) -> np.ndarray:
     """Exact fractional-delay DAS by per-bin phase steering, circular in P.
 
@@ -224,7 +245,8 @@ def envelope(b_win, taps, Q: int, R: int) -> np.ndarray:
 def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None = None,
                 gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
                 dir_index=None, return_beam: bool = False):
-    """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation) or 'fd' (exact).
+    """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation), 'td_nearest' (integer
+    delays) or 'fd' (exact).
 
     dir_index selects a subset of directions (rows of the result follow it).
     With return_beam, also returns the complex beam window b[d][G'].
@@ -249,10 +271,12 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
     n_idx = beam_window_indices(n0, Q, R, K)
     if mode == "td":
         b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
+    elif mode == "td_nearest":
+        b = das_td_nearest(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
     elif mode == "fd":
         b = das_fd(matched_filter_spectrum(x, chirp, P, fs, band), Dl, n_idx)
     else:
-        raise ValueError("mode must be 'td' or 'fd'")
+        raise ValueError("mode must be 'td', 'td_nearest' or 'fd'")
     E = envelope(b, h, Q, R)
     return (E, b) if return_beam else E
 

@@ -1,0 +1,39 @@
+"""Pins of the oracle's variant readings (CPU): integer-delay delay-and-sum."""
+
+import numpy as np
+
+import oracle as O
+
+
+def test_nearest_offsets_follow_the_stated_rounding():
+    """The delay rounded to the nearest sample with ties toward the later sample: beamforming reads
+    channel m at n + o, o = -round(Dl), so a tie Dl = k + 1/2 reads sample n - k."""
+    cases = [(-2.5, 3), (2.5, -2), (0.49, 0), (0.51, -1), (-0.49, 0), (-0.51, 1), (3.0, -3), (-3.0, 3)]
+    for dl, o in cases:
+        assert int(O.nearest_offsets(np.array([[dl]]))[0, 0]) == o, (dl, o)
+
+
+def test_nearest_equals_linear_and_exact_at_integer_delays():
+    rng = np.random.default_rng(21)
+    M, P, D = 4, 128, 5
+    Y = np.zeros((M, P), dtype=np.complex128)
+    Y[:, :P // 2 + 1] = rng.standard_normal((M, P // 2 + 1)) + 1j * rng.standard_normal((M, P // 2 + 1))
+    y = np.fft.ifft(Y, axis=1)
+    Dl = rng.integers(-6, 7, size=(D, M)).astype(np.float64)
+    n_idx = np.arange(-10, 90)
+    bn = O.das_td_nearest(y, Dl, n_idx)
+    assert np.allclose(bn, O.das_td(y, Dl, n_idx), rtol=0, atol=1e-14)
+    assert np.allclose(bn, O.das_fd(Y, Dl, n_idx), rtol=0, atol=1e-12)
+
+
+def test_nearest_moves_an_impulse_by_the_rounded_delay():
+    """One channel holding a unit impulse at sample s: the beam has 1/M at n = s - o only."""
+    M, P = 3, 64
+    y = np.zeros((M, P), dtype=np.complex128)
+    y[1, 20] = 1.0
+    Dl = np.array([[0.0, 2.4, 0.0], [0.0, -3.6, 0.0]])     # channel 1: o = -2 and o = 4
+    b = O.das_td_nearest(y, Dl, np.arange(P))
+    for d, o in enumerate((-2, 4)):
+        expect = np.zeros(P)
+        expect[20 - o] = 1.0 / M
+        assert np.array_equal(b[d], expect.astype(np.complex128))
