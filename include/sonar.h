@@ -65,10 +65,14 @@ enum sonar_status {
  *              with a Hankel matrix of samples; weights and samples are each
  *              split into two BF16 terms (hi + lo), three products.  Only the
  *              fused beamformer + envelope runs on MFMA; sonar_beamform in
- *              this mode returns the FP32 beam.                                 */
+ *              this mode returns the FP32 beam.
+ *  TD_NEAREST: integer delays (the delay rounded to the nearest sample, ties
+ *              toward the later sample): o = floor(-Dl + 1/2),
+ *              b_d[n] = (1/M) sum_m yhat_m[(n + o) mod P]; FP32, same kernels
+ *              and buffers as TD_LINEAR with the second weight zero.          */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
-  SONAR_BF_TD_BF16 = 4
+  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5
 };
 
 /* Element type of the microphone samples x. */
@@ -296,6 +300,8 @@ int sonar_energyscape_vjp(sonar_plan plan, const void* mf_in, void* beam_inout, 
  * created with).
  */
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
+/* (TD_NEAREST plans move like TD_LINEAR ones; their dL/dp is zero almost everywhere, so
+ * sonar_energyscape_vjp returns SONAR_E_UNSUPPORTED for dpos_out on them.) */
 
 /*
  * PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density

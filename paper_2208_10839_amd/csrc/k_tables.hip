@@ -4,7 +4,8 @@
 //
 //  * delays      Dl[d][m] = fs (p_m . u_d) / c, and for the time-domain
 //                beamformer o = floor(-Dl), alpha = -Dl - o, stored as
-//                {o - omin, (1-alpha)/M, alpha/M};
+//                {o - omin, (1-alpha)/M, alpha/M} (integer delays: o = floor(-Dl + 1/2),
+//                alpha = 0);
 //  * chirp       C[k] = beta[k] W[k] conj(S[k]), S[k] = sum_l s[l] exp(-2 pi i k l/P),
 //                with the phase index k l reduced mod P exactly in integers;
 //  * twiddles    FFT tables (layout in plan.hpp), exp(-2 pi i e / NF) and
@@ -17,15 +18,15 @@
 namespace {
 
 __global__ void delay_table_kernel(const double* __restrict__ pos, const double* __restrict__ dirs,
-                                   int M, int D, double fs, double c, int omin, int spread,
+                                   int M, int D, double fs, double c, int omin, int spread, int nearest,
                                    int4* __restrict__ dtab, double* __restrict__ dl) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= static_cast<long long>(D) * M) return;
   const int d = static_cast<int>(i / M), m = static_cast<int>(i % M);
   const double pu = pos[3 * m] * dirs[3 * d] + pos[3 * m + 1] * dirs[3 * d + 1] + pos[3 * m + 2] * dirs[3 * d + 2];
   const double Dl = fs * pu / c;
-  const double o = floor(-Dl);
-  const double a = -Dl - o;
+  const double o = nearest ? floor(-Dl + 0.5) : floor(-Dl);
+  const double a = nearest ? 0.0 : -Dl - o;
   int rel = static_cast<int>(o) - omin;
   rel = rel < 0 ? 0 : (rel > spread ? spread : rel);
   const float w0 = static_cast<float>((1.0 - a) / M);
@@ -124,7 +125,8 @@ hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s) {
 hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;
   hipLaunchKernelGGL(delay_table_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s,
-                     p->d_pos, p->d_dirs, p->M, p->D, p->fs, p->c, p->omin, p->spread, p->d_dtab, p->d_dl);
+                     p->d_pos, p->d_dirs, p->M, p->D, p->fs, p->c, p->omin, p->spread,
+                     p->bf_mode == SONAR_BF_TD_NEAREST ? 1 : 0, p->d_dtab, p->d_dl);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ bool finite_all(const double* v, size_t n) {
 }
 
 bool is_td(const sonar_plan_s* p) {
-  return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16;
+  return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST;
 }
 
 // Coordinates z_d in which distances between directions equal distances between their
@@ -378,7 +378,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_BF16)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -703,7 +703,7 @@ namespace {
 
 // beamformer + envelope from a matched-filter buffer of this plan's layout
 hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hipStream_t s) {
-  if (p->bf_mode == SONAR_BF_TD_LINEAR) return launch_das_td_env(p, mf, F, E, s);
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST) return launch_das_td_env(p, mf, F, E, s);
   if (p->bf_mode == SONAR_BF_TD_BF16) return launch_das_mfma_env(p, mf, F, E, s);
   hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
   if (e != hipSuccess) return e;
@@ -865,6 +865,8 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (!beam_inout) return fail(SONAR_E_INVALID, "beam_inout is NULL");
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
+  if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
+    return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
   if (dx_out && p->NF > (1 << 14))
     return fail(SONAR_E_UNSUPPORTED, "dx_out: FFT length %d above 32768 is not supported for gradients", p->P);
   const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),
@@ -878,9 +880,10 @@ int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t st
     return fail(SONAR_E_UNSUPPORTED, "TD_BF16 tiles are built for one geometry: create a new plan");
   for (int i = 0; i < 3 * p->M; ++i)
     if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
-  if (p->bf_mode == SONAR_BF_TD_LINEAR) {
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST) {
+    // offsets o in [floor(-bmax), floor(bmax) + 1] (nearest rounds up by one at most), read up to o + 1
     const double bmax = delay_bound(mic_pos, p->M, p->fs, p->c);
-    if (static_cast<int>(std::floor(-bmax)) < p->omin || static_cast<int>(std::floor(bmax)) + 1 > p->omax)
+    if (static_cast<int>(std::floor(-bmax)) < p->omin || static_cast<int>(std::floor(bmax)) + 2 > p->omax)
       return fail(SONAR_E_UNSUPPORTED, "new positions need delays beyond the plan's range [%d, %d]: create a new plan",
                   p->omin, p->omax);
   }
