@@ -12,6 +12,7 @@ from .sonar_oracle import (  # noqa: F401
     analytic_weights,
     band_mask,
     beam_window_indices,
+    butterworth_lowpass,
     chirp_spectrum_filter,
     das_fd,
     das_fd_vjp,
@@ -24,7 +25,9 @@ from .sonar_oracle import (  # noqa: F401
     energyscape,
     energyscape_vjp_fd,
     energyscape_vjp_td,
+    lfilter,
     envelope,
+    envelope_iir,
     envelope_vjp,
     matched_filter,
     matched_filter_spectrum,

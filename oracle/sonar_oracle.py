@@ -238,18 +238,72 @@ def envelope(b_win, taps, Q: int, R: int) -> np.ndarray:
     return E
 
 
+# IIR reading of the envelope filter (§4.3: the CPU implementation designs the
+# filters as Butterworth filters and runs them with SciPy's lfilter, i.e. causal,
+# group delay kept).  The IIR runs over the beam window from zero state at its
+# first sample; output q is the filter's value at window position qR + (K-1)/2,
+# the sample n0 + qR of the FIR reading.
+
+def butterworth_lowpass(order: int, fc_over_fs: float):
+    """(b, a) of the digital Butterworth low-pass of the given order with -3 dB at fc:
+    analog prototype poles exp(i pi (2k + order + 1) / (2 order)), k < order, scaled to the
+    prewarped cutoff W = 2 fs tan(pi fc / fs), mapped by the bilinear transform
+    z = (2 fs + s) / (2 fs - s) (all zeros at z = -1); substituting s into W^order / prod(s - p)
+    gives the gain W^order / prod(2 fs - p) of (z + 1)^order / prod(z - z_p) (unit gain at DC); a[0] = 1."""
+    k = np.arange(order)
+    poles_a = np.exp(1j * np.pi * (2 * k + order + 1) / (2 * order))
+    fs = 1.0
+    W = 2.0 * fs * np.tan(np.pi * fc_over_fs / fs)
+    p = W * poles_a
+    z_d = (2 * fs + p) / (2 * fs - p)
+    a = np.real(np.poly(z_d))
+    gain = np.real(W ** order / np.prod(2 * fs - p))
+    b = gain * np.real(np.poly(-np.ones(order)))
+    return b, a
+
+
+def lfilter(b, a, x) -> np.ndarray:
+    """Causal IIR from zero state: a[0] y[n] = sum_k b[k] x[n-k] - sum_{k>=1} a[k] y[n-k]."""
+    b = np.asarray(b, dtype=np.float64)
+    a = np.asarray(a, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.zeros(x.shape[-1])
+    for n in range(x.shape[-1]):
+        acc = 0.0
+        for k in range(b.size):
+            if n - k >= 0:
+                acc += b[k] * x[n - k]
+        for k in range(1, a.size):
+            if n - k >= 0:
+                acc -= a[k] * y[n - k]
+        y[n] = acc / a[0]
+    return y
+
+
+def envelope_iir(b_win, bcoef, acoef, Q: int, R: int, K: int) -> np.ndarray:
+    """E[d][q] = lfilter(bcoef, acoef, |b_d| over the window)[qR + (K-1)/2]."""
+    e = np.abs(np.asarray(b_win))
+    hk = (K - 1) // 2
+    E = np.zeros((e.shape[0], Q))
+    for d in range(e.shape[0]):
+        y = lfilter(bcoef, acoef, e[d])
+        E[d] = y[hk + R * np.arange(Q)]
+    return E
+
+
 # ---------------------------------------------------------------------------
 # Whole pipeline (Fig. 3 order: matched filter, beamformer, envelope).
 # ---------------------------------------------------------------------------
 
 def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None = None,
                 gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
-                dir_index=None, return_beam: bool = False):
+                dir_index=None, return_beam: bool = False, iir=None):
     """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation), 'td_nearest' (integer
     delays) or 'fd' (exact).
 
     dir_index selects a subset of directions (rows of the result follow it).
     With return_beam, also returns the complex beam window b[d][G'].
+    iir = (b, a) selects the IIR envelope reading (envelope_iir) instead of the FIR.
     """
     x = np.asarray(x, dtype=np.float64)
     M, N = x.shape
@@ -277,7 +331,7 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
         b = das_fd(matched_filter_spectrum(x, chirp, P, fs, band), Dl, n_idx)
     else:
         raise ValueError("mode must be 'td', 'td_nearest' or 'fd'")
-    E = envelope(b, h, Q, R)
+    E = envelope(b, h, Q, R) if iir is None else envelope_iir(b, iir[0], iir[1], Q, R, K)
     return (E, b) if return_beam else E
 
 

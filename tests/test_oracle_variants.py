@@ -37,3 +37,39 @@ def test_nearest_moves_an_impulse_by_the_rounded_delay():
         expect = np.zeros(P)
         expect[20 - o] = 1.0 / M
         assert np.array_equal(b[d], expect.astype(np.complex128))
+
+
+def test_butterworth_design_matches_scipy():
+    import scipy.signal as ss
+    for order in (1, 2, 3, 4, 5, 8):
+        for wn in (0.02, 0.1, 0.2, 0.45):
+            b, a = O.butterworth_lowpass(order, wn / 2)          # fc / fs = Wn / 2
+            bs, as_ = ss.butter(order, wn)
+            assert np.allclose(b, bs, rtol=1e-10, atol=1e-15), (order, wn)
+            assert np.allclose(a, as_, rtol=1e-10, atol=1e-13), (order, wn)
+
+
+def test_butterworth_is_minus_3db_at_cutoff():
+    b, a = O.butterworth_lowpass(4, 0.05)
+    z = np.exp(-2j * np.pi * 0.05)
+    H = np.polyval(b[::-1], z) / np.polyval(a[::-1], z)
+    assert abs(abs(H) ** 2 - 0.5) < 1e-12
+    assert abs(np.sum(b) / np.sum(a) - 1.0) < 1e-12
+
+
+def test_lfilter_matches_scipy():
+    import scipy.signal as ss
+    rng = np.random.default_rng(22)
+    b, a = O.butterworth_lowpass(4, 0.05)
+    x = rng.standard_normal(500)
+    assert np.allclose(O.lfilter(b, a, x), ss.lfilter(b, a, x), rtol=1e-10, atol=1e-13)
+    b2, a2 = rng.standard_normal(3), np.array([2.0, -0.5, 0.1])
+    assert np.allclose(O.lfilter(b2, a2, x), ss.lfilter(b2, a2, x), rtol=1e-10, atol=1e-13)
+
+
+def test_envelope_iir_identity_filter_samples_the_magnitude():
+    rng = np.random.default_rng(23)
+    R, Q, K = 4, 9, 9
+    bw = rng.standard_normal((3, (Q - 1) * R + K)) + 1j * rng.standard_normal((3, (Q - 1) * R + K))
+    E = O.envelope_iir(bw, [1.0], [1.0], Q, R, K)
+    assert np.array_equal(E, np.abs(bw)[:, (K - 1) // 2 + R * np.arange(Q)])
