@@ -328,6 +328,27 @@ def pdm_path(args, stream, x_shape):
                                     "ms_per_step": round(ms_e2e, 4), "mode": "td_bf16"}}
 
 
+def variants_path(w, x, args, stream):
+    """The variant readings on the headline batch: integer delays (TD_NEAREST) and the Butterworth IIR
+    envelope (order 4, beam window in HBM, chunked scan), energyscapes/s."""
+    from paper_2208_10839_amd import binding
+    import torch
+    F, N, D = x.shape[0], x.shape[2], w.dirs.shape[0]
+    out = {}
+    for name, mode, iir in (("td_nearest_fir", "td_nearest", 0), ("td_linear_iir4", "td", 2)):
+        plan = binding.Plan(w.mic_pos, w.chirp, w.dirs, N, fs=w.fs, c=w.c, band=w.cfg.band, decim=w.cfg.decim,
+                            mode=mode, max_frames=F)
+        if iir:
+            plan.set_envelope_iir(iir)
+        E = torch.empty((F, D, plan.Q), dtype=torch.float32, device=x.device)
+        for _ in range(2):
+            plan.energyscape(x, out=E)
+        ms = time_calls(lambda: plan.energyscape(x, out=E), args.steps, stream)
+        out[name] = {"value": round(F / (ms / 1e3), 2), "unit": "energyscapes/s", "ms_per_step": round(ms, 4)}
+        plan.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -359,6 +380,8 @@ def main():
     adjoint = adjoint_path(args, stream)
     print("[bench] PDM front end", file=sys.stderr, flush=True)
     pdm_fe = pdm_path(args, stream, tuple(x.shape))
+    print("[bench] variant readings", file=sys.stderr, flush=True)
+    variants = variants_path(w, x, args, stream)
 
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * 1024 * 1024 // 4
@@ -393,6 +416,7 @@ def main():
         "sensor_network_batch": network,
         "self_calibration_step": adjoint,
         "pdm_front_end": pdm_fe,
+        "variant_readings": variants,
     }
     print(json.dumps(out), flush=True)
 

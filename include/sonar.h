@@ -339,6 +339,26 @@ int sonar_pdm_destroy(sonar_pdm pdm);
  */
 int sonar_pdm_demodulate(sonar_pdm pdm, const uint32_t* words, int32_t F, float* x, hipStream_t stream);
 
+/*
+ * sonar_plan_set_envelope_iir -- the IIR reading of the envelope filter (§4.3:
+ * the CPU implementation runs Butterworth filters through a causal lfilter).
+ * Afterwards every envelope of the plan (sonar_envelope, sonar_beamform_envelope,
+ * sonar_energyscape_batch) is
+ *   y_d = causal IIR of |b_d| over the beam window from zero state at its first
+ *         sample n0 - (K-1)/2,      E[d][q] = y_d at sample n0 + qR,
+ * with the beam window materialised in the plan's workspace (allocated here, once)
+ * instead of the fused FIR epilogue.
+ *   n_sections : 1..4 second-order sections, or 0 to return to the FIR envelope.
+ *   sos        : [n_sections][6] host array {b0, b1, b2, a0, a1, a2} per section (the
+ *                cascade's transfer function is the product), or NULL for the
+ *                Butterworth low-pass of order 2 n_sections with -3 dB at fs/(2R)
+ *                (bilinear transform with prewarping, unit DC gain).
+ * The cascade runs as one state-space recurrence in FP32, evaluated in parallel
+ * over 64 chunks of each row by a scan of chunk end states.  Gradients
+ * (sonar_energyscape_vjp) are built for the FIR envelope only.
+ */
+int sonar_plan_set_envelope_iir(sonar_plan plan, int32_t n_sections, const double* sos, hipStream_t stream);
+
 /* Static text for a status code. */
 const char* sonar_status_string(int status);
 

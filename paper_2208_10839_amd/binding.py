@@ -84,6 +84,7 @@ _SIGNATURES = {
     "sonar_pdm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sonar_pdm_demodulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                              ctypes.c_void_p]),
+    "sonar_plan_set_envelope_iir": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "sonar_last_error": (ctypes.c_char_p, []),
 }
@@ -276,6 +277,14 @@ class Plan:
                                      ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
                "sonar_envelope")
         return E
+
+    def set_envelope_iir(self, n_sections: int = 2, sos=None, stream=None):
+        """IIR envelope reading: n_sections second-order sections [S][6] (b0, b1, b2, a0, a1, a2), or the
+        default Butterworth of order 2 n_sections at fs/(2R); n_sections = 0 returns to the FIR."""
+        arr = None if sos is None else _f64(sos, (int(n_sections), 6))
+        _check(load().sonar_plan_set_envelope_iir(self._h, int(n_sections), _ptr(arr), _stream_handle(stream)),
+               "sonar_plan_set_envelope_iir")
+        self._keep_sos = arr
 
     def enable_gradients(self):
         _check(load().sonar_plan_enable_gradients(self._h), "sonar_plan_enable_gradients")

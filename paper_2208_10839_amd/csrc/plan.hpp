@@ -79,7 +79,8 @@ struct sonar_plan_s {
   float2* d_big = nullptr;     // NF > 2^MB_LOGN2: matched-filter scratch, [max_frames][M][2 NF]
   float2* d_tw2 = nullptr;     // NF > 2^MB_LOGN2: twiddles of the 2^MB_LOGN2-point row transforms
   float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
-  float2* d_beam = nullptr;    // FD fallback: beam window [max_frames][D][G'] (unfused plans only)
+  float2* d_beam = nullptr;    // beam window [max_frames][D][G'] (unfused FD plans, IIR envelope), else a placeholder
+  size_t beam_cap = 0;         // complex elements d_beam holds
   int2* d_mt_g = nullptr;      // TD BF16: tap groups {mic, first tap offset}, [tiles][MT_RES][gmax]
   unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][MT_RES][kcmax][hi, lo][64 lanes][8] BF16
   int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][MT_RES]
@@ -92,7 +93,16 @@ struct sonar_plan_s {
   float2* d_gband = nullptr;   // gradients (FD): beam-spectrum gradient G_B, [max_frames][D][kb]
   float2* d_gspec = nullptr;   // gradients (FD): conj(C) G_Y on [0, NF], [max_frames][M][NF + 1]
   bool grad_on = false;
+  int iir_ns = 0;              // IIR envelope: state dimension (2 per section); 0 = the FIR envelope
+  int iir_chunk = 0;           // IIR envelope: window samples per lane, ceil(G'/64)
+  float* d_iir = nullptr;      // IIR envelope tables (layout: IIR_TAB_LEN below)
 };
+
+// IIR envelope tables: A [ns][ns], B [ns], C [ns], D at offset 0 (packed for the
+// section count in use), then A^(chunk 2^k), k < 6, [6][ns][ns] from IIR_POW_OFFSET
+constexpr int IIR_MAX_SECTIONS = 4;
+constexpr int IIR_POW_OFFSET = 96;
+constexpr int IIR_TAB_LEN = IIR_POW_OFFSET + 6 * 64;
 
 // PDM front end (k_pdm.hip): PDM_THREADS threads per workgroup, each workgroup makes
 // NB outputs of every microphone of one frame
@@ -175,4 +185,5 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
 hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, float2* beam, hipStream_t s);
 hipError_t launch_envelope(const sonar_plan_s* p, const float2* beam, int F, float* E, hipStream_t s);
+hipError_t launch_iir_envelope(const sonar_plan_s* p, const float2* beam, int F, float* E, hipStream_t s);
 hipError_t init_td_kernel_attributes();

@@ -86,6 +86,7 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_gscr);
   (void)hipFree(p->d_gband);
   (void)hipFree(p->d_gspec);
+  (void)hipFree(p->d_iir);
   (void)hipFree(p->d_tw2);
   (void)hipFree(p->d_mt_g);
   (void)hipFree(p->d_mt_w);
@@ -614,6 +615,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     return fail(SONAR_E_NOMEM, "device allocation of %zu bytes failed", total);
   }
   p->ws_bytes = total;
+  p->beam_cap = beam_elems;
 
   std::vector<float> taps_f(taps.begin(), taps.end());
   ok = hipMemcpyAsync(p->d_pos, d.mic_pos, 3 * sizeof(double) * p->M, hipMemcpyHostToDevice, stream) == hipSuccess &&
@@ -695,7 +697,8 @@ int sonar_beamform(sonar_plan p, const void* mf_in, int32_t F, void* beam_out, h
 int sonar_envelope(sonar_plan p, const void* beam_in, int32_t F, float* E, hipStream_t stream) {
   int st = check_exec(p, beam_in, E, F);
   if (st != SONAR_OK) return st;
-  hipError_t e = launch_envelope(p, static_cast<const float2*>(beam_in), F, E, stream);
+  hipError_t e = p->iir_ns > 0 ? launch_iir_envelope(p, static_cast<const float2*>(beam_in), F, E, stream)
+                               : launch_envelope(p, static_cast<const float2*>(beam_in), F, E, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "envelope launch");
 }
 
@@ -703,6 +706,16 @@ namespace {
 
 // beamformer + envelope from a matched-filter buffer of this plan's layout
 hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hipStream_t s) {
+  if (p->iir_ns > 0) {
+    hipError_t e;
+    if (is_td(p)) {
+      e = launch_das_td_beam(p, mf, F, p->d_beam, s);
+    } else {
+      e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
+      if (e == hipSuccess) e = launch_fd_ifft_beam(p, p->d_bspec, F, p->d_beam, s);
+    }
+    return e == hipSuccess ? launch_iir_envelope(p, p->d_beam, F, E, s) : e;
+  }
   if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST) return launch_das_td_env(p, mf, F, E, s);
   if (p->bf_mode == SONAR_BF_TD_BF16) return launch_das_mfma_env(p, mf, F, E, s);
   hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
@@ -864,6 +877,7 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (st != SONAR_OK) return st;
   if (!beam_inout) return fail(SONAR_E_INVALID, "beam_inout is NULL");
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
+  if (p->iir_ns > 0) return fail(SONAR_E_UNSUPPORTED, "gradients are built for the FIR envelope only");
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
   if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
@@ -891,6 +905,122 @@ int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t st
   if (e == hipSuccess) e = launch_delay_tables(p, stream);
   if (e == hipSuccess && !is_td(p)) e = launch_fd_step_table(p, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "position update");
+}
+
+namespace {
+
+// default sections: Butterworth of order 2 S, -3 dB at fc / fs; the analog poles
+// W exp(i pi (2k + 2S + 1) / (4S)), k < S (one of each conjugate pair), prewarped
+// W = 2 tan(pi fc / fs) (fs = 1), bilinear z = (2 + p) / (2 - p), double zero at -1,
+// each section scaled to unit gain at DC
+void butterworth_sections(int S, double fc_over_fs, std::vector<double>& sos) {
+  const int order = 2 * S;
+  const double W = 2.0 * std::tan(M_PI * fc_over_fs);
+  sos.assign(6 * static_cast<size_t>(S), 0.0);
+  for (int k = 0; k < S; ++k) {
+    const double th = M_PI * (2.0 * k + order + 1) / (2.0 * order);
+    const double pr = W * std::cos(th), pi = W * std::sin(th);
+    // z = (2 + p) / (2 - p)
+    const double nr = 2.0 + pr, ni = pi, dr = 2.0 - pr, di = -pi;
+    const double den = dr * dr + di * di;
+    const double zr = (nr * dr + ni * di) / den, zi = (ni * dr - nr * di) / den;
+    const double a1 = -2.0 * zr, a2 = zr * zr + zi * zi;
+    const double g = (1.0 + a1 + a2) / 4.0;
+    double* s = &sos[6 * static_cast<size_t>(k)];
+    s[0] = g; s[1] = 2.0 * g; s[2] = g; s[3] = 1.0; s[4] = a1; s[5] = a2;
+  }
+}
+
+}  // namespace
+
+int sonar_plan_set_envelope_iir(sonar_plan p, int32_t n_sections, const double* sos_in, hipStream_t stream) {
+  if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
+  if (n_sections < 0 || n_sections > IIR_MAX_SECTIONS)
+    return fail(SONAR_E_INVALID, "n_sections=%d outside [0, %d]", n_sections, IIR_MAX_SECTIONS);
+  if (n_sections == 0) {
+    p->iir_ns = 0;
+    return SONAR_OK;
+  }
+  std::vector<double> sos;
+  if (sos_in) {
+    sos.assign(sos_in, sos_in + 6 * static_cast<size_t>(n_sections));
+  } else {
+    butterworth_sections(n_sections, 1.0 / (2.0 * p->R), sos);
+  }
+  for (double v : sos)
+    if (!std::isfinite(v)) return fail(SONAR_E_INVALID, "sos must be finite");
+  const int ns = 2 * n_sections;
+  // cascade -> one state-space system (x: input |b|, u_s: input of section s)
+  std::vector<double> A(ns * ns, 0.0), B(ns, 0.0), Cu(ns, 0.0);
+  double Du = 1.0;
+  for (int s = 0; s < n_sections; ++s) {
+    const double* q = &sos[6 * static_cast<size_t>(s)];
+    if (q[3] == 0.0) return fail(SONAR_E_INVALID, "section %d has a0 = 0", s);
+    const double b0 = q[0] / q[3], b1 = q[1] / q[3], b2 = q[2] / q[3], a1 = q[4] / q[3], a2 = q[5] / q[3];
+    const double Bs[2] = {b1 - a1 * b0, b2 - a2 * b0};
+    const int r = 2 * s;
+    // x_s' = A_s x_s + B_s u_s, u_s = Cu . x + Du x_in (transposed direct form II)
+    for (int i = 0; i < 2; ++i) {
+      for (int j = 0; j < ns; ++j) A[(r + i) * ns + j] += Bs[i] * Cu[j];
+      B[r + i] = Bs[i] * Du;
+    }
+    A[r * ns + r] += -a1;
+    A[r * ns + r + 1] += 1.0;
+    A[(r + 1) * ns + r] += -a2;
+    // y_s = x_s[0] + b0 u_s becomes the next section's input
+    for (int j = 0; j < ns; ++j) Cu[j] *= b0;
+    Cu[r] += 1.0;
+    Du *= b0;
+  }
+  const int L = (p->G + 63) / 64;
+  std::vector<float> tab(IIR_TAB_LEN, 0.0f);
+  for (int i = 0; i < ns * ns; ++i) tab[i] = static_cast<float>(A[i]);
+  for (int i = 0; i < ns; ++i) {
+    tab[ns * ns + i] = static_cast<float>(B[i]);
+    tab[ns * ns + ns + i] = static_cast<float>(Cu[i]);
+  }
+  tab[ns * ns + 2 * ns] = static_cast<float>(Du);
+  // P = A^L by squaring, then A^(L 2^k) by repeated squaring
+  auto mul = [ns](const std::vector<double>& X, const std::vector<double>& Y) {
+    std::vector<double> Z(ns * ns, 0.0);
+    for (int i = 0; i < ns; ++i)
+      for (int k = 0; k < ns; ++k)
+        for (int j = 0; j < ns; ++j) Z[i * ns + j] += X[i * ns + k] * Y[k * ns + j];
+    return Z;
+  };
+  std::vector<double> P(ns * ns, 0.0), base = A;
+  for (int i = 0; i < ns; ++i) P[i * ns + i] = 1.0;
+  for (int e = L; e > 0; e >>= 1) {
+    if (e & 1) P = mul(P, base);
+    base = mul(base, base);
+  }
+  for (int k = 0; k < 6; ++k) {
+    for (int i = 0; i < ns * ns; ++i) tab[IIR_POW_OFFSET + k * ns * ns + i] = static_cast<float>(P[i]);
+    P = mul(P, P);
+  }
+  size_t total = 0;
+  if (!p->d_iir && dev_alloc(&p->d_iir, static_cast<size_t>(IIR_TAB_LEN), &total) != hipSuccess)
+    return fail(SONAR_E_NOMEM, "IIR table allocation failed");
+  // the beam window workspace: plans with a fused envelope hold only a placeholder
+  const size_t beam_need = static_cast<size_t>(p->max_frames) * p->D * p->G;
+  if (p->beam_cap < beam_need) {
+    float2* nb = nullptr;
+    if (dev_alloc(&nb, beam_need, &total) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(SONAR_E_NOMEM, "beam window workspace (%zu bytes) for the IIR envelope failed",
+                  sizeof(float2) * beam_need);
+    }
+    (void)hipFree(p->d_beam);
+    p->d_beam = nb;
+    p->beam_cap = beam_need;
+  }
+  p->ws_bytes += total;
+  hipError_t e = hipMemcpyAsync(p->d_iir, tab.data(), sizeof(float) * IIR_TAB_LEN, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "IIR table upload");
+  p->iir_ns = ns;
+  p->iir_chunk = L;
+  return SONAR_OK;
 }
 
 int sonar_pdm_destroy(sonar_pdm p) {

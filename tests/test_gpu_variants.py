@@ -1,5 +1,6 @@
 """Variant readings on the GPU against the FP64 oracle: integer-delay delay-and-sum
-(TD_NEAREST).  FP32 bar: relative L2 <= 1e-5 per energyscape."""
+(TD_NEAREST) and the IIR (Butterworth, causal lfilter) envelope.  FP32 bar: relative
+L2 <= 1e-5 per energyscape."""
 
 import sys
 
@@ -67,3 +68,42 @@ def test_td_nearest_positions_and_gradients(gpu, torch_mod):
     dE = torch.ones((1, plan.D, plan.Q), dtype=torch.float32, device="cuda")
     with pytest.raises(gpu.SonarError):
         plan.vjp(mf, beam, dE, want_dx=False, want_dpos=True)
+
+
+@pytest.mark.parametrize("mode,sections", [("td", 2), ("fd_fp32", 2), ("td_nearest", 1), ("td", 3)])
+def test_iir_envelope_matches_oracle(gpu, torch_mod, mode, sections):
+    import scipy.signal as ss
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=13)
+    _say(f"case iir envelope: mode={mode} sections={sections} N=4096 D=13 F=2")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
+                    decim=w.cfg.decim, mode=mode, max_frames=2)
+    x = torch.from_numpy(w.x).cuda()
+    E_fir = plan.energyscape(x).cpu().numpy()
+    if sections == 3:
+        sos = ss.butter(6, 0.15, output="sos")           # a custom cascade: order 6, -3 dB at 0.075 fs
+        plan.set_envelope_iir(3, sos)
+        bco, aco = np.array([1.0]), np.array([1.0])
+        for q in sos:
+            bco, aco = np.polymul(bco, q[:3]), np.polymul(aco, q[3:])
+    else:
+        plan.set_envelope_iir(sections)                  # Butterworth of order 2 S at fs / (2R)
+        bco, aco = O.butterworth_lowpass(2 * sections, 1.0 / (2 * w.cfg.decim))
+    E = plan.energyscape(x).cpu().numpy()
+    omode = "fd" if mode.startswith("fd") else mode
+    for f in range(2):
+        Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P,
+                           band=w.cfg.band, mode=omode, iir=(bco, aco))
+        err = rel_l2(E[f], Eo)
+        _say(f"iir {mode} S={sections} frame {f}: rel L2 {err:.2e}")
+        assert err <= 1e-5
+    # the stage calls give the same result
+    mf = plan.matched_filter(x)
+    E_stage = plan.envelope(plan.beamform(mf)).cpu().numpy()
+    assert np.array_equal(E_stage, E)
+    # gradients stay with the FIR envelope
+    with pytest.raises(gpu.SonarError):
+        plan.vjp(mf, plan.beamform(mf), torch.zeros((2, plan.D, plan.Q), dtype=torch.float32, device="cuda"))
+    # and switching back restores the FIR result exactly
+    plan.set_envelope_iir(0)
+    assert np.array_equal(plan.energyscape(x).cpu().numpy(), E_fir)
