@@ -17,6 +17,7 @@ from .sonar_oracle import (  # noqa: F401
     das_fd,
     das_fd_vjp,
     das_td,
+    das_td_cubic,
     das_td_nearest,
     das_td_vjp,
     default_lowpass,
@@ -25,6 +26,7 @@ from .sonar_oracle import (  # noqa: F401
     energyscape,
     energyscape_vjp_fd,
     energyscape_vjp_td,
+    lagrange4_weights,
     lfilter,
     envelope,
     envelope_iir,

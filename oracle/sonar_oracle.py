@@ -168,6 +168,39 @@ def das_td_nearest(yhat, Dl, n_idx) -> np.ndarray:
     return b
 
 
+def lagrange4_weights(alpha):
+    """Weights of the 4-point Lagrange interpolator through samples -1, 0, 1, 2 evaluated at
+    alpha in [0, 1): L_k(alpha) = prod_{j != k} (alpha - j) / (k - j).  Returns [..., 4]."""
+    a = np.asarray(alpha, dtype=np.float64)
+    nodes = (-1, 0, 1, 2)
+    out = []
+    for k in nodes:
+        w = np.ones_like(a)
+        for j in nodes:
+            if j != k:
+                w = w * (a - j) / (k - j)
+        out.append(w)
+    return np.stack(out, axis=-1)
+
+
+def das_td_cubic(yhat, Dl, n_idx) -> np.ndarray:
+    """Fractional-delay DAS with 4-point (cubic) Lagrange interpolation, circular in P:
+    o = floor(-Dl), alpha = -Dl - o,
+    b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(alpha) yhat_m[(n + o + k) mod P]."""
+    yhat = np.asarray(yhat)
+    M, P = yhat.shape
+    o, alpha = td_offsets(Dl)
+    L = lagrange4_weights(alpha)
+    n_idx = np.asarray(n_idx, dtype=np.int64)
+    b = np.zeros((o.shape[0], n_idx.size), dtype=np.complex128)
+    for d in range(o.shape[0]):
+        for m in range(M):
+            for i, k in enumerate((-1, 0, 1, 2)):
+                b[d] += L[d, m, i] * yhat[m, np.mod(n_idx + o[d, m] + k, P)]
+        b[d] /= M
+    return b
+
+
 def das_fd(Yspec, Dl, n_idx) -> np.ndarray:
     """Exact fractional-delay DAS by per-bin phase steering, circular in P.
 
@@ -299,7 +332,7 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
                 gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
                 dir_index=None, return_beam: bool = False, iir=None):
     """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation), 'td_nearest' (integer
-    delays) or 'fd' (exact).
+    delays), 'td_cubic' (4-point Lagrange interpolation) or 'fd' (exact).
 
     dir_index selects a subset of directions (rows of the result follow it).
     With return_beam, also returns the complex beam window b[d][G'].
@@ -327,10 +360,12 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
         b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
     elif mode == "td_nearest":
         b = das_td_nearest(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
+    elif mode == "td_cubic":
+        b = das_td_cubic(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
     elif mode == "fd":
         b = das_fd(matched_filter_spectrum(x, chirp, P, fs, band), Dl, n_idx)
     else:
-        raise ValueError("mode must be 'td', 'td_nearest' or 'fd'")
+        raise ValueError("mode must be 'td', 'td_nearest', 'td_cubic' or 'fd'")
     E = envelope(b, h, Q, R) if iir is None else envelope_iir(b, iir[0], iir[1], Q, R, K)
     return (E, b) if return_beam else E
 

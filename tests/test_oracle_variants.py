@@ -73,3 +73,45 @@ def test_envelope_iir_identity_filter_samples_the_magnitude():
     bw = rng.standard_normal((3, (Q - 1) * R + K)) + 1j * rng.standard_normal((3, (Q - 1) * R + K))
     E = O.envelope_iir(bw, [1.0], [1.0], Q, R, K)
     assert np.array_equal(E, np.abs(bw)[:, (K - 1) // 2 + R * np.arange(Q)])
+
+
+def test_lagrange4_weights_at_nodes_and_sum():
+    for a, k in ((0.0, 1),):
+        w = O.lagrange4_weights(np.array(a))
+        assert np.allclose(w, np.eye(4)[k], atol=0)
+    a = np.linspace(0, 1, 17, endpoint=False)
+    assert np.allclose(O.lagrange4_weights(a).sum(axis=-1), 1.0, atol=1e-15)
+
+
+def test_cubic_interpolation_is_exact_for_cubic_polynomials():
+    """Away from the circular wrap, a cubic sample sequence is reproduced exactly at any fractional
+    delay: b[n] = (1/M) sum_m poly(n - Dl[m]) (linear interpolation is not)."""
+    rng = np.random.default_rng(24)
+    M, P, D = 3, 256, 4
+    c = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    n = np.arange(P, dtype=np.float64)
+    poly = lambda t: c[0] + c[1] * t + c[2] * t ** 2 + c[3] * t ** 3   # noqa: E731
+    y = np.tile(poly(n), (M, 1))
+    Dl = rng.uniform(-5, 5, size=(D, M))
+    n_idx = np.arange(20, 200)
+    b = O.das_td_cubic(y, Dl, n_idx)
+    expect = np.stack([np.mean([poly(n_idx - Dl[d, m]) for m in range(M)], axis=0) for d in range(D)])
+    assert np.allclose(b, expect, rtol=1e-12, atol=1e-9)
+    assert not np.allclose(O.das_td(y, Dl, n_idx), expect, rtol=1e-6)
+
+
+def test_cubic_is_closer_to_the_exact_delay_than_linear():
+    """On a band-limited analytic signal (the beamformer's input) the cubic interpolator's error
+    against the exact per-bin phase delay is well below the linear one's."""
+    rng = np.random.default_rng(25)
+    M, P, D = 4, 512, 6
+    Y = np.zeros((M, P), dtype=np.complex128)
+    k = np.arange(P // 2 + 1)
+    Y[:, :P // 2 + 1] = (rng.standard_normal((M, k.size)) + 1j * rng.standard_normal((M, k.size))) * (k < P // 10)
+    y = np.fft.ifft(Y, axis=1)
+    Dl = rng.uniform(-8, 8, size=(D, M))
+    n_idx = np.arange(P)
+    ex = O.das_fd(Y, Dl, n_idx)
+    e_lin = np.linalg.norm(O.das_td(y, Dl, n_idx) - ex)
+    e_cub = np.linalg.norm(O.das_td_cubic(y, Dl, n_idx) - ex)
+    assert e_cub < 0.2 * e_lin, (e_cub, e_lin)
