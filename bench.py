@@ -329,13 +329,14 @@ def pdm_path(args, stream, x_shape):
 
 
 def variants_path(w, x, args, stream):
-    """The variant readings on the headline batch: integer delays (TD_NEAREST) and the Butterworth IIR
-    envelope (order 4, beam window in HBM, chunked scan), energyscapes/s."""
+    """The variant readings on the headline batch: integer delays (TD_NEAREST), 4-point Lagrange delays
+    (TD_CUBIC) and the Butterworth IIR envelope (order 4, beam window in HBM, chunked scan), energyscapes/s."""
     from paper_2208_10839_amd import binding
     import torch
     F, N, D = x.shape[0], x.shape[2], w.dirs.shape[0]
     out = {}
-    for name, mode, iir in (("td_nearest_fir", "td_nearest", 0), ("td_linear_iir4", "td", 2)):
+    for name, mode, iir in (("td_nearest_fir", "td_nearest", 0), ("td_cubic_fir", "td_cubic", 0),
+                            ("td_linear_iir4", "td", 2)):
         plan = binding.Plan(w.mic_pos, w.chirp, w.dirs, N, fs=w.fs, c=w.c, band=w.cfg.band, decim=w.cfg.decim,
                             mode=mode, max_frames=F)
         if iir:

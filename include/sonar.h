@@ -69,10 +69,14 @@ enum sonar_status {
  *  TD_NEAREST: integer delays (the delay rounded to the nearest sample, ties
  *              toward the later sample): o = floor(-Dl + 1/2),
  *              b_d[n] = (1/M) sum_m yhat_m[(n + o) mod P]; FP32, same kernels
- *              and buffers as TD_LINEAR with the second weight zero.          */
+ *              and buffers as TD_LINEAR with the second weight zero.
+ *  TD_CUBIC  : 4-point Lagrange (cubic) fractional delay: o = floor(-Dl),
+ *              a = -Dl - o, b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(a) yhat_m[n+o+k],
+ *              L_k(a) = prod_{j != k} (a - j)/(k - j); FP32 on the TD_LINEAR
+ *              kernels, each microphone taken as two two-tap entries.  M <= 64. */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
-  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5
+  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6
 };
 
 /* Element type of the microphone samples x. */
@@ -300,8 +304,9 @@ int sonar_energyscape_vjp(sonar_plan plan, const void* mf_in, void* beam_inout, 
  * created with).
  */
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
-/* (TD_NEAREST plans move like TD_LINEAR ones; their dL/dp is zero almost everywhere, so
- * sonar_energyscape_vjp returns SONAR_E_UNSUPPORTED for dpos_out on them.) */
+/* (TD_NEAREST and TD_CUBIC plans move like TD_LINEAR ones.  TD_NEAREST's dL/dp is zero
+ * almost everywhere, so sonar_energyscape_vjp returns SONAR_E_UNSUPPORTED for dpos_out on
+ * it; TD_CUBIC has no gradient kernels (SONAR_E_UNSUPPORTED).) */
 
 /*
  * PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density

@@ -38,9 +38,11 @@ __device__ __forceinline__ float from_next_lane(float v, int lane) {
 // immediate offsets), then stores them.  The table entries (o - omin, w0, w1)
 // of the wavefront's direction sit one microphone per lane (up to 128 mics)
 // and are broadcast with readlane.
+// M counts table entries; entry m reads matched-filter row m >> vshift (TD_CUBIC
+// takes each microphone as two two-tap entries).
 template <int NB, int NW>
 __device__ __forceinline__ void das_accumulate(const float2* __restrict__ yrow0, long long row,
-                                               const int4* __restrict__ dtab_d, int M, int mc, int ws,
+                                               const int4* __restrict__ dtab_d, int M, int vshift, int mc, int ws,
                                                bool active, float2 (&A)[NB], float2 (&C)[NB],
                                                int wv, int lane) {
   extern __shared__ float2 smem[];
@@ -60,7 +62,7 @@ __device__ __forceinline__ void das_accumulate(const float2* __restrict__ yrow0,
     if (wv < rows) {
       // rows are staged whole: 64 * MAXL pairs per row (ws = 128 * MAXL samples);
       // the matched-filter rows are padded so these loads stay in the allocation
-      const float4* src = reinterpret_cast<const float4*>(yrow0 + static_cast<long long>(m0 + wv) * row) + lane;
+      const float4* src = reinterpret_cast<const float4*>(yrow0 + static_cast<long long>((m0 + wv) >> vshift) * row) + lane;
       float4* dst = reinterpret_cast<float4*>(smem + wv * ws) + lane;
       float4 stage[MAXL];
 #pragma unroll
@@ -103,8 +105,8 @@ __device__ __forceinline__ float2 beam_sample(const float2 (&A)[NB], const float
 template <int NB, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_env_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, const float* __restrict__ taps,
-    float* __restrict__ E, long long fstride, int M, int D, int Q, int row, int R, int K, int qc, int nqc, int ws,
-    int mc, int nwin) {
+    float* __restrict__ E, long long fstride, int M, int vshift, int D, int Q, int row, int R, int K, int qc, int nqc,
+    int ws, int mc, int nwin) {
   extern __shared__ float2 smem[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -125,7 +127,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
 
   float2 A[NB], C[NB];
   das_accumulate<NB, NW>(yext + f * fstride + i0, row,
-                         dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
+                         dtab + static_cast<long long>(active ? d : 0) * M, M, vshift, mc, ws, active,
                          A, C, wv, lane);
 
   float* absb = reinterpret_cast<float*>(smem);
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
 template <int NB, int NW>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVES_PER_EU, TD_WAVES_PER_EU))) void das_td_beam_kernel(
     const float2* __restrict__ yext, const int4* __restrict__ dtab, float2* __restrict__ beam,
-    long long fstride, int M, int D, int G, int row, int tc, int nbc, int ws, int mc) {
+    long long fstride, int M, int vshift, int D, int G, int row, int tc, int nbc, int ws, int mc) {
   extern __shared__ float2 smem[];
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(TD_WAVE
 
   float2 A[NB], C[NB];
   das_accumulate<NB, NW>(yext + f * fstride + i0, row,
-                         dtab + static_cast<long long>(active ? d : 0) * M, M, mc, ws, active,
+                         dtab + static_cast<long long>(active ? d : 0) * M, M, vshift, mc, ws, active,
                          A, C, wv, lane);
 #pragma unroll
   for (int t = 0; t < NB; ++t) {
@@ -242,7 +244,8 @@ hipError_t launch_das_td_env(const sonar_plan_s* p, const float2* yext, int F, f
   const int nwin = F * p->td_nqc;
   const long long nblk = static_cast<long long>((nwin + TD_XCDS - 1) / TD_XCDS) * TD_XCDS * ndt;
   hipLaunchKernelGGL((das_td_env_kernel<TD_NB, TD_NW>), dim3(static_cast<unsigned>(nblk)), dim3(TD_NW * 64),
-                     smem, s, yext, p->d_dtab, p->d_taps, E, p->mf_fstride, p->M, p->D, p->Q, p->row, p->R, p->K,
+                     smem, s, yext, p->d_dtab, p->d_taps, E, p->mf_fstride, p->M << p->td_vshift, p->td_vshift, p->D,
+                     p->Q, p->row, p->R, p->K,
                      p->td_qc, p->td_nqc, p->td_ws, p->td_mc, nwin);
   return hipGetLastError();
 }
@@ -252,7 +255,8 @@ hipError_t launch_das_td_beam(const sonar_plan_s* p, const float2* yext, int F, 
   const size_t smem = td_smem_bytes(p);
   const long long nblk = static_cast<long long>(F) * p->td_nbc * ndt;
   hipLaunchKernelGGL((das_td_beam_kernel<TD_NB, TD_NW>), dim3(static_cast<unsigned>(nblk)), dim3(TD_NW * 64),
-                     smem, s, yext, p->d_dtab, beam, p->mf_fstride, p->M, p->D, p->G, p->row, p->td_tn, p->td_nbc,
+                     smem, s, yext, p->d_dtab, beam, p->mf_fstride, p->M << p->td_vshift, p->td_vshift, p->D, p->G,
+                     p->row, p->td_tn, p->td_nbc,
                      p->td_ws, p->td_mc);
   return hipGetLastError();
 }

@@ -5,7 +5,8 @@
 //  * delays      Dl[d][m] = fs (p_m . u_d) / c, and for the time-domain
 //                beamformer o = floor(-Dl), alpha = -Dl - o, stored as
 //                {o - omin, (1-alpha)/M, alpha/M} (integer delays: o = floor(-Dl + 1/2),
-//                alpha = 0);
+//                alpha = 0; cubic: two entries per microphone, {o - 1 - omin, L_-1/M, L_0/M}
+//                and {o + 1 - omin, L_1/M, L_2/M}, the 4-point Lagrange weights);
 //  * chirp       C[k] = beta[k] W[k] conj(S[k]), S[k] = sum_l s[l] exp(-2 pi i k l/P),
 //                with the phase index k l reduced mod P exactly in integers;
 //  * twiddles    FFT tables (layout in plan.hpp), exp(-2 pi i e / NF) and
@@ -18,21 +19,33 @@
 namespace {
 
 __global__ void delay_table_kernel(const double* __restrict__ pos, const double* __restrict__ dirs,
-                                   int M, int D, double fs, double c, int omin, int spread, int nearest,
+                                   int M, int D, double fs, double c, int omin, int spread, int interp,
                                    int4* __restrict__ dtab, double* __restrict__ dl) {
   const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= static_cast<long long>(D) * M) return;
   const int d = static_cast<int>(i / M), m = static_cast<int>(i % M);
   const double pu = pos[3 * m] * dirs[3 * d] + pos[3 * m + 1] * dirs[3 * d + 1] + pos[3 * m + 2] * dirs[3 * d + 2];
   const double Dl = fs * pu / c;
+  const bool nearest = interp == 1;
   const double o = nearest ? floor(-Dl + 0.5) : floor(-Dl);
   const double a = nearest ? 0.0 : -Dl - o;
+  dl[i] = Dl;
+  if (interp == 2) {
+    // 4-point Lagrange weights at a for the samples o - 1 .. o + 2
+    const double lm = -a * (a - 1.0) * (a - 2.0) / 6.0, l0 = (a + 1.0) * (a - 1.0) * (a - 2.0) / 2.0;
+    const double l1 = -(a + 1.0) * a * (a - 2.0) / 2.0, l2 = (a + 1.0) * a * (a - 1.0) / 6.0;
+    int r0 = static_cast<int>(o) - 1 - omin, r1 = static_cast<int>(o) + 1 - omin;
+    r0 = r0 < 0 ? 0 : (r0 > spread ? spread : r0);
+    r1 = r1 < 0 ? 0 : (r1 > spread ? spread : r1);
+    dtab[2 * i] = make_int4(r0, __float_as_int(static_cast<float>(lm / M)), __float_as_int(static_cast<float>(l0 / M)), 0);
+    dtab[2 * i + 1] = make_int4(r1, __float_as_int(static_cast<float>(l1 / M)), __float_as_int(static_cast<float>(l2 / M)), 0);
+    return;
+  }
   int rel = static_cast<int>(o) - omin;
   rel = rel < 0 ? 0 : (rel > spread ? spread : rel);
   const float w0 = static_cast<float>((1.0 - a) / M);
   const float w1 = static_cast<float>(a / M);
   dtab[i] = make_int4(rel, __float_as_int(w0), __float_as_int(w1), 0);
-  dl[i] = Dl;
 }
 
 // roots[t] = exp(-2 pi i t / P), t < P
@@ -126,7 +139,8 @@ hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;
   hipLaunchKernelGGL(delay_table_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s,
                      p->d_pos, p->d_dirs, p->M, p->D, p->fs, p->c, p->omin, p->spread,
-                     p->bf_mode == SONAR_BF_TD_NEAREST ? 1 : 0, p->d_dtab, p->d_dl);
+                     p->bf_mode == SONAR_BF_TD_NEAREST ? 1 : (p->bf_mode == SONAR_BF_TD_CUBIC ? 2 : 0),
+                     p->d_dtab, p->d_dl);
   return hipGetLastError();
 }
 

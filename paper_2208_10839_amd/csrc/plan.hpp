@@ -45,6 +45,7 @@ struct sonar_plan_s {
   int td_qc = 0;        // range bins per tile
   int td_nqc = 0;       // range-bin tiles
   int td_nbc = 0;       // beam-sample tiles (beamform-only kernel)
+  int td_vshift = 0;    // delay-table entries per microphone = 1 << td_vshift (2 for TD_CUBIC)
 
   // frequency-domain layout: stored band bins [k_lo, k_lo + kb); the
   // per-direction inverse transform runs as fd_R polyphase transforms of

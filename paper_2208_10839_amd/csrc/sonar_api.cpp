@@ -113,7 +113,8 @@ bool finite_all(const double* v, size_t n) {
 }
 
 bool is_td(const sonar_plan_s* p) {
-  return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST;
+  return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST ||
+         p->bf_mode == SONAR_BF_TD_CUBIC;
 }
 
 // Coordinates z_d in which distances between directions equal distances between their
@@ -379,7 +380,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_NEAREST)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_CUBIC)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -469,9 +470,11 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     delete p;
     return fail(SONAR_E_UNSUPPORTED, "low-pass length %d above %d is not supported", p->K, p->td_tn);
   }
-  if (p->M > TD_MAX_MICS) {
+  p->td_vshift = p->bf_mode == SONAR_BF_TD_CUBIC ? 1 : 0;
+  if ((p->M << p->td_vshift) > TD_MAX_MICS) {
     delete p;
-    return fail(SONAR_E_UNSUPPORTED, "more than %d microphones is not supported", TD_MAX_MICS);
+    return fail(SONAR_E_UNSUPPORTED, "more than %d microphones is not supported%s", TD_MAX_MICS >> p->td_vshift,
+                p->td_vshift ? " by TD_CUBIC" : "");
   }
   if (64 * TD_NB + p->spread + 1 > 2 * TD_MAX_ROW_PAIRS) {
     delete p;
@@ -581,6 +584,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   // one-time allocation of every device buffer
   size_t total = 0;
   const size_t dm = static_cast<size_t>(p->D) * p->M;
+  const size_t dtab_elems = dm << p->td_vshift;
   const size_t mf_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->mf_fstride;
   const size_t spec_elems = fd ? 0 : static_cast<size_t>(p->max_frames) * p->M * (p->NF + 1);
   const size_t band_elems = fd ? static_cast<size_t>(p->max_frames) * p->kb * p->M : 0;
@@ -591,7 +595,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   const bool big = p->NF > (1 << MB_LOGN2);
   const size_t big_elems = big ? static_cast<size_t>(p->max_frames) * p->M * 2 * p->NF : 0;
   const size_t tw2_elems = big ? static_cast<size_t>(fft_tw_len(1 << MB_LOGN2)) : 0;
-  bool ok = dev_alloc(&p->d_dtab, dm, &total) == hipSuccess &&
+  bool ok = dev_alloc(&p->d_dtab, dtab_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_dl, dm, &total) == hipSuccess &&
             dev_alloc(&p->d_pos, 3 * static_cast<size_t>(p->M), &total) == hipSuccess &&
             dev_alloc(&p->d_dirs, 3 * static_cast<size_t>(p->D), &total) == hipSuccess &&
@@ -716,7 +720,8 @@ hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hi
     }
     return e == hipSuccess ? launch_iir_envelope(p, p->d_beam, F, E, s) : e;
   }
-  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST) return launch_das_td_env(p, mf, F, E, s);
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC)
+    return launch_das_td_env(p, mf, F, E, s);
   if (p->bf_mode == SONAR_BF_TD_BF16) return launch_das_mfma_env(p, mf, F, E, s);
   hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
   if (e != hipSuccess) return e;
@@ -878,6 +883,7 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (!beam_inout) return fail(SONAR_E_INVALID, "beam_inout is NULL");
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
   if (p->iir_ns > 0) return fail(SONAR_E_UNSUPPORTED, "gradients are built for the FIR envelope only");
+  if (p->bf_mode == SONAR_BF_TD_CUBIC) return fail(SONAR_E_UNSUPPORTED, "TD_CUBIC has no gradient kernels");
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
   if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
@@ -894,10 +900,11 @@ int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t st
     return fail(SONAR_E_UNSUPPORTED, "TD_BF16 tiles are built for one geometry: create a new plan");
   for (int i = 0; i < 3 * p->M; ++i)
     if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
-  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST) {
-    // offsets o in [floor(-bmax), floor(bmax) + 1] (nearest rounds up by one at most), read up to o + 1
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC) {
+    // offsets o in [floor(-bmax), floor(bmax) + 1] (nearest rounds up by one at most); the taps read
+    // o .. o + 1 (linear), o - 1 .. o + 2 (cubic)
     const double bmax = delay_bound(mic_pos, p->M, p->fs, p->c);
-    if (static_cast<int>(std::floor(-bmax)) < p->omin || static_cast<int>(std::floor(bmax)) + 2 > p->omax)
+    if (static_cast<int>(std::floor(-bmax)) - 1 < p->omin || static_cast<int>(std::floor(bmax)) + 2 > p->omax)
       return fail(SONAR_E_UNSUPPORTED, "new positions need delays beyond the plan's range [%d, %d]: create a new plan",
                   p->omin, p->omax);
   }

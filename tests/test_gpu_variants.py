@@ -1,5 +1,6 @@
 """Variant readings on the GPU against the FP64 oracle: integer-delay delay-and-sum
-(TD_NEAREST) and the IIR (Butterworth, causal lfilter) envelope.  FP32 bar: relative
+(TD_NEAREST), 4-point Lagrange fractional delay (TD_CUBIC) and the IIR (Butterworth,
+causal lfilter) envelope.  FP32 bar: relative
 L2 <= 1e-5 per energyscape."""
 
 import sys
@@ -107,3 +108,52 @@ def test_iir_envelope_matches_oracle(gpu, torch_mod, mode, sections):
     # and switching back restores the FIR result exactly
     plan.set_envelope_iir(0)
     assert np.array_equal(plan.energyscape(x).cpu().numpy(), E_fir)
+
+
+@pytest.mark.parametrize("cfg,n_samples,n_dirs,frames", [("c1", None, None, 1), ("c2", 4096, 37, 2),
+                                                         ("c2", 16384, 1500, 1)])
+def test_td_cubic_matches_oracle(gpu, torch_mod, cfg, n_samples, n_dirs, frames):
+    torch = torch_mod
+    w = synth.make_workload(cfg, frames=frames, n_samples=n_samples, n_dirs=n_dirs)
+    D = w.dirs.shape[0]
+    _say(f"case td_cubic: {cfg} N={w.x.shape[2]} D={D} F={frames}")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
+                    decim=w.cfg.decim, mode="td_cubic", max_frames=frames)
+    x = torch.from_numpy(w.x).cuda()
+    E = plan.energyscape(x).cpu().numpy()
+    sel = np.arange(0, D, 50) if D > 200 else np.arange(D)
+    for f in range(frames):
+        Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P,
+                           band=w.cfg.band, mode="td_cubic", dir_index=sel)
+        err = rel_l2(E[f][sel], Eo)
+        _say(f"td_cubic {cfg} frame {f}: rel L2 {err:.2e}")
+        assert err <= 1e-5
+    # closer to the exact (FD) energyscape than linear interpolation
+    Ef = O.energyscape(w.x[0].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P,
+                       band=w.cfg.band, mode="fd", dir_index=sel)
+    Et = O.energyscape(w.x[0].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P,
+                       band=w.cfg.band, mode="td", dir_index=sel)
+    _say(f"td_cubic vs exact {rel_l2(E[0][sel], Ef):.2e}, linear vs exact {rel_l2(Et, Ef):.2e}")
+    assert rel_l2(E[0][sel], Ef) < rel_l2(Et, Ef)
+    # the beam stage agrees with the fused path
+    mf = plan.matched_filter(x)
+    beam = plan.beamform(mf)
+    assert rel_l2(plan.envelope(beam).cpu().numpy(), E) <= 1e-6
+    with pytest.raises(gpu.SonarError):
+        plan.vjp(mf, beam, torch.zeros((frames, plan.D, plan.Q), dtype=torch.float32, device="cuda"))
+
+
+def test_td_cubic_positions_and_limits(gpu, torch_mod):
+    torch = torch_mod
+    w = synth.make_workload("c1", n_dirs=11)
+    _say("case td_cubic set_positions / 64-mic limit")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, decim=w.cfg.decim, mode="td_cubic")
+    pos2 = w.mic_pos + np.random.default_rng(np.random.SeedSequence([5, 0, 0, 2])).normal(0, 0.5e-3, w.mic_pos.shape)
+    plan.set_positions(pos2)
+    E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()[0]
+    Eo = O.energyscape(w.x[0].astype(np.float64), w.chirp, pos2, w.dirs, fs=w.fs, c=w.c, P=plan.P, mode="td_cubic")
+    assert rel_l2(E, Eo) <= 1e-5
+    pos65 = np.zeros((65, 3))
+    pos65[:, 0] = np.linspace(-0.01, 0.01, 65)
+    with pytest.raises(gpu.SonarError):
+        gpu.Plan(pos65, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, mode="td_cubic")
