@@ -217,10 +217,17 @@ int sonar_energyscape_batch(sonar_plan plan, const void* x, int32_t F, float* E,
  * grid and mode): E_i = sonar_energyscape_batch(plans[i], x[i], frames[i]).
  * This is the sensor network's batch (§3: many sensors' measurements are
  * processed by the same GPU service; §5).  All items are validated before any
- * work is enqueued; the items then run in order on `stream`.  The call enqueues
- * kernels only (no allocation, no synchronisation, no memset), so a caller may
- * capture it in a HIP graph and replay it; replays reuse the plans' workspaces,
- * so replays of graphs that share a plan must not overlap.
+ * work is enqueued.  Items then run concurrently: forked from `stream` onto
+ * it and up to three library-owned side streams of the device (created with
+ * its first plan, default priority), largest items first onto the least
+ * loaded stream, items sharing a plan on one stream in order, and joined back
+ * into `stream` by events, so work enqueued on `stream` afterwards sees every
+ * E_i.  The call enqueues kernels and event records/waits only (no
+ * allocation, no synchronisation, no memset), so a caller may capture it in a
+ * HIP graph on `stream` (the branches become parallel graph nodes) and replay
+ * it; replays reuse the plans' workspaces, so replays of graphs that share a
+ * plan must not overlap.  Concurrent calls on one device are serialised on
+ * the host while they enqueue.
  *   plans  : n plan handles (a plan may appear more than once).
  *   x      : n device pointers, x[i] = [frames[i]][M_i][N_i] samples.
  *   frames : n frame counts, 1 <= frames[i] <= max_frames of plans[i].
@@ -270,7 +277,8 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
  * the forward pass given.
  *
  * sonar_plan_enable_gradients -- allocates the gradient workspace of the plan
- * (once; the bytes are added to SONAR_Q_WORKSPACE_BYTES).  Frequency-domain
+ * (once; the bytes are added to SONAR_Q_WORKSPACE_BYTES), including the beam
+ * window [max_frames][D][G'] that sonar_energyscape_backward fills.  Frequency-domain
  * plans need P <= 32768 (SONAR_E_UNSUPPORTED otherwise).
  */
 int sonar_plan_enable_gradients(sonar_plan plan);
@@ -293,6 +301,17 @@ int sonar_plan_enable_gradients(sonar_plan plan);
 int sonar_energyscape_vjp(sonar_plan plan, const void* mf_in, void* beam_inout, const float* dE,
                           int32_t F, void* dyhat_out, float* dx_out, double* dpos_out,
                           hipStream_t stream);
+
+/*
+ * sonar_energyscape_backward -- the whole backward pass from the samples:
+ * matched filter, beam window (both in the plan's workspace) and the
+ * derivatives above, for F frames of x [F][M][N] (sample_dtype) and
+ * dE [F][D][Q].  dx_out float [F][M][N] or NULL, dpos_out double [M][3] or NULL
+ * (summed over the frames).  Needs sonar_plan_enable_gradients (which also
+ * allocates the beam window and matched-filter gradient this call uses).
+ */
+int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, int32_t F, float* dx_out,
+                               double* dpos_out, hipStream_t stream);
 
 /*
  * sonar_plan_set_positions -- new microphone positions [M][3] (metres): the

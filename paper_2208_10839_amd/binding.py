@@ -80,6 +80,8 @@ _SIGNATURES = {
                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
     "sonar_plan_set_positions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_energyscape_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_pdm_create": (ctypes.c_int, [ctypes.POINTER(PdmDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "sonar_pdm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sonar_pdm_demodulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -322,6 +324,22 @@ class Plan:
                                             ctypes.c_void_p(dpos.data_ptr() if dpos is not None else 0),
                                             _stream_handle(stream)), "sonar_energyscape_vjp")
         return dy, dx, (dpos.cpu().numpy() if dpos is not None else None)
+
+    def backward(self, x, dE, want_dx=True, want_dpos=True, stream=None):
+        """sonar_energyscape_backward: (dx [F][M][N] float32 or None, dpos [M][3] float64 numpy or None)."""
+        import torch
+        self.enable_gradients()
+        F = self._samples(x)
+        self._frames(dE, (self.D, self.Q), "dE")
+        if dE.dtype != torch.float32 or dE.shape[0] != F:
+            raise ValueError("dE must be float32 [F][D][Q] with the frames of x")
+        dx = torch.empty((F, self.M, self.N), dtype=torch.float32, device=x.device) if want_dx else None
+        dpos = torch.empty((self.M, 3), dtype=torch.float64, device=x.device) if want_dpos else None
+        _check(load().sonar_energyscape_backward(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(dE.data_ptr()),
+                                                 F, ctypes.c_void_p(dx.data_ptr() if dx is not None else 0),
+                                                 ctypes.c_void_p(dpos.data_ptr() if dpos is not None else 0),
+                                                 _stream_handle(stream)), "sonar_energyscape_backward")
+        return dx, (dpos.cpu().numpy() if dpos is not None else None)
 
     def beamform_envelope(self, mf, out=None, stream=None):
         """E[F][D][Q] from a matched-filter buffer, beam kept on chip."""

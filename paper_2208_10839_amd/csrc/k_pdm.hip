@@ -14,10 +14,13 @@
 //     microphone's bits as a time-ordered bit string;
 //  2. filter: with the taps reversed (g[i] = h[K-1-i], i = tick - first tick of the
 //     window), the sum over K taps is a sum over ceil(K/8) byte lookups: table c maps
-//     the 8 bits of ticks 8c..8c+7 of the window to sum_i g[8c+i] (+-1).  A lane aligns
-//     its window with v_alignbit on pairs of LDS words and adds one table entry per
-//     byte (the tables are built once per filter, in FP64, rounded to FP32);
-//  3. windows that reach outside [0, T) take the tap-by-tap sum with bounds checks.
+//     the 8 bits of ticks 8c..8c+7 of the window to sum_i g[8c+i] (+-1).  A lane loads
+//     the NW + 1 words under its window, aligns them with v_alignbit and issues all
+//     4 NW table reads at once into four partial sums (tables past the filter's end
+//     are zero); the tables are built once per filter, in FP64, rounded to FP32;
+//  3. ticks outside [0, T) are staged as clear bits, so the tables count them as -1;
+//     a window that reaches outside adds back g over its outside prefix and suffix
+//     (prefix sums of g, built in FP64 with the tables).
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -39,14 +42,22 @@ __global__ void pdm_lut_kernel(const double* __restrict__ taps, int K, int C, fl
   lut[e] = static_cast<float>(s);
 }
 
-__global__ void pdm_taps_f32_kernel(const double* __restrict__ taps, int K, float* __restrict__ rev) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < K) rev[i] = static_cast<float>(taps[K - 1 - i]);
+// gcum[i] = sum_{j<i} g[j], i <= K (one thread: K is at most a few hundred)
+__global__ void pdm_prefix_kernel(const double* __restrict__ taps, int K, float* __restrict__ gcum) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  double s = 0.0;
+  gcum[0] = 0.f;
+  for (int i = 0; i < K; ++i) {
+    s += taps[K - 1 - i];
+    gcum[i + 1] = static_cast<float>(s);
+  }
 }
 
+template <int NW>
 __global__ __launch_bounds__(PDM_THREADS) void pdm_demod_kernel(
-    const unsigned* __restrict__ words, const float* __restrict__ lut_g, const float* __restrict__ grev,
-    float* __restrict__ x, int M, int W, int N, int D, int K, int C, int NB, int SW, int ntile) {
+    const unsigned* __restrict__ words, const float* __restrict__ lut_g, const float* __restrict__ gcum,
+    float* __restrict__ x, int M, int W, int N, int D, int K, int NB, int SW, int ntile) {
+  constexpr int C = 4 * NW;                               // byte tables, zero past the filter
   extern __shared__ unsigned smem[];
   unsigned* bits = smem;                                  // [M][SW]
   float* lut = reinterpret_cast<float*>(smem + M * SW);   // [C][256]
@@ -62,14 +73,20 @@ __global__ __launch_bounds__(PDM_THREADS) void pdm_demod_kernel(
 
   for (int i = threadIdx.x; i < C * 256; i += PDM_THREADS) lut[i] = lut_g[i];
 
-  // 1. bit transpose: 64-tick chunks, wave-strided
+  // 1. bit transpose: 64-tick chunks, wave-strided; the next chunk's first word is
+  //    loaded while the current one is turned into masks
   const int nchunk = SW >> 1;
-  for (int ch = wv; ch < nchunk; ch += PDM_THREADS / 64) {
+  auto load_word = [&](int ch, int w) -> unsigned {
     const long long t = tb + 64LL * ch + lane;
-    const bool in = t >= 0 && t < T;
+    return (ch < nchunk && t >= 0 && t < T) ? wf[t * W + w] : 0u;
+  };
+  unsigned next0 = load_word(wv, 0);
+  for (int ch = wv; ch < nchunk; ch += PDM_THREADS / 64) {
+    const unsigned first = next0;
+    next0 = load_word(ch + PDM_THREADS / 64, 0);
     unsigned long long keep0 = 0, keep1 = 0;
     for (int w = 0; w < W; ++w) {
-      const unsigned word = in ? wf[t * W + w] : 0u;
+      const unsigned word = w == 0 ? first : load_word(ch, w);
       const int mend = M - 32 * w < 32 ? M - 32 * w : 32;
       for (int b = 0; b < mend; ++b) {
         const unsigned long long mask = __ballot((word >> b) & 1u);
@@ -92,7 +109,6 @@ __global__ __launch_bounds__(PDM_THREADS) void pdm_demod_kernel(
   __syncthreads();
 
   // 2./3. filter and subsample: wave w takes microphones w, w+4, ...; lanes take samples
-  const int nw = (K + 31) >> 5;   // aligned words covering the window
   float* xf = x + f * static_cast<long long>(M) * N;
   for (int m = wv; m < M; m += PDM_THREADS / 64) {
     const unsigned* bm = bits + m * SW;
@@ -101,25 +117,23 @@ __global__ __launch_bounds__(PDM_THREADS) void pdm_demod_kernel(
       if (n >= N) break;
       const long long ts = static_cast<long long>(n) * D - hk;   // first tick of the window
       const int a = static_cast<int>(ts - tb);                   // its bit offset in the staged string
-      float acc = 0.f;
-      if (ts >= 0 && ts + K <= T) {
-        const int w0 = a >> 5, sh = a & 31;
-        for (int k = 0; k < nw; ++k) {
-          const unsigned al = __builtin_amdgcn_alignbit(bm[w0 + k + 1], bm[w0 + k], sh);
-          const int c0 = 4 * k;
+      const int w0 = a >> 5, sh = a & 31;
+      unsigned wd[NW + 1];
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            if (c0 + cc < C) acc += lut[(c0 + cc) * 256 + ((al >> (8 * cc)) & 255u)];
-          }
-        }
-      } else {
-        for (int i = 0; i < K; ++i) {
-          const long long t = ts + i;
-          if (t < 0 || t >= T) continue;
-          const int p = a + i;
-          const float g = grev[i];
-          acc += ((bm[p >> 5] >> (p & 31)) & 1u) ? g : -g;
-        }
+      for (int k = 0; k <= NW; ++k) wd[k] = bm[w0 + k];
+      float part[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int k = 0; k < NW; ++k) {
+        const unsigned al = __builtin_amdgcn_alignbit(wd[k + 1], wd[k], sh);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) part[cc] += lut[(4 * k + cc) * 256 + ((al >> (8 * cc)) & 255u)];
+      }
+      float acc = (part[0] + part[1]) + (part[2] + part[3]);
+      if (ts < 0 || ts + K > T) {
+        // window positions i < lo and i >= hi lie outside the recording
+        const int lo = ts < 0 ? static_cast<int>(ts < -K ? K : -ts) : 0;
+        const int hi = ts + K > T ? static_cast<int>(T - ts > 0 ? T - ts : 0) : K;
+        acc += gcum[lo] + (gcum[K] - gcum[hi > lo ? hi : lo]);
       }
       xf[static_cast<long long>(m) * N + n] = acc;
     }
@@ -136,6 +150,9 @@ int pdm_span_words(int NB, int D, int K) {
   return static_cast<int>((words + 1) & ~1LL);
 }
 
+// byte tables per filter length: 4 per aligned 32-bit word of the window
+int pdm_tables(int K) { return 4 * ((K + 31) / 32); }
+
 size_t pdm_lds_bytes(int M, int SW, int C) {
   return (static_cast<size_t>(M) * SW + static_cast<size_t>(C) * 256) * 4;
 }
@@ -145,19 +162,47 @@ hipError_t launch_pdm_tables(sonar_pdm_s* p, const double* d_taps64, hipStream_t
   hipLaunchKernelGGL(pdm_lut_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d_taps64, p->K, p->C, p->d_lut);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(pdm_taps_f32_kernel, dim3((p->K + 255) / 256), dim3(256), 0, s, d_taps64, p->K, p->d_grev);
+  hipLaunchKernelGGL(pdm_prefix_kernel, dim3(1), dim3(64), 0, s, d_taps64, p->K, p->d_gcum);
   return hipGetLastError();
 }
 
-hipError_t init_pdm_kernel_attributes(size_t lds) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(pdm_demod_kernel),
+namespace {
+
+template <int NW>
+hipError_t set_attr(size_t lds) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(pdm_demod_kernel<NW>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
 }
 
-hipError_t launch_pdm_demod(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s) {
+template <int NW>
+hipError_t launch_nw(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s) {
   const int ntile = (p->N + p->NB - 1) / p->NB;
   const size_t lds = pdm_lds_bytes(p->M, p->SW, p->C);
-  hipLaunchKernelGGL(pdm_demod_kernel, dim3(static_cast<unsigned>(F) * ntile), dim3(PDM_THREADS), lds, s, words,
-                     p->d_lut, p->d_grev, x, p->M, p->W, p->N, p->D, p->K, p->C, p->NB, p->SW, ntile);
+  hipLaunchKernelGGL(pdm_demod_kernel<NW>, dim3(static_cast<unsigned>(F) * ntile), dim3(PDM_THREADS), lds, s, words,
+                     p->d_lut, p->d_gcum, x, p->M, p->W, p->N, p->D, p->K, p->NB, p->SW, ntile);
   return hipGetLastError();
+}
+
+}  // namespace
+
+#define SONAR_PDM_NW_DISPATCH(NAME, NWV, ...)                                            \
+  switch (NWV) {                                                                          \
+    case 1: return NAME<1>(__VA_ARGS__);   case 2: return NAME<2>(__VA_ARGS__);           \
+    case 3: return NAME<3>(__VA_ARGS__);   case 4: return NAME<4>(__VA_ARGS__);           \
+    case 5: return NAME<5>(__VA_ARGS__);   case 6: return NAME<6>(__VA_ARGS__);           \
+    case 7: return NAME<7>(__VA_ARGS__);   case 8: return NAME<8>(__VA_ARGS__);           \
+    case 9: return NAME<9>(__VA_ARGS__);   case 10: return NAME<10>(__VA_ARGS__);         \
+    case 11: return NAME<11>(__VA_ARGS__); case 12: return NAME<12>(__VA_ARGS__);         \
+    case 13: return NAME<13>(__VA_ARGS__); case 14: return NAME<14>(__VA_ARGS__);         \
+    case 15: return NAME<15>(__VA_ARGS__); case 16: return NAME<16>(__VA_ARGS__);         \
+    case 17: return NAME<17>(__VA_ARGS__);                                                \
+    default: return hipErrorInvalidValue;                                                 \
+  }
+
+hipError_t init_pdm_kernel_attributes(const sonar_pdm_s* p, size_t lds) {
+  SONAR_PDM_NW_DISPATCH(set_attr, p->C / 4, lds)
+}
+
+hipError_t launch_pdm_demod(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s) {
+  SONAR_PDM_NW_DISPATCH(launch_nw, p->C / 4, p, words, F, x, s)
 }

@@ -93,6 +93,8 @@ struct sonar_plan_s {
                                // of G_b [max_frames][D][2][NF] (FD)
   float2* d_gband = nullptr;   // gradients (FD): beam-spectrum gradient G_B, [max_frames][D][kb]
   float2* d_gspec = nullptr;   // gradients (FD): conj(C) G_Y on [0, NF], [max_frames][M][NF + 1]
+  float2* d_gy = nullptr;      // gradients: matched-filter gradient for sonar_energyscape_backward
+                               // ([max_frames][M][P] TD, [max_frames][kb][M] FD)
   bool grad_on = false;
   int iir_ns = 0;              // IIR envelope: state dimension (2 per section); 0 = the FIR envelope
   int iir_chunk = 0;           // IIR envelope: window samples per lane, ceil(G'/64)
@@ -115,14 +117,15 @@ constexpr size_t PDM_LDS_LIMIT = 150 * 1024;
 struct sonar_pdm_s {
   int M = 0, N = 0, D = 1, K = 0, C = 0, W = 1, max_frames = 1, device = 0;
   int NB = 0, SW = 0;          // outputs per workgroup, staged words per microphone
-  float* d_lut = nullptr;      // [C][256] byte tables of the reversed taps
-  float* d_grev = nullptr;     // [K] reversed taps, FP32 (windows at the recording's edges)
+  float* d_lut = nullptr;      // [C][256] byte tables of the reversed taps (C = 4 ceil(K/32), zero past K)
+  float* d_gcum = nullptr;     // [K + 1] prefix sums of the reversed taps (windows at the recording's edges)
 };
 
 int pdm_span_words(int NB, int D, int K);
+int pdm_tables(int K);
 size_t pdm_lds_bytes(int M, int SW, int C);
 hipError_t launch_pdm_tables(sonar_pdm_s* p, const double* d_taps64, hipStream_t s);
-hipError_t init_pdm_kernel_attributes(size_t lds);
+hipError_t init_pdm_kernel_attributes(const sonar_pdm_s* p, size_t lds);
 hipError_t launch_pdm_demod(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s);
 
 // FFT twiddle table layout inside d_tw (all FP32 values built from FP64):

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -86,6 +87,7 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_gscr);
   (void)hipFree(p->d_gband);
   (void)hipFree(p->d_gspec);
+  (void)hipFree(p->d_gy);
   (void)hipFree(p->d_iir);
   (void)hipFree(p->d_tw2);
   (void)hipFree(p->d_mt_g);
@@ -338,6 +340,40 @@ double delay_bound(const double* pos, int M, double fs, double c) {
   return bmax * (1.0 + 1e-9) + 1e-9;
 }
 
+// Side streams of sonar_energyscape_multi, one pool per device, created with the device's
+// first plan (outside any graph capture) and kept until the process ends; default priority.
+constexpr int MULTI_SIDE_STREAMS = 3;
+constexpr int MULTI_MAX_DEVICES = 64;
+struct side_pool {
+  bool ready = false;
+  hipStream_t s[MULTI_SIDE_STREAMS] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[MULTI_SIDE_STREAMS] = {};
+  std::mutex mu;
+};
+side_pool g_side_pools[MULTI_MAX_DEVICES];
+std::mutex g_side_pools_mu;
+
+void create_side_pool(int dev) {
+  if (dev < 0 || dev >= MULTI_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_side_pools_mu);
+  side_pool& p = g_side_pools[dev];
+  if (p.ready) return;
+  hipError_t e = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming);
+  for (int i = 0; i < MULTI_SIDE_STREAMS && e == hipSuccess; ++i) {
+    e = hipStreamCreateWithFlags(&p.s[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&p.join[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) p.ready = true;
+  else (void)hipGetLastError();   // without the pool, multi enqueues everything on the caller's stream
+}
+
+side_pool* side_pool_of(int dev) {
+  if (dev < 0 || dev >= MULTI_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_side_pools_mu);
+  return g_side_pools[dev].ready ? &g_side_pools[dev] : nullptr;
+}
+
 int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
   if (!a || !b) return fail(SONAR_E_INVALID, "NULL buffer");
@@ -574,6 +610,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     delete p;
     return fail(SONAR_E_HIP, "hipGetDevice failed");
   }
+  create_side_pool(p->device);
   hipError_t e = init_td_kernel_attributes();
   if (e == hipSuccess) e = init_mt_kernel_attributes();
   if (e != hipSuccess) {
@@ -765,11 +802,49 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
       return fail(st, "multi item %d: %s", i, why.c_str());
     }
   }
-  for (int i = 0; i < n; ++i) {
-    const int st = sonar_energyscape_batch(plans[i], x[i], frames[i], E[i], stream);
-    if (st != SONAR_OK) return st;
+  if (n == 0) return SONAR_OK;
+  side_pool* pool = side_pool_of(plans[0]->device);
+  if (n < 2 || !pool) {
+    for (int i = 0; i < n; ++i) {
+      const int st = sonar_energyscape_batch(plans[i], x[i], frames[i], E[i], stream);
+      if (st != SONAR_OK) return st;
+    }
+    return SONAR_OK;
   }
-  return SONAR_OK;
+  // Independent items run on the caller's stream and the device's side streams, forked from
+  // and joined back into the caller's stream (a graph captured on it gets parallel branches).
+  // Items of one plan share its workspace and stay on one stream, in order.  Items go
+  // largest first to the least loaded stream (load = frames x directions x samples).
+  constexpr int NL = MULTI_SIDE_STREAMS + 1;
+  std::vector<int> order(n), lane(n, -1);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  auto cost = [&](int i) { return static_cast<double>(frames[i]) * plans[i]->D * plans[i]->N; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+  double load[NL] = {0.0};
+  for (int i : order) {
+    for (int j = 0; j < n; ++j)
+      if (lane[j] >= 0 && plans[j] == plans[i]) lane[i] = lane[j];
+    if (lane[i] < 0) lane[i] = static_cast<int>(std::min_element(load, load + NL) - load);
+    load[lane[i]] += cost(i);
+  }
+  std::lock_guard<std::mutex> lk(pool->mu);   // the pool's events are reused by every call
+  bool used[NL] = {false};
+  for (int i = 0; i < n; ++i) used[lane[i]] = true;
+  hipError_t e = hipEventRecord(pool->fork, stream);
+  for (int k = 1; k < NL && e == hipSuccess; ++k)
+    if (used[k]) e = hipStreamWaitEvent(pool->s[k - 1], pool->fork, 0);
+  if (e != hipSuccess) return hip_fail(e, "multi fork");
+  int st = SONAR_OK;
+  for (int i = 0; i < n && st == SONAR_OK; ++i)
+    st = sonar_energyscape_batch(plans[i], x[i], frames[i], E[i], lane[i] == 0 ? stream : pool->s[lane[i] - 1]);
+  // join every branch, also after a failed enqueue, so the caller's stream (and a capture) stays whole
+  for (int k = 1; k < NL; ++k) {
+    if (!used[k]) continue;
+    hipError_t ej = hipEventRecord(pool->join[k - 1], pool->s[k - 1]);
+    if (ej == hipSuccess) ej = hipStreamWaitEvent(stream, pool->join[k - 1], 0);
+    if (ej != hipSuccess && st == SONAR_OK) st = hip_fail(ej, "multi join");
+  }
+  return st;
 }
 
 int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
@@ -846,6 +921,25 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
 }
 
 
+namespace {
+
+// the beam window workspace [max_frames][D][G'] (plans with a fused envelope hold only a placeholder)
+int ensure_beam_workspace(sonar_plan_s* p, size_t* total) {
+  const size_t need = static_cast<size_t>(p->max_frames) * p->D * p->G;
+  if (p->beam_cap >= need) return SONAR_OK;
+  float2* nb = nullptr;
+  if (dev_alloc(&nb, need, total) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(SONAR_E_NOMEM, "beam window workspace (%zu bytes) failed", sizeof(float2) * need);
+  }
+  (void)hipFree(p->d_beam);
+  p->d_beam = nb;
+  p->beam_cap = need;
+  return SONAR_OK;
+}
+
+}  // namespace
+
 int sonar_plan_enable_gradients(sonar_plan p) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
   const bool td = is_td(p);
@@ -859,18 +953,25 @@ int sonar_plan_enable_gradients(sonar_plan p) {
   if (ok && !td)
     ok = dev_alloc(&p->d_gband, mf * p->D * p->kb, &total) == hipSuccess &&
          dev_alloc(&p->d_gspec, mf * p->M * (static_cast<size_t>(p->NF) + 1), &total) == hipSuccess;
+  if (ok)
+    ok = dev_alloc(&p->d_gy, mf * (td ? static_cast<size_t>(p->M) * p->P : static_cast<size_t>(p->kb) * p->M),
+                   &total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     (void)hipFree(p->d_gdl);
     (void)hipFree(p->d_gscr);
     (void)hipFree(p->d_gband);
     (void)hipFree(p->d_gspec);
+    (void)hipFree(p->d_gy);
     p->d_gdl = nullptr;
     p->d_gscr = nullptr;
     p->d_gband = nullptr;
     p->d_gspec = nullptr;
+    p->d_gy = nullptr;
     return fail(SONAR_E_NOMEM, "gradient workspace allocation (%zu bytes) failed", total);
   }
+  const int st = ensure_beam_workspace(p, &total);
+  if (st != SONAR_OK) return st;
   p->ws_bytes += total;
   p->grad_on = true;
   return SONAR_OK;
@@ -892,6 +993,27 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),
                                               dE, F, static_cast<float2*>(dyhat_out), dx_out, dpos_out, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "gradient launch");
+}
+
+int sonar_energyscape_backward(sonar_plan p, const void* x, const float* dE, int32_t F, float* dx_out,
+                               double* dpos_out, hipStream_t stream) {
+  int st = check_exec(p, x, dE, F);
+  if (st != SONAR_OK) return st;
+  if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
+  hipError_t e;
+  const float2* mf;
+  if (is_td(p)) {
+    e = launch_mf_td(p, x, F, p->d_mf, stream);
+    mf = p->d_mf;
+    if (e == hipSuccess) e = launch_das_td_beam(p, mf, F, p->d_beam, stream);
+  } else {
+    e = launch_mf_fd(p, x, F, p->d_fdspec, stream);
+    mf = p->d_fdspec;
+    if (e == hipSuccess) e = launch_fd_gemm(p, mf, F, p->d_bspec, stream);
+    if (e == hipSuccess) e = launch_fd_ifft_beam(p, p->d_bspec, F, p->d_beam, stream);
+  }
+  if (e != hipSuccess) return hip_fail(e, "backward forward pass");
+  return sonar_energyscape_vjp(p, mf, p->d_beam, dE, F, dx_out ? p->d_gy : nullptr, dx_out, dpos_out, stream);
 }
 
 int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t stream) {
@@ -1008,19 +1130,8 @@ int sonar_plan_set_envelope_iir(sonar_plan p, int32_t n_sections, const double* 
   size_t total = 0;
   if (!p->d_iir && dev_alloc(&p->d_iir, static_cast<size_t>(IIR_TAB_LEN), &total) != hipSuccess)
     return fail(SONAR_E_NOMEM, "IIR table allocation failed");
-  // the beam window workspace: plans with a fused envelope hold only a placeholder
-  const size_t beam_need = static_cast<size_t>(p->max_frames) * p->D * p->G;
-  if (p->beam_cap < beam_need) {
-    float2* nb = nullptr;
-    if (dev_alloc(&nb, beam_need, &total) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(SONAR_E_NOMEM, "beam window workspace (%zu bytes) for the IIR envelope failed",
-                  sizeof(float2) * beam_need);
-    }
-    (void)hipFree(p->d_beam);
-    p->d_beam = nb;
-    p->beam_cap = beam_need;
-  }
+  const int st = ensure_beam_workspace(p, &total);
+  if (st != SONAR_OK) return st;
   p->ws_bytes += total;
   hipError_t e = hipMemcpyAsync(p->d_iir, tab.data(), sizeof(float) * IIR_TAB_LEN, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1033,7 +1144,7 @@ int sonar_plan_set_envelope_iir(sonar_plan p, int32_t n_sections, const double* 
 int sonar_pdm_destroy(sonar_pdm p) {
   if (!p) return SONAR_OK;
   (void)hipFree(p->d_lut);
-  (void)hipFree(p->d_grev);
+  (void)hipFree(p->d_gcum);
   delete p;
   return SONAR_OK;
 }
@@ -1075,7 +1186,7 @@ int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* 
   p->N = d.n_out;
   p->D = d.decim;
   p->K = K;
-  p->C = (K + 7) / 8;
+  p->C = pdm_tables(K);
   p->W = (d.n_mics + 31) / 32;
   p->max_frames = d.max_frames;
   if (hipGetDevice(&p->device) != hipSuccess) {
@@ -1097,13 +1208,13 @@ int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* 
   size_t total = 0;
   double* d_taps64 = nullptr;
   bool ok = dev_alloc(&p->d_lut, static_cast<size_t>(p->C) * 256, &total) == hipSuccess &&
-            dev_alloc(&p->d_grev, static_cast<size_t>(K), &total) == hipSuccess &&
+            dev_alloc(&p->d_gcum, static_cast<size_t>(K) + 1, &total) == hipSuccess &&
             hipMalloc(&d_taps64, sizeof(double) * K) == hipSuccess;
   hipError_t e = ok ? hipMemcpyAsync(d_taps64, taps.data(), sizeof(double) * K, hipMemcpyHostToDevice, stream)
                     : hipErrorOutOfMemory;
   if (e == hipSuccess) e = launch_pdm_tables(p, d_taps64, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e == hipSuccess) e = init_pdm_kernel_attributes(pdm_lds_bytes(p->M, p->SW, p->C));
+  if (e == hipSuccess) e = init_pdm_kernel_attributes(p, pdm_lds_bytes(p->M, p->SW, p->C));
   (void)hipFree(d_taps64);
   if (e != hipSuccess) {
     (void)hipGetLastError();

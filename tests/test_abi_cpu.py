@@ -137,6 +137,7 @@ def test_null_arguments_rejected():
     assert lib.sonar_pdm_demodulate(None, None, 1, None, None) == binding.SONAR_E_INVALID
     assert lib.sonar_pdm_destroy(None) == binding.SONAR_OK
     assert lib.sonar_plan_set_envelope_iir(None, 2, None, None) == binding.SONAR_E_INVALID
+    assert lib.sonar_energyscape_backward(None, None, None, 1, None, None, None) == binding.SONAR_E_INVALID
 
 
 @pytest.mark.parametrize("field,value,status", [

@@ -185,6 +185,24 @@ def test_autograd_function_matches_vjp(gpu, torch_mod):
     assert np.array_equal(pos.grad.numpy(), dpos)
 
 
+@pytest.mark.parametrize("mode", ["td", "fd"])
+def test_backward_from_samples_matches_vjp(gpu, torch_mod, mode):
+    """sonar_energyscape_backward (x -> dx, dp in one call) equals matched filter + beamform + VJP."""
+    torch = torch_mod
+    w = synth.make_workload("c1", frames=2, n_dirs=19)
+    _say(f"case backward {mode}: c1 D=19 F=2")
+    plan = _plan(gpu, w, mode, max_frames=2)
+    x = torch.from_numpy(w.x).cuda()
+    dE = torch.from_numpy(np.random.default_rng(np.random.SeedSequence([4, 0, 0, 9]))
+                          .standard_normal((2, plan.D, plan.Q)).astype(np.float32)).cuda()
+    dx, dpos = plan.backward(x, dE)
+    mf = plan.matched_filter(x)
+    _, dx2, dpos2 = plan.vjp(mf, plan.beamform(mf), dE)
+    torch.cuda.synchronize()
+    assert torch.equal(dx, dx2)
+    assert np.array_equal(dpos, dpos2)
+
+
 def _cal_loss_grad(plan, mf, cells, torch):
     """L = -sum of E at the reflector cells, and dL/dp from sonar_energyscape_vjp."""
     beam = plan.beamform(mf)

@@ -75,6 +75,23 @@ def test_network_multi(gpu, torch_mod, network, mode):
         _check_against_oracle(w, E.cpu().numpy(), pl.P, mode, f"sensor {s}")
 
 
+def test_network_multi_shared_plan(gpu, torch_mod, network):
+    """Items that share a plan (and so its workspace) stay ordered on one stream while the
+    other items run beside them: every result equals its own single call."""
+    torch = torch_mod
+    _say("case network multi with a shared plan: td")
+    plans = [_plan(gpu, w, mode="td") for w in network[:3]]
+    xs = [torch.from_numpy(w.x).cuda() for w in network[:3]]
+    x0b = (xs[0] * 0.5).contiguous()
+    items_p = [plans[0], plans[1], plans[0], plans[2], plans[0]]
+    items_x = [xs[0], xs[1], x0b, xs[2], xs[0][:2].contiguous()]
+    Es = gpu.energyscape_multi(items_p, items_x)
+    singles = [pl.energyscape(x) for pl, x in zip(items_p, items_x)]
+    torch.cuda.synchronize()
+    for E, E1 in zip(Es, singles):
+        assert torch.equal(E, E1)
+
+
 def test_network_graph_replay(gpu, torch_mod, network):
     """The multi call captured once in a graph, replayed on new inputs: every replay equals the
     eager result for the same inputs."""

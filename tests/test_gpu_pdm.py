@@ -1,10 +1,13 @@
 """PDM front end on the GPU (sonar_pdm_demodulate) against the FP64 oracle.
 
-Bar: relative L2 error <= 1e-6 per frame and absolute error <= 1e-5 sum|h| everywhere
-(sum|h| bounds |x|: 1 for the unit-gain default filter; the kernel adds ceil(K/8) FP32
-table entries, each an FP64 sum of 8 taps rounded once).  Shapes cover one and several words per
-tick, partial words, ragged last tiles, windows cut by both ends of the recording,
-custom filters, and the full 32 x 16384 x 10 size of the headline workload.
+Bars: every output within 1e-6 sum|h| of the oracle (sum|h| is the full-scale output of
+the +-1 input; the kernel adds 4 ceil(K/32) FP32 table entries, each an FP64 sum of 8 taps
+rounded once, plus, for windows reaching past the recording, an FP32 prefix-sum
+correction of the same scale), and a relative L2 error <= 1e-6 per frame for recordings
+at least one filter long (shorter ones have only edge windows, whose small outputs come
+from that full-scale arithmetic).  Shapes cover one and several words per tick, partial
+words, ragged last tiles, windows cut by both ends of the recording, custom filters, and
+the full 32 x 16384 x 10 size of the headline workload.
 """
 
 import sys
@@ -18,7 +21,7 @@ from workloads import pdm
 pytestmark = pytest.mark.gpu
 
 TOL_REL = 1e-6
-TOL_ABS = 1e-5
+TOL_FULL_SCALE = 1e-6
 
 
 def _say(*args):
@@ -38,11 +41,14 @@ def _words_tensor(torch, words):
 
 def _check(x_gpu, words, M, N, D, taps, label):
     x_o = np.stack([O.pdm_demodulate(words[f], M, N, D, taps) for f in range(words.shape[0])])
-    err_abs = float(np.max(np.abs(x_gpu - x_o)))
+    full_scale = float(np.sum(np.abs(taps)))
+    err_abs = float(np.max(np.abs(x_gpu - x_o))) / full_scale
     err_rel = max(float(np.linalg.norm(x_gpu[f] - x_o[f]) / max(np.linalg.norm(x_o[f]), 1e-30))
                   for f in range(words.shape[0]))
-    _say(f"pdm {label}: rel L2 {err_rel:.2e}, max abs {err_abs:.2e}")
-    assert err_rel <= TOL_REL and err_abs <= TOL_ABS * max(1.0, float(np.sum(np.abs(taps)))), (label, err_rel, err_abs)
+    _say(f"pdm {label}: rel L2 {err_rel:.2e}, max abs / full scale {err_abs:.2e}")
+    assert err_abs <= TOL_FULL_SCALE, (label, err_abs)
+    if N * D >= np.asarray(taps).size:
+        assert err_rel <= TOL_REL, (label, err_rel)
 
 
 def test_pdm_sigma_delta_recording_matches_oracle(gpu, torch_mod):
