@@ -70,13 +70,19 @@ enum sonar_status {
  *              toward the later sample): o = floor(-Dl + 1/2),
  *              b_d[n] = (1/M) sum_m yhat_m[(n + o) mod P]; FP32, same kernels
  *              and buffers as TD_LINEAR with the second weight zero.
+ *  TD_BF16X2 : as TD_BF16 with the samples carried as one BF16 term (the
+ *              weights still split): two products, four MFMAs per K-chunk,
+ *              two BF16 planes per microphone.  Its error is the samples'
+ *              BF16 rounding averaged over the microphones: within 1e-3 for
+ *              arrays of 32 or more microphones (SONAR_PREC_BF16 picks it only
+ *              there).
  *  TD_CUBIC  : 4-point Lagrange (cubic) fractional delay: o = floor(-Dl),
  *              a = -Dl - o, b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(a) yhat_m[n+o+k],
  *              L_k(a) = prod_{j != k} (a - j)/(k - j); FP32 on the TD_LINEAR
  *              kernels, each microphone taken as two two-tap entries.  M <= 64. */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
-  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6
+  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6, SONAR_BF_TD_BF16X2 = 7
 };
 
 /* Element type of the microphone samples x. */
@@ -160,7 +166,8 @@ int sonar_plan_query(sonar_plan plan, int32_t what, int64_t* value);
  *            appends to each frame the same samples as BF16 planes
  *            [M][4][row] (re hi, re lo, im hi, im lo; hi = bf16(v),
  *            lo = bf16(v - hi), round to nearest even), so a frame holds
- *            2*M*row complex64 elements.
+ *            2*M*row complex64 elements; TD_BF16X2 appends [M][2][row]
+ *            (re hi, im hi), 1.5*M*row complex64 elements per frame.
  *            FD modes: [F][Kb][M] (bin-major), element (j, m) holding the
  *            spectrum Yhat_m[k] = beta W X_m conj(S) at bin k = band_lo_bin + j
  *            (Kb = SONAR_Q_BAND_BINS; bins outside are zero by definition).
@@ -240,7 +247,7 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
 /* Precision classes for sonar_plan_create_tuned. */
 enum sonar_precision {
   SONAR_PREC_FP32 = 0,   /* modes within 1e-5 of the definition: TD_LINEAR, FD_FP32, FD_BF16X3  */
-  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, and FD_BF16 for >= 32 mics   */
+  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, and FD_BF16 and TD_BF16X2 for >= 32 mics */
 };
 
 /*

@@ -25,6 +25,11 @@
 // separately, so each K-chunk costs six MFMAs per 32 x 32 output tile.  The
 // matched filter writes the samples already split, as four BF16 planes per
 // microphone (re hi, re lo, im hi, im lo), so staging a tile is a plain copy.
+// With NPL = 2 planes (re, im: TD_BF16X2) the samples are one BF16 term and
+// the product is hi*s + lo*s: four MFMAs per K-chunk.  A weight's rounding is
+// the same for every sample and would add up coherently, so the weights stay
+// split; the samples' rounding is independent from sample to sample and
+// microphone to microphone and averages down in the sum over the array.
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -47,16 +52,17 @@ __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
 // Workgroup: one tile of 32 directions x NWAVE * 128 beam samples of one frame.
 // Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
 // wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
-template <int NWAVE>
+template <int NWAVE, int NPL>
 __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
     int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off) {
-  extern __shared__ unsigned short sm[];    // 4 planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo)
+  extern __shared__ unsigned short sm[];    // NPL planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
   constexpr int NT = NWAVE * 64;
   static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
+  static_assert(NPL == 4 || NPL == 2, "four split planes or two single ones");
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int rho = wv % MT_RES;
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   // first sample of the wavefront, as an index into the staged rows
   const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
   const int plane = MT_MICS * wrow;
-  const int bufsz = 4 * plane;               // one staging buffer: 4 planes x MT_MICS rows
+  const int bufsz = NPL * plane;             // one staging buffer: NPL planes x MT_MICS rows
   const unsigned short* src = planes + f * fstride + s0a;
   // slot -> direction of this tile, kept in LDS past every other region (read by the stores)
   int* permL = reinterpret_cast<int*>(reinterpret_cast<char*>(sm) + perm_off);
@@ -89,7 +95,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
   }
 
   // Staging: rows m0.. of this frame, samples [s0a, s0a + wrow) of each BF16 plane,
-  // copied in 16-byte chunks; chunk i of a microphone group is segment sg = 4 ml + c
+  // copied in 16-byte chunks; chunk i of a microphone group is segment sg = NPL ml + c
   // (plane c of microphone m0 + ml), column k.  Thread t owns chunks t + NT j, j < MT_SPT.
   // Two LDS buffers: the loads for group mc + 1 are in flight while group mc runs.
   const int cw = wrow >> 3;
@@ -107,23 +113,23 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
     sg += 1;                                                                                           \
   }
 #define MT_LD(R_)                                                                                      \
-  R_ = *reinterpret_cast<const uint4*>(src + static_cast<long long>(m0n * 4 + (sg < nseg ? sg : 0)) * row + \
+  R_ = *reinterpret_cast<const uint4*>(src + static_cast<long long>(m0n * NPL + (sg < nseg ? sg : 0)) * row + \
                                         8 * (sg < nseg ? k : 0));                                       \
   MT_ADV
 #define MT_ST(R_)                                                                                      \
-  if (sg < nseg) *reinterpret_cast<uint4*>(dstb + (sg & 3) * plane + (sg >> 2) * wrow + 8 * k) = R_;   \
+  if (sg < nseg) *reinterpret_cast<uint4*>(dstb + (sg % NPL) * plane + (sg / NPL) * wrow + 8 * k) = R_; \
   MT_ADV
 #define MT_STAGE_LOAD(MC)                                                                              \
   {                                                                                                    \
     const int m0n = (MC) * MT_MICS;                                                                    \
-    const int nseg = 4 * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                      \
+    const int nseg = NPL * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                    \
     int sg = sgh, k = kh;                                                                              \
     MT_LD(st0) MT_LD(st1) MT_LD(st2) MT_LD(st3) MT_LD(st4)                                             \
   }
 #define MT_STAGE_STORE(MC, BUF)                                                                        \
   {                                                                                                    \
     const int m0n = (MC) * MT_MICS;                                                                    \
-    const int nseg = 4 * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                      \
+    const int nseg = NPL * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                    \
     unsigned short* dstb = (BUF);                                                                      \
     int sg = sgh, k = kh;                                                                              \
     MT_ST(st0) MT_ST(st1) MT_ST(st2) MT_ST(st3) MT_ST(st4)                                             \
@@ -173,18 +179,30 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
             g_next = gt[2 * (kc + 1)];
           }
           const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+          if constexpr (NPL == 4) {
 #pragma unroll
-          for (int nt = 0; nt < 4; ++nt) {
-            const bf16x8 brh = lds_frag(p + 128 * nt);
-            const bf16x8 brl = lds_frag(p + plane + 128 * nt);
-            const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
-            const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
-            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
-            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
-            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
-            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
-            cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
-            cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
+            for (int nt = 0; nt < 4; ++nt) {
+              const bf16x8 brh = lds_frag(p + 128 * nt);
+              const bf16x8 brl = lds_frag(p + plane + 128 * nt);
+              const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
+              const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
+              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
+              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
+              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
+              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
+              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
+              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
+            }
+          } else {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+              const bf16x8 br = lds_frag(p + 128 * nt);
+              const bf16x8 bi = lds_frag(p + plane + 128 * nt);
+              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, br, cre[nt], 0, 0, 0);
+              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bi, cim[nt], 0, 0, 0);
+              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, br, cre[nt], 0, 0, 0);
+              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bi, cim[nt], 0, 0, 0);
+            }
           }
         }
       }
@@ -319,7 +337,7 @@ __global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
 static size_t mt_perm_offset(const sonar_plan_s* p) {
-  const size_t planes = 2 * 4 * static_cast<size_t>(MT_MICS) * p->mt_wrow * sizeof(unsigned short);
+  const size_t planes = 2 * static_cast<size_t>(mt_planes(p)) * MT_MICS * p->mt_wrow * sizeof(unsigned short);
   const size_t absb = (32 * static_cast<size_t>(MT_NSP) + MT_FIR_TAIL) * sizeof(unsigned int);
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
@@ -327,7 +345,10 @@ static size_t mt_perm_offset(const sonar_plan_s* p) {
 size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * sizeof(int); }
 
 hipError_t init_mt_kernel_attributes() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE, 4>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE, 2>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
@@ -337,11 +358,20 @@ hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F,
   const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
   // the BF16 planes of frame f follow its M complex rows
   const unsigned short* planes = reinterpret_cast<const unsigned short*>(yext + static_cast<long long>(p->M) * p->row);
-  hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
-                     mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
-                     reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
-                     p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K, p->mt_qc, p->mt_nqt,
-                     p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
-                     static_cast<int>(mt_perm_offset(p)));
+  if (mt_planes(p) == 4) {
+    hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE, 4>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
+                       mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
+                       reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
+                       p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
+                       p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                       static_cast<int>(mt_perm_offset(p)));
+  } else {
+    hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE, 2>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
+                       mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
+                       reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
+                       p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
+                       p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                       static_cast<int>(mt_perm_offset(p)));
+  }
   return hipGetLastError();
 }

@@ -158,10 +158,10 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   const long long f = ch / M;
   const int m = static_cast<int>(ch - f * M);
   float2* out = yext + f * fstride + static_cast<long long>(m) * row;
-  // BF16 planes (re hi, re lo, im hi, im lo) of the same samples after the
-  // complex rows of the frame: [M][4][row]
+  // BF16 planes of the same samples after the complex rows of the frame:
+  // [M][4][row] (re hi, re lo, im hi, im lo) or [M][2][row] (re, im)
   unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
-                       static_cast<long long>(m) * 4 * row;
+                       static_cast<long long>(m) * planes * row;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int n = 2 * S::out_index(tid, i) + par;
@@ -169,17 +169,22 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     unsigned short rh = 0, rl = 0, ih = 0, il = 0;
     if (planes) {
       rh = bf16_rne(y.x);
-      rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
       ih = bf16_rne(y.y);
-      il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+      if (planes == 4) {
+        rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
+        il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+      }
     }
     for (int j = (n - origin) & (P - 1); j < row; j += P) {
       out[j] = y;
-      if (planes) {
+      if (planes == 4) {
         pl[j] = rh;
         pl[row + j] = rl;
         pl[2 * row + j] = ih;
         pl[3 * row + j] = il;
+      } else if (planes == 2) {
+        pl[j] = rh;
+        pl[row + j] = ih;
       }
     }
   }
@@ -248,7 +253,7 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
                      p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     p->bf_mode == SONAR_BF_TD_BF16 ? 1 : 0);
+                     mt_planes(p));
   return hipGetLastError();
 }
 

@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ 
   const int m = static_cast<int>(ch - f * M);
   float2* out = yext + f * fstride + static_cast<long long>(m) * row;
   unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
-                       static_cast<long long>(m) * 4 * row;
+                       static_cast<long long>(m) * planes * row;
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) {
     const int n = 2 * (N2 * n1 + n2) + par;
@@ -219,17 +219,22 @@ __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ 
     unsigned short rh = 0, rl = 0, ih = 0, il = 0;
     if (planes) {
       rh = bf16_rne(y.x);
-      rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
       ih = bf16_rne(y.y);
-      il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+      if (planes == 4) {
+        rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
+        il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+      }
     }
     for (int j = (n - origin) & (P - 1); j < row; j += P) {
       out[j] = y;
-      if (planes) {
+      if (planes == 4) {
         pl[j] = rh;
         pl[row + j] = rl;
         pl[2 * row + j] = ih;
         pl[3 * row + j] = il;
+      } else if (planes == 2) {
+        pl[j] = rh;
+        pl[row + j] = ih;
       }
     }
   }
@@ -259,7 +264,7 @@ hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s) 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((big_inv_radix<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, p->d_spec, p->d_tw, p->d_big,
                      yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     p->bf_mode == SONAR_BF_TD_BF16 ? 1 : 0);
+                     mt_planes(p));
   return hipGetLastError();
 }
 

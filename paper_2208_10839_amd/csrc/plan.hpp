@@ -101,6 +101,13 @@ struct sonar_plan_s {
   float* d_iir = nullptr;      // IIR envelope tables (layout: IIR_TAB_LEN below)
 };
 
+// BF16 sample planes per microphone the matched filter appends for the MFMA
+// time-domain beamformer: 4 (re hi, re lo, im hi, im lo) for TD_BF16, 2 (re, im)
+// for TD_BF16X2, 0 for the other modes
+inline int mt_planes(const sonar_plan_s* p) {
+  return p->bf_mode == SONAR_BF_TD_BF16 ? 4 : (p->bf_mode == SONAR_BF_TD_BF16X2 ? 2 : 0);
+}
+
 // IIR envelope tables: A [ns][ns], B [ns], C [ns], D at offset 0 (packed for the
 // section count in use), then A^(chunk 2^k), k < 6, [6][ns][ns] from IIR_POW_OFFSET
 constexpr int IIR_MAX_SECTIONS = 4;

@@ -116,7 +116,7 @@ bool finite_all(const double* v, size_t n) {
 
 bool is_td(const sonar_plan_s* p) {
   return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST ||
-         p->bf_mode == SONAR_BF_TD_CUBIC;
+         p->bf_mode == SONAR_BF_TD_CUBIC || p->bf_mode == SONAR_BF_TD_BF16X2;
 }
 
 // Coordinates z_d in which distances between directions equal distances between their
@@ -307,7 +307,9 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   // every (tile, residue) K-chunk runs on MT_NWAVE / MT_RES wavefronts x 4 output tiles x 6 MFMAs
   long long chunks = 0;
   for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / 2;
-  p->mt_flop_per_frame = chunks * (MT_NWAVE / MT_RES) * 4 * 6 * (2LL * 32 * 32 * 16) * p->mt_nqt;
+  // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples) or 4 (single-term samples)
+  const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : 4;
+  p->mt_flop_per_frame = chunks * (MT_NWAVE / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {   // low-pass: 3 MFMAs per K-step and column block
     const int nval = std::min(32, p->mt_qc - q0);
     p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * 3 * (2LL * 32 * 32 * 16) *
@@ -416,7 +418,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_CUBIC)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_BF16X2)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -541,7 +543,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   const long long need_env = static_cast<long long>(p->td_nqc - 1) * p->td_qc * p->R + 2 * TD_MAX_ROW_PAIRS;
   const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + 2 * TD_MAX_ROW_PAIRS;
   long long row = need_env > need_beam ? need_env : need_beam;
-  if (p->bf_mode == SONAR_BF_TD_BF16) {
+  if (mt_planes(p)) {
     // MFMA tiles: MT_NWAVE * 128 beam samples, rows staged over the tile plus the delay span
     const int ns = MT_NWAVE * 128;
     p->mt_qc = (ns - p->K) / p->R + 1;
@@ -554,7 +556,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
     p->mt_ntiles = (p->D + 31) / 32;
     p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
-    if (4LL * MT_MICS * (p->mt_wrow / 8) > static_cast<long long>(MT_SPT) * MT_NWAVE * 64 ||
+    if (static_cast<long long>(mt_planes(p)) * MT_MICS * (p->mt_wrow / 8) > static_cast<long long>(MT_SPT) * MT_NWAVE * 64 ||
         mt_smem_bytes(p) > 160 * 1024) {
       delete p;
       return fail(SONAR_E_UNSUPPORTED, "array aperture too large for the BF16 time-domain beamformer");
@@ -564,7 +566,8 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   }
   row = (row + 7) / 8 * 8;
   p->row = static_cast<int>(row);
-  p->mf_fstride = static_cast<long long>(p->bf_mode == SONAR_BF_TD_BF16 ? 2 : 1) * p->M * p->row;
+  // complex rows, then (MFMA modes) mt_planes(p) BF16 planes per microphone: 4 BF16 values per complex64
+  p->mf_fstride = static_cast<long long>(p->M) * p->row * (4 + mt_planes(p)) / 4;
   p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
 
   // frequency-domain layout: the stored bins are exactly those the band mask keeps
@@ -670,7 +673,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   }
   e = launch_build_tables(p, stream);
   if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
-  if (e == hipSuccess && p->bf_mode == SONAR_BF_TD_BF16) {
+  if (e == hipSuccess && mt_planes(p)) {
     const int st = build_mt_tables(p, d.mic_pos, d.dirs, taps, stream, &total);
     if (st != SONAR_OK) {
       free_plan(p);
@@ -759,7 +762,7 @@ hipError_t beam_env(const sonar_plan_s* p, const float2* mf, int F, float* E, hi
   }
   if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC)
     return launch_das_td_env(p, mf, F, E, s);
-  if (p->bf_mode == SONAR_BF_TD_BF16) return launch_das_mfma_env(p, mf, F, E, s);
+  if (mt_planes(p)) return launch_das_mfma_env(p, mf, F, E, s);
   hipError_t e = launch_fd_gemm(p, mf, F, p->d_bspec, s);
   if (e != hipSuccess) return e;
   if (p->fd_fused) return launch_fd_ifft_env(p, p->d_bspec, F, E, s);
@@ -855,7 +858,10 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   std::vector<int> modes = {SONAR_BF_TD_LINEAR, SONAR_BF_FD_FP32, SONAR_BF_FD_BF16X3};
   if (precision == SONAR_PREC_BF16) {
     modes.push_back(SONAR_BF_TD_BF16);
-    if (desc->n_mics >= 32) modes.push_back(SONAR_BF_FD_BF16);
+    if (desc->n_mics >= 32) {
+      modes.push_back(SONAR_BF_FD_BF16);
+      modes.push_back(SONAR_BF_TD_BF16X2);
+    }
   }
   const int F = desc->max_frames > 0 ? desc->max_frames : 1;
   const size_t in_bytes = static_cast<size_t>(F) * (desc->n_mics > 0 ? desc->n_mics : 1) *
@@ -1018,8 +1024,8 @@ int sonar_energyscape_backward(sonar_plan p, const void* x, const float* dE, int
 
 int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t stream) {
   if (!p || !mic_pos) return fail(SONAR_E_INVALID, "plan and mic_pos must not be NULL");
-  if (p->bf_mode == SONAR_BF_TD_BF16)
-    return fail(SONAR_E_UNSUPPORTED, "TD_BF16 tiles are built for one geometry: create a new plan");
+  if (mt_planes(p))
+    return fail(SONAR_E_UNSUPPORTED, "TD_BF16 / TD_BF16X2 tiles are built for one geometry: create a new plan");
   for (int i = 0; i < 3 * p->M; ++i)
     if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
   if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC) {
