@@ -127,7 +127,7 @@ def test_tuned_plan(gpu, torch_mod, network, tune):
     torch = torch_mod
     w = network[3]                                     # 16384 samples, 1500 directions
     pl = _plan(gpu, w, tune=tune)
-    allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16"}}
+    allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16", "td_bf16x2"}}
     _say(f"case tuned {tune}: chose {pl.mode}")
     assert pl.mode in allowed[tune]
     E = pl.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
