@@ -6,8 +6,10 @@
 // built and raised to powers on the host in FP64.
 //
 // One wavefront per row: lane c owns the chunk [c L, c L + L) of the window (L =
-// ceil(G'/64)).  Pass 1 runs each chunk from zero state to get its end state e_c;
-// a Hillis-Steele scan over the lanes with the tables A^(L 2^k) turns these into the
+// ceil(G'/64)).  The row is read in steps of IIR_TB samples per chunk: the wave
+// loads 64 chunks x IIR_TB consecutive samples (16 lanes per 128-byte run) into
+// LDS, then each lane runs its chunk's IIR_TB samples from there.  Pass 1 runs
+// each chunk from zero state to get its end state e_c; a Hillis-Steele scan over the lanes with the tables A^(L 2^k) turns these into the
 // true start state of every chunk (start_c = sum_{j<c} A^(L (c-1-j)) e_j); pass 2 reruns
 // each chunk from its start state and writes the subsampled outputs.
 #include <hip/hip_runtime.h>
@@ -15,6 +17,24 @@
 #include "plan.hpp"
 
 namespace {
+
+constexpr int IIR_TB = 16;
+
+// |b| of samples [t0, t0 + IIR_TB) of every chunk into seg[chunk][.] (0 past the chunk or the row)
+__device__ __forceinline__ void stage_abs(const float2* __restrict__ b, float (*seg)[IIR_TB + 1], int t0, int L,
+                                          int G, int lane) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int c = 4 * j + (lane >> 4), tt = lane & 15;
+    const int i = c * L + t0 + tt;
+    float v = 0.f;
+    if (t0 + tt < L && i < G) {
+      const float2 z = b[i];
+      v = sqrtf(z.x * z.x + z.y * z.y);
+    }
+    seg[c][tt] = v;
+  }
+}
 
 template <int NS>
 __device__ __forceinline__ void step(const float* A, const float* B, float* s, float x) {
@@ -34,6 +54,7 @@ template <int NS>
 __global__ __launch_bounds__(64) void iir_env_kernel(const float2* __restrict__ beam, const float* __restrict__ tab,
                                                      float* __restrict__ E, int G, int Q, int R, int hk, int L) {
   __shared__ float t[IIR_TAB_LEN];
+  __shared__ float seg[64][IIR_TB + 1];
   const int lane = threadIdx.x;
   for (int i = lane; i < IIR_TAB_LEN; i += 64) t[i] = tab[i];
   __syncthreads();
@@ -50,9 +71,12 @@ __global__ __launch_bounds__(64) void iir_env_kernel(const float2* __restrict__ 
   float s[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) s[i] = 0.f;
-  for (int i = i0; i < i1; ++i) {
-    const float2 v = b[i];
-    step<NS>(A, B, s, sqrtf(v.x * v.x + v.y * v.y));
+  for (int t0 = 0; t0 < L; t0 += IIR_TB) {
+    stage_abs(b, seg, t0, L, G, lane);
+    __syncthreads();
+    for (int tt = 0; tt < IIR_TB; ++tt)
+      if (i0 + t0 + tt < i1) step<NS>(A, B, s, seg[lane][tt]);
+    __syncthreads();
   }
   // inclusive scan of the chunk end states: V_c = sum_{j<=c} A^(L (c-j)) e_j
 #pragma unroll
@@ -79,19 +103,25 @@ __global__ __launch_bounds__(64) void iir_env_kernel(const float2* __restrict__ 
     s[i] = lane == 0 ? 0.f : v;
   }
   float* e = E + row * Q;
-  for (int i = i0; i < i1; ++i) {
-    const float2 v = b[i];
-    const float x = sqrtf(v.x * v.x + v.y * v.y);
-    if (i >= hk && (i - hk) % R == 0) {
-      const int q = (i - hk) / R;
-      if (q < Q) {
-        float y = Dd * x;
+  for (int t0 = 0; t0 < L; t0 += IIR_TB) {
+    stage_abs(b, seg, t0, L, G, lane);
+    __syncthreads();
+    for (int tt = 0; tt < IIR_TB; ++tt) {
+      const int i = i0 + t0 + tt;
+      if (i >= i1) break;
+      const float x = seg[lane][tt];
+      if (i >= hk && (i - hk) % R == 0) {
+        const int q = (i - hk) / R;
+        if (q < Q) {
+          float y = Dd * x;
 #pragma unroll
-        for (int j = 0; j < NS; ++j) y = fmaf(C[j], s[j], y);
-        e[q] = y;
+          for (int j = 0; j < NS; ++j) y = fmaf(C[j], s[j], y);
+          e[q] = y;
+        }
       }
+      step<NS>(A, B, s, x);
     }
-    step<NS>(A, B, s, x);
+    __syncthreads();
   }
 }
 
