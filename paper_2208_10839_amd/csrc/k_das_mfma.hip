@@ -53,7 +53,7 @@ __device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
 // Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
 // wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
 template <int NWAVE, int NPL>
-__global__ __launch_bounds__(NWAVE * 64) void das_mfma_env_kernel(
+__global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_kernel(
     const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,

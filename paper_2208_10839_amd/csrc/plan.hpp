@@ -155,7 +155,7 @@ __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L 
 // beam samples per workgroup; wavefront w computes the samples of residue
 // w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time
 constexpr int DELAY_MARGIN = 3;   // samples of delay range kept beyond the geometry's bound
-constexpr int MT_NWAVE = 8;
+constexpr int MT_NWAVE = 4;
 // matched filters with NF > 2^MB_LOGN2 run as a radix-(NF / 2^MB_LOGN2) pass over
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
 constexpr int MB_LOGN2 = 14;
