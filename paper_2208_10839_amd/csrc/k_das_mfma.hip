@@ -216,10 +216,10 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 #undef MT_ADV
   __syncthreads();
 
-  // |b| of the tile into LDS as [32][MT_NSP] words {bf16 hi, bf16 lo}: lane holds rows
+  // |b| of the tile into LDS as [32][NSP] words {bf16 hi, bf16 lo}: lane holds rows
   // 8(v/4) + 4(lane/32) + v%4 (directions) of column lane%32 (window sample
   // sw + 128 nt + 4 column) for each output tile
-  constexpr int NSP = MT_NSP;
+  constexpr int NSP = mt_nsp(NWAVE);
   unsigned int* bw = reinterpret_cast<unsigned int*>(sm);
   const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
 #pragma unroll
@@ -338,40 +338,51 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
 static size_t mt_perm_offset(const sonar_plan_s* p) {
   const size_t planes = 2 * static_cast<size_t>(mt_planes(p)) * MT_MICS * p->mt_wrow * sizeof(unsigned short);
-  const size_t absb = (32 * static_cast<size_t>(MT_NSP) + MT_FIR_TAIL) * sizeof(unsigned int);
+  const size_t absb = (32 * static_cast<size_t>(mt_nsp(p->mt_nwave)) + MT_FIR_TAIL) * sizeof(unsigned int);
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
 
 size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * sizeof(int); }
 
-hipError_t init_mt_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE, 4>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<MT_NWAVE, 2>),
+namespace {
+
+template <int NWAVE, int NPL>
+hipError_t set_mt_attr() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
+template <int NWAVE, int NPL>
+hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
   const int nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
   const int tpx = (p->mt_ntiles + nx - 1) / nx;
   const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
+  hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
+                     mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
+                     reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
+                     p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
+                     p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                     static_cast<int>(mt_perm_offset(p)));
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t init_mt_kernel_attributes() {
+  hipError_t e = set_mt_attr<MT_NWAVE_SMALL, 4>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 4>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2>();
+  return e;
+}
+
+hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
   // the BF16 planes of frame f follow its M complex rows
   const unsigned short* planes = reinterpret_cast<const unsigned short*>(yext + static_cast<long long>(p->M) * p->row);
-  if (mt_planes(p) == 4) {
-    hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE, 4>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
-                       mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
-                       reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
-                       p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
-                       p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
-                       static_cast<int>(mt_perm_offset(p)));
-  } else {
-    hipLaunchKernelGGL((das_mfma_env_kernel<MT_NWAVE, 2>), dim3(static_cast<unsigned>(nblk)), dim3(MT_NWAVE * 64),
-                       mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
-                       reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
-                       p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
-                       p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
-                       static_cast<int>(mt_perm_offset(p)));
-  }
-  return hipGetLastError();
+  const bool four = mt_planes(p) == 4;
+  if (p->mt_nwave == MT_NWAVE_SMALL)
+    return four ? launch_mt<MT_NWAVE_SMALL, 4>(p, planes, F, E, s) : launch_mt<MT_NWAVE_SMALL, 2>(p, planes, F, E, s);
+  if (p->mt_nwave == MT_NWAVE_LARGE)
+    return four ? launch_mt<MT_NWAVE_LARGE, 4>(p, planes, F, E, s) : launch_mt<MT_NWAVE_LARGE, 2>(p, planes, F, E, s);
+  return hipErrorInvalidValue;
 }

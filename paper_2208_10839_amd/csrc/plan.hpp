@@ -58,6 +58,7 @@ struct sonar_plan_s {
 
   // time-domain BF16-MFMA beamformer tiling (see k_das_mfma.hip)
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
+  int mt_nwave = 0;     // wavefronts per workgroup (MT_NWAVE_SMALL or MT_NWAVE_LARGE)
   long long mt_flop_per_frame = 0;   // matrix-core flops issued per frame
 
   int device = 0;
@@ -151,23 +152,26 @@ __host__ __device__ inline int fft_tw_len(int NF) { return fft_nhi(NF) + 64 + ff
 //   [.., +64)          : exp(-2 pi i * t / P)        t < 64
 __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L / 64 : 1) + 64 + P / 64 + 1 + 64; }
 
-// time-domain beamformer on BF16 MFMA: tiles of 32 directions x MT_NWAVE * 128
+// time-domain beamformer on BF16 MFMA: tiles of 32 directions x nwave * 128
 // beam samples per workgroup; wavefront w computes the samples of residue
-// w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time
+// w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time.
+// Plans take 4-wave workgroups (two share a CU) and fall back to 8 waves when the
+// staged window of a wide aperture does not fit the 4-wave staging budget.
 constexpr int DELAY_MARGIN = 3;   // samples of delay range kept beyond the geometry's bound
-constexpr int MT_NWAVE = 4;
+constexpr int MT_NWAVE_SMALL = 4;
+constexpr int MT_NWAVE_LARGE = 8;
 // matched filters with NF > 2^MB_LOGN2 run as a radix-(NF / 2^MB_LOGN2) pass over
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
 constexpr int MB_LOGN2 = 14;
 constexpr int MB_MAX_R = 16;
 constexpr int MT_MICS = 8;
-constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: 4 planes x MT_MICS rows x wrow / 8 <= MT_SPT x 512
+constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: planes x MT_MICS rows x wrow / 8 <= MT_SPT x threads
 constexpr int MT_RES = 4;
-constexpr int MT_XCDS = 8;
-// |b| rows in LDS for the matrix-core low-pass (one 32-bit word per sample): MT_NWAVE * 128
+constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that workgroups are spread over
+// |b| rows in LDS for the matrix-core low-pass (one 32-bit word per sample): nwave * 128
 // samples + a zeroed tail, padded so that a row is 16 bytes past a multiple of 256 (bank spread)
-constexpr int MT_NSP = MT_NWAVE * 128 + 4;
-constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row   // accelerator dies (each with its own L2) that workgroups are spread over
+__host__ __device__ constexpr int mt_nsp(int nwave) { return nwave * 128 + 4; }
+constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row
 
 constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)

@@ -304,12 +304,12 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   }
   p->mt_gmax = gmax;
   p->mt_kcmax = kcmax;
-  // every (tile, residue) K-chunk runs on MT_NWAVE / MT_RES wavefronts x 4 output tiles x 6 MFMAs
+  // every (tile, residue) K-chunk runs on nwave / MT_RES wavefronts x 4 output tiles
   long long chunks = 0;
   for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / 2;
   // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples) or 4 (single-term samples)
   const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : 4;
-  p->mt_flop_per_frame = chunks * (MT_NWAVE / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
+  p->mt_flop_per_frame = chunks * (p->mt_nwave / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {   // low-pass: 3 MFMAs per K-step and column block
     const int nval = std::min(32, p->mt_qc - q0);
     p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * 3 * (2LL * 32 * 32 * 16) *
@@ -544,22 +544,29 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   const long long need_beam = static_cast<long long>(p->td_nbc - 1) * p->td_tn + 2 * TD_MAX_ROW_PAIRS;
   long long row = need_env > need_beam ? need_env : need_beam;
   if (mt_planes(p)) {
-    // MFMA tiles: MT_NWAVE * 128 beam samples, rows staged over the tile plus the delay span
-    const int ns = MT_NWAVE * 128;
-    p->mt_qc = (ns - p->K) / p->R + 1;
-    while (p->mt_qc > 0 && (p->mt_qc * p->R) % 4 != 0) p->mt_qc -= 1;
-    if (p->mt_qc < 1) {
-      delete p;
-      return fail(SONAR_E_UNSUPPORTED, "low-pass length %d too long for the BF16 time-domain beamformer", p->K);
-    }
-    p->mt_nqt = (p->Q + p->mt_qc - 1) / p->mt_qc;
-    p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
+    // MFMA tiles: nwave * 128 beam samples, rows staged over the tile plus the delay span;
+    // 4-wave workgroups where the staging fits (two per CU), else 8 waves
     p->mt_ntiles = (p->D + 31) / 32;
     p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
-    if (static_cast<long long>(mt_planes(p)) * MT_MICS * (p->mt_wrow / 8) > static_cast<long long>(MT_SPT) * MT_NWAVE * 64 ||
-        mt_smem_bytes(p) > 160 * 1024) {
+    p->mt_nwave = 0;
+    for (const int nwave : {MT_NWAVE_SMALL, MT_NWAVE_LARGE}) {
+      const int ns = nwave * 128;
+      int qc = (ns - p->K) / p->R + 1;
+      while (qc > 0 && (qc * p->R) % 4 != 0) qc -= 1;
+      if (qc < 1) continue;
+      p->mt_nwave = nwave;
+      p->mt_qc = qc;
+      p->mt_nqt = (p->Q + qc - 1) / qc;
+      p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
+      const size_t lds_cap = nwave == MT_NWAVE_SMALL ? 80 * 1024 : 160 * 1024;
+      if (static_cast<long long>(mt_planes(p)) * MT_MICS * (p->mt_wrow / 8) <= static_cast<long long>(MT_SPT) * nwave * 64 &&
+          mt_smem_bytes(p) <= lds_cap)
+        break;
+      p->mt_nwave = 0;
+    }
+    if (p->mt_nwave == 0) {
       delete p;
-      return fail(SONAR_E_UNSUPPORTED, "array aperture too large for the BF16 time-domain beamformer");
+      return fail(SONAR_E_UNSUPPORTED, "array aperture or low-pass length too large for the BF16 time-domain beamformer");
     }
     const long long need_mt = static_cast<long long>(p->mt_nqt - 1) * p->mt_qc * p->R + p->mt_wrow;
     if (need_mt > row) row = need_mt;
