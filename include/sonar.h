@@ -123,8 +123,10 @@ enum sonar_query {
   SONAR_Q_WORKSPACE_BYTES = 7,/* device bytes owned by the plan                            */
   SONAR_Q_LPF_LEN = 8,        /* K                                                          */
   SONAR_Q_MF_FRAME_ELEMS = 9, /* complex elements per frame of the MF buffer               */
-  SONAR_Q_MATRIX_FLOP_PER_FRAME = 10  /* TD_BF16: matrix-core flops issued per frame by the
+  SONAR_Q_MATRIX_FLOP_PER_FRAME = 10, /* TD_BF16: matrix-core flops issued per frame by the
                                          fused beamformer (padding included); 0 otherwise  */
+  SONAR_Q_MT_WAVES = 11               /* TD_BF16 / TD_BF16X2: wavefronts per beamformer workgroup
+                                         (4: two workgroups per CU; 8: wide apertures); else 0 */
 };
 
 /*
@@ -255,7 +257,10 @@ enum sonar_precision {
  * measurement: every mode of the precision class that the build supports for
  * the descriptor is planned and timed on max_frames frames of zero samples
  * (the kernels' time does not depend on the sample values), and the fastest
- * plan is returned; desc->bf_mode is ignored.  The call synchronises `stream`.
+ * plan is returned; desc->bf_mode is ignored.  The MFMA time-domain modes are
+ * tried with both workgroup shapes (4 and 8 wavefronts of 32 directions x 128
+ * samples each; SONAR_Q_MT_WAVES reports the one kept).  The call synchronises
+ * `stream`.
  *   *chosen_mode (may be NULL) receives the selected enum sonar_bf_mode.
  * Returns the status of sonar_plan_create when no mode can be planned.
  */

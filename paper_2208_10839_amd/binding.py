@@ -29,6 +29,7 @@ DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 Q_RANGE_BINS, Q_BEAM_LEN, Q_FFT_LEN, Q_MF_ROW, Q_MF_ORIGIN = 0, 1, 2, 3, 4
 Q_BAND_LO_BIN, Q_BAND_BINS, Q_WORKSPACE_BYTES, Q_LPF_LEN, Q_MF_FRAME_ELEMS = 5, 6, 7, 8, 9
 Q_MATRIX_FLOP_PER_FRAME = 10
+Q_MT_WAVES = 11
 
 _dp = ctypes.POINTER(ctypes.c_double)
 

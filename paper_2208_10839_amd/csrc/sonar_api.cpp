@@ -376,6 +376,11 @@ side_pool* side_pool_of(int dev) {
   return g_side_pools[dev].ready ? &g_side_pools[dev] : nullptr;
 }
 
+// workgroup size the next plan creation on this thread must give the MFMA beamformer
+// (0: the largest-throughput rule, 4 waves where the staging fits, else 8); set only by
+// sonar_plan_create_tuned while it tries the candidates
+thread_local int g_mt_nwave_hint = 0;
+
 int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
   if (!a || !b) return fail(SONAR_E_INVALID, "NULL buffer");
@@ -550,6 +555,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
     p->mt_nwave = 0;
     for (const int nwave : {MT_NWAVE_SMALL, MT_NWAVE_LARGE}) {
+      if (g_mt_nwave_hint != 0 && nwave != g_mt_nwave_hint) continue;
       const int ns = nwave * 128;
       int qc = (ns - p->K) / p->R + 1;
       while (qc > 0 && (qc * p->R) % 4 != 0) qc -= 1;
@@ -715,6 +721,7 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
     case SONAR_Q_WORKSPACE_BYTES: *value = static_cast<int64_t>(p->ws_bytes); break;
     case SONAR_Q_LPF_LEN: *value = p->K; break;
     case SONAR_Q_MATRIX_FLOP_PER_FRAME: *value = p->mt_flop_per_frame; break;
+    case SONAR_Q_MT_WAVES: *value = p->mt_nwave; break;
     case SONAR_Q_MF_FRAME_ELEMS:
       *value = is_td(p) ? static_cast<int64_t>(p->mf_fstride)
                                                 : static_cast<int64_t>(p->kb) * p->M;
@@ -870,6 +877,16 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
       modes.push_back(SONAR_BF_TD_BF16X2);
     }
   }
+  // candidates: (mode, MFMA workgroup size); the MFMA modes are tried with both tile shapes
+  std::vector<std::pair<int, int>> cands;
+  for (int m : modes) {
+    if (m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2) {
+      cands.push_back({m, MT_NWAVE_SMALL});
+      cands.push_back({m, MT_NWAVE_LARGE});
+    } else {
+      cands.push_back({m, 0});
+    }
+  }
   const int F = desc->max_frames > 0 ? desc->max_frames : 1;
   const size_t in_bytes = static_cast<size_t>(F) * (desc->n_mics > 0 ? desc->n_mics : 1) *
                           (desc->n_samples > 0 ? desc->n_samples : 1) *
@@ -885,11 +902,13 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he == hipSuccess) he = hipMalloc(&xin, in_bytes);
   if (he == hipSuccess) he = hipMemsetAsync(xin, 0, in_bytes, stream);
-  for (size_t i = 0; he == hipSuccess && i < modes.size(); ++i) {
+  for (size_t i = 0; he == hipSuccess && i < cands.size(); ++i) {
     sonar_plan_desc d = *desc;
-    d.bf_mode = modes[i];
+    d.bf_mode = cands[i].first;
     sonar_plan p = nullptr;
+    g_mt_nwave_hint = cands[i].second;
     const int st = sonar_plan_create(&d, stream, &p);
+    g_mt_nwave_hint = 0;
     if (st != SONAR_OK) {
       last_status = st;
       last_msg = sonar_last_error();
@@ -913,7 +932,7 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
       if (best) sonar_plan_destroy(best);
       best = p;
       best_ms = ms;
-      best_mode = modes[i];
+      best_mode = cands[i].first;
     } else {
       sonar_plan_destroy(p);
     }

@@ -128,7 +128,9 @@ def test_tuned_plan(gpu, torch_mod, network, tune):
     w = network[3]                                     # 16384 samples, 1500 directions
     pl = _plan(gpu, w, tune=tune)
     allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16", "td_bf16x2"}}
-    _say(f"case tuned {tune}: chose {pl.mode}")
+    waves = pl.query(gpu.Q_MT_WAVES)
+    _say(f"case tuned {tune}: chose {pl.mode} (MFMA workgroup waves: {waves})")
     assert pl.mode in allowed[tune]
+    assert waves in ((4, 8) if pl.mode.startswith("td_bf16") else (0,))
     E = pl.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
     _check_against_oracle(w, E, pl.P, pl.mode, f"tuned {tune}")
