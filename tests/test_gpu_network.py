@@ -92,12 +92,13 @@ def test_network_multi_shared_plan(gpu, torch_mod, network):
         assert torch.equal(E, E1)
 
 
-def test_network_graph_replay(gpu, torch_mod, network):
+@pytest.mark.parametrize("mode", ["td_bf16", "td_bf16x2"])
+def test_network_graph_replay(gpu, torch_mod, network, mode):
     """The multi call captured once in a graph, replayed on new inputs: every replay equals the
     eager result for the same inputs."""
     torch = torch_mod
-    _say("case network graph replay: td_bf16")
-    plans = [_plan(gpu, w, mode="td_bf16") for w in network]
+    _say(f"case network graph replay: {mode}")
+    plans = [_plan(gpu, w, mode=mode) for w in network]
     xs = [torch.from_numpy(w.x).cuda() for w in network]
     outs = [torch.empty((w.x.shape[0], w.dirs.shape[0], pl.Q), dtype=torch.float32, device="cuda")
             for w, pl in zip(network, plans)]
