@@ -58,7 +58,8 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
     int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off) {
-  extern __shared__ unsigned short sm[];    // NPL planes x MT_MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
+  constexpr int MICS = NPL == 2 ? 2 * MT_MICS : MT_MICS;   // microphones staged per group
+  extern __shared__ unsigned short sm[];    // NPL planes x MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
   constexpr int NT = NWAVE * 64;
   static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
@@ -80,8 +81,8 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   const int s0a = s0 & ~7;                   // staged from here: 16-byte aligned rows
   // first sample of the wavefront, as an index into the staged rows
   const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
-  const int plane = MT_MICS * wrow;
-  const int bufsz = NPL * plane;             // one staging buffer: NPL planes x MT_MICS rows
+  const int plane = MICS * wrow;
+  const int bufsz = NPL * plane;             // one staging buffer: NPL planes x MICS rows
   const unsigned short* src = planes + f * fstride + s0a;
   // slot -> direction of this tile, kept in LDS past every other region (read by the stores)
   int* permL = reinterpret_cast<int*>(reinterpret_cast<char*>(sm) + perm_off);
@@ -121,15 +122,15 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   MT_ADV
 #define MT_STAGE_LOAD(MC)                                                                              \
   {                                                                                                    \
-    const int m0n = (MC) * MT_MICS;                                                                    \
-    const int nseg = NPL * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                    \
+    const int m0n = (MC) * MICS;                                                                       \
+    const int nseg = NPL * (M - m0n < MICS ? M - m0n : MICS);                                          \
     int sg = sgh, k = kh;                                                                              \
     MT_LD(st0) MT_LD(st1) MT_LD(st2) MT_LD(st3) MT_LD(st4)                                             \
   }
 #define MT_STAGE_STORE(MC, BUF)                                                                        \
   {                                                                                                    \
-    const int m0n = (MC) * MT_MICS;                                                                    \
-    const int nseg = NPL * (M - m0n < MT_MICS ? M - m0n : MT_MICS);                                    \
+    const int m0n = (MC) * MICS;                                                                       \
+    const int nseg = NPL * (M - m0n < MICS ? M - m0n : MICS);                                          \
     unsigned short* dstb = (BUF);                                                                      \
     int sg = sgh, k = kh;                                                                              \
     MT_ST(st0) MT_ST(st1) MT_ST(st2) MT_ST(st3) MT_ST(st4)                                             \
@@ -152,7 +153,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   uint4 ah_next = wt[kfirst * 128], al_next = wt[kfirst * 128 + 64];
   int2 g_next = gt[2 * kfirst];
   for (int mc = 0; mc < nmc; ++mc) {
-    const int m0 = mc * MT_MICS;
+    const int m0 = mc * MICS;
     unsigned short* buf = sm + (mc & 1) * bufsz;
     unsigned short* nbuf = sm + ((mc + 1) & 1) * bufsz;
     const bool next = mc + 1 < nmc;
@@ -337,7 +338,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
 static size_t mt_perm_offset(const sonar_plan_s* p) {
-  const size_t planes = 2 * static_cast<size_t>(mt_planes(p)) * MT_MICS * p->mt_wrow * sizeof(unsigned short);
+  const size_t planes = 2 * static_cast<size_t>(mt_planes(p)) * mt_mics(p) * p->mt_wrow * sizeof(unsigned short);
   const size_t absb = (32 * static_cast<size_t>(mt_nsp(p->mt_nwave)) + MT_FIR_TAIL) * sizeof(unsigned int);
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }

@@ -164,7 +164,9 @@ constexpr int MT_NWAVE_LARGE = 8;
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
 constexpr int MB_LOGN2 = 14;
 constexpr int MB_MAX_R = 16;
-constexpr int MT_MICS = 8;
+constexpr int MT_MICS = 8;      // microphones staged per group with four planes (16 with two)
+// microphones staged per group: the staged bytes per group stay the same for both plane counts
+inline int mt_mics(const sonar_plan_s* p) { return mt_planes(p) == 2 ? 2 * MT_MICS : MT_MICS; }
 constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: planes x MT_MICS rows x wrow / 8 <= MT_SPT x threads
 constexpr int MT_RES = 4;
 constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that workgroups are spread over

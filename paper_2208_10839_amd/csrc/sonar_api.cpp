@@ -211,7 +211,8 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   std::vector<int> order(D);
   for (int d = 0; d < D; ++d) order[d] = d;
   kd_tiles(order, 0, D, z);
-  const int nt = (D + 31) / 32, nmc = (M + MT_MICS - 1) / MT_MICS;
+  const int mics = mt_mics(p);
+  const int nt = (D + 31) / 32, nmc = (M + mics - 1) / mics;
   std::vector<int> perm(static_cast<size_t>(nt) * 32, -1);
   for (int i = 0; i < D; ++i) perm[i] = order[i];
   const int nlist = nt * MT_RES;   // group list per (tile, residue)
@@ -224,7 +225,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
       std::vector<int2>& gl = groups[t * MT_RES + rho];
       std::vector<char>& pl = pad[t * MT_RES + rho];
       for (int mc = 0; mc < nmc; ++mc) {
-        const int m0 = mc * MT_MICS, m1 = std::min(M, m0 + MT_MICS);
+        const int m0 = mc * mics, m1 = std::min(M, m0 + mics);
         const int g0 = static_cast<int>(gl.size());
         for (int m = m0; m < m1; ++m) {
           int rmin = 1 << 30, rmax = -(1 << 30);
@@ -552,7 +553,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     // MFMA tiles: nwave * 128 beam samples, rows staged over the tile plus the delay span;
     // 4-wave workgroups where the staging fits (two per CU), else 8 waves
     p->mt_ntiles = (p->D + 31) / 32;
-    p->mt_nmc = (p->M + MT_MICS - 1) / MT_MICS;
+    p->mt_nmc = (p->M + mt_mics(p) - 1) / mt_mics(p);
     p->mt_nwave = 0;
     for (const int nwave : {MT_NWAVE_SMALL, MT_NWAVE_LARGE}) {
       if (g_mt_nwave_hint != 0 && nwave != g_mt_nwave_hint) continue;
@@ -565,7 +566,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
       p->mt_nqt = (p->Q + qc - 1) / qc;
       p->mt_wrow = (4 + ns + p->spread + 16 + 7) / 8 * 8;   // window start aligned down by 0 or 4
       const size_t lds_cap = nwave == MT_NWAVE_SMALL ? 80 * 1024 : 160 * 1024;
-      if (static_cast<long long>(mt_planes(p)) * MT_MICS * (p->mt_wrow / 8) <= static_cast<long long>(MT_SPT) * nwave * 64 &&
+      if (static_cast<long long>(mt_planes(p)) * mt_mics(p) * (p->mt_wrow / 8) <= static_cast<long long>(MT_SPT) * nwave * 64 &&
           mt_smem_bytes(p) <= lds_cap)
         break;
       p->mt_nwave = 0;
