@@ -79,10 +79,26 @@ enum sonar_status {
  *  TD_CUBIC  : 4-point Lagrange (cubic) fractional delay: o = floor(-Dl),
  *              a = -Dl - o, b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(a) yhat_m[n+o+k],
  *              L_k(a) = prod_{j != k} (a - j)/(k - j); FP32 on the TD_LINEAR
- *              kernels, each microphone taken as two two-tap entries.  M <= 64. */
+ *              kernels, each microphone taken as two two-tap entries.  M <= 64.
+ *  TD_F16    : TD_LINEAR with the fractional delay on a grid of 1/2048
+ *              sample (alpha = rint(2048 (-Dl - o)) / 2048, o = floor(-Dl),
+ *              alpha = 1 taken as o + 1, alpha = 0), computed on FP16 MFMA
+ *              with FP32 accumulation: the weights 1 - alpha and alpha are
+ *              exact in FP16, the samples are one FP16 term scaled per frame
+ *              by a power of two 2^e chosen from a bound on |yhat| (so the
+ *              scaled samples stay below 2^14), and E is scaled back by
+ *              2^-e / M in FP32.  Two products (re, im), two MFMAs per
+ *              K-chunk, two FP16 planes per microphone.  The grid moves a
+ *              delay by at most 1/4096 sample; with the samples' FP16
+ *              rounding the result is within about 1e-4 of TD_LINEAR.
+ *              Samples below 2^-28 of the frame's bound are FP16 subnormals
+ *              (less relative precision, far below the 1e-4 scale of the
+ *              error); e is clamped to [-100, 100], so frames whose bound
+ *              lies outside [2^-86, 2^114] overflow or underflow. */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
-  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6, SONAR_BF_TD_BF16X2 = 7
+  SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6, SONAR_BF_TD_BF16X2 = 7,
+  SONAR_BF_TD_F16 = 8
 };
 
 /* Element type of the microphone samples x. */
@@ -123,9 +139,9 @@ enum sonar_query {
   SONAR_Q_WORKSPACE_BYTES = 7,/* device bytes owned by the plan                            */
   SONAR_Q_LPF_LEN = 8,        /* K                                                          */
   SONAR_Q_MF_FRAME_ELEMS = 9, /* complex elements per frame of the MF buffer               */
-  SONAR_Q_MATRIX_FLOP_PER_FRAME = 10, /* TD_BF16: matrix-core flops issued per frame by the
+  SONAR_Q_MATRIX_FLOP_PER_FRAME = 10, /* MFMA TD modes: matrix-core flops issued per frame by the
                                          fused beamformer (padding included); 0 otherwise  */
-  SONAR_Q_MT_WAVES = 11               /* TD_BF16 / TD_BF16X2: wavefronts per beamformer workgroup
+  SONAR_Q_MT_WAVES = 11               /* MFMA TD modes: wavefronts per beamformer workgroup
                                          (4: two workgroups per CU; 8: wide apertures); else 0 */
 };
 
@@ -169,7 +185,12 @@ int sonar_plan_query(sonar_plan plan, int32_t what, int64_t* value);
  *            [M][4][row] (re hi, re lo, im hi, im lo; hi = bf16(v),
  *            lo = bf16(v - hi), round to nearest even), so a frame holds
  *            2*M*row complex64 elements; TD_BF16X2 appends [M][2][row]
- *            (re hi, im hi), 1.5*M*row complex64 elements per frame.
+ *            (re hi, im hi), 1.5*M*row complex64 elements per frame;
+ *            TD_F16 appends [M][2][row] FP16 planes (re, im of 2^e yhat)
+ *            and one 16-byte frame header whose first float is 2^-e / M,
+ *            1.5*M*row + 2 complex64 elements per frame (the beamformer
+ *            reads the scale from there, so a buffer stays valid for
+ *            sonar_beamform_envelope after later matched-filter calls).
  *            FD modes: [F][Kb][M] (bin-major), element (j, m) holding the
  *            spectrum Yhat_m[k] = beta W X_m conj(S) at bin k = band_lo_bin + j
  *            (Kb = SONAR_Q_BAND_BINS; bins outside are zero by definition).
@@ -249,7 +270,7 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
 /* Precision classes for sonar_plan_create_tuned. */
 enum sonar_precision {
   SONAR_PREC_FP32 = 0,   /* modes within 1e-5 of the definition: TD_LINEAR, FD_FP32, FD_BF16X3  */
-  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, and FD_BF16 and TD_BF16X2 for >= 32 mics */
+  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, TD_F16, and FD_BF16 and TD_BF16X2 for >= 32 mics */
 };
 
 /*
@@ -329,7 +350,7 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
  * sonar_plan_set_positions -- new microphone positions [M][3] (metres): the
  * delay tables (§4.1 delays) are rebuilt on `stream` without reallocating,
  * ordered after the work already queued there.  TD_LINEAR and FD modes;
- * SONAR_E_UNSUPPORTED for TD_BF16 (its tiles are built for one geometry) and for
+ * SONAR_E_UNSUPPORTED for the MFMA TD modes (their tiles are built for one geometry) and for
  * a TD_LINEAR plan whose new geometry needs delays outside the plan's range
  * (the plan keeps 3 samples of slack on each side of the geometry it was
  * created with).
@@ -337,7 +358,9 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
 /* (TD_NEAREST and TD_CUBIC plans move like TD_LINEAR ones.  TD_NEAREST's dL/dp is zero
  * almost everywhere, so sonar_energyscape_vjp returns SONAR_E_UNSUPPORTED for dpos_out on
- * it; TD_CUBIC has no gradient kernels (SONAR_E_UNSUPPORTED).) */
+ * it, and on TD_F16, whose delays lie on a 1/2048-sample grid; dx_out of a TD_F16 plan is the
+ * adjoint of TD_LINEAR on the gridded delays; TD_CUBIC has no gradient kernels
+ * (SONAR_E_UNSUPPORTED).) */
 
 /*
  * PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density

@@ -26,6 +26,7 @@ from .sonar_oracle import (  # noqa: F401
     energyscape,
     energyscape_vjp_fd,
     energyscape_vjp_td,
+    gridded_offsets,
     lagrange4_weights,
     lfilter,
     envelope,

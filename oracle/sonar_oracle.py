@@ -119,21 +119,33 @@ def td_offsets(Dl):
     return o.astype(np.int64), (-Dl - o)
 
 
+def gridded_offsets(Dl, steps: int):
+    """td_offsets with alpha rounded to a multiple of 1/steps (half-way cases to even):
+    alpha' = rint(steps alpha) / steps; alpha' = 1 is taken as offset o + 1 with alpha' = 0.
+    (A reading of this build, not of the paper: the fractional delay on a grid of 1/steps
+    sample, which makes the interpolation weights exact in a short floating-point format.)"""
+    o, alpha = td_offsets(Dl)
+    a = np.rint(alpha * steps) / steps
+    up = a >= 1.0
+    return o + up.astype(np.int64), np.where(up, 0.0, a)
+
+
 # ---------------------------------------------------------------------------
 # Delay-and-sum beamforming (§4.1: simple delay-and-sum steering; §4.3: a device
 # kernel on the GPU).
 # ---------------------------------------------------------------------------
 
-def das_td(yhat, Dl, n_idx) -> np.ndarray:
+def das_td(yhat, Dl, n_idx, alpha_steps: int | None = None) -> np.ndarray:
     """Fractional-delay DAS with linear interpolation, circular in P.
 
     b_d[n] = (1/M) sum_m [(1 - alpha) yhat_m[(n + o) mod P] + alpha yhat_m[(n + o + 1) mod P]]
-    evaluated at the sample indices n_idx (which may be negative).
+    evaluated at the sample indices n_idx (which may be negative).  With alpha_steps, o and
+    alpha come from gridded_offsets.
     Returns complex128 [D][len(n_idx)].
     """
     yhat = np.asarray(yhat)
     M, P = yhat.shape
-    o, alpha = td_offsets(Dl)
+    o, alpha = td_offsets(Dl) if alpha_steps is None else gridded_offsets(Dl, alpha_steps)
     n_idx = np.asarray(n_idx, dtype=np.int64)
     D = o.shape[0]
     b = np.zeros((D, n_idx.size), dtype=np.complex128)
@@ -330,9 +342,10 @@ def envelope_iir(b_win, bcoef, acoef, Q: int, R: int, K: int) -> np.ndarray:
 
 def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None = None,
                 gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
-                dir_index=None, return_beam: bool = False, iir=None):
+                dir_index=None, return_beam: bool = False, iir=None, alpha_steps: int | None = None):
     """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation), 'td_nearest' (integer
-    delays), 'td_cubic' (4-point Lagrange interpolation) or 'fd' (exact).
+    delays), 'td_cubic' (4-point Lagrange interpolation) or 'fd' (exact).  alpha_steps (mode
+    'td') puts the fractional delays on a grid of 1/alpha_steps sample (gridded_offsets).
 
     dir_index selects a subset of directions (rows of the result follow it).
     With return_beam, also returns the complex beam window b[d][G'].
@@ -357,7 +370,7 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
     Dl = delays(mic_pos, u, fs, c)
     n_idx = beam_window_indices(n0, Q, R, K)
     if mode == "td":
-        b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
+        b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx, alpha_steps)
     elif mode == "td_nearest":
         b = das_td_nearest(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
     elif mode == "td_cubic":

@@ -8,16 +8,17 @@
 // dense product.  Directions are grouped into tiles of 32 neighbours (plan
 // time, compact in delay space), so within a tile the
 // integer offsets o[d][m] of one microphone span only a few samples.  For
-// each microphone the tile covers that span with groups of 8 consecutive
+// each microphone the tile covers that span with groups of 4 consecutive
 // taps; the tap weights form a sparse 32 x K matrix W (two nonzeros per
 // direction and microphone) and the samples a Hankel matrix
 //   Y[(m, toff + j)][n] = yhat_m[n + toff + j],
 // so b = W Y runs on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  A
-// B-operand fragment (8 consecutive taps of one sample) is 8 consecutive
-// samples of one row.  The 32 columns of an output tile are samples
-// 4c + rho of one residue rho, and the tap groups used for residue rho start
-// at t0 with t0 + rho = 0 mod 4, so every fragment read starts on an 8-byte
-// boundary.
+// B-operand fragment (8 consecutive K rows of one sample) is two groups:
+// 4 consecutive samples of one row each (with four planes, 8 consecutive
+// samples of one row: the groups come in pairs).  The 32 columns of an output tile
+// are samples 4c + rho of one residue rho, and the tap groups used for
+// residue rho start at t0 with t0 + rho = 0 mod 4, so every group read is
+// one aligned 8-byte load.
 //
 // Precision: weights and samples are each carried as two BF16 terms
 // (hi = bf16(v), lo = bf16(v - hi)); the product keeps hi*hi + hi*lo + lo*hi
@@ -30,6 +31,12 @@
 // the same for every sample and would add up coherently, so the weights stay
 // split; the samples' rounding is independent from sample to sample and
 // microphone to microphone and averages down in the sum over the array.
+//
+// F16 (TD_F16): the fractional delays lie on a 1/2048-sample grid, so the
+// weights 1 - alpha and alpha are exact in FP16; the samples are one FP16
+// term of 2^e yhat (e per frame, from the matched filter's bound on |yhat|),
+// and v_mfma_f32_32x32x16_f16 takes two MFMAs per K-chunk (re, im).  The
+// energyscape is scaled back by the frame header's 2^-e / M at the store.
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
@@ -37,24 +44,34 @@
 namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 
-// 8 BF16 values at an 8-byte aligned LDS address
-__device__ __forceinline__ bf16x8 lds_frag(const unsigned short* p) {
+// 4 + 4 16-bit values at two 8-byte aligned LDS addresses
+__device__ __forceinline__ uint4 lds_frag(const unsigned short* p, const unsigned short* q) {
   const uint2 a = *reinterpret_cast<const uint2*>(p);
-  const uint2 b = *reinterpret_cast<const uint2*>(p + 4);
-  return __builtin_bit_cast(bf16x8, make_uint4(a.x, a.y, b.x, b.y));
+  const uint2 b = *reinterpret_cast<const uint2*>(q);
+  return make_uint4(a.x, a.y, b.x, b.y);
+}
+
+__device__ __forceinline__ f32x16 mfma_bf16(uint4 a, uint4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c, 0, 0,
+                                                 0);
+}
+
+__device__ __forceinline__ f32x16 mfma_f16(uint4 a, uint4 b, f32x16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
 // Workgroup: one tile of 32 directions x NWAVE * 128 beam samples of one frame.
 // Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
 // wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
-template <int NWAVE, int NPL>
+template <int NWAVE, int NPL, bool F16>
 __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_kernel(
-    const unsigned short* __restrict__ planes, long long fstride, const int2* __restrict__ gtab,
+    const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
     int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off) {
@@ -64,6 +81,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   constexpr int NT = NWAVE * 64;
   static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
   static_assert(NPL == 4 || NPL == 2, "four split planes or two single ones");
+  static_assert(!F16 || NPL == 2, "FP16 samples come as two planes");
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   const int rho = wv % MT_RES;
@@ -146,12 +164,14 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   // the one-ahead prefetch of weight fragments runs across group and half boundaries.
   const int li = tile * MT_RES + rho;
   const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-  const int2* gt = gtab + static_cast<long long>(li) * gmax + (lane >> 5);
+  // K-chunk kc: groups 4 kc .. 4 kc + 3; lanes 0-31 read the first two, lanes 32-63 the others
+  const int4* gt = gtab + static_cast<long long>(li) * (gmax / 2) + (lane >> 5);
   const int kend = kcr[(tile * nmc + nmc - 1) * MT_RES + rho].y;
   int kfirst = kcr[tile * nmc * MT_RES + rho].x;
   if (kfirst >= kend) kfirst = 0;            // no chunks at all: harmless in-table prefetch
-  uint4 ah_next = wt[kfirst * 128], al_next = wt[kfirst * 128 + 64];
-  int2 g_next = gt[2 * kfirst];
+  // weight fragments: hi and lo BF16 terms, or the one exact FP16 term
+  uint4 ah_next = wt[kfirst * 128], al_next = F16 ? make_uint4(0, 0, 0, 0) : wt[kfirst * 128 + 64];
+  int4 g_next = gt[2 * kfirst];
   for (int mc = 0; mc < nmc; ++mc) {
     const int m0 = mc * MICS;
     unsigned short* buf = sm + (mc & 1) * bufsz;
@@ -171,38 +191,48 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
       const int ka = hk ? kmid : kr.x, kb = hk ? kr.y : kmid;
       {
         for (int kc = ka; kc < kb; ++kc) {
-          const bf16x8 ah = __builtin_bit_cast(bf16x8, ah_next);
-          const bf16x8 al = __builtin_bit_cast(bf16x8, al_next);
-          const int2 g = g_next;
+          const uint4 ah = ah_next;
+          const uint4 al = al_next;
+          const int4 g = g_next;
           if (kc + 1 < kend) {
             ah_next = wt[(kc + 1) * 128];
-            al_next = wt[(kc + 1) * 128 + 64];
+            if constexpr (!F16) al_next = wt[(kc + 1) * 128 + 64];
             g_next = gt[2 * (kc + 1)];
           }
           const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+          // four planes: the two groups are always taps t, t + 4 of one microphone (registers are short)
+          const unsigned short* p2 = NPL == 4 ? p + 4 : buf + (g.z - m0) * wrow + g.w + sb + 4 * (lane & 31);
           if constexpr (NPL == 4) {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-              const bf16x8 brh = lds_frag(p + 128 * nt);
-              const bf16x8 brl = lds_frag(p + plane + 128 * nt);
-              const bf16x8 bih = lds_frag(p + 2 * plane + 128 * nt);
-              const bf16x8 bil = lds_frag(p + 3 * plane + 128 * nt);
-              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brh, cre[nt], 0, 0, 0);
-              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bih, cim[nt], 0, 0, 0);
-              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, brl, cre[nt], 0, 0, 0);
-              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bil, cim[nt], 0, 0, 0);
-              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, brh, cre[nt], 0, 0, 0);
-              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bih, cim[nt], 0, 0, 0);
+              const uint4 brh = lds_frag(p + 128 * nt, p2 + 128 * nt);
+              const uint4 brl = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+              const uint4 bih = lds_frag(p + 2 * plane + 128 * nt, p2 + 2 * plane + 128 * nt);
+              const uint4 bil = lds_frag(p + 3 * plane + 128 * nt, p2 + 3 * plane + 128 * nt);
+              cre[nt] = mfma_bf16(ah, brh, cre[nt]);
+              cim[nt] = mfma_bf16(ah, bih, cim[nt]);
+              cre[nt] = mfma_bf16(ah, brl, cre[nt]);
+              cim[nt] = mfma_bf16(ah, bil, cim[nt]);
+              cre[nt] = mfma_bf16(al, brh, cre[nt]);
+              cim[nt] = mfma_bf16(al, bih, cim[nt]);
+            }
+          } else if constexpr (F16) {
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+              const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
+              const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+              cre[nt] = mfma_f16(ah, br, cre[nt]);
+              cim[nt] = mfma_f16(ah, bi, cim[nt]);
             }
           } else {
 #pragma unroll
             for (int nt = 0; nt < 4; ++nt) {
-              const bf16x8 br = lds_frag(p + 128 * nt);
-              const bf16x8 bi = lds_frag(p + plane + 128 * nt);
-              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, br, cre[nt], 0, 0, 0);
-              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bi, cim[nt], 0, 0, 0);
-              cre[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, br, cre[nt], 0, 0, 0);
-              cim[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bi, cim[nt], 0, 0, 0);
+              const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
+              const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+              cre[nt] = mfma_bf16(ah, br, cre[nt]);
+              cim[nt] = mfma_bf16(ah, bi, cim[nt]);
+              cre[nt] = mfma_bf16(al, br, cre[nt]);
+              cim[nt] = mfma_bf16(al, bi, cim[nt]);
             }
           }
         }
@@ -312,6 +342,15 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
       }
     }
     const int d = permL[lane & 31];
+    if constexpr (F16) {
+      // frame header: 2^-e / M
+      const float esc = *reinterpret_cast<const float*>(planes + f * fstride + 2LL * M * row);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        acc[v] *= esc;
+        acc2[v] *= esc;
+      }
+    }
     if (d >= 0) {
       float* erow = E + (static_cast<long long>(f) * D + d) * Q + static_cast<long long>(qt) * qc;
 #pragma unroll
@@ -347,19 +386,19 @@ size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * si
 
 namespace {
 
-template <int NWAVE, int NPL>
+template <int NWAVE, int NPL, bool F16>
 hipError_t set_mt_attr() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL, F16>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
-template <int NWAVE, int NPL>
+template <int NWAVE, int NPL, bool F16>
 hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
   const int nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
   const int tpx = (p->mt_ntiles + nx - 1) / nx;
   const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
-  hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
-                     mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, p->d_mt_g,
+  hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL, F16>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
+                     mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, reinterpret_cast<const int4*>(p->d_mt_g),
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
                      p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
@@ -370,20 +409,26 @@ hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F,
 }  // namespace
 
 hipError_t init_mt_kernel_attributes() {
-  hipError_t e = set_mt_attr<MT_NWAVE_SMALL, 4>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 4>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2>();
+  hipError_t e = set_mt_attr<MT_NWAVE_SMALL, 4, false>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2, false>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2, true>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 4, false>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, false>();
+  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, true>();
   return e;
 }
 
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
   // the BF16 planes of frame f follow its M complex rows
   const unsigned short* planes = reinterpret_cast<const unsigned short*>(yext + static_cast<long long>(p->M) * p->row);
-  const bool four = mt_planes(p) == 4;
+  const bool four = mt_planes(p) == 4, f16 = mt_f16(p);
   if (p->mt_nwave == MT_NWAVE_SMALL)
-    return four ? launch_mt<MT_NWAVE_SMALL, 4>(p, planes, F, E, s) : launch_mt<MT_NWAVE_SMALL, 2>(p, planes, F, E, s);
+    return four  ? launch_mt<MT_NWAVE_SMALL, 4, false>(p, planes, F, E, s)
+           : f16 ? launch_mt<MT_NWAVE_SMALL, 2, true>(p, planes, F, E, s)
+                 : launch_mt<MT_NWAVE_SMALL, 2, false>(p, planes, F, E, s);
   if (p->mt_nwave == MT_NWAVE_LARGE)
-    return four ? launch_mt<MT_NWAVE_LARGE, 4>(p, planes, F, E, s) : launch_mt<MT_NWAVE_LARGE, 2>(p, planes, F, E, s);
+    return four  ? launch_mt<MT_NWAVE_LARGE, 4, false>(p, planes, F, E, s)
+           : f16 ? launch_mt<MT_NWAVE_LARGE, 2, true>(p, planes, F, E, s)
+                 : launch_mt<MT_NWAVE_LARGE, 2, false>(p, planes, F, E, s);
   return hipErrorInvalidValue;
 }

@@ -126,7 +126,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
 template <int LOGNF>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
-    long long fstride, int M, int row, int origin, int P, int planes) {
+    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -158,18 +158,26 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   const long long f = ch / M;
   const int m = static_cast<int>(ch - f * M);
   float2* out = yext + f * fstride + static_cast<long long>(m) * row;
-  // BF16 planes of the same samples after the complex rows of the frame:
+  // 16-bit planes of the same samples after the complex rows of the frame:
   // [M][4][row] (re hi, re lo, im hi, im lo) or [M][2][row] (re, im)
   unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
                        static_cast<long long>(m) * planes * row;
+  // TD_F16: FP16 planes of 2^e yhat (e from the frame's channel bounds), 2^-e / M in the frame header
+  float sc = 0.f;
+  if (fbound) {
+    const int e = mf_f16_exponent(fbound, f, M);
+    sc = ldexpf(1.0f, e);
+    if (m == 0 && par == 0 && tid == 0)
+      *reinterpret_cast<float*>(yext + f * fstride + mf_f16_header(M, row)) = ldexpf(1.0f / static_cast<float>(M), -e);
+  }
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const int n = 2 * S::out_index(tid, i) + par;
     const float2 y = make_float2((v[i].x + sgn * ny.x) * inv_p, (v[i].y + sgn * ny.y) * inv_p);
     unsigned short rh = 0, rl = 0, ih = 0, il = 0;
     if (planes) {
-      rh = bf16_rne(y.x);
-      ih = bf16_rne(y.y);
+      rh = mf_plane_word(y.x, sc);
+      ih = mf_plane_word(y.y, sc);
       if (planes == 4) {
         rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
         il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
@@ -250,10 +258,11 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
                      static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess && mt_f16(p)) e = launch_mf_bound(p, F, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
                      p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p));
+                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr);
   return hipGetLastError();
 }
 
@@ -276,6 +285,34 @@ hipError_t launch_mf_td_dt(const sonar_plan_s* p, const void* x, int F, float2* 
 }
 
 }  // namespace
+
+namespace {
+
+// (1/P) sum_{k <= NF} |Yhat[k]| per channel: the inverse transform sums NF + 1 terms of these
+// magnitudes (times unit phases) over P, so this bounds |yhat[n]| for every n
+__global__ __launch_bounds__(256) void mf_bound_kernel(const float2* __restrict__ spec, int NF, float inv_p,
+                                                       float* __restrict__ bound) {
+  __shared__ float part[4];
+  const long long ch = blockIdx.x;
+  const float2* sp = spec + ch * (NF + 1);
+  float acc = 0.f;
+  for (int k = threadIdx.x; k <= NF; k += 256) {
+    const float2 v = sp[k];
+    acc += sqrtf(v.x * v.x + v.y * v.y);
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) bound[ch] = ((part[0] + part[1]) + (part[2] + part[3])) * inv_p;
+}
+
+}  // namespace
+
+hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s) {
+  hipLaunchKernelGGL(mf_bound_kernel, dim3(static_cast<unsigned>(F) * p->M), dim3(256), 0, s, p->d_spec, p->NF,
+                     1.0f / static_cast<float>(p->P), p->d_fbound);
+  return hipGetLastError();
+}
 
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
   if (p->NF > (1 << MB_LOGN2)) return launch_mf_big_td(p, x, F, yext, s);

@@ -190,7 +190,7 @@ template <int R>
 __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ spec, const float2* __restrict__ tw_g,
                                                      const float2* __restrict__ scratch, float2* __restrict__ yext,
                                                      long long fstride, int M, int row, int origin, int P,
-                                                     int planes) {
+                                                     int planes, const float* __restrict__ fbound) {
   constexpr int NF = R * N2;
   const int n2 = blockIdx.x * 256 + threadIdx.x;
   const int par = blockIdx.y & 1;
@@ -212,14 +212,22 @@ __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ 
   float2* out = yext + f * fstride + static_cast<long long>(m) * row;
   unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
                        static_cast<long long>(m) * planes * row;
+  // TD_F16: FP16 planes of 2^e yhat (e from the frame's channel bounds), 2^-e / M in the frame header
+  float sc = 0.f;
+  if (fbound) {
+    const int e = mf_f16_exponent(fbound, f, M);
+    sc = ldexpf(1.0f, e);
+    if (m == 0 && par == 0 && n2 == 0)
+      *reinterpret_cast<float*>(yext + f * fstride + mf_f16_header(M, row)) = ldexpf(1.0f / static_cast<float>(M), -e);
+  }
 #pragma unroll
   for (int n1 = 0; n1 < R; ++n1) {
     const int n = 2 * (N2 * n1 + n2) + par;
     const float2 y = make_float2((v[n1].x + sgn * ny.x) * inv_p, (v[n1].y + sgn * ny.y) * inv_p);
     unsigned short rh = 0, rl = 0, ih = 0, il = 0;
     if (planes) {
-      rh = bf16_rne(y.x);
-      ih = bf16_rne(y.y);
+      rh = mf_plane_word(y.x, sc);
+      ih = mf_plane_word(y.y, sc);
       if (planes == 4) {
         rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
         il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
@@ -264,7 +272,7 @@ hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s) 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((big_inv_radix<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, p->d_spec, p->d_tw, p->d_big,
                      yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p));
+                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr);
   return hipGetLastError();
 }
 
@@ -292,6 +300,7 @@ hipError_t forward(const sonar_plan_s* p, const void* x, int F, float2* spec, fl
 
 hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
   hipError_t e = forward(p, x, F, p->d_spec, nullptr, s);
+  if (e == hipSuccess && mt_f16(p)) e = launch_mf_bound(p, F, s);
   if (e != hipSuccess) return e;
   switch (p->NF / N2) {
     case 2: return inverse_t<2>(p, F, yext, s);

@@ -6,7 +6,8 @@
 //                beamformer o = floor(-Dl), alpha = -Dl - o, stored as
 //                {o - omin, (1-alpha)/M, alpha/M} (integer delays: o = floor(-Dl + 1/2),
 //                alpha = 0; cubic: two entries per microphone, {o - 1 - omin, L_-1/M, L_0/M}
-//                and {o + 1 - omin, L_1/M, L_2/M}, the 4-point Lagrange weights);
+//                and {o + 1 - omin, L_1/M, L_2/M}, the 4-point Lagrange weights; gridded
+//                (TD_F16): alpha rounded to a multiple of 1/2048, alpha = 1 taken as o + 1);
 //  * chirp       C[k] = beta[k] W[k] conj(S[k]), S[k] = sum_l s[l] exp(-2 pi i k l/P),
 //                with the phase index k l reduced mod P exactly in integers;
 //  * twiddles    FFT tables (layout in plan.hpp), exp(-2 pi i e / NF) and
@@ -27,8 +28,15 @@ __global__ void delay_table_kernel(const double* __restrict__ pos, const double*
   const double pu = pos[3 * m] * dirs[3 * d] + pos[3 * m + 1] * dirs[3 * d + 1] + pos[3 * m + 2] * dirs[3 * d + 2];
   const double Dl = fs * pu / c;
   const bool nearest = interp == 1;
-  const double o = nearest ? floor(-Dl + 0.5) : floor(-Dl);
-  const double a = nearest ? 0.0 : -Dl - o;
+  double o = nearest ? floor(-Dl + 0.5) : floor(-Dl);
+  double a = nearest ? 0.0 : -Dl - o;
+  if (interp == 3) {
+    a = rint(a * 2048.0) / 2048.0;
+    if (a >= 1.0) {
+      o += 1.0;
+      a = 0.0;
+    }
+  }
   dl[i] = Dl;
   if (interp == 2) {
     // 4-point Lagrange weights at a for the samples o - 1 .. o + 2
@@ -139,7 +147,10 @@ hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s) {
   const long long dm = static_cast<long long>(p->D) * p->M;
   hipLaunchKernelGGL(delay_table_kernel, dim3(static_cast<unsigned>((dm + 255) / 256)), dim3(256), 0, s,
                      p->d_pos, p->d_dirs, p->M, p->D, p->fs, p->c, p->omin, p->spread,
-                     p->bf_mode == SONAR_BF_TD_NEAREST ? 1 : (p->bf_mode == SONAR_BF_TD_CUBIC ? 2 : 0),
+                     p->bf_mode == SONAR_BF_TD_NEAREST ? 1
+                     : p->bf_mode == SONAR_BF_TD_CUBIC ? 2
+                     : p->bf_mode == SONAR_BF_TD_F16   ? 3
+                                                       : 0,
                      p->d_dtab, p->d_dl);
   return hipGetLastError();
 }

@@ -100,14 +100,41 @@ struct sonar_plan_s {
   int iir_ns = 0;              // IIR envelope: state dimension (2 per section); 0 = the FIR envelope
   int iir_chunk = 0;           // IIR envelope: window samples per lane, ceil(G'/64)
   float* d_iir = nullptr;      // IIR envelope tables (layout: IIR_TAB_LEN below)
+  float* d_fbound = nullptr;   // TD_F16: per channel bound (1/P) sum_k |Yhat[k]| >= max |yhat|, [max_frames][M]
 };
 
-// BF16 sample planes per microphone the matched filter appends for the MFMA
-// time-domain beamformer: 4 (re hi, re lo, im hi, im lo) for TD_BF16, 2 (re, im)
-// for TD_BF16X2, 0 for the other modes
+// 16-bit sample planes per microphone the matched filter appends for the MFMA
+// time-domain beamformer: 4 BF16 (re hi, re lo, im hi, im lo) for TD_BF16, 2 (re, im)
+// for TD_BF16X2 (BF16) and TD_F16 (FP16, scaled per frame), 0 for the other modes
 inline int mt_planes(const sonar_plan_s* p) {
-  return p->bf_mode == SONAR_BF_TD_BF16 ? 4 : (p->bf_mode == SONAR_BF_TD_BF16X2 ? 2 : 0);
+  return p->bf_mode == SONAR_BF_TD_BF16 ? 4 : (p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16 ? 2 : 0);
 }
+
+inline bool mt_f16(const sonar_plan_s* p) { return p->bf_mode == SONAR_BF_TD_F16; }
+// TD_F16 frame header after the planes: complex64 elements (16 bytes, keeps frames 16-byte aligned);
+// float 0 = 2^-e / M, the factor that takes the energyscape of the scaled FP16 samples back
+constexpr int MF_F16_HEADER = 2;
+// TD_F16 sample scale: 2^e with e = MF_F16_TOP - exponent of the frame's bound, |e| <= MF_F16_EMAX
+constexpr int MF_F16_TOP = 14;
+constexpr int MF_F16_EMAX = 100;
+// complex64 offset of the TD_F16 frame header within a frame: after M rows and 2 M 16-bit rows
+__host__ __device__ inline long long mf_f16_header(int M, int row) { return static_cast<long long>(M) * row * 3 / 2; }
+#ifdef __HIPCC__
+// TD_F16 sample exponent of frame f from its channels' bounds
+__device__ inline int mf_f16_exponent(const float* fbound, long long f, int M) {
+  float b = 0.f;
+  for (int i = 0; i < M; ++i) b = fmaxf(b, fbound[f * M + i]);
+  int ex = 0;
+  (void)frexpf(b, &ex);   // b = mant 2^ex, mant in [0.5, 1) (ex = 0 for b = 0)
+  const int e = MF_F16_TOP - ex;
+  return e < -MF_F16_EMAX ? -MF_F16_EMAX : (e > MF_F16_EMAX ? MF_F16_EMAX : e);
+}
+// 16-bit plane words of a matched-filter value v: FP16 of sc v (sc != 0, TD_F16) or BF16 of v
+__device__ __forceinline__ unsigned short mf_plane_word(float v, float sc) {
+  return sc != 0.f ? __builtin_bit_cast(unsigned short, static_cast<_Float16>(v * sc))
+                   : __builtin_bit_cast(unsigned short, static_cast<__bf16>(v));
+}
+#endif
 
 // IIR envelope tables: A [ns][ns], B [ns], C [ns], D at offset 0 (packed for the
 // section count in use), then A^(chunk 2^k), k < 6, [6][ns][ns] from IIR_POW_OFFSET
@@ -169,6 +196,8 @@ constexpr int MT_MICS = 8;      // microphones staged per group with four planes
 inline int mt_mics(const sonar_plan_s* p) { return mt_planes(p) == 2 ? 2 * MT_MICS : MT_MICS; }
 constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: planes x MT_MICS rows x wrow / 8 <= MT_SPT x threads
 constexpr int MT_RES = 4;
+constexpr int MT_GROUP_TAPS = 4;         // consecutive taps of one microphone per tap group (one 8-byte read)
+constexpr int MT_GROUPS_PER_CHUNK = 4;   // tap groups per 16-row K-chunk of the MFMA
 constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that workgroups are spread over
 // |b| rows in LDS for the matrix-core low-pass (one 32-bit word per sample): nwave * 128
 // samples + a zeroed tail, padded so that a row is 16 bytes past a multiple of 256 (bank spread)
@@ -195,6 +224,7 @@ hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F,
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
 size_t fd_env_static_lds(int logL, int P);
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s);
 hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_fd_step_table(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float2* beam_grad, const float* dE, int F,

@@ -89,6 +89,7 @@ void free_plan(sonar_plan_s* p) {
   (void)hipFree(p->d_gspec);
   (void)hipFree(p->d_gy);
   (void)hipFree(p->d_iir);
+  (void)hipFree(p->d_fbound);
   (void)hipFree(p->d_tw2);
   (void)hipFree(p->d_mt_g);
   (void)hipFree(p->d_mt_w);
@@ -116,7 +117,7 @@ bool finite_all(const double* v, size_t n) {
 
 bool is_td(const sonar_plan_s* p) {
   return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST ||
-         p->bf_mode == SONAR_BF_TD_CUBIC || p->bf_mode == SONAR_BF_TD_BF16X2;
+         p->bf_mode == SONAR_BF_TD_CUBIC || p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16;
 }
 
 // Coordinates z_d in which distances between directions equal distances between their
@@ -194,11 +195,12 @@ uint16_t to_bf16_bits(float v) {
 // delay table: directions cut into tiles of 32 that are compact in delay space
 // (a k-d split of the coordinates of delay_space_coords).  Beam samples are
 // split by residue mod MT_RES; for residue rho, per tile and microphone the
-// span of integer offsets is covered by groups of 8 taps whose first tap t0
-// has t0 + rho = 0 mod MT_RES, so every sample fragment read by the kernel
-// starts on an 8-byte boundary.  A group pair is one K-chunk of
-// v_mfma_f32_32x32x16_bf16, whose A fragments (tap weights as BF16 hi and lo
-// terms) are stored in lane order.
+// span of integer offsets is covered by groups of 4 taps whose first tap t0
+// has t0 + rho = 0 mod MT_RES, so every sample group read by the kernel
+// is one 8-byte aligned load (four planes: groups in pairs, one microphone's
+// taps t, t + 4, read as 8 consecutive samples).  Four groups are one K-chunk of
+// v_mfma_f32_32x32x16_bf16 (K rows 4 i .. 4 i + 3 from group i), whose A
+// fragments (tap weights as BF16 hi and lo terms) are stored in lane order.
 int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, const std::vector<double>& taps,
                     hipStream_t stream, size_t* total) {
   const int D = p->D, M = p->M;
@@ -219,7 +221,11 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   std::vector<std::vector<int2>> groups(nlist);
   std::vector<std::vector<char>> pad(nlist);   // zero-weight group completing a K-chunk
   std::vector<int2> kcr(static_cast<size_t>(nt) * nmc * MT_RES);
-  int gmax = 2;
+  int gmax = MT_GROUPS_PER_CHUNK;
+  const bool f16 = mt_f16(p);
+  // taps per microphone are allotted in runs of 4 (two planes) or 8 (four planes: the
+  // kernel reads a group pair as 8 consecutive samples)
+  const int span = mt_planes(p) == 4 ? 2 * MT_GROUP_TAPS : MT_GROUP_TAPS;
   for (int t = 0; t < nt; ++t) {
     for (int rho = 0; rho < MT_RES; ++rho) {
       std::vector<int2>& gl = groups[t * MT_RES + rho];
@@ -236,42 +242,60 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
             rmax = std::max(rmax, dtab[static_cast<size_t>(d) * M + m].x);
           }
           const int t0 = rmin - (rmin + rho) % MT_RES;   // rmin >= 0, so t0 + rho >= 0
-          const int ng = (rmax + 2 - t0 + 7) / 8;          // taps t0 .. rmax + 1
-          for (int g = 0; g < ng; ++g) {
-            gl.push_back(make_int2(m, t0 + 8 * g));
+          const int ng = (rmax + 2 - t0 + span - 1) / span;   // taps t0 .. rmax + 1
+          for (int g = 0; g < ng * (span / MT_GROUP_TAPS); ++g) {
+            gl.push_back(make_int2(m, t0 + MT_GROUP_TAPS * g));
             pl.push_back(0);
           }
         }
-        if ((gl.size() - g0) & 1) {
+        while ((gl.size() - g0) % MT_GROUPS_PER_CHUNK) {
           gl.push_back(make_int2(m0, (MT_RES - rho) % MT_RES));
           pl.push_back(1);
         }
-        kcr[(static_cast<size_t>(t) * nmc + mc) * MT_RES + rho] = make_int2(g0 / 2, static_cast<int>(gl.size()) / 2);
+        kcr[(static_cast<size_t>(t) * nmc + mc) * MT_RES + rho] =
+            make_int2(g0 / MT_GROUPS_PER_CHUNK, static_cast<int>(gl.size()) / MT_GROUPS_PER_CHUNK);
       }
       gmax = std::max(gmax, static_cast<int>(gl.size()));
     }
   }
-  const int kcmax = gmax / 2;
+  const int kcmax = gmax / MT_GROUPS_PER_CHUNK;
   std::vector<int2> gtab(static_cast<size_t>(nlist) * gmax, make_int2(0, 0));
   std::vector<uint16_t> wtab(static_cast<size_t>(nlist) * kcmax * 2 * 64 * 8, 0);
   for (int li = 0; li < nlist; ++li) {
     const int t = li / MT_RES;
     for (size_t g = 0; g < groups[li].size(); ++g) gtab[static_cast<size_t>(li) * gmax + g] = groups[li][g];
-    for (int kc = 0; kc < static_cast<int>(groups[li].size()) / 2; ++kc) {
+    for (int kc = 0; kc < static_cast<int>(groups[li].size()) / MT_GROUPS_PER_CHUNK; ++kc) {
       for (int l = 0; l < 64; ++l) {
         const int d = perm[t * 32 + (l & 31)];
-        const int gi = 2 * kc + (l >> 5);
-        const int2 g = groups[li][gi];
-        const bool zero = d < 0 || pad[li][gi];
         for (int j = 0; j < 8; ++j) {
+          // K row 8 (l / 32) + j: tap j % 4 of group 4 kc + 2 (l / 32) + j / 4
+          const int gi = MT_GROUPS_PER_CHUNK * kc + 2 * (l >> 5) + j / MT_GROUP_TAPS;
+          const int2 g = groups[li][gi];
+          const int tap = g.y + j % MT_GROUP_TAPS;
           float w = 0.f;
-          if (!zero) {
+          if (d >= 0 && !pad[li][gi]) {
             const int4 en = dtab[static_cast<size_t>(d) * M + g.x];
             float w0, w1;
             std::memcpy(&w0, &en.y, 4);
             std::memcpy(&w1, &en.z, 4);
-            if (g.y + j == en.x) w = w0;
-            else if (g.y + j == en.x + 1) w = w1;
+            if (f16) {
+              // gridded delay: alpha = k / 2048 recovered exactly from alpha / M; the weights 1 - alpha
+              // and alpha (without 1/M, applied with the sample scale) are exact in FP16
+              const double a = std::rint(static_cast<double>(w1) * M * 2048.0) / 2048.0;
+              w0 = static_cast<float>(1.0 - a);
+              w1 = static_cast<float>(a);
+            }
+            if (tap == en.x) w = w0;
+            else if (tap == en.x + 1) w = w1;
+          }
+          if (f16) {
+            const _Float16 h = static_cast<_Float16>(w);
+            uint16_t hb;
+            std::memcpy(&hb, &h, 2);
+            const size_t at = ((static_cast<size_t>(li) * kcmax + kc) * 128 + l) * 8 + j;
+            wtab[at] = hb;
+            wtab[at + 64 * 8] = 0;
+            continue;
           }
           const uint16_t hi = to_bf16_bits(w);
           const uint32_t hb = static_cast<uint32_t>(hi) << 16;
@@ -307,9 +331,9 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   p->mt_kcmax = kcmax;
   // every (tile, residue) K-chunk runs on nwave / MT_RES wavefronts x 4 output tiles
   long long chunks = 0;
-  for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / 2;
-  // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples) or 4 (single-term samples)
-  const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : 4;
+  for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / MT_GROUPS_PER_CHUNK;
+  // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples), 4 (single-term samples) or 2 (FP16)
+  const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : (f16 ? 2 : 4);
   p->mt_flop_per_frame = chunks * (p->mt_nwave / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {   // low-pass: 3 MFMAs per K-step and column block
     const int nval = std::min(32, p->mt_qc - q0);
@@ -424,7 +448,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_BF16X2)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_F16)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -580,8 +604,9 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   }
   row = (row + 7) / 8 * 8;
   p->row = static_cast<int>(row);
-  // complex rows, then (MFMA modes) mt_planes(p) BF16 planes per microphone: 4 BF16 values per complex64
-  p->mf_fstride = static_cast<long long>(p->M) * p->row * (4 + mt_planes(p)) / 4;
+  // complex rows, then (MFMA modes) mt_planes(p) 16-bit planes per microphone: 4 16-bit values per
+  // complex64; TD_F16 frames end with a 16-byte header (the sample scale)
+  p->mf_fstride = static_cast<long long>(p->M) * p->row * (4 + mt_planes(p)) / 4 + (mt_f16(p) ? MF_F16_HEADER : 0);
   p->origin = static_cast<long long>(p->n0) - p->hk + p->omin;
 
   // frequency-domain layout: the stored bins are exactly those the band mask keeps
@@ -666,6 +691,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
             dev_alloc(&p->d_fdstep, fd ? dm : 0, &total) == hipSuccess &&
             dev_alloc(&p->d_big, big_elems, &total) == hipSuccess &&
             dev_alloc(&p->d_tw2, tw2_elems, &total) == hipSuccess &&
+            dev_alloc(&p->d_fbound, mt_f16(p) ? static_cast<size_t>(p->max_frames) * p->M : 0, &total) == hipSuccess &&
             dev_alloc(reinterpret_cast<char**>(&p->d_aux), aux_bytes, &total) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
@@ -873,6 +899,7 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   std::vector<int> modes = {SONAR_BF_TD_LINEAR, SONAR_BF_FD_FP32, SONAR_BF_FD_BF16X3};
   if (precision == SONAR_PREC_BF16) {
     modes.push_back(SONAR_BF_TD_BF16);
+    modes.push_back(SONAR_BF_TD_F16);
     if (desc->n_mics >= 32) {
       modes.push_back(SONAR_BF_FD_BF16);
       modes.push_back(SONAR_BF_TD_BF16X2);
@@ -881,7 +908,7 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   // candidates: (mode, MFMA workgroup size); the MFMA modes are tried with both tile shapes
   std::vector<std::pair<int, int>> cands;
   for (int m : modes) {
-    if (m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2) {
+    if (m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2 || m == SONAR_BF_TD_F16) {
       cands.push_back({m, MT_NWAVE_SMALL});
       cands.push_back({m, MT_NWAVE_LARGE});
     } else {
@@ -1021,6 +1048,8 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
   if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
+  if (dpos_out && p->bf_mode == SONAR_BF_TD_F16)
+    return fail(SONAR_E_UNSUPPORTED, "TD_F16: gridded delays are piecewise constant in the positions");
   if (dx_out && p->NF > (1 << 14))
     return fail(SONAR_E_UNSUPPORTED, "dx_out: FFT length %d above 32768 is not supported for gradients", p->P);
   const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),
@@ -1052,7 +1081,7 @@ int sonar_energyscape_backward(sonar_plan p, const void* x, const float* dE, int
 int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t stream) {
   if (!p || !mic_pos) return fail(SONAR_E_INVALID, "plan and mic_pos must not be NULL");
   if (mt_planes(p))
-    return fail(SONAR_E_UNSUPPORTED, "TD_BF16 / TD_BF16X2 tiles are built for one geometry: create a new plan");
+    return fail(SONAR_E_UNSUPPORTED, "MFMA TD tiles are built for one geometry: create a new plan");
   for (int i = 0; i < 3 * p->M; ++i)
     if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
   if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC) {

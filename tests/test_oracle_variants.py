@@ -115,3 +115,57 @@ def test_cubic_is_closer_to_the_exact_delay_than_linear():
     e_lin = np.linalg.norm(O.das_td(y, Dl, n_idx) - ex)
     e_cub = np.linalg.norm(O.das_td_cubic(y, Dl, n_idx) - ex)
     assert e_cub < 0.2 * e_lin, (e_cub, e_lin)
+
+
+def _analytic_rows(rng, M, P):
+    Y = np.zeros((M, P), dtype=np.complex128)
+    Y[:, :P // 2 + 1] = rng.standard_normal((M, P // 2 + 1)) + 1j * rng.standard_normal((M, P // 2 + 1))
+    return np.fft.ifft(Y, axis=1)
+
+
+def test_gridded_offsets_round_to_the_grid():
+    """alpha on multiples of 1/steps, half-way cases to even, alpha' = 1 moved to the next sample."""
+    steps = 2048
+    cases = [(-0.3, 0, round(0.3 * steps) / steps), (-(5 + 1.5 / steps), 5, 2 / steps),
+             (-(5 + 2.5 / steps), 5, 2 / steps), (-(2 + 1 - 0.4 / steps), 3, 0.0), (-7.0, 7, 0.0),
+             (1.25, -2, 0.75)]
+    for dl, o_exp, a_exp in cases:
+        o, a = O.gridded_offsets(np.array([[dl]]), steps)
+        assert int(o[0, 0]) == o_exp and float(a[0, 0]) == a_exp, (dl, o, a)
+
+
+def test_gridded_with_one_step_is_nearest():
+    """A grid of one sample rounds alpha to 0 or 1: the nearest-sample delay (no ties drawn)."""
+    rng = np.random.default_rng(31)
+    M, P, D = 5, 96, 7
+    y = _analytic_rows(rng, M, P)
+    Dl = rng.uniform(-9, 9, size=(D, M))
+    n_idx = np.arange(-12, 80)
+    assert np.array_equal(O.das_td(y, Dl, n_idx, alpha_steps=1), O.das_td_nearest(y, Dl, n_idx))
+
+
+def test_gridded_equals_linear_for_delays_on_the_grid():
+    rng = np.random.default_rng(32)
+    M, P, D, steps = 4, 128, 6, 2048
+    y = _analytic_rows(rng, M, P)
+    Dl = -(rng.integers(-6, 7, size=(D, M)) + rng.integers(0, steps, size=(D, M)) / steps)
+    n_idx = np.arange(-10, 100)
+    assert np.allclose(O.das_td(y, Dl, n_idx, alpha_steps=steps), O.das_td(y, Dl, n_idx), rtol=0, atol=1e-15)
+
+
+def test_gridded_error_is_bounded_by_half_a_step():
+    """b' - b = (1/M) sum_m (alpha' - alpha)(y[i+1] - y[i]) with |alpha' - alpha| <= 1/(2 steps)."""
+    rng = np.random.default_rng(33)
+    M, P, D, steps = 6, 128, 9, 16
+    y = _analytic_rows(rng, M, P)
+    Dl = rng.uniform(-8, 8, size=(D, M))
+    n_idx = np.arange(-5, 110)
+    diff = np.abs(O.das_td(y, Dl, n_idx, alpha_steps=steps) - O.das_td(y, Dl, n_idx))
+    o, _ = O.td_offsets(Dl)
+    for d in range(D):
+        bound = np.zeros(n_idx.size)
+        for m in range(M):
+            i0 = np.mod(n_idx + o[d, m], P)
+            bound += np.abs(y[m, np.mod(i0 + 1, P)] - y[m, i0])
+        assert np.all(diff[d] <= bound / M / (2 * steps) + 1e-15)
+    assert diff.max() > 0
