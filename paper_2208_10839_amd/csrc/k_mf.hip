@@ -97,11 +97,12 @@ __device__ __forceinline__ void forward_mf(const TIn* __restrict__ x, int N,
 }
 
 // Forward transform and matched-filter product of one channel per workgroup;
-// writes the one-sided spectrum Yhat[0..NF] to spec[ch][0..NF].
+// writes the one-sided spectrum Yhat[0..NF] to spec[ch][0..NF] and, when bound is
+// given (TD_F16), (1/P) sum_k |Yhat[k]| to bound[ch] (the sample-scale bound).
 template <int LOGNF, typename TIn>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
     const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
-    const float2* __restrict__ tw_g, float2* __restrict__ spec) {
+    const float2* __restrict__ tw_g, float2* __restrict__ spec, float* __restrict__ bound, float inv_p) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -116,8 +117,27 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
   __syncthreads();
   forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
   float2* out = spec + ch * (NF + 1);
-  for (int k = tid; k < NF; k += T) out[k] = lds[padi(k)];
-  if (tid == 0) out[NF] = nyq;
+  float acc = 0.f;
+  for (int k = tid; k < NF; k += T) {
+    const float2 v = lds[padi(k)];
+    out[k] = v;
+    acc += sqrtf(v.x * v.x + v.y * v.y);
+  }
+  if (tid == 0) {
+    out[NF] = nyq;
+    acc += sqrtf(nyq.x * nyq.x + nyq.y * nyq.y);
+  }
+  if (bound) {   // a kernel argument: the whole workgroup takes this branch
+    __syncthreads();   // every read of the spectrum in LDS is done: reuse it for the sum
+    float* red = reinterpret_cast<float*>(lds);
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = T / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    if (tid == 0) bound[ch] = red[0] * inv_p;
+  }
 }
 
 // Inverse transform of one output parity of one channel per workgroup:
@@ -256,9 +276,9 @@ template <int LOGNF, typename TIn>
 hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
   constexpr int T = (1 << LOGNF) / 16;
   hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
-                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec);
+                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec,
+                     mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P));
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess && mt_f16(p)) e = launch_mf_bound(p, F, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
                      p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
