@@ -83,7 +83,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   static_assert(NPL == 4 || NPL == 2, "four split planes or two single ones");
   static_assert(!F16 || NPL == 2, "FP16 samples come as two planes");
   const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int rho = wv % MT_RES;
   // Workgroups are handed to the XCDs round-robin by index: XCD x = index % nx
   // keeps the weights of its own tpx direction tiles in its L2 and runs them
@@ -160,18 +160,38 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   MT_STAGE_STORE(0, sm)
   MT_STAGE_LOAD(0)
   MT_STAGE_STORE(0, sm)
-  // The wavefront's K-chunks of all microphone groups are consecutive in the tables, so
-  // the one-ahead prefetch of weight fragments runs across group and half boundaries.
+  // The wavefront's K-chunks of all microphone groups are consecutive in the tables, so the
+  // prefetch runs across group and half boundaries.  Chunk kc's operands sit in register set
+  // (kc - kfirst) & 1 and are loaded two chunks ahead, after the products of the body that last
+  // reads that set, so no register copy has to wait for a load (a one-ahead prefetch into a
+  // single set needed one).  The group table is read through the scalar cache (its address is
+  // wave-uniform), so only the weight fragments use vector loads.
   const int li = tile * MT_RES + rho;
   const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-  // K-chunk kc: groups 4 kc .. 4 kc + 3; lanes 0-31 read the first two, lanes 32-63 the others
-  const int4* gt = gtab + static_cast<long long>(li) * (gmax / 2) + (lane >> 5);
+  // K-chunk kc: groups 4 kc .. 4 kc + 3 as {mic, first tap} x 4; lanes 0-31 read the first two,
+  // lanes 32-63 the others
+  const int* gs = reinterpret_cast<const int*>(gtab) + static_cast<long long>(li) * gmax * 2;
+  const bool upper = lane >= 32;
   const int kend = kcr[(tile * nmc + nmc - 1) * MT_RES + rho].y;
   int kfirst = kcr[tile * nmc * MT_RES + rho].x;
   if (kfirst >= kend) kfirst = 0;            // no chunks at all: harmless in-table prefetch
-  // weight fragments: hi and lo BF16 terms, or the one exact FP16 term
-  uint4 ah_next = wt[kfirst * 128], al_next = F16 ? make_uint4(0, 0, 0, 0) : wt[kfirst * 128 + 64];
-  int4 g_next = gt[2 * kfirst];
+  struct Operands {
+    uint4 ah, al;                            // weight fragments: BF16 hi and lo terms, or one FP16 term
+    int4 glo, ghi;                           // groups of lanes 0-31 and of lanes 32-63 (uniform)
+  };
+  // every body issues the same loads (past the last chunk, an in-table one)
+  auto load_ops = [&](Operands& o, int kc) {
+    const int kl = kc < kend ? kc : kfirst;
+    o.ah = wt[kl * 128];
+    if constexpr (!F16) o.al = wt[kl * 128 + 64];
+    const int* q = gs + 8 * kl;
+    o.glo = make_int4(q[0], q[1], q[2], q[3]);
+    o.ghi = make_int4(q[4], q[5], q[6], q[7]);
+  };
+  Operands op0, op1;
+  op0.al = op1.al = make_uint4(0, 0, 0, 0);
+  load_ops(op0, kfirst);
+  load_ops(op1, kfirst + 1);
   for (int mc = 0; mc < nmc; ++mc) {
     const int m0 = mc * MICS;
     unsigned short* buf = sm + (mc & 1) * bufsz;
@@ -182,6 +202,46 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     kh = k0;
     const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
     const int kmid = (kr.x + kr.y) >> 1;
+    auto kbody = [&](int kc, Operands& o) {
+      const int4 g = upper ? o.ghi : o.glo;
+      const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+      // four planes: the two groups are always taps t, t + 4 of one microphone (registers are short)
+      const unsigned short* p2 = NPL == 4 ? p + 4 : buf + (g.z - m0) * wrow + g.w + sb + 4 * (lane & 31);
+      if constexpr (NPL == 4) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const uint4 brh = lds_frag(p + 128 * nt, p2 + 128 * nt);
+          const uint4 brl = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          const uint4 bih = lds_frag(p + 2 * plane + 128 * nt, p2 + 2 * plane + 128 * nt);
+          const uint4 bil = lds_frag(p + 3 * plane + 128 * nt, p2 + 3 * plane + 128 * nt);
+          cre[nt] = mfma_bf16(o.ah, brh, cre[nt]);
+          cim[nt] = mfma_bf16(o.ah, bih, cim[nt]);
+          cre[nt] = mfma_bf16(o.ah, brl, cre[nt]);
+          cim[nt] = mfma_bf16(o.ah, bil, cim[nt]);
+          cre[nt] = mfma_bf16(o.al, brh, cre[nt]);
+          cim[nt] = mfma_bf16(o.al, bih, cim[nt]);
+        }
+      } else if constexpr (F16) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
+          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          cre[nt] = mfma_f16(o.ah, br, cre[nt]);
+          cim[nt] = mfma_f16(o.ah, bi, cim[nt]);
+        }
+      } else {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
+          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
+          cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
+          cre[nt] = mfma_bf16(o.al, br, cre[nt]);
+          cim[nt] = mfma_bf16(o.al, bi, cim[nt]);
+        }
+      }
+      load_ops(o, kc + 2);
+    };
     // the next group is staged in two halves, each loaded during one half of the K-chunks
     for (int hk = 0; hk < 2; ++hk) {
       if (next) {
@@ -189,54 +249,13 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
         MT_STAGE_LOAD(mc + 1)
       }
       const int ka = hk ? kmid : kr.x, kb = hk ? kr.y : kmid;
-      {
-        for (int kc = ka; kc < kb; ++kc) {
-          const uint4 ah = ah_next;
-          const uint4 al = al_next;
-          const int4 g = g_next;
-          if (kc + 1 < kend) {
-            ah_next = wt[(kc + 1) * 128];
-            if constexpr (!F16) al_next = wt[(kc + 1) * 128 + 64];
-            g_next = gt[2 * (kc + 1)];
-          }
-          const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
-          // four planes: the two groups are always taps t, t + 4 of one microphone (registers are short)
-          const unsigned short* p2 = NPL == 4 ? p + 4 : buf + (g.z - m0) * wrow + g.w + sb + 4 * (lane & 31);
-          if constexpr (NPL == 4) {
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-              const uint4 brh = lds_frag(p + 128 * nt, p2 + 128 * nt);
-              const uint4 brl = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
-              const uint4 bih = lds_frag(p + 2 * plane + 128 * nt, p2 + 2 * plane + 128 * nt);
-              const uint4 bil = lds_frag(p + 3 * plane + 128 * nt, p2 + 3 * plane + 128 * nt);
-              cre[nt] = mfma_bf16(ah, brh, cre[nt]);
-              cim[nt] = mfma_bf16(ah, bih, cim[nt]);
-              cre[nt] = mfma_bf16(ah, brl, cre[nt]);
-              cim[nt] = mfma_bf16(ah, bil, cim[nt]);
-              cre[nt] = mfma_bf16(al, brh, cre[nt]);
-              cim[nt] = mfma_bf16(al, bih, cim[nt]);
-            }
-          } else if constexpr (F16) {
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-              const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
-              const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
-              cre[nt] = mfma_f16(ah, br, cre[nt]);
-              cim[nt] = mfma_f16(ah, bi, cim[nt]);
-            }
-          } else {
-#pragma unroll
-            for (int nt = 0; nt < 4; ++nt) {
-              const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
-              const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
-              cre[nt] = mfma_bf16(ah, br, cre[nt]);
-              cim[nt] = mfma_bf16(ah, bi, cim[nt]);
-              cre[nt] = mfma_bf16(al, br, cre[nt]);
-              cim[nt] = mfma_bf16(al, bi, cim[nt]);
-            }
-          }
-        }
+      int kc = ka;
+      if (kc < kb && ((kc - kfirst) & 1)) kbody(kc++, op1);
+      for (; kc + 1 < kb; kc += 2) {
+        kbody(kc, op0);
+        kbody(kc + 1, op1);
       }
+      if (kc < kb) kbody(kc, op0);
     }
     if (next) MT_STAGE_STORE(mc + 1, nbuf)
   }
