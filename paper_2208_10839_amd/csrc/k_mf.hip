@@ -146,7 +146,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
 template <int LOGNF>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
-    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound) {
+    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound, int rows) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
       }
     }
     for (int j = (n - origin) & (P - 1); j < row; j += P) {
-      out[j] = y;
+      if (rows) out[j] = y;
       if (planes == 4) {
         pl[j] = rh;
         pl[row + j] = rl;
@@ -273,7 +273,7 @@ hipError_t launch_mf_band_dt(const sonar_plan_s* p, const void* x, int F, float2
 }
 
 template <int LOGNF, typename TIn>
-hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows) {
   constexpr int T = (1 << LOGNF) / 16;
   hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
                      static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec,
@@ -282,24 +282,24 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
                      p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr);
+                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr, rows ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename TIn>
-hipError_t launch_mf_td_dt(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+hipError_t launch_mf_td_dt(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows) {
   switch (p->logNF) {
-    case 4: return launch_mf_td_t<4, TIn>(p, x, F, yext, s);
-    case 5: return launch_mf_td_t<5, TIn>(p, x, F, yext, s);
-    case 6: return launch_mf_td_t<6, TIn>(p, x, F, yext, s);
-    case 7: return launch_mf_td_t<7, TIn>(p, x, F, yext, s);
-    case 8: return launch_mf_td_t<8, TIn>(p, x, F, yext, s);
-    case 9: return launch_mf_td_t<9, TIn>(p, x, F, yext, s);
-    case 10: return launch_mf_td_t<10, TIn>(p, x, F, yext, s);
-    case 11: return launch_mf_td_t<11, TIn>(p, x, F, yext, s);
-    case 12: return launch_mf_td_t<12, TIn>(p, x, F, yext, s);
-    case 13: return launch_mf_td_t<13, TIn>(p, x, F, yext, s);
-    case 14: return launch_mf_td_t<14, TIn>(p, x, F, yext, s);
+    case 4: return launch_mf_td_t<4, TIn>(p, x, F, yext, s, rows);
+    case 5: return launch_mf_td_t<5, TIn>(p, x, F, yext, s, rows);
+    case 6: return launch_mf_td_t<6, TIn>(p, x, F, yext, s, rows);
+    case 7: return launch_mf_td_t<7, TIn>(p, x, F, yext, s, rows);
+    case 8: return launch_mf_td_t<8, TIn>(p, x, F, yext, s, rows);
+    case 9: return launch_mf_td_t<9, TIn>(p, x, F, yext, s, rows);
+    case 10: return launch_mf_td_t<10, TIn>(p, x, F, yext, s, rows);
+    case 11: return launch_mf_td_t<11, TIn>(p, x, F, yext, s, rows);
+    case 12: return launch_mf_td_t<12, TIn>(p, x, F, yext, s, rows);
+    case 13: return launch_mf_td_t<13, TIn>(p, x, F, yext, s, rows);
+    case 14: return launch_mf_td_t<14, TIn>(p, x, F, yext, s, rows);
     default: return hipErrorInvalidValue;
   }
 }
@@ -334,12 +334,12 @@ hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
-  if (p->NF > (1 << MB_LOGN2)) return launch_mf_big_td(p, x, F, yext, s);
+hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows) {
+  if (p->NF > (1 << MB_LOGN2)) return launch_mf_big_td(p, x, F, yext, s, rows);
   switch (p->dtype) {
-    case SONAR_F32: return launch_mf_td_dt<float>(p, x, F, yext, s);
-    case SONAR_F16: return launch_mf_td_dt<__half>(p, x, F, yext, s);
-    case SONAR_BF16: return launch_mf_td_dt<__hip_bfloat16>(p, x, F, yext, s);
+    case SONAR_F32: return launch_mf_td_dt<float>(p, x, F, yext, s, rows);
+    case SONAR_F16: return launch_mf_td_dt<__half>(p, x, F, yext, s, rows);
+    case SONAR_BF16: return launch_mf_td_dt<__hip_bfloat16>(p, x, F, yext, s, rows);
     default: return hipErrorInvalidValue;
   }
 }

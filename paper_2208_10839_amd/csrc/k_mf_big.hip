@@ -190,7 +190,7 @@ template <int R>
 __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ spec, const float2* __restrict__ tw_g,
                                                      const float2* __restrict__ scratch, float2* __restrict__ yext,
                                                      long long fstride, int M, int row, int origin, int P,
-                                                     int planes, const float* __restrict__ fbound) {
+                                                     int planes, const float* __restrict__ fbound, int rows) {
   constexpr int NF = R * N2;
   const int n2 = blockIdx.x * 256 + threadIdx.x;
   const int par = blockIdx.y & 1;
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ 
       }
     }
     for (int j = (n - origin) & (P - 1); j < row; j += P) {
-      out[j] = y;
+      if (rows) out[j] = y;
       if (planes == 4) {
         pl[j] = rh;
         pl[row + j] = rl;
@@ -264,7 +264,7 @@ hipError_t forward_t(const sonar_plan_s* p, const void* x, int F, float2* spec, 
 }
 
 template <int R>
-hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s) {
+hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s, bool rows) {
   const int chans = F * p->M;
   hipLaunchKernelGGL((big_inv_rows<R>), dim3(chans * 2 * R), dim3(N2 / 16), 0, s, p->d_spec, p->d_tw, p->d_tw2,
                      p->d_big);
@@ -272,7 +272,7 @@ hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s) 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((big_inv_radix<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, p->d_spec, p->d_tw, p->d_big,
                      yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr);
+                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr, rows ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -298,15 +298,15 @@ hipError_t forward(const sonar_plan_s* p, const void* x, int F, float2* spec, fl
 
 }  // namespace
 
-hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s) {
+hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows) {
   hipError_t e = forward(p, x, F, p->d_spec, nullptr, s);
   if (e == hipSuccess && mt_f16(p)) e = launch_mf_bound(p, F, s);
   if (e != hipSuccess) return e;
   switch (p->NF / N2) {
-    case 2: return inverse_t<2>(p, F, yext, s);
-    case 4: return inverse_t<4>(p, F, yext, s);
-    case 8: return inverse_t<8>(p, F, yext, s);
-    case 16: return inverse_t<16>(p, F, yext, s);
+    case 2: return inverse_t<2>(p, F, yext, s, rows);
+    case 4: return inverse_t<4>(p, F, yext, s, rows);
+    case 8: return inverse_t<8>(p, F, yext, s, rows);
+    case 16: return inverse_t<16>(p, F, yext, s, rows);
     default: return hipErrorInvalidValue;
   }
 }

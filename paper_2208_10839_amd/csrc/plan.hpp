@@ -213,7 +213,7 @@ constexpr int FD_MAX_P = 65536;   // FFT length limit of the frequency-domain in
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t init_mt_kernel_attributes();
-hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows);
 hipError_t launch_mf_big_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 size_t mt_smem_bytes(const sonar_plan_s* p);
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
@@ -223,7 +223,8 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
 size_t fd_env_static_lds(int logL, int P);
-hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s);
+// rows = false skips the complex64 rows (MFMA modes whose beamformer reads only the 16-bit planes)
+hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows = true);
 hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s);
 hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_fd_step_table(sonar_plan_s* p, hipStream_t s);

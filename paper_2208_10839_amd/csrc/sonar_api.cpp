@@ -826,7 +826,8 @@ int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hi
   if (st != SONAR_OK) return st;
   hipError_t e;
   if (is_td(p)) {
-    e = launch_mf_td(p, x, F, p->d_mf, stream);
+    // the fused MFMA beamformer reads only the 16-bit planes: the complex rows are not written
+    e = launch_mf_td(p, x, F, p->d_mf, stream, !(mt_planes(p) && p->iir_ns == 0));
     if (e == hipSuccess) e = beam_env(p, p->d_mf, F, E, stream);
   } else {
     e = launch_mf_fd(p, x, F, p->d_fdspec, stream);
