@@ -144,3 +144,18 @@ def test_td_f16_gradient_support(gpu, torch_mod):
     dE = torch.ones((1, w.dirs.shape[0], plan.Q), dtype=torch.float32, device="cuda")
     with pytest.raises(gpu.SonarError):
         plan.backward(x, dE, want_dx=False, want_dpos=True)
+
+
+@pytest.mark.parametrize("mode", ["td_f16", "td_bf16x2", "td_bf16"])
+def test_fused_energyscape_equals_staged_calls(gpu, torch_mod, mode):
+    """The fused call (whose matched filter skips the complex rows in the MFMA modes) equals the
+    matched filter into a caller buffer (rows and planes) followed by the fused beamformer +
+    envelope, bit for bit."""
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=3, n_samples=2200, n_dirs=50)
+    _say(f"case fused vs staged: {mode}")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 2200, fs=w.fs, c=w.c, band=w.cfg.band, max_frames=3, mode=mode)
+    x = torch.from_numpy(w.x).cuda()
+    E1 = plan.energyscape(x)
+    E2 = plan.beamform_envelope(plan.matched_filter(x))
+    assert torch.equal(E1, E2)
