@@ -334,49 +334,52 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h_lo, __builtin_bit_cast(bf16x8, ahi), ACC, 0, 0, 0); \
     ACC = __builtin_amdgcn_mfma_f32_32x32x16_bf16(h_hi, __builtin_bit_cast(bf16x8, alo), ACC, 0, 0, 0); \
   }
-  for (int cb = wv; cb < nqb; cb += NWAVE) {
-    f32x16 acc = f32x16{}, acc2 = f32x16{};   // even and odd K-steps (independent MFMA chains)
-    const int q0 = 32 * cb;
-    const int nval = qc - q0 < 32 ? qc - q0 : 32;
-    const int nks4 = (((nval - 1) * R + K + 15) / 16 + 3) & ~3;   // K-steps, in batches of 4
-    const unsigned int* ah = bw + (lane & 31) * NSP + q0 * R + 8 * (lane >> 5);
-    {
-      uint4 ah0, al0, ah1, al1, ah2, al2, ah3, al3;   // tap fragments, batch A
-      uint4 bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3;   // batch B
-      MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, 0)
-      for (int kb = 0; kb < nks4; kb += 8) {
-        const bool more = kb + 4 < nks4;
-        if (more) MT_FIR_LOAD(bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3, kb + 4)
-        MT_FIR_STEP(ah0, al0, kb, acc)
-        MT_FIR_STEP(ah1, al1, kb + 1, acc2)
-        MT_FIR_STEP(ah2, al2, kb + 2, acc)
-        MT_FIR_STEP(ah3, al3, kb + 3, acc2)
-        if (more) {
-          if (kb + 8 < nks4) MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, kb + 8)
-          MT_FIR_STEP(bh0, bl0, kb + 4, acc)
-          MT_FIR_STEP(bh1, bl1, kb + 5, acc2)
-          MT_FIR_STEP(bh2, bl2, kb + 6, acc)
-          MT_FIR_STEP(bh3, bl3, kb + 7, acc2)
-        }
+  // K-steps [k0, k1) (multiples of 4) of column block cb into acc (even K-steps) and acc2 (odd):
+  // two independent MFMA chains
+  auto fir_block = [&](int cb, int k0, int k1, f32x16& acc, f32x16& acc2) {
+    const unsigned int* ah = bw + (lane & 31) * NSP + 32 * cb * R + 8 * (lane >> 5);
+    uint4 ah0, al0, ah1, al1, ah2, al2, ah3, al3;   // tap fragments, batch A
+    uint4 bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3;   // batch B
+    MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, k0)
+    for (int kb = k0; kb < k1; kb += 8) {
+      const bool more = kb + 4 < k1;
+      if (more) MT_FIR_LOAD(bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3, kb + 4)
+      MT_FIR_STEP(ah0, al0, kb, acc)
+      MT_FIR_STEP(ah1, al1, kb + 1, acc2)
+      MT_FIR_STEP(ah2, al2, kb + 2, acc)
+      MT_FIR_STEP(ah3, al3, kb + 3, acc2)
+      if (more) {
+        if (kb + 8 < k1) MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, kb + 8)
+        MT_FIR_STEP(bh0, bl0, kb + 4, acc)
+        MT_FIR_STEP(bh1, bl1, kb + 5, acc2)
+        MT_FIR_STEP(bh2, bl2, kb + 6, acc)
+        MT_FIR_STEP(bh3, bl3, kb + 7, acc2)
       }
     }
+  };
+  // K-steps of column block cb (rounded up to a multiple of 4)
+  auto fir_ksteps = [&](int cb) {
+    const int nval = qc - 32 * cb < 32 ? qc - 32 * cb : 32;
+    return (((nval - 1) * R + K + 15) / 16 + 3) & ~3;
+  };
+  auto store_block = [&](int cb, f32x16 acc, const f32x16& acc2) {
+    const int q0 = 32 * cb;
     const int d = permL[lane & 31];
     if constexpr (F16) {
       // frame header: 2^-e / M
       const float esc = *reinterpret_cast<const float*>(planes + f * fstride + 2LL * M * row);
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        acc[v] *= esc;
-        acc2[v] *= esc;
-      }
+      for (int v = 0; v < 16; ++v) acc[v] = (acc[v] + acc2[v]) * esc;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
     }
     if (d >= 0) {
       float* erow = E + (static_cast<long long>(f) * D + d) * Q + static_cast<long long>(qt) * qc;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         const int q = q0 + 8 * g + 4 * (lane >> 5);
-        const float4 o = make_float4(acc[4 * g] + acc2[4 * g], acc[4 * g + 1] + acc2[4 * g + 1],
-                                     acc[4 * g + 2] + acc2[4 * g + 2], acc[4 * g + 3] + acc2[4 * g + 3]);
+        const float4 o = make_float4(acc[4 * g], acc[4 * g + 1], acc[4 * g + 2], acc[4 * g + 3]);
         const int lim = (qc < Q - qt * qc ? qc : Q - qt * qc) - q;   // valid bins from q on
         if (lim >= 4) {
           __builtin_memcpy(erow + q, &o, 16);
@@ -387,6 +390,34 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
         }
       }
     }
+  };
+  if (2 * nqb <= NWAVE) {
+    // few column blocks: each block's K-steps are split over two wavefronts; the second half's
+    // sums go through LDS (after the |b| rows and their zero tail, which the products never read)
+    float* part = reinterpret_cast<float*>(bw + 32 * NSP + MT_FIR_TAIL);   // [NWAVE / 2][16][64 lanes]
+    const int cb = wv % nqb, half = wv / nqb;
+    f32x16 acc = f32x16{}, acc2 = f32x16{};
+    if (wv < 2 * nqb) {
+      const int nks4 = fir_ksteps(cb);
+      const int kmid = (nks4 / 2) & ~3;
+      fir_block(cb, half ? kmid : 0, half ? nks4 : kmid, acc, acc2);
+      if (half) {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) part[(cb * 16 + v) * 64 + lane] = acc[v] + acc2[v];
+      }
+    }
+    __syncthreads();
+    if (wv < nqb) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] += part[(cb * 16 + v) * 64 + lane];
+      store_block(cb, acc, acc2);
+    }
+  } else {
+    for (int cb = wv; cb < nqb; cb += NWAVE) {
+      f32x16 acc = f32x16{}, acc2 = f32x16{};
+      fir_block(cb, 0, fir_ksteps(cb), acc, acc2);
+      store_block(cb, acc, acc2);
+    }
   }
 #undef MT_FIR_LOAD
 #undef MT_FIR_STEP
@@ -395,9 +426,11 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 }  // namespace
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
+// (|b| rows, their zero tail, and the split low-pass partial sums [nwave / 2][16][64] floats)
 static size_t mt_perm_offset(const sonar_plan_s* p) {
   const size_t planes = 2 * static_cast<size_t>(mt_planes(p)) * mt_mics(p) * p->mt_wrow * sizeof(unsigned short);
-  const size_t absb = (32 * static_cast<size_t>(mt_nsp(p->mt_nwave)) + MT_FIR_TAIL) * sizeof(unsigned int);
+  const size_t absb = (32 * static_cast<size_t>(mt_nsp(p->mt_nwave)) + MT_FIR_TAIL) * sizeof(unsigned int) +
+                      static_cast<size_t>(p->mt_nwave / 2) * 16 * 64 * sizeof(float);
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
 
