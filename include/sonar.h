@@ -75,7 +75,11 @@ enum sonar_status {
  *              two BF16 planes per microphone.  Its error is the samples'
  *              BF16 rounding averaged over the microphones: within 1e-3 for
  *              arrays of 32 or more microphones (SONAR_PREC_BF16 picks it only
- *              there).
+ *              there).  In TD_BF16X2 and TD_F16 the envelope's low-pass runs on
+ *              FP16 MFMA: |b| as one FP16 term scaled per tile of 32 directions
+ *              by a power of two (largest scaled value below 2^14), the taps as
+ *              two FP16 terms (SONAR_E_UNSUPPORTED for taps of magnitude 2^15 or
+ *              more).
  *  TD_CUBIC  : 4-point Lagrange (cubic) fractional delay: o = floor(-Dl),
  *              a = -Dl - o, b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(a) yhat_m[n+o+k],
  *              L_k(a) = prod_{j != k} (a - j)/(k - j); FP32 on the TD_LINEAR

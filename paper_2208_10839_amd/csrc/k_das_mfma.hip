@@ -266,12 +266,59 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 #undef MT_ADV
   __syncthreads();
 
-  // |b| of the tile into LDS as [32][NSP] words {bf16 hi, bf16 lo}: lane holds rows
-  // 8(v/4) + 4(lane/32) + v%4 (directions) of column lane%32 (window sample
-  // sw + 128 nt + 4 column) for each output tile
+  // |b| of the tile into LDS: lane holds rows 8(v/4) + 4(lane/32) + v%4 (directions) of
+  // column lane%32 (window sample sw + 128 nt + 4 column) for each output tile.
+  //  * two sample planes (FIR16): [32][NSP16] FP16 of 2^e |b|, e per workgroup from the tile's
+  //    largest |b| (so every scaled value is below 2^14); the low-pass runs on FP16 MFMA with
+  //    the taps as two FP16 terms, and E is scaled back by 2^-e;
+  //  * four planes: [32][NSP] words {bf16 hi, bf16 lo}, the taps as two BF16 terms.
+  constexpr bool FIR16 = NPL == 2;
   constexpr int NSP = mt_nsp(NWAVE);
+  constexpr int NSP16 = NS + 8;            // 16 bytes past a multiple of 256 per row (bank spread)
   unsigned int* bw = reinterpret_cast<unsigned int*>(sm);
+  unsigned short* b16 = reinterpret_cast<unsigned short*>(sm);
+  float* wmax = reinterpret_cast<float*>(permL + 32);   // [NWAVE] largest |b| per wavefront
   const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
+  float inv_scale = 1.f;
+  if constexpr (FIR16) {
+    float mx = 0.f;
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        cre[nt][v] = __builtin_amdgcn_sqrtf(cre[nt][v] * cre[nt][v] + cim[nt][v] * cim[nt][v]);
+        mx = fmaxf(mx, cre[nt][v]);
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if (lane == 0) wmax[wv] = mx;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < NWAVE; ++w) mx = fmaxf(mx, wmax[w]);
+    int ex = 0;
+    (void)frexpf(mx, &ex);                 // mx = mant 2^ex, mant in [0.5, 1) (ex = 0 for mx = 0)
+    int e = 14 - ex;
+    e = e < -MF_F16_EMAX ? -MF_F16_EMAX : (e > MF_F16_EMAX ? MF_F16_EMAX : e);
+    const float sc = ldexpf(1.0f, e);
+    inv_scale = ldexpf(1.0f, -e);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int s = sw + 128 * nt + 4 * (lane & 31);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+        b16[dl * NSP16 + s] = __builtin_bit_cast(unsigned short, static_cast<_Float16>(cre[nt][v] * sc));
+      }
+    }
+    // the K-steps of a column block (rounded up to a multiple of 4) read up to 63 samples past
+    // the window: those of each row's tail, the next row's first ones, and after the last
+    // row MT_FIR_TAIL zeros; their tap fragments are zero
+    for (int i = threadIdx.x; i < 32 * (NSP16 - NS) + MT_FIR_TAIL; i += NT) {
+      const int r = i / (NSP16 - NS), c = i - r * (NSP16 - NS);
+      b16[r < 32 ? r * NSP16 + NS + c : 32 * NSP16 + (i - 32 * (NSP16 - NS))] = 0;
+    }
+  } else {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int s = sw + 128 * nt + 4 * (lane & 31);
@@ -293,6 +340,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   for (int i = threadIdx.x; i < 32 * (NSP - NS) + MT_FIR_TAIL; i += NT) {
     const int r = i / (NSP - NS), c = i - r * (NSP - NS);
     bw[r < 32 ? r * NSP + NS + c : 32 * NSP + (i - 32 * (NSP - NS))] = 0;
+  }
   }
   __syncthreads();
   // low-pass + decimation on MFMA: E[d][q] = sum_s |b|[d][s] H[s][q], H[s][q] = h[qR + K-1 - s],
@@ -316,7 +364,14 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     H3 = fp[384];                                                                                      \
     L3 = fp[448];                                                                                      \
   }
+#define MT_FIR_STEP16(H, L, KS, ACC)                                                                   \
+  {                                                                                                    \
+    const uint4 bb = *reinterpret_cast<const uint4*>(bh + 16 * (KS));                                  \
+    ACC = mfma_f16(H, bb, ACC);                                                                        \
+    ACC = mfma_f16(L, bb, ACC);                                                                        \
+  }
 #define MT_FIR_STEP(H, L, KS, ACC)                                                                     \
+  if constexpr (FIR16) MT_FIR_STEP16(H, L, KS, ACC) else                                               \
   {                                                                                                    \
     const uint4 w0 = *reinterpret_cast<const uint4*>(ah + 16 * (KS));                                  \
     const uint4 w1 = *reinterpret_cast<const uint4*>(ah + 16 * (KS) + 4);                              \
@@ -338,6 +393,9 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   // two independent MFMA chains
   auto fir_block = [&](int cb, int k0, int k1, f32x16& acc, f32x16& acc2) {
     const unsigned int* ah = bw + (lane & 31) * NSP + 32 * cb * R + 8 * (lane >> 5);
+    const unsigned short* bh = b16 + (lane & 31) * NSP16 + 32 * cb * R + 8 * (lane >> 5);
+    (void)ah;
+    (void)bh;
     uint4 ah0, al0, ah1, al1, ah2, al2, ah3, al3;   // tap fragments, batch A
     uint4 bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3;   // batch B
     MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, k0)
@@ -373,6 +431,10 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     } else {
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[v] += acc2[v];
+    }
+    if constexpr (FIR16) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[v] *= inv_scale;
     }
     if (d >= 0) {
       float* erow = E + (static_cast<long long>(f) * D + d) * Q + static_cast<long long>(qt) * qc;
@@ -421,6 +483,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   }
 #undef MT_FIR_LOAD
 #undef MT_FIR_STEP
+#undef MT_FIR_STEP16
 }
 
 }  // namespace
@@ -434,7 +497,8 @@ static size_t mt_perm_offset(const sonar_plan_s* p) {
   return ((planes > absb ? planes : absb) + 15) / 16 * 16;
 }
 
-size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * sizeof(int); }
+// slot -> direction table (32 ints), then the per-wavefront largest |b| (up to 16 floats)
+size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * sizeof(int) + 16 * sizeof(float); }
 
 namespace {
 

@@ -203,6 +203,10 @@ uint16_t to_bf16_bits(float v) {
 // fragments (tap weights as BF16 hi and lo terms) are stored in lane order.
 int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, const std::vector<double>& taps,
                     hipStream_t stream, size_t* total) {
+  if (mt_planes(p) == 2)
+    for (double h : taps)
+      if (!(std::fabs(h) < 32768.0))
+        return fail(SONAR_E_UNSUPPORTED, "low-pass taps of magnitude %g exceed the FP16 range of this mode", h);
   const int D = p->D, M = p->M;
   std::vector<int4> dtab(static_cast<size_t>(D) * M);
   hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
@@ -309,7 +313,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
     }
   }
   // low-pass B fragments: K-step ks, lane l holds H[16 ks + 8 (l / 32) + j][l % 32],
-  // H[k][n] = h[n R + K - 1 - k], as BF16 hi and lo terms
+  // H[k][n] = h[n R + K - 1 - k], as hi and lo terms (BF16 with four sample planes, FP16 with two)
   const int nks = (31 * p->R + p->K + 15) / 16;
   // rounded up to whole batches of 4 K-steps; the extra K-steps have zero taps
   std::vector<uint16_t> ftab(static_cast<size_t>((nks + 3) & ~3) * 2 * 64 * 8, 0);
@@ -318,12 +322,22 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
       for (int j = 0; j < 8; ++j) {
         const int idx = (l & 31) * p->R + p->K - 1 - (16 * ks + 8 * (l >> 5) + j);
         const float h = idx >= 0 && idx < p->K ? static_cast<float>(taps[idx]) : 0.f;
-        const uint16_t hi = to_bf16_bits(h);
-        const uint32_t hb = static_cast<uint32_t>(hi) << 16;
-        float hv;
-        std::memcpy(&hv, &hb, 4);
+        uint16_t hi, lo;
+        if (mt_planes(p) == 2) {
+          // two sample planes: the low-pass runs on FP16 MFMA, taps as FP16 hi + lo
+          const _Float16 h1 = static_cast<_Float16>(h);
+          const _Float16 h2 = static_cast<_Float16>(h - static_cast<float>(h1));
+          std::memcpy(&hi, &h1, 2);
+          std::memcpy(&lo, &h2, 2);
+        } else {
+          hi = to_bf16_bits(h);
+          const uint32_t hb = static_cast<uint32_t>(hi) << 16;
+          float hv;
+          std::memcpy(&hv, &hb, 4);
+          lo = to_bf16_bits(h - hv);
+        }
         ftab[((static_cast<size_t>(2 * ks) * 64) + l) * 8 + j] = hi;
-        ftab[((static_cast<size_t>(2 * ks + 1) * 64) + l) * 8 + j] = to_bf16_bits(h - hv);
+        ftab[((static_cast<size_t>(2 * ks + 1) * 64) + l) * 8 + j] = lo;
       }
     }
   }
@@ -335,10 +349,13 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples), 4 (single-term samples) or 2 (FP16)
   const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : (f16 ? 2 : 4);
   p->mt_flop_per_frame = chunks * (p->mt_nwave / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
-  for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {   // low-pass: 3 MFMAs per K-step and column block
+  // low-pass: 3 MFMAs per K-step and column block (BF16 hi/lo x hi/lo), 2 with two sample planes
+  // (FP16 taps hi + lo times one FP16 term of |b|)
+  const int fir_mfma = mt_planes(p) == 2 ? 2 : 3;
+  for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {
     const int nval = std::min(32, p->mt_qc - q0);
-    p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * 3 * (2LL * 32 * 32 * 16) *
-                            nt * p->mt_nqt;
+    p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * fir_mfma *
+                            (2LL * 32 * 32 * 16) * nt * p->mt_nqt;
   }
   bool ok = dev_alloc(&p->d_mt_g, gtab.size(), total) == hipSuccess &&
             dev_alloc(&p->d_mt_w, wtab.size(), total) == hipSuccess &&

@@ -2,10 +2,11 @@
 
 The mode is the linear-interpolation beamformer with the fractional delays on a grid of
 1/2048 sample (exact FP16 weights) and the samples as one FP16 term scaled per frame by a
-power of two.  Bars: relative L2 <= 1e-4 against the oracle's gridded reading (what the
-mode computes: the only differences are the samples' FP16 rounding and FP32 sums), and
-<= 3e-4 against the oracle's plain time-domain mode (the grid moves each delay by at most
-1/4096 sample), for every array size including one microphone.  The sample scale is
+power of two.  Bars: relative L2 <= 2e-4 against the oracle's gridded reading (what the
+mode computes: the only differences are two FP16 roundings, of the samples and of |b| before
+the low-pass, each at most 2^-12 relative, and FP32 sums; with one microphone nothing averages
+them down), and <= 3e-4 against the oracle's plain time-domain mode (the grid moves each delay
+by at most 1/4096 sample), for every array size including one microphone.  The sample scale is
 checked bit by bit (planes = FP16 of 2^e yhat, header = 2^-e / M, 2^e max|yhat| < 2^14), and
 a power-of-two change of the input's scale changes the energyscape by exactly that factor.
 """
@@ -20,7 +21,7 @@ from workloads import synth
 
 pytestmark = pytest.mark.gpu
 
-BAR_GRID = 1e-4
+BAR_GRID = 2e-4
 BAR_TD = 3e-4
 STEPS = 2048
 
