@@ -1,5 +1,5 @@
-// Time-domain delay-and-sum on BF16 MFMA (§4.1 delay-and-sum toward every
-// direction; §4.3 subsampling after the envelope), fused with the envelope:
+// Time-domain delay-and-sum on BF16 or FP16 MFMA (§4.1 delay-and-sum toward
+// every direction; §4.3 subsampling after the envelope), fused with the envelope:
 //
 //   b_d[n]  = sum_m w0[d][m] yhat_m[n + o] + w1[d][m] yhat_m[n + o + 1]
 //   E[d][q] = sum_j h[j] |b_d[n0 + qR + (K-1)/2 - j]|
@@ -37,6 +37,12 @@
 // term of 2^e yhat (e per frame, from the matched filter's bound on |yhat|),
 // and v_mfma_f32_32x32x16_f16 takes two MFMAs per K-chunk (re, im).  The
 // energyscape is scaled back by the frame header's 2^-e / M at the store.
+//
+// Envelope: |b| goes through LDS (the samples of one output tile are spread over
+// the four residue wavefronts) and the low-pass + decimation runs as a banded
+// Toeplitz product on MFMA: with four planes on BF16 (|b| and taps as hi + lo
+// terms, three products), with two planes on FP16 (|b| as one FP16 term scaled
+// per workgroup by a power of two, taps as hi + lo, two products).
 #include <hip/hip_runtime.h>
 
 #include "plan.hpp"
