@@ -122,8 +122,9 @@ def td_offsets(Dl):
 def gridded_offsets(Dl, steps: int):
     """td_offsets with alpha rounded to a multiple of 1/steps (half-way cases to even):
     alpha' = rint(steps alpha) / steps; alpha' = 1 is taken as offset o + 1 with alpha' = 0.
-    (A reading of this build, not of the paper: the fractional delay on a grid of 1/steps
-    sample, which makes the interpolation weights exact in a short floating-point format.)"""
+    (A precision device of the library's FP16 mode, not a reading of the paper: the fractional
+    delay on a grid of 1/steps sample makes the interpolation weights exact in a short
+    floating-point format.)"""
     o, alpha = td_offsets(Dl)
     a = np.rint(alpha * steps) / steps
     up = a >= 1.0
