@@ -160,3 +160,23 @@ def test_fused_energyscape_equals_staged_calls(gpu, torch_mod, mode):
     E1 = plan.energyscape(x)
     E2 = plan.beamform_envelope(plan.matched_filter(x))
     assert torch.equal(E1, E2)
+
+
+def test_two_plane_modes_refuse_taps_beyond_fp16(gpu, torch_mod):
+    """The two-plane MFMA modes run the low-pass on FP16 taps: a filter with a tap of magnitude
+    2^15 or more is refused at plan time; the same filter scaled into range is accepted and gives
+    the oracle's energyscape for that filter (the FIR is linear in the taps)."""
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=1, n_samples=1500, n_dirs=20)
+    big = O.default_lowpass(10) * 1.0e6
+    for mode in ("td_bf16x2", "td_f16"):
+        with pytest.raises(gpu.SonarError):
+            gpu.Plan(w.mic_pos, w.chirp, w.dirs, 1500, fs=w.fs, c=w.c, band=w.cfg.band, taps=big, mode=mode)
+    taps = O.default_lowpass(10) * 4.0
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 1500, fs=w.fs, c=w.c, band=w.cfg.band, taps=taps, mode="td_f16")
+    E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()[0]
+    Eo = O.energyscape(w.x[0].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P, R=10,
+                       taps=taps, band=w.cfg.band, mode="td")
+    err = rel_l2(E, Eo)
+    _say(f"  custom taps x4, td_f16: rel L2 vs td oracle {err:.3e}")
+    assert err <= BAR_TD
