@@ -78,8 +78,9 @@ enum sonar_status {
  *              there).  In TD_BF16X2 and TD_F16 the envelope's low-pass runs on
  *              FP16 MFMA: |b| as one FP16 term scaled per tile of 32 directions
  *              by a power of two (largest scaled value below 2^14), the taps as
- *              two FP16 terms (SONAR_E_UNSUPPORTED for taps of magnitude 2^15 or
- *              more).
+ *              two FP16 terms after a plan-time power-of-two scale that puts the
+ *              largest tap in [2^13, 2^14) (undone in FP32 at the store, so
+ *              filters of any gain keep about 22 bits per tap).
  *  TD_CUBIC  : 4-point Lagrange (cubic) fractional delay: o = floor(-Dl),
  *              a = -Dl - o, b_d[n] = (1/M) sum_m sum_{k=-1..2} L_k(a) yhat_m[n+o+k],
  *              L_k(a) = prod_{j != k} (a - j)/(k - j); FP32 on the TD_LINEAR
@@ -125,7 +126,8 @@ typedef struct {
   const double* lpf_taps;    /* [K] envelope low-pass taps, or NULL for the default          */
   double band_lo_hz;         /* matched-filter band mask [lo, hi] in Hz;                    */
   double band_hi_hz;         /*   0, 0 disables the mask                                     */
-  int32_t fft_len;           /* P: power of two >= N + L - 1; 0 selects the smallest        */
+  int32_t fft_len;           /* P: even, >= N + L - 1; 0 selects the smallest power of two  */
+                             /*   (this build transforms powers of two 32 .. 524288 only)    */
   int32_t bf_mode;           /* enum sonar_bf_mode                                            */
   int32_t sample_dtype;      /* enum sonar_dtype of x                                         */
   int32_t max_frames;        /* F_max >= 1: the workspace is sized for this batch            */
@@ -161,7 +163,9 @@ enum sonar_query {
  *   FFT twiddles.
  * The tables are built with work enqueued on `stream`; the call synchronises
  * that stream before returning.  Returns SONAR_E_INVALID for a descriptor that
- * breaks a rule stated above; SONAR_E_UNSUPPORTED for P > 524288, for the
+ * breaks a rule stated above (an odd P or P < N + L - 1 among them);
+ * SONAR_E_UNSUPPORTED for an even P >= N + L - 1 that is not a power of two
+ * or lies outside [32, 524288], for the
  * frequency-domain modes when P > 65536 or more than 16385 bins are stored,
  * and for array apertures whose delay spread exceeds the beamformer tiles;
  * SONAR_E_NOMEM when allocation fails.  *out is set only on success.
@@ -261,7 +265,11 @@ int sonar_energyscape_batch(sonar_plan plan, const void* x, int32_t F, float* E,
  * HIP graph on `stream` (the branches become parallel graph nodes) and replay
  * it; replays reuse the plans' workspaces, so replays of graphs that share a
  * plan must not overlap.  Concurrent calls on one device are serialised on
- * the host while they enqueue.
+ * the host while they enqueue.  Side streams that joined a capture stay in it
+ * until that capture ends: while they are joined to a capture other than the
+ * one `stream` belongs to (a graph still being recorded on another stream, or
+ * an eager call during such a recording), the call runs its items in order on
+ * `stream` alone (same results, no concurrency).
  *   plans  : n plan handles (a plan may appear more than once).
  *   x      : n device pointers, x[i] = [frames[i]][M_i][N_i] samples.
  *   frames : n frame counts, 1 <= frames[i] <= max_frames of plans[i].

@@ -343,7 +343,8 @@ def envelope_iir(b_win, bcoef, acoef, Q: int, R: int, K: int) -> np.ndarray:
 
 def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None = None,
                 gate=None, R: int = 10, taps=None, band=None, mode: str = "td",
-                dir_index=None, return_beam: bool = False, iir=None, alpha_steps: int | None = None):
+                dir_index=None, return_beam: bool = False, iir=None, alpha_steps: int | None = None,
+                timings: dict | None = None):
     """E[d][q] for one recording x[M][N]; mode 'td' (linear interpolation), 'td_nearest' (integer
     delays), 'td_cubic' (4-point Lagrange interpolation) or 'fd' (exact).  alpha_steps (mode
     'td') puts the fractional delays on a grid of 1/alpha_steps sample (gridded_offsets).
@@ -351,7 +352,11 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
     dir_index selects a subset of directions (rows of the result follow it).
     With return_beam, also returns the complex beam window b[d][G'].
     iir = (b, a) selects the IIR envelope reading (envelope_iir) instead of the FIR.
+    timings, if given, receives the wall-clock seconds of the three stages ('matched_filter',
+    'beamform' (delays included), 'envelope'); it does not change what is computed.
     """
+    import time
+    clock = time.perf_counter
     x = np.asarray(x, dtype=np.float64)
     M, N = x.shape
     L = len(chirp)
@@ -368,19 +373,25 @@ def energyscape(x, chirp, mic_pos, dirs, *, fs: float, c: float, P: int | None =
     u = np.asarray(dirs, dtype=np.float64)
     if dir_index is not None:
         u = u[np.asarray(dir_index)]
+    if mode not in ("td", "td_nearest", "td_cubic", "fd"):
+        raise ValueError("mode must be 'td', 'td_nearest', 'td_cubic' or 'fd'")
+    t0 = clock()
+    y = matched_filter_spectrum(x, chirp, P, fs, band) if mode == "fd" else matched_filter(x, chirp, P, fs, band)
+    t1 = clock()
     Dl = delays(mic_pos, u, fs, c)
     n_idx = beam_window_indices(n0, Q, R, K)
     if mode == "td":
-        b = das_td(matched_filter(x, chirp, P, fs, band), Dl, n_idx, alpha_steps)
+        b = das_td(y, Dl, n_idx, alpha_steps)
     elif mode == "td_nearest":
-        b = das_td_nearest(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
+        b = das_td_nearest(y, Dl, n_idx)
     elif mode == "td_cubic":
-        b = das_td_cubic(matched_filter(x, chirp, P, fs, band), Dl, n_idx)
-    elif mode == "fd":
-        b = das_fd(matched_filter_spectrum(x, chirp, P, fs, band), Dl, n_idx)
+        b = das_td_cubic(y, Dl, n_idx)
     else:
-        raise ValueError("mode must be 'td', 'td_nearest', 'td_cubic' or 'fd'")
+        b = das_fd(y, Dl, n_idx)
+    t2 = clock()
     E = envelope(b, h, Q, R) if iir is None else envelope_iir(b, iir[0], iir[1], Q, R, K)
+    if timings is not None:
+        timings.update(matched_filter=t1 - t0, beamform=t2 - t1, envelope=clock() - t2)
     return (E, b) if return_beam else E
 
 

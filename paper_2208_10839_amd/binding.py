@@ -416,11 +416,15 @@ class Energyscape:
         class _Fn(torch.autograd.Function):
             @staticmethod
             def forward(ctx, x, pos, plan):
-                plan.set_positions(pos.detach().cpu().numpy())
+                pos_np = np.array(pos.detach().cpu().numpy(), dtype=np.float64, copy=True)
+                plan.set_positions(pos_np)
                 mf = plan.matched_filter(x)
                 beam = plan.beamform(mf)
                 E = plan.envelope(beam)
                 ctx.plan = plan
+                # the VJP kernels read the plan's delay tables: a later forward on the same plan
+                # moves them, so backward puts this forward's geometry back first
+                ctx.pos = pos_np
                 ctx.save_for_backward(mf, beam)
                 return E
 
@@ -428,6 +432,7 @@ class Energyscape:
             def backward(ctx, dE):
                 mf, beam = ctx.saved_tensors
                 want_dx, want_dpos = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+                ctx.plan.set_positions(ctx.pos)
                 _, dx, dpos = ctx.plan.vjp(mf, beam.clone(), dE.contiguous(), want_dx=want_dx, want_dpos=want_dpos)
                 return dx, (torch.from_numpy(dpos) if dpos is not None else None), None
 

@@ -80,7 +80,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off) {
+    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale) {
   constexpr int MICS = NPL == 2 ? 2 * MT_MICS : MT_MICS;   // microphones staged per group
   extern __shared__ unsigned short sm[];    // NPL planes x MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
@@ -276,7 +276,8 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   // column lane%32 (window sample sw + 128 nt + 4 column) for each output tile.
   //  * two sample planes (FIR16): [32][NSP16] FP16 of 2^e |b|, e per workgroup from the tile's
   //    largest |b| (so every scaled value is below 2^14); the low-pass runs on FP16 MFMA with
-  //    the taps as two FP16 terms, and E is scaled back by 2^-e;
+  //    the taps (scaled by the plan's power of two) as two FP16 terms, and E is scaled back by
+  //    2^-e and the taps' 2^-ts;
   //  * four planes: [32][NSP] words {bf16 hi, bf16 lo}, the taps as two BF16 terms.
   constexpr bool FIR16 = NPL == 2;
   constexpr int NSP = mt_nsp(NWAVE);
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     }
     if constexpr (FIR16) {
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[v] *= inv_scale;
+      for (int v = 0; v < 16; ++v) acc[v] = acc[v] * inv_scale * fir_unscale;   // two steps: each factor >= 2^-100
     }
     if (d >= 0) {
       float* erow = E + (static_cast<long long>(f) * D + d) * Q + static_cast<long long>(qt) * qc;
@@ -524,7 +525,7 @@ hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F,
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
                      p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
-                     static_cast<int>(mt_perm_offset(p)));
+                     static_cast<int>(mt_perm_offset(p)), p->mt_fir_unscale);
   return hipGetLastError();
 }
 

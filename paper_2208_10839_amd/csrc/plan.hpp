@@ -60,6 +60,7 @@ struct sonar_plan_s {
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
   int mt_nwave = 0;     // wavefronts per workgroup (MT_NWAVE_SMALL or MT_NWAVE_LARGE)
   long long mt_flop_per_frame = 0;   // matrix-core flops issued per frame
+  float mt_fir_unscale = 1.f;          // 2^-ts: the two-plane modes' low-pass taps are stored times 2^ts
 
   int device = 0;
   size_t ws_bytes = 0;

@@ -203,10 +203,20 @@ uint16_t to_bf16_bits(float v) {
 // fragments (tap weights as BF16 hi and lo terms) are stored in lane order.
 int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, const std::vector<double>& taps,
                     hipStream_t stream, size_t* total) {
-  if (mt_planes(p) == 2)
-    for (double h : taps)
-      if (!(std::fabs(h) < 32768.0))
-        return fail(SONAR_E_UNSUPPORTED, "low-pass taps of magnitude %g exceed the FP16 range of this mode", h);
+  // two sample planes: the low-pass runs on FP16 taps, scaled by 2^ts so that the largest lands in
+  // [2^13, 2^14) (FP16 hi + lo terms keep ~22 bits of every tap whatever the filter's gain); the kernel
+  // multiplies the result by 2^-ts at the store
+  int ts = 0;
+  if (mt_planes(p) == 2) {
+    double hmax = 0.0;
+    for (double h : taps) hmax = std::fmax(hmax, std::fabs(h));
+    if (hmax > 0.0) {
+      int ex = 0;
+      (void)std::frexp(hmax, &ex);   // hmax = mant 2^ex, mant in [0.5, 1)
+      ts = std::max(-100, std::min(100, 14 - ex));
+    }
+  }
+  p->mt_fir_unscale = static_cast<float>(std::ldexp(1.0, -ts));
   const int D = p->D, M = p->M;
   std::vector<int4> dtab(static_cast<size_t>(D) * M);
   hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
@@ -321,7 +331,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
     for (int l = 0; l < 64; ++l) {
       for (int j = 0; j < 8; ++j) {
         const int idx = (l & 31) * p->R + p->K - 1 - (16 * ks + 8 * (l >> 5) + j);
-        const float h = idx >= 0 && idx < p->K ? static_cast<float>(taps[idx]) : 0.f;
+        const float h = idx >= 0 && idx < p->K ? static_cast<float>(std::ldexp(taps[idx], ts)) : 0.f;
         uint16_t hi, lo;
         if (mt_planes(p) == 2) {
           // two sample planes: the low-pass runs on FP16 MFMA, taps as FP16 hi + lo
@@ -510,9 +520,14 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (P == 0) {
     P = 32;
     while (P < need) P *= 2;
-  } else if (!is_pow2(P) || P < need || P < 32) {
+  } else if (P < need || (P % 2) != 0) {
     delete p;
-    return fail(SONAR_E_INVALID, "fft_len %d must be a power of two >= max(N + L - 1, 32)", d.fft_len);
+    return fail(SONAR_E_INVALID, "fft_len %d must be even and >= N + L - 1 = %lld", d.fft_len, need);
+  } else if (!is_pow2(P) || P < 32) {
+    // a valid length (the definition only needs P even and >= N + L - 1) that the transforms of
+    // this build do not cover: they are radix-2^k
+    delete p;
+    return fail(SONAR_E_UNSUPPORTED, "fft_len %d: this build transforms powers of two >= 32 only", d.fft_len);
   }
   if (P > 2LL * MB_MAX_R * (1 << MB_LOGN2)) {
     delete p;
@@ -890,6 +905,30 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
     load[lane[i]] += cost(i);
   }
   std::lock_guard<std::mutex> lk(pool->mu);   // the pool's events are reused by every call
+  // A side stream that joined a capture stays in it until that capture ends.  If one is joined to
+  // a capture other than the caller's (another stream's graph still being recorded, or the caller
+  // is eager while some capture is open), the items run in order on the caller's stream instead.
+  {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    unsigned long long cid = 0;
+    hipError_t ec = hipStreamGetCaptureInfo(stream, &cs, &cid);
+    bool clash = ec != hipSuccess;
+    for (int k = 0; k < MULTI_SIDE_STREAMS && !clash; ++k) {
+      hipStreamCaptureStatus ss = hipStreamCaptureStatusNone;
+      unsigned long long sid = 0;
+      ec = hipStreamGetCaptureInfo(pool->s[k], &ss, &sid);
+      if (ec != hipSuccess) clash = true;
+      else if (ss != hipStreamCaptureStatusNone && !(cs == hipStreamCaptureStatusActive && sid == cid)) clash = true;
+    }
+    if (ec != hipSuccess) (void)hipGetLastError();
+    if (clash) {
+      for (int i = 0; i < n; ++i) {
+        const int st = sonar_energyscape_batch(plans[i], x[i], frames[i], E[i], stream);
+        if (st != SONAR_OK) return st;
+      }
+      return SONAR_OK;
+    }
+  }
   bool used[NL] = {false};
   for (int i = 0; i < n; ++i) used[lane[i]] = true;
   hipError_t e = hipEventRecord(pool->fork, stream);

@@ -69,8 +69,11 @@ def _desc(**over):
     ("decim", 0, binding.SONAR_E_INVALID),
     ("max_frames", 0, binding.SONAR_E_INVALID),
     ("fs_hz", -1.0, binding.SONAR_E_INVALID),
-    ("fft_len", 100, binding.SONAR_E_INVALID),        # not a power of two
+    ("fft_len", 107, binding.SONAR_E_INVALID),        # odd (N + L - 1 = 107): not a valid length
     ("fft_len", 64, binding.SONAR_E_INVALID),         # below N + L - 1
+    ("fft_len", 106, binding.SONAR_E_INVALID),        # even, but below N + L - 1
+    ("fft_len", 108, binding.SONAR_E_UNSUPPORTED),    # valid (even, >= N + L - 1), not a power of two
+    ("fft_len", 120, binding.SONAR_E_UNSUPPORTED),    # valid: 2^3 3 5, radices this build does not have
     ("fft_len", 1048576, binding.SONAR_E_UNSUPPORTED),  # above 2 x 16 x 16384
     ("gate_begin", 50, binding.SONAR_E_INVALID),      # gate_end 0 -> n0 >= n1
     ("lpf_len", 4, binding.SONAR_E_INVALID),          # even, and no taps

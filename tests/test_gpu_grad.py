@@ -185,6 +185,40 @@ def test_autograd_function_matches_vjp(gpu, torch_mod):
     assert np.array_equal(pos.grad.numpy(), dpos)
 
 
+def test_autograd_backward_uses_its_own_forward_geometry(gpu, torch_mod):
+    """Two forwards on one plan at different positions, then backward of the first: its gradients
+    are those of the first geometry (the plan's delay tables were moved by the second forward)."""
+    torch = torch_mod
+    w = synth.make_workload("c1", n_dirs=23)
+    _say("case autograd two geometries: c1 D=23, fd_fp32")
+    plan = _plan(gpu, w, "fd")
+    wts = torch.from_numpy(np.random.default_rng(np.random.SeedSequence([4, 0, 0, 10]))
+                           .standard_normal((1, plan.D, plan.Q)).astype(np.float32)).cuda()
+    pos1 = w.mic_pos.copy()
+    pos2 = pos1 + np.random.default_rng(np.random.SeedSequence([4, 0, 0, 11])).normal(0.0, 1e-3, pos1.shape)
+    x1 = torch.from_numpy(w.x).cuda().requires_grad_(True)
+    p1 = torch.from_numpy(pos1.copy()).requires_grad_(True)
+    x2 = torch.from_numpy(w.x).cuda().requires_grad_(True)
+    p2 = torch.from_numpy(pos2.copy()).requires_grad_(True)
+    E1 = gpu.Energyscape.apply(x1, p1, plan)
+    E2 = gpu.Energyscape.apply(x2, p2, plan)
+    (E1 * wts).sum().backward()
+    plan.set_positions(pos1)
+    mf = plan.matched_filter(x1.detach())
+    _, dx, dpos = plan.vjp(mf, plan.beamform(mf), wts)
+    torch.cuda.synchronize()
+    assert torch.equal(x1.grad, dx)
+    assert np.array_equal(p1.grad.numpy(), dpos)
+    (E2 * wts).sum().backward()
+    plan.set_positions(pos2)
+    mf = plan.matched_filter(x2.detach())
+    _, dx2, dpos2 = plan.vjp(mf, plan.beamform(mf), wts)
+    torch.cuda.synchronize()
+    assert torch.equal(x2.grad, dx2)
+    assert np.array_equal(p2.grad.numpy(), dpos2)
+    assert not np.array_equal(dpos, dpos2)
+
+
 @pytest.mark.parametrize("mode", ["td", "fd"])
 def test_backward_from_samples_matches_vjp(gpu, torch_mod, mode):
     """sonar_energyscape_backward (x -> dx, dp in one call) equals matched filter + beamform + VJP."""

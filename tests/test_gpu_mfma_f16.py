@@ -119,21 +119,6 @@ def test_td_f16_power_of_two_scale_and_zero_input(gpu, torch_mod):
     assert torch.count_nonzero(Ez).item() == 0
 
 
-def test_c2_full_size_td_f16(gpu, torch_mod):
-    torch = torch_mod
-    F = 16
-    w = synth.make_workload("c2", frames=F)
-    _say("case c2 full td_f16: F=16")
-    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 16384, fs=w.fs, c=w.c, band=w.cfg.band, max_frames=F, mode="td_f16")
-    E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
-    rng = np.random.default_rng(3)
-    sample = np.sort(np.concatenate([[0, 1499], rng.choice(1500, 10, replace=False)]))
-    for f in (0, 7, 15):
-        _check(w, E[f][sample], plan.P, 10, w.cfg.band, f, f"frame {f} sampled", dir_index=sample)
-    x = torch.from_numpy(w.x).cuda()
-    assert torch.equal(plan.energyscape(x), plan.energyscape(x))
-
-
 def test_td_f16_gradient_support(gpu, torch_mod):
     """dx is the adjoint on the gridded delays; dpos is refused (the gridded delays are piecewise
     constant in the positions)."""
@@ -162,21 +147,21 @@ def test_fused_energyscape_equals_staged_calls(gpu, torch_mod, mode):
     assert torch.equal(E1, E2)
 
 
-def test_two_plane_modes_refuse_taps_beyond_fp16(gpu, torch_mod):
-    """The two-plane MFMA modes run the low-pass on FP16 taps: a filter with a tap of magnitude
-    2^15 or more is refused at plan time; the same filter scaled into range is accepted and gives
-    the oracle's energyscape for that filter (the FIR is linear in the taps)."""
+@pytest.mark.parametrize("gain", [1.0e6, 4.0, 1.0e-4, 1.0e-9])
+def test_two_plane_modes_any_tap_gain(gpu, torch_mod, gain):
+    """The two-plane MFMA modes run the low-pass on FP16 taps, scaled at plan time by a power of two
+    that puts the largest tap near 2^14 and undone at the store: a filter with any gain gives the
+    oracle's energyscape for that filter within the modes' bars."""
     torch = torch_mod
     w = synth.make_workload("c2", frames=1, n_samples=1500, n_dirs=20)
-    big = O.default_lowpass(10) * 1.0e6
-    for mode in ("td_bf16x2", "td_f16"):
-        with pytest.raises(gpu.SonarError):
-            gpu.Plan(w.mic_pos, w.chirp, w.dirs, 1500, fs=w.fs, c=w.c, band=w.cfg.band, taps=big, mode=mode)
-    taps = O.default_lowpass(10) * 4.0
-    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 1500, fs=w.fs, c=w.c, band=w.cfg.band, taps=taps, mode="td_f16")
-    E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()[0]
-    Eo = O.energyscape(w.x[0].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P, R=10,
+    taps = O.default_lowpass(10) * gain
+    _say(f"case tap gain {gain:g}")
+    Eo = O.energyscape(w.x[0].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=2048, R=10,
                        taps=taps, band=w.cfg.band, mode="td")
-    err = rel_l2(E, Eo)
-    _say(f"  custom taps x4, td_f16: rel L2 vs td oracle {err:.3e}")
-    assert err <= BAR_TD
+    for mode in ("td_bf16x2", "td_f16"):
+        plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 1500, fs=w.fs, c=w.c, band=w.cfg.band, taps=taps, mode=mode)
+        assert plan.P == 2048
+        E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()[0]
+        err = rel_l2(E, Eo)
+        _say(f"  {mode}: rel L2 vs td oracle {err:.3e}")
+        assert err <= (BAR_TD if mode == "td_f16" else 1e-3)

@@ -92,24 +92,3 @@ def test_td_bf16x2_shapes(gpu, torch_mod, case):
     _say(f"  max rel L2 over frames = {max(errs):.3e}")
     if plan.M >= 32:
         assert max(errs) <= BAR
-
-
-def test_c2_full_size_td_bf16x2(gpu, torch_mod):
-    torch = torch_mod
-    F = 16
-    w = synth.make_workload("c2", frames=F)
-    _say("case c2 full td_bf16x2: F=16")
-    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 16384, fs=w.fs, c=w.c, band=w.cfg.band, max_frames=F,
-                    mode="td_bf16x2")
-    E = plan.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
-    rng = np.random.default_rng(3)
-    sample = np.sort(np.concatenate([[0, 1499], rng.choice(1500, 10, replace=False)]))
-    errs = []
-    for f in (0, 7, 15):
-        Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P,
-                           R=10, band=w.cfg.band, mode="td", dir_index=sample)
-        errs.append(rel_l2(E[f][sample], Eo))
-        _say(f"  frame {f}: sampled rel L2 = {errs[-1]:.3e}")
-    assert max(errs) <= BAR
-    x = torch.from_numpy(w.x).cuda()
-    assert torch.equal(plan.energyscape(x), plan.energyscape(x))

@@ -135,3 +135,38 @@ def test_tuned_plan(gpu, torch_mod, network, tune):
     assert waves in ((4, 8) if pl.mode.startswith("td_bf16") or pl.mode == "td_f16" else (0,))
     E = pl.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
     _check_against_oracle(w, E, pl.P, pl.mode, f"tuned {tune}")
+
+
+def test_network_eager_call_while_another_stream_captures(gpu, torch_mod, network):
+    """A multi call captured on one stream leaves the library's side streams joined to that capture
+    until it ends; an eager multi call on another stream in that window must neither land in the
+    graph nor fail: it runs (in order, on its own stream) and gives the single-call results, and
+    the graph still replays the captured call."""
+    torch = torch_mod
+    _say("case network: eager multi on a second stream during a capture")
+    sub = network[:3]
+    plans_a = [_plan(gpu, w, mode="td_bf16x2") for w in sub]
+    plans_b = [_plan(gpu, w, mode="td_bf16x2") for w in sub]
+    xs = [torch.from_numpy(w.x).cuda() for w in sub]
+    outs_a = [torch.empty((w.x.shape[0], w.dirs.shape[0], pl.Q), dtype=torch.float32, device="cuda")
+              for w, pl in zip(sub, plans_a)]
+    outs_b = [torch.zeros_like(o) for o in outs_a]
+    gpu.energyscape_multi(plans_a, xs, outs_a)
+    torch.cuda.synchronize()
+    s2 = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        gpu.energyscape_multi(plans_a, xs, outs_a)
+        gpu.energyscape_multi(plans_b, xs, outs_b, stream=s2)
+    torch.cuda.synchronize()
+    ref = [pl.energyscape(x) for pl, x in zip(plans_b, xs)]
+    torch.cuda.synchronize()
+    for a, b in zip(outs_b, ref):
+        assert torch.equal(a, b)
+    for o in outs_a:
+        o.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for a, b in zip(outs_a, ref):
+        assert torch.equal(a, b)

@@ -137,48 +137,37 @@ def test_odd_shapes_match_oracle(gpu, torch_mod, case):
         assert err <= TOL_F32
 
 
+# compute-only bar per mode (against the oracle on the rounded samples) and its oracle reading
+HALF_MODES = {"td": (1e-5, "td", None), "td_bf16x2": (1e-3, "td", None), "td_f16": (3e-4, "td", None),
+              "fd_bf16": (1e-3, "fd", None), "fd_bf16x3": (1e-5, "fd", None), "td_bf16": (1e-3, "td", None)}
+
+
+@pytest.mark.parametrize("mode", list(HALF_MODES))
 @pytest.mark.parametrize("dt", ["f16", "bf16"])
-def test_half_precision_samples(gpu, torch_mod, dt):
+def test_half_precision_samples(gpu, torch_mod, dt, mode):
+    """FP16 / BF16 samples into every mode: the compute-only error (against the oracle on the rounded
+    samples) meets the mode's bar; the end-to-end error against the oracle on the FP32 samples, which
+    adds the input rounding, stays within 1e-3."""
     torch = torch_mod
-    w = synth.make_workload("c2", frames=2, n_samples=4000, n_dirs=48)
-    _say(f"case half samples {dt}")
+    w = synth.make_workload("c2", frames=2, n_samples=4000, n_dirs=96)
+    _say(f"case half samples {dt} -> {mode}")
+    bar, omode, _ = HALF_MODES[mode]
     tdt = {"f16": torch.float16, "bf16": torch.bfloat16}[dt]
     plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 4000, fs=w.fs, c=w.c, band=w.cfg.band, sample_dtype=dt,
-                    max_frames=2)
+                    max_frames=2, mode=mode)
     xh = torch.from_numpy(w.x).to(tdt)
     E = plan.energyscape(xh.cuda()).cpu().numpy()
     xr = xh.float().numpy().astype(np.float64)            # the rounded samples
     for f in range(2):
         Eo_r = O.energyscape(xr[f], w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c, P=plan.P, R=10,
-                             band=w.cfg.band)
+                             band=w.cfg.band, mode=omode)
         Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c,
-                           P=plan.P, R=10, band=w.cfg.band)
+                           P=plan.P, R=10, band=w.cfg.band, mode=omode)
         e_compute = rel_l2(E[f], Eo_r)
         e_total = rel_l2(E[f], Eo)
-        _say(f"  {dt} frame {f}: compute-only rel L2 = {e_compute:.3e}, vs FP32 samples = {e_total:.3e}")
-        assert e_compute <= TOL_F32
+        _say(f"  {dt} {mode} frame {f}: compute-only rel L2 = {e_compute:.3e}, vs FP32 samples = {e_total:.3e}")
+        assert e_compute <= bar
         assert e_total <= 1e-3
-
-
-def test_c2_full_size_sampled_directions(gpu, torch_mod):
-    """Full 32 x 16384 x 1500 workload, batch of 4: sampled directions against the oracle."""
-    torch = torch_mod
-    F = 4
-    w = synth.make_workload("c2", frames=F)
-    _say("case c2 full: M=32 N=16384 D=1500 F=4")
-    plan = _plan(gpu, w, max_frames=F)
-    x = torch.from_numpy(w.x).cuda()
-    E = plan.energyscape(x).cpu().numpy()
-    assert E.shape == (F, 1500, 1639)
-    assert np.all(np.isfinite(E))
-    rng = np.random.default_rng(7)
-    sample = np.sort(np.concatenate([[0, 15, 16, 1499], rng.choice(1500, 20, replace=False)]))
-    for f in range(F):
-        Eo = O.energyscape(w.x[f].astype(np.float64), w.chirp, w.mic_pos, w.dirs, fs=w.fs, c=w.c,
-                           P=plan.P, R=10, band=w.cfg.band, mode="td", dir_index=sample)
-        err = rel_l2(E[f][sample], Eo)
-        _say(f"  frame {f}: sampled-direction rel L2 = {err:.3e}")
-        assert err <= TOL_F32
 
 
 def test_deterministic_and_batch_independent(gpu, torch_mod):
