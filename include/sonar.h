@@ -250,6 +250,27 @@ int sonar_energyscape_batch(sonar_plan plan, const void* x, int32_t F, float* E,
                             hipStream_t stream);
 
 /*
+ * sonar_energyscape_batch_static -- for callers that cannot allocate device
+ * memory or touch allocation calls at all (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the result of
+ * sonar_energyscape_batch bit for bit (the same kernels), with every
+ * per-frame buffer beyond x and E (matched-filter spectra and rows or planes,
+ * band and beam spectra, transform scratch, frame bounds) taken from a
+ * 128 MiB static device array of the library instead of the plan's
+ * workspace.  The call allocates and frees nothing.  Each device holds its
+ * own copy of the array from the time the library is loaded until the process
+ * ends; its device address is taken when the first plan is created on that
+ * device.  Every call on a device shares that device's array and leaves its
+ * contents behind (nothing in it needs to start at zero): calls that overlap
+ * on one device, on any streams, race, and must be ordered by the caller.
+ *   x : [F][M][N] samples of sample_dtype;  E : float [F][D][Q].
+ * SONAR_E_INVALID (nothing enqueued) when F frames of this plan need more than
+ * the 128 MiB (the message states how many frames fit).
+ */
+int sonar_energyscape_batch_static(sonar_plan plan, const void* x, int32_t F, float* E,
+                                   hipStream_t stream);
+
+/*
  * sonar_energyscape_multi -- the whole chain for n independent items, each
  * with its own plan (its own sensor geometry, recording length, direction
  * grid and mode): E_i = sonar_energyscape_batch(plans[i], x[i], frames[i]).

@@ -71,6 +71,8 @@ _SIGNATURES = {
     "sonar_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_beamform_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_energyscape_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_energyscape_batch_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                       ctypes.c_void_p]),
     "sonar_energyscape_multi": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_void_p),
                                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_void_p),
                                                 ctypes.c_int32, ctypes.c_void_p]),
@@ -249,6 +251,18 @@ class Plan:
         _check(load().sonar_energyscape_batch(self._h, ctypes.c_void_p(x.data_ptr()), F,
                                               ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
                "sonar_energyscape_batch")
+        return E
+
+    def energyscape_static(self, x, out=None, stream=None):
+        """sonar_energyscape_batch_static: E[F][D][Q] with the per-frame buffers in the library's static
+        device scratch (no allocation in the call; calls on one device must not overlap).  `out`
+        should be given by callers that cannot allocate."""
+        import torch
+        F = self._samples(x)
+        E = self._out(out, (F, self.D, self.Q), torch.float32, x.device)
+        _check(load().sonar_energyscape_batch_static(self._h, ctypes.c_void_p(x.data_ptr()), F,
+                                                     ctypes.c_void_p(E.data_ptr()), _stream_handle(stream)),
+               "sonar_energyscape_batch_static")
         return E
 
     def matched_filter(self, x, out=None, stream=None):

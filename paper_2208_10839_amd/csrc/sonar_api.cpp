@@ -15,10 +15,15 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "plan.hpp"
 #include "sonar.h"
+
+// Static scratch of sonar_energyscape_batch_static (128 MiB per device, see below).
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -428,6 +433,31 @@ side_pool* side_pool_of(int dev) {
   return g_side_pools[dev].ready ? &g_side_pools[dev] : nullptr;
 }
 
+// Static scratch of sonar_energyscape_batch_static: device memory that needs no allocation call.
+// Each device holds its own copy from the time the code object is loaded until the process ends.
+// Host code never uses the array's name as an address: the device address is taken once per
+// device by hipGetSymbolAddress (with that device current) and kept in g_scratch_addr.
+struct scratch_slot {
+  bool tried = false;
+  void* addr = nullptr;
+  hipError_t err = hipSuccess;
+};
+scratch_slot g_scratch_addr[MULTI_MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+// takes the device address of `scratch` on device dev (the current device), once
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= MULTI_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  scratch_slot& s = g_scratch_addr[dev];
+  if (s.tried) return;
+  s.tried = true;
+  void* ptr = nullptr;
+  s.err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (s.err == hipSuccess) s.addr = ptr;
+  else (void)hipGetLastError();
+}
+
 // workgroup size the next plan creation on this thread must give the MFMA beamformer
 // (0: the largest-throughput rule, 4 waves where the staging fits, else 8); set only by
 // sonar_plan_create_tuned while it tries the candidates
@@ -685,6 +715,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     return fail(SONAR_E_HIP, "hipGetDevice failed");
   }
   create_side_pool(p->device);
+  resolve_scratch(p->device);
   hipError_t e = init_td_kernel_attributes();
   if (e == hipSuccess) e = init_mt_kernel_attributes();
   if (e != hipSuccess) {
@@ -853,9 +884,10 @@ int sonar_beamform_envelope(sonar_plan p, const void* mf_in, int32_t F, float* E
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform-envelope launch");
 }
 
-int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hipStream_t stream) {
-  int st = check_exec(p, x, E, F);
-  if (st != SONAR_OK) return st;
+namespace {
+
+// the whole chain for F frames on the workspace buffers that p points at
+hipError_t energyscape_enqueue(const sonar_plan_s* p, const void* x, int F, float* E, hipStream_t stream) {
   hipError_t e;
   if (is_td(p)) {
     // the fused MFMA beamformer reads only the 16-bit planes: the complex rows are not written
@@ -865,7 +897,69 @@ int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hi
     e = launch_mf_fd(p, x, F, p->d_fdspec, stream);
     if (e == hipSuccess) e = beam_env(p, p->d_fdspec, F, E, stream);
   }
+  return e;
+}
+
+// Per-frame workspace of sonar_energyscape_batch, laid out in `base` (256-byte aligned pieces)
+// on a copy of the plan; returns the bytes F frames need (nothing is written when base is null).
+size_t carve_workspace(sonar_plan_s* q, int F, unsigned char* base) {
+  size_t off = 0;
+  auto take = [&](auto** ptr, size_t elems, size_t elem_bytes) {
+    off = (off + 255) / 256 * 256;
+    if (base) *ptr = reinterpret_cast<std::remove_reference_t<decltype(**ptr)>*>(base + off);
+    off += elems * elem_bytes;
+  };
+  const size_t f = static_cast<size_t>(F);
+  const bool fd = !is_td(q);
+  const bool big = q->NF > (1 << MB_LOGN2);
+  if (!fd) {
+    take(&q->d_mf, f * q->mf_fstride, sizeof(float2));
+    take(&q->d_spec, f * q->M * (static_cast<size_t>(q->NF) + 1), sizeof(float2));
+    if (mt_f16(q)) take(&q->d_fbound, f * q->M, sizeof(float));
+  } else {
+    take(&q->d_fdspec, f * q->kb * q->M, sizeof(float2));
+    take(&q->d_bspec, f * q->D * q->kb_pad, sizeof(float2));
+  }
+  if ((fd && !q->fd_fused) || q->iir_ns > 0) take(&q->d_beam, f * q->D * q->G, sizeof(float2));
+  if (big) take(&q->d_big, f * q->M * 2 * static_cast<size_t>(q->NF), sizeof(float2));
+  return off;
+}
+
+}  // namespace
+
+int sonar_energyscape_batch(sonar_plan p, const void* x, int32_t F, float* E, hipStream_t stream) {
+  int st = check_exec(p, x, E, F);
+  if (st != SONAR_OK) return st;
+  const hipError_t e = energyscape_enqueue(p, x, F, E, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape launch");
+}
+
+int sonar_energyscape_batch_static(sonar_plan p, const void* x, int32_t F, float* E, hipStream_t stream) {
+  int st = check_exec(p, x, E, F);
+  if (st != SONAR_OK) return st;
+  const int dev = p->device;
+  void* base = nullptr;
+  hipError_t se = hipSuccess;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= 0 && dev < MULTI_MAX_DEVICES) {
+      base = g_scratch_addr[dev].addr;
+      se = g_scratch_addr[dev].err;
+    }
+  }
+  if (!base)
+    return se != hipSuccess ? hip_fail(se, "static scratch address")
+                            : fail(SONAR_E_HIP, "static scratch of device %d has no address", dev);
+  sonar_plan_s q = *p;   // same tables; per-frame buffers re-pointed into the static scratch
+  const size_t need = carve_workspace(&q, F, nullptr);
+  if (need > STATIC_SCRATCH_BYTES) {
+    const size_t per = carve_workspace(&q, 1, nullptr);
+    return fail(SONAR_E_INVALID, "F=%d needs %zu bytes of scratch; the static scratch holds %zu (%zu frames of this plan)",
+                F, need, STATIC_SCRATCH_BYTES, per > 0 ? STATIC_SCRATCH_BYTES / per : 0);
+  }
+  carve_workspace(&q, F, static_cast<unsigned char*>(base));
+  const hipError_t e = energyscape_enqueue(&q, x, F, E, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape launch (static scratch)");
 }
 
 int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const int32_t* frames,
