@@ -165,10 +165,13 @@ enum sonar_query {
  * that stream before returning.  Returns SONAR_E_INVALID for a descriptor that
  * breaks a rule stated above (an odd P or P < N + L - 1 among them);
  * SONAR_E_UNSUPPORTED for an even P >= N + L - 1 that is not a power of two
- * or lies outside [32, 524288], for the
- * frequency-domain modes when P > 65536 or more than 16385 bins are stored,
- * and for array apertures whose delay spread exceeds the beamformer tiles;
- * SONAR_E_NOMEM when allocation fails.  *out is set only on success.
+ * or lies outside [32, 524288], and for array apertures whose delay spread
+ * exceeds the beamformer tiles; SONAR_E_NOMEM when allocation fails.  *out is
+ * set only on success.  The frequency-domain modes run their per-direction
+ * inverse as P / L transforms of L <= 16384 points with the stored bins folded
+ * modulo L; when at most two bins fold onto a slot and Q <= L / 2 the inverse,
+ * magnitude and low-pass are one kernel (no beam window in memory), otherwise
+ * the beam window is kept in the plan's workspace ([max_frames][D][G']).
  */
 int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_plan* out);
 

@@ -29,6 +29,12 @@ using namespace fftk;
 
 namespace {
 
+int ilog2_host(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
@@ -77,15 +83,21 @@ constexpr int YS_FRAME = CHB * 32 + 2;  // float2 per frame row in LDS (padded)
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fd_gemm_kernel(
     const float2* __restrict__ band, const double* __restrict__ dl, const float2* __restrict__ step,
-    float2* __restrict__ bspec, int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt) {
+    float2* __restrict__ bspec, int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt,
+    int nyt) {
   __shared__ float2 ys[FD_GEMM_FRAMES * YS_FRAME];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  int bid = blockIdx.x;
-  const int bt = bid % nbt;
-  bid /= nbt;
-  const int dt = bid % ndt;
-  const int ft = bid / ndt;
+  // Workgroups go to the XCDs round-robin by index.  All ndt direction tiles of one sample tile
+  // (bin tile bt, frame tile ft) are given to one XCD back to back, so that XCD reads the tile
+  // from HBM once and its other ndt - 1 readers find it in the XCD's L2.
+  const int xcd = blockIdx.x % FD_XCDS;
+  const int jx = blockIdx.x / FD_XCDS;       // position in this XCD's sequence
+  const int dt = jx % ndt;
+  const int yt = xcd + FD_XCDS * (jx / ndt);
+  if (yt >= nyt) return;
+  const int bt = yt % nbt;
+  const int ft = yt / nbt;
   const int r16 = lane & 15, grp = lane >> 4;
   const int d_st = dt * FD_GEMM_DIRS + wv * 16 + r16;    // direction this lane steers
   const bool d_ok = d_st < D;
@@ -230,107 +242,103 @@ struct FdTw {
   static constexpr int LH = L / 64 > 0 ? L / 64 : 1;
 };
 
-// Loads the phase-r input of one direction: thread t holds B'[k'] exp(2 pi i k' r / P)
-// for k' = t + s L/16; returns the extra-bin term B'[L] exp(2 pi i r / R').
+// exp(-2 pi i e / P) from the plan's two-level P tables (in global memory)
+__device__ __forceinline__ float2 twp(const float2* __restrict__ twp_hi, const float2* __restrict__ twp_lo, int e) {
+  return cmul(twp_hi[e >> 6], twp_lo[e & 63]);
+}
+
+// Loads the phase-r input of one direction: thread t holds, for slot s (k' = t + s L/16),
+// the fold sum_f B'[k' + f L] exp(2 pi i (k' + f L) r / P) over every stored bin of that class.
 template <int LOGL>
-__device__ __forceinline__ float2 load_phase(const float2* __restrict__ in, int kb, int r, const float2* twp_hi,
-                                             const float2* twp_lo, float2 (&v)[16], int tid) {
+__device__ __forceinline__ void load_phase(const float2* __restrict__ in, int kb, int r, int P,
+                                           const float2* twp_hi, const float2* twp_lo, float2 (&v)[16], int tid) {
   constexpr int L = 1 << LOGL;
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
-    const int k = tid + s * (L / 16);
-    float2 x = make_float2(0.f, 0.f);
-    if (k < kb) {
-      x = in[k];
-      if (r != 0) {
-        const int e = k * r;
-        x = cmul(x, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
-      }
+    float2 acc = make_float2(0.f, 0.f);
+    for (int k = tid + s * (L / 16); k < kb; k += L) {
+      float2 x = in[k];
+      if (r != 0) x = cmul(x, cconj(twp(twp_hi, twp_lo, (k * r) & (P - 1))));
+      acc = cadd(acc, x);
     }
-    v[s] = x;
+    v[s] = acc;
   }
-  float2 extra = make_float2(0.f, 0.f);
-  if (kb == L + 1) {
-    extra = in[L];
-    if (r != 0) {
-      const int e = L * r;
-      extra = cmul(extra, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
-    }
-  }
-  return extra;
 }
 
-template <int LOGL>
-__device__ __forceinline__ void load_fd_tw(float2* tw, const float2* __restrict__ tw_g, int P, int tid, int nt) {
-  const int len = FdTw<LOGL>::LH + 64 + P / 64 + 1 + 64;
-  for (int i = tid; i < len; i += nt) tw[i] = tw_g[i];
-}
-
-constexpr int FD_MAX_TW_P = FD_MAX_P / 64 + 1 + 64;   // P tables for P <= FD_MAX_P
-
-// One direction of one frame per workgroup.  The stored spectrum is read once;
-// each phase's transform lands as |b| in an LDS copy of the beam window (the
-// samples n = R' a + r of phase r), and the FIR runs once over that window.
-template <int LOGL>
+// One direction of one frame per workgroup: the fused inverse transform and envelope.
+// The stored bins are read once into registers (NFOLD per slot, k' = t + s L/16 + f L).  For each
+// phase r the folded, rotated spectrum goes through one L-point inverse transform in LDS; the
+// magnitudes |b[R' a + r]| of that phase replace the transform's data in LDS, and every thread adds
+// to its own outputs q = t + T i (registers) the low-pass taps j that read phase r:
+//   E[q] = sum_j h[j] |b[n_start + qR + K - 1 - j]|,   tap j reads phase (n_start + qR + K - 1 - j) mod R'.
+// No copy of the whole beam window is kept, so the window length is not bounded by LDS.
+template <int LOGL, int NFOLD>
 __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
     const float2* __restrict__ bspec, const float2* __restrict__ tw_g, const float* __restrict__ taps,
-    float* __restrict__ E, int kb, int kb_pad, int Rp, int P, int n_start, int G, int Q, int R, int K) {
+    float* __restrict__ E, int kb, int kb_pad, int Rp, int logRp, int P, int n_start, int Q, int R, int K) {
   using S = FftShape<LOGL>;
   constexpr int L = S::NF;
   constexpr int T = S::T;
   constexpr int LH = FdTw<LOGL>::LH;
-  __shared__ float2 lds[S::LDS_ELEMS];
-  __shared__ float2 tw[LH + 64 + FD_MAX_TW_P];
-  __shared__ float hs[FD_MAX_TAPS];
-  extern __shared__ float mag[];              // |b| over the beam window, G floats
+  __shared__ float2 buf[S::LDS_ELEMS];
+  __shared__ float2 tw[LH + 64];
+  extern __shared__ float hs[];               // K taps
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
-  load_fd_tw<LOGL>(tw, tw_g, P, tid, T);
+  for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
   for (int j = tid; j < K; j += T) hs[j] = taps[j];
+  const float2* twp_hi = tw_g + LH + 64;
+  const float2* twp_lo = twp_hi + P / 64 + 1;
   const float2* in = bspec + fd * kb_pad;
-  float2 bin[16];
+  float2 bin[NFOLD][16];
 #pragma unroll
-  for (int s = 0; s < 16; ++s) {
-    const int k = tid + s * (L / 16);
-    bin[s] = k < kb ? in[k] : make_float2(0.f, 0.f);
-  }
-  const float2 top = kb == L + 1 ? in[L] : make_float2(0.f, 0.f);
-  __syncthreads();
-  const float2* tw_hi = tw;
-  const float2* tw_lo = tw + LH;
-  const float2* twp_hi = tw + LH + 64;
-  const float2* twp_lo = tw + LH + 64 + P / 64 + 1;
+  for (int f = 0; f < NFOLD; ++f)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = tid + s * (L / 16) + f * L;
+      bin[f][s] = k < kb ? in[k] : make_float2(0.f, 0.f);
+    }
+  float acc[FD_NQ];
+#pragma unroll
+  for (int i = 0; i < FD_NQ; ++i) acc[i] = 0.f;
   const float invP = 1.0f / static_cast<float>(P);
+  float* mr = reinterpret_cast<float*>(buf);   // |b| of the current phase, index a
 
   for (int r = 0; r < Rp; ++r) {
     float2 v[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-      const int e = (tid + s * (L / 16)) * r;          // < P
-      v[s] = r == 0 ? bin[s] : cmul(bin[s], cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
-    }
-    float2 extra = top;
-    if (r != 0) {
-      const int e = L * r;
-      extra = cmul(top, cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63])));
-    }
-    fft_lds<LOGL, true>(v, lds, tw_hi, tw_lo, tid);
+      float2 x = make_float2(0.f, 0.f);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int n = Rp * S::out_index(tid, i) + r;
-      const int w = (n - n_start) & (P - 1);             // window position of sample n
-      if (w < G) {
-        const float ux = v[i].x + extra.x, uy = v[i].y + extra.y;
-        mag[w] = __builtin_amdgcn_sqrtf(ux * ux + uy * uy) * invP;
+      for (int f = 0; f < NFOLD; ++f) {
+        const int k = tid + s * (L / 16) + f * L;
+        x = cadd(x, r == 0 ? bin[f][s] : cmul(bin[f][s], cconj(twp(twp_hi, twp_lo, (k * r) & (P - 1)))));
+      }
+      v[s] = x;
+    }
+    fft_lds<LOGL, true>(v, buf, tw, tw + LH, tid);   // starts with a barrier
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 16; ++i) mr[S::out_index(tid, i)] = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < FD_NQ; ++i) {
+      const int q = tid + T * i;
+      if (q < Q) {
+        const int base = n_start + q * R + K - 1;        // sample read by tap j = 0
+        float a = acc[i];
+        for (int j = (base - r) & (Rp - 1); j < K; j += Rp) {
+          // sample base - j lies in phase r: its index within the phase, modulo L (circular in P)
+          a = fmaf(hs[j], mr[((base - j - r) >> logRp) & (L - 1)], a);
+        }
+        acc[i] = a;
       }
     }
   }
-  __syncthreads();
-  for (int q = tid; q < Q; q += T) {
-    const float* a = mag + q * R + K - 1;
-    float acc = 0.f;
-    for (int j = 0; j < K; ++j) acc = fmaf(hs[j], a[-j], acc);
-    E[fd * Q + q] = acc;
+#pragma unroll
+  for (int i = 0; i < FD_NQ; ++i) {
+    const int q = tid + T * i;
+    if (q < Q) E[fd * Q + q] = acc[i];
   }
 }
 
@@ -344,27 +352,24 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_beam_kernel(
   constexpr int T = S::T;
   constexpr int LH = FdTw<LOGL>::LH;
   __shared__ float2 lds[S::LDS_ELEMS];
-  __shared__ float2 tw[LH + 64 + FD_MAX_TW_P];
+  __shared__ float2 tw[LH + 64];
   const int tid = threadIdx.x;
   const int r = blockIdx.x % Rp;
   const long long fd = blockIdx.x / Rp;
-  load_fd_tw<LOGL>(tw, tw_g, P, tid, T);
-  __syncthreads();
-  const float2* tw_hi = tw;
-  const float2* tw_lo = tw + LH;
-  const float2* twp_hi = tw + LH + 64;
-  const float2* twp_lo = tw + LH + 64 + P / 64 + 1;
+  for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
+  const float2* twp_hi = tw_g + LH + 64;
+  const float2* twp_lo = twp_hi + P / 64 + 1;
   float2 v[16];
-  const float2 extra = load_phase<LOGL>(bspec + fd * kb_pad, kb, r, twp_hi, twp_lo, v, tid);
-  fft_lds<LOGL, true>(v, lds, tw_hi, tw_lo, tid);
+  load_phase<LOGL>(bspec + fd * kb_pad, kb, r, P, twp_hi, twp_lo, v, tid);
+  fft_lds<LOGL, true>(v, lds, tw, tw + LH, tid);   // starts with a barrier (after the twiddle copy)
   const float invP = 1.0f / static_cast<float>(P);
   float2* out = beam + fd * G;
 #pragma unroll
   for (int i = 0; i < 16; ++i) {
     const long long n = static_cast<long long>(Rp) * S::out_index(tid, i) + r;
     const int e = static_cast<int>((static_cast<long long>(k_lo) * n) % P);   // exp(2 pi i k_lo n / P)
-    const float2 rot = cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63]));
-    const float2 y = cmul(make_float2((v[i].x + extra.x) * invP, (v[i].y + extra.y) * invP), rot);
+    const float2 rot = cconj(twp(twp_hi, twp_lo, e));
+    const float2 y = cmul(make_float2(v[i].x * invP, v[i].y * invP), rot);
     for (int j = static_cast<int>((n - n_start) & (P - 1)); j < G; j += P) out[j] = y;
   }
 }
@@ -375,19 +380,21 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
   const int nbt = (p->kb_pad + FD_GEMM_BINS - 1) / FD_GEMM_BINS;
   const int ndt = (p->D + FD_GEMM_DIRS - 1) / FD_GEMM_DIRS;
   const int nft = (F + FD_GEMM_FRAMES - 1) / FD_GEMM_FRAMES;
-  const dim3 grid(static_cast<unsigned>(nbt) * ndt * nft);
+  const int nyt = nbt * nft;                                  // sample tiles
+  const int nyt8 = (nyt + FD_XCDS - 1) / FD_XCDS * FD_XCDS;   // padded to whole rounds over the XCDs
+  const dim3 grid(static_cast<unsigned>(nyt8) * ndt);
   switch (p->bf_mode) {
     case SONAR_BF_FD_FP32:
       hipLaunchKernelGGL(fd_gemm_kernel<MODE_FP32>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
-                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt, nyt);
       break;
     case SONAR_BF_FD_BF16:
       hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
-                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt, nyt);
       break;
     case SONAR_BF_FD_BF16X3:
       hipLaunchKernelGGL(fd_gemm_kernel<MODE_BF16X3>, grid, dim3(256), 0, s, band, p->d_dl, p->d_fdstep, bspec, F, p->D, p->M,
-                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt);
+                         p->kb, p->kb_pad, p->k_lo, p->P, nbt, ndt, nyt);
       break;
     default:
       return hipErrorInvalidValue;
@@ -395,30 +402,34 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
   return hipGetLastError();
 }
 
-template <int LOGL>
+template <int LOGL, int NFOLD>
 hipError_t launch_env_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
-  const size_t smem = static_cast<size_t>(p->G) * sizeof(float);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fd_ifft_env_kernel<LOGL>),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
-                     smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, p->P,
-                     p->n0 - p->hk, p->G, p->Q, p->R, p->K);
+  const size_t smem = static_cast<size_t>(p->K) * sizeof(float);
+  hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL, NFOLD>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
+                     smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, ilog2_host(p->fd_R), p->P,
+                     p->n0 - p->hk, p->Q, p->R, p->K);
   return hipGetLastError();
 }
 
+template <int LOGL>
+hipError_t launch_env_f(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  return p->fd_nfold == 1 ? launch_env_t<LOGL, 1>(p, bspec, F, E, s) : launch_env_t<LOGL, 2>(p, bspec, F, E, s);
+}
+
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  if (!p->fd_fused || p->fd_nfold < 1 || p->fd_nfold > FD_MAX_FOLD) return hipErrorInvalidValue;
   switch (p->fd_logL) {
-    case 4: return launch_env_t<4>(p, bspec, F, E, s);
-    case 5: return launch_env_t<5>(p, bspec, F, E, s);
-    case 6: return launch_env_t<6>(p, bspec, F, E, s);
-    case 7: return launch_env_t<7>(p, bspec, F, E, s);
-    case 8: return launch_env_t<8>(p, bspec, F, E, s);
-    case 9: return launch_env_t<9>(p, bspec, F, E, s);
-    case 10: return launch_env_t<10>(p, bspec, F, E, s);
-    case 11: return launch_env_t<11>(p, bspec, F, E, s);
-    case 12: return launch_env_t<12>(p, bspec, F, E, s);
-    case 13: return launch_env_t<13>(p, bspec, F, E, s);
+    case 4: return launch_env_f<4>(p, bspec, F, E, s);
+    case 5: return launch_env_f<5>(p, bspec, F, E, s);
+    case 6: return launch_env_f<6>(p, bspec, F, E, s);
+    case 7: return launch_env_f<7>(p, bspec, F, E, s);
+    case 8: return launch_env_f<8>(p, bspec, F, E, s);
+    case 9: return launch_env_f<9>(p, bspec, F, E, s);
+    case 10: return launch_env_f<10>(p, bspec, F, E, s);
+    case 11: return launch_env_f<11>(p, bspec, F, E, s);
+    case 12: return launch_env_f<12>(p, bspec, F, E, s);
+    case 13: return launch_env_f<13>(p, bspec, F, E, s);
+    case 14: return launch_env_f<14>(p, bspec, F, E, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -446,14 +457,4 @@ hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F
     case 14: return launch_beam_t<14>(p, bspec, F, beam, s);
     default: return hipErrorInvalidValue;
   }
-}
-
-// static LDS of the fused kernel for a transform of 2^logL points (the beam
-// window |b| comes on top as dynamic LDS)
-size_t fd_env_static_lds(int logL, int P) {
-  const int L = 1 << logL;
-  const int lh = L / 64 > 0 ? L / 64 : 1;
-  (void)P;
-  return static_cast<size_t>(L + L / 16) * sizeof(float2) +
-         static_cast<size_t>(lh + 64 + FD_MAX_TW_P) * sizeof(float2) + FD_MAX_TAPS * sizeof(float);
 }

@@ -49,12 +49,11 @@ struct sonar_plan_s {
 
   // frequency-domain layout: stored band bins [k_lo, k_lo + kb); the
   // per-direction inverse transform runs as fd_R polyphase transforms of
-  // fd_L = P / fd_R points (fd_L >= kb - 1; a bin at k' = fd_L adds a constant
-  // per phase)
+  // fd_L = P / fd_R points, the stored bins folded modulo fd_L (fd_nfold = ceil(kb / fd_L))
   int k_lo = 0, kb = 0;
   int kb_pad = 0;       // row stride (bins) of the per-direction spectra
-  int fd_L = 0, fd_logL = 0, fd_R = 0;
-  bool fd_fused = false;   // fd_L small enough for the fused inverse + envelope kernel
+  int fd_L = 0, fd_logL = 0, fd_R = 0, fd_nfold = 0;
+  bool fd_fused = false;   // the fused inverse + envelope kernel serves this plan (else beam window + envelope)
 
   // time-domain BF16-MFMA beamformer tiling (see k_das_mfma.hip)
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
@@ -205,12 +204,15 @@ constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that 
 __host__ __device__ constexpr int mt_nsp(int nwave) { return nwave * 128 + 4; }
 constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row
 
-constexpr int FD_MAX_FUSED_L = 8192;   // largest per-phase transform of the fused FD kernel
+constexpr int FD_MAX_LOGL = 14;        // largest per-phase transform of the FD inverse (LDS): 16384 points
+constexpr int FD_MAX_FOLD = 2;         // stored bins per slot held in registers by the fused FD inverse
+constexpr int FD_FOLD1_MAX_L = 8192;   // the default layout keeps one bin per slot up to this transform length
+constexpr int FD_NQ = 8;               // range bins per thread of the fused FD inverse: Q <= FD_NQ * fd_L / 16
 constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
-constexpr int FD_MAX_TAPS = 1024;
-constexpr int FD_MAX_P = 65536;   // FFT length limit of the frequency-domain inverse (LDS twiddle tables)
+constexpr int FD_XCDS = 8;             // accelerator dies the FD GEMM's sample tiles are grouped by
+constexpr int FD_MAX_TAPS = 4096;       // low-pass taps of the fused FD inverse (LDS)
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t init_mt_kernel_attributes();
@@ -223,7 +225,6 @@ hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* ban
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
-size_t fd_env_static_lds(int logL, int P);
 // rows = false skips the complex64 rows (MFMA modes whose beamformer reads only the 16-bit planes)
 hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows = true);
 hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s);

@@ -462,6 +462,9 @@ void resolve_scratch(int dev) {
 // (0: the largest-throughput rule, 4 waves where the staging fits, else 8); set only by
 // sonar_plan_create_tuned while it tries the candidates
 thread_local int g_mt_nwave_hint = 0;
+// log2 of the smallest per-phase transform length the next frequency-domain plan on this thread
+// must use (0: the default rule); set only by sonar_plan_create_tuned while it tries the candidates
+thread_local int g_fd_logl_hint = 0;
 
 int check_exec(const sonar_plan_s* p, const void* a, const void* b, int F) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
@@ -692,23 +695,29 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     p->kb = p->NF + 1;
   }
   p->kb_pad = (p->kb + 15) / 16 * 16;
-  p->fd_L = 16;
-  while (p->fd_L < p->kb - 1) p->fd_L *= 2;
-  p->fd_logL = ilog2(p->fd_L);
-  p->fd_R = p->P / p->fd_L;
-  p->fd_fused = p->fd_L <= FD_MAX_FUSED_L && p->K <= FD_MAX_TAPS &&
-                fd_env_static_lds(p->fd_logL, p->P) + static_cast<size_t>(p->G) * sizeof(float) <= 160 * 1024;
+  {
+    // Inverse layout: phases of L points with the stored bins folded modulo L.  The fused inverse +
+    // envelope keeps at most FD_MAX_FOLD bins per slot in registers and FD_NQ range bins per thread,
+    // so L >= kb / FD_MAX_FOLD and L >= 16 Q / FD_NQ; by default one bin per slot (L >= kb) while
+    // L <= FD_FOLD1_MAX_L.  The tuner may ask for another L (g_fd_logl_hint).
+    auto pow2_at_least = [](long long v) {
+      long long l = 16;
+      while (l < v) l *= 2;
+      return l;
+    };
+    const long long need_q = 16LL * ((p->Q + FD_NQ - 1) / FD_NQ);
+    const long long need_fold = (p->kb + FD_MAX_FOLD - 1) / FD_MAX_FOLD;
+    long long L = pow2_at_least(std::max({need_q, need_fold}));
+    if (pow2_at_least(p->kb) <= FD_FOLD1_MAX_L) L = std::max(L, pow2_at_least(p->kb));
+    if (g_fd_logl_hint > 0) L = std::max(L, 1LL << g_fd_logl_hint);
+    p->fd_fused = L <= (1LL << FD_MAX_LOGL) && L <= p->P && p->K <= FD_MAX_TAPS;
+    if (!p->fd_fused) L = std::min<long long>(pow2_at_least(need_fold), std::min<long long>(1LL << FD_MAX_LOGL, p->P));
+    p->fd_L = static_cast<int>(L);
+    p->fd_logL = ilog2(p->fd_L);
+    p->fd_R = p->P / p->fd_L;
+    p->fd_nfold = (p->kb + p->fd_L - 1) / p->fd_L;
+  }
   const bool fd = !is_td(p);
-  if (fd && p->P > FD_MAX_P) {
-    delete p;
-    return fail(SONAR_E_UNSUPPORTED, "frequency-domain beamformer: FFT length %d above %d", p->P, FD_MAX_P);
-  }
-  if (fd && p->fd_L > (1 << 14)) {
-    delete p;
-    return fail(SONAR_E_UNSUPPORTED,
-                "frequency-domain beamformer: %d stored bins need a %d-point inverse transform (at most 16384)", p->kb,
-                p->fd_L);
-  }
 
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
