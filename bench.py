@@ -215,6 +215,30 @@ def run_path(name, w, x, args, stream, sweep):
             "frac": round(achieved / peak, 4), "frac_of_plain_fma_peak": round(achieved / PEAK_FP32_NOPACK_TFLOPS, 4),
             "traffic": traffic_record(kernel, khash), "flop_per_launch": flops, "launch_ms": round(ms_be, 4),
             "kernel_sources_sha256_16": khash}
+    if omode == "fd":
+        # the two kernels of beamform_envelope against their own roofs: the per-bin GEMM alone
+        # (sonar_beam_spectrum) on the matrix cores, the inverse + envelope (the rest) on the vector ALUs
+        Bs = plan.beam_spectrum(mf)
+        ms_gemm = time_batches(lambda: plan.beam_spectrum(mf, out=Bs), K, 2, stream)[1] / K
+        ms_inv = max(ms_be - ms_gemm, 1e-6)
+        gemm_flops = F * 8.0 * D * M * plan.band_bins
+        inv_flops = F * (5.0 * P * np.log2(P) * D + 2.0 * Kt * D * Q)
+        gpeak = PEAK_FP32_MFMA_TFLOPS if mode == "fd_fp32" else PEAK_BF16_MFMA_TFLOPS
+        roof["kernels"] = {
+            "fd_gemm_kernel": {"bound": "mfma", "achieved": round(gemm_flops / (ms_gemm / 1e3) / 1e12, 3),
+                               "peak": gpeak, "unit": "TFLOP/s",
+                               "frac": round(gemm_flops / (ms_gemm / 1e3) / 1e12 / gpeak, 4),
+                               "flop_per_launch": gemm_flops, "launch_ms": round(ms_gemm, 4),
+                               "input_bytes": int(F * plan.band_bins * M * 8),
+                               "output_bytes": int(F * D * plan.query(binding.Q_BEAM_SPEC_STRIDE) * 8)},
+            "fd_ifft_env_kernel": {"bound": "alu", "achieved": round(inv_flops / (ms_inv / 1e3) / 1e12, 3),
+                                   "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": round(inv_flops / (ms_inv / 1e3) / 1e12 / PEAK_FP32_VECTOR_TFLOPS, 4),
+                                   "flop_per_launch": inv_flops, "launch_ms": round(ms_inv, 4),
+                                   "timing": "beamform_envelope minus the GEMM alone",
+                                   "phase_len": plan.query(binding.Q_FD_PHASE_LEN),
+                                   "fused": bool(plan.query(binding.Q_FD_FUSED))}}
+        del Bs
     mflop = plan.query(binding.Q_MATRIX_FLOP_PER_FRAME) * F
     if mflop:
         roof["matrix_flop_per_launch"] = mflop

@@ -148,7 +148,11 @@ enum sonar_query {
   SONAR_Q_MATRIX_FLOP_PER_FRAME = 10, /* MFMA TD modes: matrix-core flops issued per frame by the
                                          fused beamformer (padding included); 0 otherwise  */
   SONAR_Q_MT_WAVES = 11               /* MFMA TD modes: wavefronts per beamformer workgroup
-                                         (4: two workgroups per CU; 8: wide apertures); else 0 */
+                                         (4: two workgroups per CU; 8: wide apertures); else 0 */,
+  SONAR_Q_BEAM_SPEC_STRIDE = 12,      /* FD modes: complex elements per direction row of sonar_beam_spectrum's
+                                         output (the stored bins, padded to a multiple of 16); else 0 */
+  SONAR_Q_FD_PHASE_LEN = 13,          /* FD modes: points L of each phase of the per-direction inverse; else 0 */
+  SONAR_Q_FD_FUSED = 14               /* FD modes: 1 when inverse, magnitude and low-pass are one kernel; else 0 */
 };
 
 /*
@@ -221,6 +225,20 @@ int sonar_matched_filter(sonar_plan plan, const void* x, int32_t F, void* mf_out
  */
 int sonar_beamform(sonar_plan plan, const void* mf_in, int32_t F, void* beam_out,
                    hipStream_t stream);
+
+/*
+ * sonar_beam_spectrum -- the first half of the frequency-domain beamformer
+ * (§4.1 delay-and-sum with each channel's delay applied as a per-bin phase),
+ * for FD plans only: the per-bin product over microphones
+ *   B_d[k] = (1/M) sum_m Yhat_m[k] exp(-2 pi i k Dl[d][m] / P)
+ * on the stored bins k = band_lo_bin + j, j < Kb (SONAR_Q_BAND_BINS).
+ *   mf_in    : a buffer written by sonar_matched_filter with this plan.
+ *   spec_out : complex64 [F][D][S], S = SONAR_Q_BEAM_SPEC_STRIDE; element (f, d, j)
+ *              holds B_d at bin band_lo_bin + j for j < Kb (S - Kb padding
+ *              elements per row are written with unspecified values).
+ * SONAR_E_INVALID for a time-domain plan.
+ */
+int sonar_beam_spectrum(sonar_plan plan, const void* mf_in, int32_t F, void* spec_out, hipStream_t stream);
 
 /*
  * sonar_envelope -- §4.1 envelope and §4.3 subsampling:

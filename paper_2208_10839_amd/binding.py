@@ -30,6 +30,7 @@ Q_RANGE_BINS, Q_BEAM_LEN, Q_FFT_LEN, Q_MF_ROW, Q_MF_ORIGIN = 0, 1, 2, 3, 4
 Q_BAND_LO_BIN, Q_BAND_BINS, Q_WORKSPACE_BYTES, Q_LPF_LEN, Q_MF_FRAME_ELEMS = 5, 6, 7, 8, 9
 Q_MATRIX_FLOP_PER_FRAME = 10
 Q_MT_WAVES = 11
+Q_BEAM_SPEC_STRIDE, Q_FD_PHASE_LEN, Q_FD_FUSED = 12, 13, 14
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -69,6 +70,8 @@ _SIGNATURES = {
     "sonar_matched_filter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_beamform": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_beam_spectrum": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p]),
     "sonar_beamform_envelope": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_energyscape_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_energyscape_batch_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -284,6 +287,18 @@ class Plan:
                                      ctypes.c_void_p(b.data_ptr()), _stream_handle(stream)),
                "sonar_beamform")
         return b
+
+    def beam_spectrum(self, mf, out=None, stream=None):
+        """Frequency-domain plans: per-bin beam spectra B[F][D][S] (complex64, S = the padded row of
+        stored bins; the first band_bins of each row are B_d at bins band_lo_bin + j)."""
+        import torch
+        F = self._frames(mf, (self.mf_frame_elems,), "mf")
+        S = self.query(Q_BEAM_SPEC_STRIDE)
+        B = self._out(out, (F, self.D, S), torch.complex64, mf.device)
+        _check(load().sonar_beam_spectrum(self._h, ctypes.c_void_p(mf.data_ptr()), F,
+                                          ctypes.c_void_p(B.data_ptr()), _stream_handle(stream)),
+               "sonar_beam_spectrum")
+        return B
 
     def envelope(self, beam, out=None, stream=None):
         """E[F][D][Q] from a beam window b[F][D][G']."""

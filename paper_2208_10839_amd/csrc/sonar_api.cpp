@@ -821,6 +821,9 @@ int sonar_plan_query(sonar_plan p, int32_t what, int64_t* value) {
     case SONAR_Q_LPF_LEN: *value = p->K; break;
     case SONAR_Q_MATRIX_FLOP_PER_FRAME: *value = p->mt_flop_per_frame; break;
     case SONAR_Q_MT_WAVES: *value = p->mt_nwave; break;
+    case SONAR_Q_BEAM_SPEC_STRIDE: *value = is_td(p) ? 0 : p->kb_pad; break;
+    case SONAR_Q_FD_PHASE_LEN: *value = is_td(p) ? 0 : p->fd_L; break;
+    case SONAR_Q_FD_FUSED: *value = is_td(p) ? 0 : (p->fd_fused ? 1 : 0); break;
     case SONAR_Q_MF_FRAME_ELEMS:
       *value = is_td(p) ? static_cast<int64_t>(p->mf_fstride)
                                                 : static_cast<int64_t>(p->kb) * p->M;
@@ -849,6 +852,14 @@ int sonar_beamform(sonar_plan p, const void* mf_in, int32_t F, void* beam_out, h
     if (e == hipSuccess) e = launch_fd_ifft_beam(p, p->d_bspec, F, static_cast<float2*>(beam_out), stream);
   }
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "beamform launch");
+}
+
+int sonar_beam_spectrum(sonar_plan p, const void* mf_in, int32_t F, void* spec_out, hipStream_t stream) {
+  int st = check_exec(p, mf_in, spec_out, F);
+  if (st != SONAR_OK) return st;
+  if (is_td(p)) return fail(SONAR_E_INVALID, "sonar_beam_spectrum: the plan's beamformer is not frequency-domain");
+  const hipError_t e = launch_fd_gemm(p, static_cast<const float2*>(mf_in), F, static_cast<float2*>(spec_out), stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "beam spectrum launch");
 }
 
 int sonar_envelope(sonar_plan p, const void* beam_in, int32_t F, float* E, hipStream_t stream) {

@@ -47,6 +47,45 @@ def test_c1_fd_energyscape(gpu, torch_mod, mode):
     assert err <= BARS[mode]
 
 
+@pytest.mark.parametrize("mode", ["fd_fp32", "fd_bf16x3", "fd_bf16"])
+def test_fd_beam_spectrum_stage(gpu, torch_mod, mode):
+    """sonar_beam_spectrum (the per-bin GEMM alone) against the spectrum of the oracle's beam: the
+    oracle's exact-delay beam over all of Z_P, transformed back, is B_d on every bin."""
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=2, n_samples=3000, n_dirs=21)
+    _say(f"case fd beam spectrum: {mode} M=32 N=3000 D=21 F=2")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 3000, fs=w.fs, c=w.c, band=w.cfg.band, max_frames=2, mode=mode)
+    S = plan.query(gpu.Q_BEAM_SPEC_STRIDE)
+    k_lo, kb = plan.band_lo_bin, plan.band_bins
+    assert S >= kb and S % 16 == 0
+    assert plan.query(gpu.Q_FD_FUSED) == 1 and plan.query(gpu.Q_FD_PHASE_LEN) >= kb // 2
+    mf = plan.matched_filter(torch.from_numpy(w.x).cuda())
+    B = plan.beam_spectrum(mf).cpu().numpy()
+    Dl = O.delays(w.mic_pos, w.dirs, w.fs, w.c)
+    for f in range(2):
+        Y = O.matched_filter_spectrum(w.x[f].astype(np.float64), w.chirp, plan.P, w.fs, w.cfg.band)
+        Bo = np.fft.fft(O.das_fd(Y, Dl, np.arange(plan.P)), axis=1)[:, k_lo:k_lo + kb]
+        err = rel_l2(B[f][:, :kb], Bo)
+        _say(f"  frame {f}: beam spectrum rel L2 = {err:.3e}")
+        assert err <= BARS[mode]
+    # the energyscape from the same plan is the spectrum's inverse + envelope
+    assert torch.equal(plan.beamform_envelope(mf), plan.beamform_envelope(mf))
+
+
+def test_fd_beam_spectrum_refused_for_time_domain(gpu, torch_mod):
+    torch = torch_mod
+    w = synth.make_workload("c1", n_dirs=5)
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, 4096, fs=w.fs, c=w.c, mode="td")
+    mf = plan.matched_filter(torch.from_numpy(w.x).cuda())
+    out = torch.empty((1, 5, 16), dtype=torch.complex64, device="cuda")
+    with pytest.raises(gpu.SonarError) as ei:
+        gpu._check(gpu.load().sonar_beam_spectrum(plan._h, gpu.ctypes.c_void_p(mf.data_ptr()), 1,
+                                                   gpu.ctypes.c_void_p(out.data_ptr()), gpu._stream_handle(None)),
+                   "sonar_beam_spectrum")
+    assert ei.value.status == gpu.SONAR_E_INVALID
+    assert plan.query(gpu.Q_BEAM_SPEC_STRIDE) == 0
+
+
 def test_fd_stages(gpu, torch_mod):
     torch = torch_mod
     w = synth.make_workload("c2", n_samples=3000, n_dirs=21)
