@@ -334,13 +334,28 @@ enum sonar_precision {
  * (the kernels' time does not depend on the sample values), and the fastest
  * plan is returned; desc->bf_mode is ignored.  The MFMA time-domain modes are
  * tried with both workgroup shapes (4 and 8 wavefronts of 32 directions x 128
- * samples each; SONAR_Q_MT_WAVES reports the one kept).  The call synchronises
+ * samples each; SONAR_Q_MT_WAVES reports the one kept), the frequency-domain
+ * modes with their default phase length and half and twice it where the fused
+ * inverse allows (SONAR_Q_FD_PHASE_LEN reports the one kept).  The call synchronises
  * `stream`.
  *   *chosen_mode (may be NULL) receives the selected enum sonar_bf_mode.
  * Returns the status of sonar_plan_create when no mode can be planned.
  */
 int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
                             sonar_plan* out, int32_t* chosen_mode);
+
+/*
+ * sonar_tune_cache -- persist the choices of sonar_plan_create_tuned: with a
+ * path set, a tuned creation first looks the descriptor up in that file and,
+ * when found, creates the recorded plan (mode, MFMA workgroup size, frequency-
+ * domain phase length) without timing anything; otherwise it tunes and appends
+ * one JSON object per line, {"key": ..., "mode": m, "mt_waves": w,
+ * "fd_logl": l, "ms": t}, the key naming every descriptor size, the precision
+ * class, the device architecture and a hash of the geometry, directions,
+ * sweep and taps.  NULL or "" switches the cache off (the default).  Process-
+ * wide; the file is read and appended under a lock.
+ */
+int sonar_tune_cache(const char* path);
 
 /*
  * Reverse-mode derivatives of the pipeline (the adjoint used to self-calibrate

@@ -82,6 +82,7 @@ _SIGNATURES = {
     "sonar_plan_create_tuned": (ctypes.c_int, [ctypes.POINTER(PlanDesc), ctypes.c_int32, ctypes.c_void_p,
                                                 ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_int32)]),
     "sonar_plan_enable_gradients": (ctypes.c_int, [ctypes.c_void_p]),
+    "sonar_tune_cache": (ctypes.c_int, [ctypes.c_char_p]),
     "sonar_energyscape_vjp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
@@ -472,6 +473,11 @@ class Energyscape:
         if cls._fn is None:
             cls._fn = cls._make()
         return cls._fn.apply(x, pos, plan)
+
+
+def tune_cache(path):
+    """sonar_tune_cache: JSON-lines file that persists tuned plan choices (None switches it off)."""
+    _check(load().sonar_tune_cache(None if path is None else os.fsencode(path)), "sonar_tune_cache")
 
 
 def energyscape_multi(plans, xs, outs=None, stream=None):

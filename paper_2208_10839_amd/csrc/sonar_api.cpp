@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <mutex>
@@ -707,9 +708,10 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     };
     const long long need_q = 16LL * ((p->Q + FD_NQ - 1) / FD_NQ);
     const long long need_fold = (p->kb + FD_MAX_FOLD - 1) / FD_MAX_FOLD;
-    long long L = pow2_at_least(std::max({need_q, need_fold}));
+    const long long hard = pow2_at_least(std::max({need_q, need_fold}));
+    long long L = hard;
     if (pow2_at_least(p->kb) <= FD_FOLD1_MAX_L) L = std::max(L, pow2_at_least(p->kb));
-    if (g_fd_logl_hint > 0) L = std::max(L, 1LL << g_fd_logl_hint);
+    if (g_fd_logl_hint > 0) L = std::max(hard, 1LL << g_fd_logl_hint);
     p->fd_fused = L <= (1LL << FD_MAX_LOGL) && L <= p->P && p->K <= FD_MAX_TAPS;
     if (!p->fd_fused) L = std::min<long long>(pow2_at_least(need_fold), std::min<long long>(1LL << FD_MAX_LOGL, p->P));
     p->fd_L = static_cast<int>(L);
@@ -1062,11 +1064,132 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
   return st;
 }
 
+namespace {
+
+// Tuning cache: one JSON object per line, {"key": "...", "mode": m, "mt_waves": w, "fd_logl": l, "ms": t},
+// keyed by every descriptor field that shapes the plan, the precision class, the device's architecture and
+// a hash of the geometry, directions, sweep and taps (the choice depends on all of them).  Read at every
+// tuned creation (the last line of a key wins), appended after each tuning.
+std::string g_tune_cache_path;
+std::mutex g_tune_mu;
+
+struct tune_choice {
+  int mode = -1, nwave = 0, logl = 0;
+};
+
+uint64_t fnv1a(uint64_t h, const void* data, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 1099511628211ULL;
+  }
+  return h;
+}
+
+void tune_key(const sonar_plan_desc& d, int precision, std::string* key) {
+  uint64_t h = 14695981039346656037ULL;
+  if (d.mic_pos && d.n_mics > 0) h = fnv1a(h, d.mic_pos, sizeof(double) * 3 * static_cast<size_t>(d.n_mics));
+  if (d.dirs && d.n_dirs > 0) h = fnv1a(h, d.dirs, sizeof(double) * 3 * static_cast<size_t>(d.n_dirs));
+  if (d.chirp && d.chirp_len > 0) h = fnv1a(h, d.chirp, sizeof(double) * static_cast<size_t>(d.chirp_len));
+  if (d.lpf_taps && d.lpf_len > 0) h = fnv1a(h, d.lpf_taps, sizeof(double) * static_cast<size_t>(d.lpf_len));
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  std::string arch = "unknown";
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) arch = prop.gcnArchName;
+  else (void)hipGetLastError();
+  char buf[512];
+  snprintf(buf, sizeof(buf),
+           "%s M%d L%d D%d N%d gate%d-%d R%d K%d P%d band%.9g-%.9g fs%.9g c%.9g dtype%d F%d prec%d h%016llx",
+           arch.c_str(), d.n_mics, d.chirp_len, d.n_dirs, d.n_samples, d.gate_begin, d.gate_end, d.decim, d.lpf_len,
+           d.fft_len, d.band_lo_hz, d.band_hi_hz, d.fs_hz, d.c_mps, d.sample_dtype, d.max_frames, precision,
+           static_cast<unsigned long long>(h));
+  *key = buf;
+}
+
+// integer field "name": value of a cache line
+bool json_int(const std::string& line, const char* name, int* v) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at = line.find(pat);
+  if (at == std::string::npos) return false;
+  char* end = nullptr;
+  const long x = std::strtol(line.c_str() + at + pat.size(), &end, 10);
+  if (end == line.c_str() + at + pat.size()) return false;
+  *v = static_cast<int>(x);
+  return true;
+}
+
+bool cache_lookup(const std::string& path, const std::string& key, tune_choice* c) {
+  FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  const std::string want = "\"key\":\"" + key + "\"";
+  bool found = false;
+  char buf[2048];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    const std::string line(buf);
+    if (line.find(want) == std::string::npos) continue;
+    tune_choice t;
+    if (json_int(line, "mode", &t.mode) && json_int(line, "mt_waves", &t.nwave) && json_int(line, "fd_logl", &t.logl)) {
+      *c = t;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void cache_append(const std::string& path, const std::string& key, const tune_choice& c, float ms) {
+  FILE* f = std::fopen(path.c_str(), "a");
+  if (!f) return;
+  std::fprintf(f, "{\"key\":\"%s\",\"mode\":%d,\"mt_waves\":%d,\"fd_logl\":%d,\"ms\":%.4f}\n", key.c_str(), c.mode,
+               c.nwave, c.logl, ms);
+  std::fclose(f);
+}
+
+// sonar_plan_create with the tile hints of a choice
+int create_with_choice(const sonar_plan_desc* desc, const tune_choice& c, hipStream_t stream, sonar_plan* out) {
+  sonar_plan_desc d = *desc;
+  d.bf_mode = c.mode;
+  g_mt_nwave_hint = c.nwave;
+  g_fd_logl_hint = c.logl;
+  const int st = sonar_plan_create(&d, stream, out);
+  g_mt_nwave_hint = 0;
+  g_fd_logl_hint = 0;
+  return st;
+}
+
+bool is_mt_mode(int m) { return m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2 || m == SONAR_BF_TD_F16; }
+bool is_fd_mode(int m) { return m == SONAR_BF_FD_FP32 || m == SONAR_BF_FD_BF16 || m == SONAR_BF_FD_BF16X3; }
+
+}  // namespace
+
+int sonar_tune_cache(const char* path) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache_path = path ? path : "";
+  return SONAR_OK;
+}
+
 int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipStream_t stream,
                             sonar_plan* out, int32_t* chosen_mode) {
   if (!desc || !out) return fail(SONAR_E_INVALID, "desc and out must not be NULL");
   if (precision != SONAR_PREC_FP32 && precision != SONAR_PREC_BF16)
     return fail(SONAR_E_INVALID, "precision %d is not a sonar_precision", precision);
+  std::string cache;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    cache = g_tune_cache_path;
+  }
+  std::string key;
+  if (!cache.empty()) tune_key(*desc, precision, &key);
+  tune_choice hit;
+  if (!cache.empty() && cache_lookup(cache, key, &hit)) {
+    sonar_plan p = nullptr;
+    if (create_with_choice(desc, hit, stream, &p) == SONAR_OK) {
+      *out = p;
+      if (chosen_mode) *chosen_mode = hit.mode;
+      return SONAR_OK;
+    }
+    g_last_error.clear();   // a stale entry: tune again
+  }
   std::vector<int> modes = {SONAR_BF_TD_LINEAR, SONAR_BF_FD_FP32, SONAR_BF_FD_BF16X3};
   if (precision == SONAR_PREC_BF16) {
     modes.push_back(SONAR_BF_TD_BF16);
@@ -1076,14 +1199,15 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
       modes.push_back(SONAR_BF_TD_BF16X2);
     }
   }
-  // candidates: (mode, MFMA workgroup size); the MFMA modes are tried with both tile shapes
-  std::vector<std::pair<int, int>> cands;
+  // candidates: the MFMA time-domain modes with both workgroup shapes; the frequency-domain modes
+  // with their default phase length, then half and twice it (added once the default is known)
+  std::vector<tune_choice> cands;
   for (int m : modes) {
-    if (m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2 || m == SONAR_BF_TD_F16) {
-      cands.push_back({m, MT_NWAVE_SMALL});
-      cands.push_back({m, MT_NWAVE_LARGE});
+    if (is_mt_mode(m)) {
+      cands.push_back({m, MT_NWAVE_SMALL, 0});
+      cands.push_back({m, MT_NWAVE_LARGE, 0});
     } else {
-      cands.push_back({m, 0});
+      cands.push_back({m, 0, 0});
     }
   }
   const int F = desc->max_frames > 0 ? desc->max_frames : 1;
@@ -1093,26 +1217,39 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
   void* xin = nullptr;
   float* eout = nullptr;
   sonar_plan best = nullptr;
-  int best_mode = -1, last_status = SONAR_E_UNSUPPORTED;
+  tune_choice best_c;
+  int last_status = SONAR_E_UNSUPPORTED;
   float best_ms = 0.f;
   std::string last_msg = "no beamformer mode could be planned";
+  std::vector<std::pair<int, int>> fd_seen;   // (mode, phase length) already timed
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
   if (he == hipSuccess) he = hipMalloc(&xin, in_bytes);
   if (he == hipSuccess) he = hipMemsetAsync(xin, 0, in_bytes, stream);
   for (size_t i = 0; he == hipSuccess && i < cands.size(); ++i) {
-    sonar_plan_desc d = *desc;
-    d.bf_mode = cands[i].first;
+    const tune_choice c = cands[i];
     sonar_plan p = nullptr;
-    g_mt_nwave_hint = cands[i].second;
-    const int st = sonar_plan_create(&d, stream, &p);
-    g_mt_nwave_hint = 0;
+    const int st = create_with_choice(desc, c, stream, &p);
     if (st != SONAR_OK) {
       last_status = st;
       last_msg = sonar_last_error();
       if (st == SONAR_E_INVALID) break;   // the descriptor itself is bad
       continue;
+    }
+    tune_choice got = c;
+    got.nwave = is_mt_mode(c.mode) ? p->mt_nwave : 0;
+    got.logl = is_fd_mode(c.mode) ? p->fd_logL : 0;
+    if (is_fd_mode(c.mode)) {
+      if (std::find(fd_seen.begin(), fd_seen.end(), std::make_pair(c.mode, p->fd_logL)) != fd_seen.end()) {
+        sonar_plan_destroy(p);   // the hint was clamped to a length already timed
+        continue;
+      }
+      fd_seen.push_back({c.mode, p->fd_logL});
+      if (c.logl == 0 && p->fd_fused) {
+        if (p->fd_logL > 4) cands.push_back({c.mode, 0, p->fd_logL - 1});
+        if (p->fd_logL < FD_MAX_LOGL) cands.push_back({c.mode, 0, p->fd_logL + 1});
+      }
     }
     if (!eout) he = hipMalloc(reinterpret_cast<void**>(&eout), static_cast<size_t>(F) * p->D * p->Q * sizeof(float));
     float ms = 0.f;
@@ -1131,7 +1268,7 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
       if (best) sonar_plan_destroy(best);
       best = p;
       best_ms = ms;
-      best_mode = cands[i].first;
+      best_c = got;
     } else {
       sonar_plan_destroy(p);
     }
@@ -1146,8 +1283,12 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
     return hip_fail(he, "mode tuning");
   }
   if (!best) return fail(last_status, "%s", last_msg.c_str());
+  if (!cache.empty()) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    cache_append(cache, key, best_c, best_ms / 3.0f);
+  }
   *out = best;
-  if (chosen_mode) *chosen_mode = best_mode;
+  if (chosen_mode) *chosen_mode = best_c.mode;
   return SONAR_OK;
 }
 

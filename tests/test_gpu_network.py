@@ -170,3 +170,35 @@ def test_network_eager_call_while_another_stream_captures(gpu, torch_mod, networ
     torch.cuda.synchronize()
     for a, b in zip(outs_a, ref):
         assert torch.equal(a, b)
+
+
+def test_tune_cache_persists_the_choice(gpu, torch_mod, network, tmp_path):
+    """sonar_tune_cache: the first tuned creation times the candidates and appends its choice as one
+    JSON line; the second finds it and creates the same plan without timing (no new line); a
+    different descriptor gets its own line."""
+    import json
+    torch = torch_mod
+    path = tmp_path / "tune.jsonl"
+    gpu.tune_cache(str(path))
+    try:
+        w = network[3]
+        _say("case tune cache: tuned plan twice, then another direction grid")
+        p1 = _plan(gpu, w, tune="bf16")
+        lines = path.read_text().splitlines()
+        assert len(lines) == 1
+        rec = json.loads(lines[0])
+        assert gpu.BF_MODES[p1.mode] == rec["mode"]
+        p2 = _plan(gpu, w, tune="bf16")
+        assert len(path.read_text().splitlines()) == 1
+        assert p2.mode == p1.mode
+        for q in (gpu.Q_MT_WAVES, gpu.Q_FD_PHASE_LEN):
+            assert p2.query(q) == p1.query(q)
+        x = torch.from_numpy(w.x).cuda()
+        assert torch.equal(p1.energyscape(x), p2.energyscape(x))
+        _say(f"  chose {p1.mode} ({rec})")
+        p3 = gpu.Plan(w.mic_pos, w.chirp, w.dirs[:700], w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
+                      max_frames=w.x.shape[0], tune="fp32")
+        assert len(path.read_text().splitlines()) == 2
+        assert p3.mode in ("td", "fd_fp32", "fd_bf16x3")
+    finally:
+        gpu.tune_cache(None)
