@@ -297,7 +297,14 @@ int sonar_energyscape_batch_static(sonar_plan plan, const void* x, int32_t F, fl
  * grid and mode): E_i = sonar_energyscape_batch(plans[i], x[i], frames[i]).
  * This is the sensor network's batch (§3: many sensors' measurements are
  * processed by the same GPU service; §5).  All items are validated before any
- * work is enqueued.  Items then run concurrently: forked from `stream` onto
+ * work is enqueued.  Items whose plans are MFMA time-domain modes (TD_BF16,
+ * TD_BF16X2, TD_F16) with the FIR envelope, each plan once in the call, run
+ * first, on `stream`: their matched filters, then ONE persistent
+ * beamformer + envelope launch per group of up to 16 items with the same mode
+ * and workgroup shape (a fixed grid of workgroups walks a work list of every
+ * item's tiles of 32 directions x range; item descriptors travel as kernel
+ * arguments), bit-identical to the items' own batch calls.  The other items
+ * then run concurrently: forked from `stream` onto
  * it and up to three library-owned side streams of the device (created with
  * its first plan, default priority), largest items first onto the least
  * loaded stream, items sharing a plan on one stream in order, and joined back

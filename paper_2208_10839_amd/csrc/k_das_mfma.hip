@@ -45,6 +45,8 @@
 // per workgroup by a power of two, taps as hi + lo, two products).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "plan.hpp"
 
 namespace {
@@ -74,13 +76,15 @@ __device__ __forceinline__ f32x16 mfma_f16(uint4 a, uint4 b, f32x16 c) {
 
 // Workgroup: one tile of 32 directions x NWAVE * 128 beam samples of one frame.
 // Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
-// wv / MT_RES: 4 output tiles of 32 samples (4c + rho).
+// wv / MT_RES: 4 output tiles of 32 samples (4c + rho).  `block` is the tile's index in the
+// plan's grid (the workgroup index of a one-plan launch, a work-list position of the persistent one).
 template <int NWAVE, int NPL, bool F16>
-__global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_kernel(
+__device__ __forceinline__ void mt_tile(
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale) {
+    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale,
+    int block) {
   constexpr int MICS = NPL == 2 ? 2 * MT_MICS : MT_MICS;   // microphones staged per group
   extern __shared__ unsigned short sm[];    // NPL planes x MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
@@ -94,8 +98,8 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
   // Workgroups are handed to the XCDs round-robin by index: XCD x = index % nx
   // keeps the weights of its own tpx direction tiles in its L2 and runs them
   // back to back on each staged window (frame f, range tile qt).
-  const int bx = blockIdx.x % nx;
-  int bid = blockIdx.x / nx;
+  const int bx = block % nx;
+  int bid = block / nx;
   const int tile = bx * tpx + bid % tpx;
   if (tile >= ntiles) return;
   bid /= tpx;
@@ -493,6 +497,55 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 #undef MT_FIR_STEP16
 }
 
+template <int NWAVE, int NPL, bool F16>
+__global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_kernel(
+    const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
+    const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
+    const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
+    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale) {
+  mt_tile<NWAVE, NPL, F16>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx,
+                           gmax, kcmax, nmc, wrow, perm_off, fir_unscale, static_cast<int>(blockIdx.x));
+}
+
+// Persistent launch over the items of a sensor-network batch (each item: one plan, its frames):
+// a work list of every item's tiles, item after item, each item's run padded to whole rounds of
+// MT_XCDS so that the XCD mapping of one-plan launches is kept (tile slot bx of every item on XCD
+// bx).  A fixed grid of workgroups (a few per CU) walks the list with a stride of its size.
+struct MtItem {
+  const unsigned short* planes;
+  const int4* gtab;
+  const uint4* wtab;
+  const int2* kcr;
+  const int* perm;
+  const uint4* ftab;
+  float* E;
+  long long fstride;
+  int M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, gmax, kcmax, nmc, wrow, perm_off;
+  float fir_unscale;
+  int work_begin;   // first work-list position of the item (a multiple of MT_XCDS)
+  int work_count;   // its tiles: frames x nqt x nx x tpx (positions up to the next item are padding)
+};
+struct MtWork {
+  MtItem item[MT_MULTI_MAX_ITEMS];
+  int n_items;
+  int total;        // work-list length
+};
+
+template <int NWAVE, int NPL, bool F16>
+__global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_multi_kernel(
+    const MtWork work) {
+  for (int w = blockIdx.x; w < work.total; w += gridDim.x) {
+    int i = 0;
+    while (i + 1 < work.n_items && work.item[i + 1].work_begin <= w) ++i;   // wave-uniform
+    const MtItem& it = work.item[i];
+    if (w - it.work_begin >= it.work_count) continue;   // padding up to the next item (uniform)
+    mt_tile<NWAVE, NPL, F16>(it.planes, it.fstride, it.gtab, it.wtab, it.kcr, it.perm, it.ftab, it.E, it.M, it.D, it.Q,
+                             it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.nx, it.tpx, it.gmax, it.kcmax, it.nmc,
+                             it.wrow, it.perm_off, it.fir_unscale, w - it.work_begin);
+    __syncthreads();   // the next tile's staging rewrites the LDS this tile's epilogue reads
+  }
+}
+
 }  // namespace
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
@@ -511,8 +564,12 @@ namespace {
 
 template <int NWAVE, int NPL, bool F16>
 hipError_t set_mt_attr() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL, F16>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL, F16>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_multi_kernel<NWAVE, NPL, F16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  return e;
 }
 
 template <int NWAVE, int NPL, bool F16>
@@ -539,6 +596,82 @@ hipError_t init_mt_kernel_attributes() {
   if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, false>();
   if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, true>();
   return e;
+}
+
+namespace {
+
+template <int NWAVE, int NPL, bool F16>
+hipError_t launch_mt_multi(const MtWork& work, size_t smem, int grid, hipStream_t s) {
+  hipLaunchKernelGGL((das_mfma_env_multi_kernel<NWAVE, NPL, F16>), dim3(static_cast<unsigned>(grid)), dim3(NWAVE * 64),
+                     smem, s, work);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool mt_multi_compatible(const sonar_plan_s* a, const sonar_plan_s* b) {
+  return mt_planes(a) == mt_planes(b) && mt_f16(a) == mt_f16(b) && a->mt_nwave == b->mt_nwave &&
+         a->device == b->device;
+}
+
+hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const float2* const* yext, const int* frames,
+                                     float* const* E, int n, hipStream_t s) {
+  if (n < 1 || n > MT_MULTI_MAX_ITEMS) return hipErrorInvalidValue;
+  MtWork work{};
+  size_t smem = 0;
+  int pos = 0;
+  for (int i = 0; i < n; ++i) {
+    const sonar_plan_s* p = plans[i];
+    if (!mt_planes(p) || !mt_multi_compatible(p, plans[0])) return hipErrorInvalidValue;
+    MtItem& it = work.item[i];
+    it.planes = reinterpret_cast<const unsigned short*>(yext[i] + static_cast<long long>(p->M) * p->row);
+    it.gtab = reinterpret_cast<const int4*>(p->d_mt_g);
+    it.wtab = reinterpret_cast<const uint4*>(p->d_mt_w);
+    it.kcr = p->d_mt_kcr;
+    it.perm = p->d_mt_perm;
+    it.ftab = reinterpret_cast<const uint4*>(p->d_mt_fir);
+    it.E = E[i];
+    it.fstride = 4 * p->mf_fstride;
+    it.M = p->M;
+    it.D = p->D;
+    it.Q = p->Q;
+    it.row = p->row;
+    it.R = p->R;
+    it.K = p->K;
+    it.qc = p->mt_qc;
+    it.nqt = p->mt_nqt;
+    it.ntiles = p->mt_ntiles;
+    it.nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
+    it.tpx = (p->mt_ntiles + it.nx - 1) / it.nx;
+    it.gmax = p->mt_gmax;
+    it.kcmax = p->mt_kcmax;
+    it.nmc = p->mt_nmc;
+    it.wrow = p->mt_wrow;
+    it.perm_off = static_cast<int>(mt_perm_offset(p));
+    it.fir_unscale = p->mt_fir_unscale;
+    it.work_begin = pos;
+    it.work_count = frames[i] * p->mt_nqt * it.nx * it.tpx;
+    pos += (it.work_count + MT_XCDS - 1) / MT_XCDS * MT_XCDS;
+    smem = std::max(smem, mt_smem_bytes(p));
+  }
+  work.n_items = n;
+  work.total = pos;
+  // a fixed grid: the workgroups the CUs hold at once (two 4-wave or one 8-wave workgroup per CU
+  // at two waves per SIMD), a whole number of rounds over the XCDs, no more than the work
+  const sonar_plan_s* p0 = plans[0];
+  int grid = p0->cu_count * (p0->mt_nwave == MT_NWAVE_SMALL ? 2 : 1);
+  grid = grid / MT_XCDS * MT_XCDS;
+  if (grid < MT_XCDS) grid = MT_XCDS;
+  if (grid > pos) grid = pos;
+  if (grid < 1) return hipSuccess;
+  const bool four = mt_planes(p0) == 4, f16 = mt_f16(p0);
+  if (p0->mt_nwave == MT_NWAVE_SMALL)
+    return four  ? launch_mt_multi<MT_NWAVE_SMALL, 4, false>(work, smem, grid, s)
+           : f16 ? launch_mt_multi<MT_NWAVE_SMALL, 2, true>(work, smem, grid, s)
+                 : launch_mt_multi<MT_NWAVE_SMALL, 2, false>(work, smem, grid, s);
+  return four  ? launch_mt_multi<MT_NWAVE_LARGE, 4, false>(work, smem, grid, s)
+         : f16 ? launch_mt_multi<MT_NWAVE_LARGE, 2, true>(work, smem, grid, s)
+               : launch_mt_multi<MT_NWAVE_LARGE, 2, false>(work, smem, grid, s);
 }
 
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {

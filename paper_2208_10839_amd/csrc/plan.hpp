@@ -62,6 +62,7 @@ struct sonar_plan_s {
   float mt_fir_unscale = 1.f;          // 2^-ts: the two-plane modes' low-pass taps are stored times 2^ts
 
   int device = 0;
+  int cu_count = 0;     // compute units of the device
   size_t ws_bytes = 0;
 
   // device buffers (owned)
@@ -203,6 +204,7 @@ constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that 
 // samples + a zeroed tail, padded so that a row is 16 bytes past a multiple of 256 (bank spread)
 __host__ __device__ constexpr int mt_nsp(int nwave) { return nwave * 128 + 4; }
 constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row
+constexpr int MT_MULTI_MAX_ITEMS = 16;   // items of one persistent multi launch (descriptors travel as kernel arguments)
 
 constexpr int FD_MAX_LOGL = 14;        // largest per-phase transform of the FD inverse (LDS): 16384 points
 constexpr int FD_MAX_FOLD = 2;         // stored bins per slot held in registers by the fused FD inverse
@@ -220,6 +222,10 @@ hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2*
 hipError_t launch_mf_big_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 size_t mt_smem_bytes(const sonar_plan_s* p);
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
+// persistent beamformer + envelope over n <= MT_MULTI_MAX_ITEMS items of compatible MFMA TD plans
+bool mt_multi_compatible(const sonar_plan_s* a, const sonar_plan_s* b);
+hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const float2* const* yext, const int* frames,
+                                     float* const* E, int n, hipStream_t s);
 hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);

@@ -727,6 +727,11 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   }
   create_side_pool(p->device);
   resolve_scratch(p->device);
+  if (hipDeviceGetAttribute(&p->cu_count, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+      p->cu_count < 1) {
+    (void)hipGetLastError();
+    p->cu_count = 256;
+  }
   hipError_t e = init_td_kernel_attributes();
   if (e == hipSuccess) e = init_mt_kernel_attributes();
   if (e != hipSuccess) {
@@ -996,6 +1001,63 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
     }
   }
   if (n == 0) return SONAR_OK;
+  // Items of the MFMA time-domain modes (FIR envelope, each plan once in the call) run as one
+  // persistent beamformer launch per compatible group of up to MT_MULTI_MAX_ITEMS items, after
+  // their matched filters, all on the caller's stream; the other items follow below.
+  std::vector<int> rest;
+  {
+    std::vector<int> elig;
+    for (int i = 0; i < n; ++i) {
+      bool unique = true;
+      for (int j = 0; j < n; ++j)
+        if (j != i && plans[j] == plans[i]) unique = false;
+      if (unique && mt_planes(plans[i]) && plans[i]->iir_ns == 0) elig.push_back(i);
+      else rest.push_back(i);
+    }
+    std::vector<char> done(n, 0);
+    for (size_t a = 0; a < elig.size(); ++a) {
+      const int i0 = elig[a];
+      if (done[i0]) continue;
+      std::vector<int> grp;
+      for (size_t b = a; b < elig.size() && static_cast<int>(grp.size()) < MT_MULTI_MAX_ITEMS; ++b)
+        if (!done[elig[b]] && mt_multi_compatible(plans[elig[b]], plans[i0])) {
+          grp.push_back(elig[b]);
+          done[elig[b]] = 1;
+        }
+      std::vector<const sonar_plan_s*> gp;
+      std::vector<const float2*> gy;
+      std::vector<int> gf;
+      std::vector<float*> ge;
+      hipError_t e = hipSuccess;
+      for (int i : grp) {
+        // the persistent beamformer reads only the 16-bit planes: the complex rows are not written
+        if (e == hipSuccess) e = launch_mf_td(plans[i], x[i], frames[i], plans[i]->d_mf, stream, false);
+        gp.push_back(plans[i]);
+        gy.push_back(plans[i]->d_mf);
+        gf.push_back(frames[i]);
+        ge.push_back(E[i]);
+      }
+      if (e == hipSuccess)
+        e = launch_das_mfma_env_multi(gp.data(), gy.data(), gf.data(), ge.data(), static_cast<int>(grp.size()), stream);
+      if (e != hipSuccess) return hip_fail(e, "multi persistent launch");
+    }
+  }
+  if (rest.empty()) return SONAR_OK;
+  std::vector<sonar_plan> rp;
+  std::vector<const void*> rx;
+  std::vector<int32_t> rf;
+  std::vector<float*> re;
+  for (int i : rest) {
+    rp.push_back(plans[i]);
+    rx.push_back(x[i]);
+    rf.push_back(frames[i]);
+    re.push_back(E[i]);
+  }
+  plans = rp.data();
+  x = rx.data();
+  frames = rf.data();
+  E = re.data();
+  n = static_cast<int32_t>(rest.size());
   side_pool* pool = side_pool_of(plans[0]->device);
   if (n < 2 || !pool) {
     for (int i = 0; i < n; ++i) {

@@ -202,3 +202,43 @@ def test_tune_cache_persists_the_choice(gpu, torch_mod, network, tmp_path):
         assert p3.mode in ("td", "fd_fp32", "fd_bf16x3")
     finally:
         gpu.tune_cache(None)
+
+
+C3_SUBSET = 250   # directions of each 1500-direction energyscape checked against the oracle (all of the 2D grids)
+
+
+@pytest.mark.parametrize("mode", ["td_bf16x2", "fd_bf16"])
+def test_network_fp16_samples(gpu, torch_mod, network, mode):
+    """The sensor network as configured: FP16 samples, BF16 matrix-core beamforming (the persistent
+    time-domain launch, or the per-bin GEMM with each sensor's 4 frames as its N dimension).  All 32
+    energyscapes against the oracle on the rounded samples (compute-only error, bar 1e-3): every
+    direction of the 91-azimuth grids, a seeded subset of 250 of the 1500-direction grids; the
+    end-to-end error against the oracle on the FP32 samples is printed beside it."""
+    from oracle import pool
+    torch = torch_mod
+    _say(f"case network FP16 samples: {mode}, 8 sensors x 4 frames")
+    plans = [_plan(gpu, w, mode=mode, sample_dtype="f16") for w in network]
+    xh = [w.x.astype(np.float16) for w in network]
+    Es = gpu.energyscape_multi(plans, [torch.from_numpy(x).cuda() for x in xh])
+    Es = [E.cpu().numpy() for E in Es]
+    omode = "fd" if mode.startswith("fd") else "td"
+    jobs, keys = [], []
+    for s, (w, pl, x) in enumerate(zip(network, plans, xh)):
+        D = w.dirs.shape[0]
+        idx = None if D <= 128 else np.sort(np.random.default_rng(100 + s).choice(D, C3_SUBSET, replace=False))
+        for f in range(w.x.shape[0]):
+            for src, tag in ((x[f], "rounded"), (w.x[f], "fp32")):
+                jobs.append(pool.Job(x=src, chirp=w.chirp, mic_pos=w.mic_pos, dirs=w.dirs, fs=w.fs, c=w.c, P=pl.P,
+                                     R=w.cfg.decim, band=w.cfg.band, mode=omode, dir_index=idx))
+                keys.append((s, f, tag, idx))
+    refs, _, wall = pool.run(jobs, workers=pool.default_workers())
+    _say(f"  oracle: {len(jobs)} energyscapes in {wall:.1f} s")
+    worst = {"rounded": 0.0, "fp32": 0.0}
+    for (s, f, tag, idx), Eo in zip(keys, refs):
+        got = Es[s][f] if idx is None else Es[s][f][idx]
+        e = rel_l2(got, Eo)
+        worst[tag] = max(worst[tag], e)
+        if tag == "rounded":
+            assert e <= BARS[mode], (s, f, e)
+    _say(f"  max compute-only rel L2 over 32 energyscapes = {worst['rounded']:.3e}; "
+         f"end to end (vs FP32 samples) = {worst['fp32']:.3e}")
