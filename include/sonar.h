@@ -99,11 +99,21 @@ enum sonar_status {
  *              Samples below 2^-28 of the frame's bound are FP16 subnormals
  *              (less relative precision, far below the 1e-4 scale of the
  *              error); e is clamped to [-100, 100], so frames whose bound
- *              lies outside [2^-86, 2^114] overflow or underflow. */
+ *              lies outside [2^-86, 2^114] overflow or underflow.
+ *  TD_BF16G  : TD_LINEAR with the fractional delay on a grid of 1/256 sample
+ *              (alpha = rint(256 (-Dl - o)) / 256, alpha = 1 taken as o + 1,
+ *              alpha = 0), computed on BF16 MFMA with FP32 accumulation: the
+ *              weights 1 - alpha and alpha are exact in one BF16 term, the
+ *              samples are one BF16 term (two BF16 planes per microphone, as in
+ *              TD_BF16X2): two products (re, im), two MFMAs per K-chunk.  The
+ *              grid moves a delay by at most 1/512 sample; with the samples'
+ *              BF16 rounding the result is within 1e-3 of TD_LINEAR for arrays
+ *              of 32 or more microphones (SONAR_PREC_BF16 offers it only there).
+ *              The low-pass runs as in TD_BF16X2. */
 enum sonar_bf_mode {
   SONAR_BF_TD_LINEAR = 0, SONAR_BF_FD_FP32 = 1, SONAR_BF_FD_BF16 = 2, SONAR_BF_FD_BF16X3 = 3,
   SONAR_BF_TD_BF16 = 4, SONAR_BF_TD_NEAREST = 5, SONAR_BF_TD_CUBIC = 6, SONAR_BF_TD_BF16X2 = 7,
-  SONAR_BF_TD_F16 = 8
+  SONAR_BF_TD_F16 = 8, SONAR_BF_TD_BF16G = 9
 };
 
 /* Element type of the microphone samples x. */

@@ -23,7 +23,8 @@ SONAR_E_HIP = -3
 SONAR_E_UNSUPPORTED = -4
 
 PRECISIONS = {"fp32": 0, "bf16": 1}
-BF_MODES = {"td": 0, "fd_fp32": 1, "fd_bf16": 2, "fd_bf16x3": 3, "td_bf16": 4, "td_nearest": 5, "td_cubic": 6, "td_bf16x2": 7, "td_f16": 8}
+BF_MODES = {"td": 0, "fd_fp32": 1, "fd_bf16": 2, "fd_bf16x3": 3, "td_bf16": 4, "td_nearest": 5, "td_cubic": 6, "td_bf16x2": 7, "td_f16": 8,
+            "td_bf16g": 9}
 DTYPES = {"f32": 0, "f16": 1, "bf16": 2}
 
 Q_RANGE_BINS, Q_BEAM_LEN, Q_FFT_LEN, Q_MF_ROW, Q_MF_ORIGIN = 0, 1, 2, 3, 4

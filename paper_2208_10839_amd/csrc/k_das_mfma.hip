@@ -78,7 +78,7 @@ __device__ __forceinline__ f32x16 mfma_f16(uint4 a, uint4 b, f32x16 c) {
 // Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
 // wv / MT_RES: 4 output tiles of 32 samples (4c + rho).  `block` is the tile's index in the
 // plan's grid (the workgroup index of a one-plan launch, a work-list position of the persistent one).
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 __device__ __forceinline__ void mt_tile(
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
@@ -92,6 +92,8 @@ __device__ __forceinline__ void mt_tile(
   static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
   static_assert(NPL == 4 || NPL == 2, "four split planes or two single ones");
   static_assert(!F16 || NPL == 2, "FP16 samples come as two planes");
+  static_assert(!F16 || W1, "FP16 weights are single terms");
+  static_assert(!W1 || NPL == 2, "single-term weights go with single-term samples");
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int rho = wv % MT_RES;
@@ -193,7 +195,7 @@ __device__ __forceinline__ void mt_tile(
   auto load_ops = [&](Operands& o, int kc) {
     const int kl = kc < kend ? kc : kfirst;
     o.ah = wt[kl * 128];
-    if constexpr (!F16) o.al = wt[kl * 128 + 64];
+    if constexpr (!W1) o.al = wt[kl * 128 + 64];
     const int* q = gs + 8 * kl;
     o.glo = make_int4(q[0], q[1], q[2], q[3]);
     o.ghi = make_int4(q[4], q[5], q[6], q[7]);
@@ -238,6 +240,15 @@ __device__ __forceinline__ void mt_tile(
           const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
           cre[nt] = mfma_f16(o.ah, br, cre[nt]);
           cim[nt] = mfma_f16(o.ah, bi, cim[nt]);
+        }
+      } else if constexpr (W1) {
+        // exact single-term BF16 weights (delays on a 1/256 grid): one product per plane
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
+          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
+          cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
         }
       } else {
 #pragma unroll
@@ -497,13 +508,13 @@ __device__ __forceinline__ void mt_tile(
 #undef MT_FIR_STEP16
 }
 
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_kernel(
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
     int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale) {
-  mt_tile<NWAVE, NPL, F16>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx,
+  mt_tile<NWAVE, NPL, F16, W1>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx,
                            gmax, kcmax, nmc, wrow, perm_off, fir_unscale, static_cast<int>(blockIdx.x));
 }
 
@@ -531,7 +542,7 @@ struct MtWork {
   int total;        // work-list length
 };
 
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void das_mfma_env_multi_kernel(
     const MtWork work) {
   for (int w = blockIdx.x; w < work.total; w += gridDim.x) {
@@ -539,7 +550,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     while (i + 1 < work.n_items && work.item[i + 1].work_begin <= w) ++i;   // wave-uniform
     const MtItem& it = work.item[i];
     if (w - it.work_begin >= it.work_count) continue;   // padding up to the next item (uniform)
-    mt_tile<NWAVE, NPL, F16>(it.planes, it.fstride, it.gtab, it.wtab, it.kcr, it.perm, it.ftab, it.E, it.M, it.D, it.Q,
+    mt_tile<NWAVE, NPL, F16, W1>(it.planes, it.fstride, it.gtab, it.wtab, it.kcr, it.perm, it.ftab, it.E, it.M, it.D, it.Q,
                              it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.nx, it.tpx, it.gmax, it.kcmax, it.nmc,
                              it.wrow, it.perm_off, it.fir_unscale, w - it.work_begin);
     __syncthreads();   // the next tile's staging rewrites the LDS this tile's epilogue reads
@@ -562,22 +573,22 @@ size_t mt_smem_bytes(const sonar_plan_s* p) { return mt_perm_offset(p) + 32 * si
 
 namespace {
 
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 hipError_t set_mt_attr() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL, F16>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_kernel<NWAVE, NPL, F16, W1>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_multi_kernel<NWAVE, NPL, F16>),
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(das_mfma_env_multi_kernel<NWAVE, NPL, F16, W1>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   return e;
 }
 
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
   const int nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
   const int tpx = (p->mt_ntiles + nx - 1) / nx;
   const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
-  hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL, F16>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
+  hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL, F16, W1>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
                      mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, reinterpret_cast<const int4*>(p->d_mt_g),
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
@@ -586,31 +597,61 @@ hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F,
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t init_mt_kernel_attributes() {
-  hipError_t e = set_mt_attr<MT_NWAVE_SMALL, 4, false>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2, false>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_SMALL, 2, true>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 4, false>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, false>();
-  if (e == hipSuccess) e = set_mt_attr<MT_NWAVE_LARGE, 2, true>();
-  return e;
-}
-
-namespace {
-
-template <int NWAVE, int NPL, bool F16>
+template <int NWAVE, int NPL, bool F16, bool W1>
 hipError_t launch_mt_multi(const MtWork& work, size_t smem, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((das_mfma_env_multi_kernel<NWAVE, NPL, F16>), dim3(static_cast<unsigned>(grid)), dim3(NWAVE * 64),
-                     smem, s, work);
+  hipLaunchKernelGGL((das_mfma_env_multi_kernel<NWAVE, NPL, F16, W1>), dim3(static_cast<unsigned>(grid)),
+                     dim3(NWAVE * 64), smem, s, work);
   return hipGetLastError();
 }
 
+// the kernel variant of a plan: four split planes (TD_BF16), two BF16 planes with split weights
+// (TD_BF16X2), FP16 (TD_F16), two BF16 planes with exact single-term weights (TD_BF16G)
+enum MtVariant { MT_V_BF16X4, MT_V_BF16X2, MT_V_F16, MT_V_BF16G };
+MtVariant mt_variant(const sonar_plan_s* p) {
+  if (mt_planes(p) == 4) return MT_V_BF16X4;
+  if (mt_f16(p)) return MT_V_F16;
+  return mt_w1(p) ? MT_V_BF16G : MT_V_BF16X2;
+}
+
+template <int NWAVE>
+hipError_t set_mt_attrs() {
+  hipError_t e = set_mt_attr<NWAVE, 4, false, false>();
+  if (e == hipSuccess) e = set_mt_attr<NWAVE, 2, false, false>();
+  if (e == hipSuccess) e = set_mt_attr<NWAVE, 2, true, true>();
+  if (e == hipSuccess) e = set_mt_attr<NWAVE, 2, false, true>();
+  return e;
+}
+
+template <int NWAVE>
+hipError_t launch_mt_v(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
+  switch (mt_variant(p)) {
+    case MT_V_BF16X4: return launch_mt<NWAVE, 4, false, false>(p, planes, F, E, s);
+    case MT_V_BF16X2: return launch_mt<NWAVE, 2, false, false>(p, planes, F, E, s);
+    case MT_V_F16: return launch_mt<NWAVE, 2, true, true>(p, planes, F, E, s);
+    default: return launch_mt<NWAVE, 2, false, true>(p, planes, F, E, s);
+  }
+}
+
+template <int NWAVE>
+hipError_t launch_mt_multi_v(const sonar_plan_s* p0, const MtWork& work, size_t smem, int grid, hipStream_t s) {
+  switch (mt_variant(p0)) {
+    case MT_V_BF16X4: return launch_mt_multi<NWAVE, 4, false, false>(work, smem, grid, s);
+    case MT_V_BF16X2: return launch_mt_multi<NWAVE, 2, false, false>(work, smem, grid, s);
+    case MT_V_F16: return launch_mt_multi<NWAVE, 2, true, true>(work, smem, grid, s);
+    default: return launch_mt_multi<NWAVE, 2, false, true>(work, smem, grid, s);
+  }
+}
+
 }  // namespace
 
+hipError_t init_mt_kernel_attributes() {
+  hipError_t e = set_mt_attrs<MT_NWAVE_SMALL>();
+  if (e == hipSuccess) e = set_mt_attrs<MT_NWAVE_LARGE>();
+  return e;
+}
+
 bool mt_multi_compatible(const sonar_plan_s* a, const sonar_plan_s* b) {
-  return mt_planes(a) == mt_planes(b) && mt_f16(a) == mt_f16(b) && a->mt_nwave == b->mt_nwave &&
+  return mt_planes(a) == mt_planes(b) && mt_variant(a) == mt_variant(b) && a->mt_nwave == b->mt_nwave &&
          a->device == b->device;
 }
 
@@ -664,27 +705,14 @@ hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const flo
   if (grid < MT_XCDS) grid = MT_XCDS;
   if (grid > pos) grid = pos;
   if (grid < 1) return hipSuccess;
-  const bool four = mt_planes(p0) == 4, f16 = mt_f16(p0);
-  if (p0->mt_nwave == MT_NWAVE_SMALL)
-    return four  ? launch_mt_multi<MT_NWAVE_SMALL, 4, false>(work, smem, grid, s)
-           : f16 ? launch_mt_multi<MT_NWAVE_SMALL, 2, true>(work, smem, grid, s)
-                 : launch_mt_multi<MT_NWAVE_SMALL, 2, false>(work, smem, grid, s);
-  return four  ? launch_mt_multi<MT_NWAVE_LARGE, 4, false>(work, smem, grid, s)
-         : f16 ? launch_mt_multi<MT_NWAVE_LARGE, 2, true>(work, smem, grid, s)
-               : launch_mt_multi<MT_NWAVE_LARGE, 2, false>(work, smem, grid, s);
+  return p0->mt_nwave == MT_NWAVE_SMALL ? launch_mt_multi_v<MT_NWAVE_SMALL>(p0, work, smem, grid, s)
+                                        : launch_mt_multi_v<MT_NWAVE_LARGE>(p0, work, smem, grid, s);
 }
 
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s) {
-  // the BF16 planes of frame f follow its M complex rows
+  // the 16-bit planes of frame f follow its M complex rows
   const unsigned short* planes = reinterpret_cast<const unsigned short*>(yext + static_cast<long long>(p->M) * p->row);
-  const bool four = mt_planes(p) == 4, f16 = mt_f16(p);
-  if (p->mt_nwave == MT_NWAVE_SMALL)
-    return four  ? launch_mt<MT_NWAVE_SMALL, 4, false>(p, planes, F, E, s)
-           : f16 ? launch_mt<MT_NWAVE_SMALL, 2, true>(p, planes, F, E, s)
-                 : launch_mt<MT_NWAVE_SMALL, 2, false>(p, planes, F, E, s);
-  if (p->mt_nwave == MT_NWAVE_LARGE)
-    return four  ? launch_mt<MT_NWAVE_LARGE, 4, false>(p, planes, F, E, s)
-           : f16 ? launch_mt<MT_NWAVE_LARGE, 2, true>(p, planes, F, E, s)
-                 : launch_mt<MT_NWAVE_LARGE, 2, false>(p, planes, F, E, s);
+  if (p->mt_nwave == MT_NWAVE_SMALL) return launch_mt_v<MT_NWAVE_SMALL>(p, planes, F, E, s);
+  if (p->mt_nwave == MT_NWAVE_LARGE) return launch_mt_v<MT_NWAVE_LARGE>(p, planes, F, E, s);
   return hipErrorInvalidValue;
 }

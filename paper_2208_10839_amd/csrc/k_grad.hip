@@ -461,7 +461,7 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p->bf_mode != SONAR_BF_TD_LINEAR && p->bf_mode != SONAR_BF_TD_BF16 && p->bf_mode != SONAR_BF_TD_NEAREST &&
-      p->bf_mode != SONAR_BF_TD_BF16X2 && p->bf_mode != SONAR_BF_TD_F16)
+      p->bf_mode != SONAR_BF_TD_BF16X2 && p->bf_mode != SONAR_BF_TD_F16 && p->bf_mode != SONAR_BF_TD_BF16G)
     return vjp_fd(p, mf, beam_grad, F, dyhat, dx, dpos, s);
   if (dpos) {
     hipLaunchKernelGGL(dl_vjp_kernel, dim3(static_cast<unsigned>(rows)), dim3(256), 0, s, beam_grad, mf, p->d_dtab,

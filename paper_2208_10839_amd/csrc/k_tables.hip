@@ -7,7 +7,8 @@
 //                {o - omin, (1-alpha)/M, alpha/M} (integer delays: o = floor(-Dl + 1/2),
 //                alpha = 0; cubic: two entries per microphone, {o - 1 - omin, L_-1/M, L_0/M}
 //                and {o + 1 - omin, L_1/M, L_2/M}, the 4-point Lagrange weights; gridded
-//                (TD_F16): alpha rounded to a multiple of 1/2048, alpha = 1 taken as o + 1);
+//                (TD_F16, TD_BF16G): alpha rounded to a multiple of 1/2048 or 1/256, alpha = 1
+//                taken as o + 1);
 //  * chirp       C[k] = beta[k] W[k] conj(S[k]), S[k] = sum_l s[l] exp(-2 pi i k l/P),
 //                with the phase index k l reduced mod P exactly in integers;
 //  * twiddles    FFT tables (layout in plan.hpp), exp(-2 pi i e / NF) and
@@ -30,8 +31,9 @@ __global__ void delay_table_kernel(const double* __restrict__ pos, const double*
   const bool nearest = interp == 1;
   double o = nearest ? floor(-Dl + 0.5) : floor(-Dl);
   double a = nearest ? 0.0 : -Dl - o;
-  if (interp == 3) {
-    a = rint(a * 2048.0) / 2048.0;
+  if (interp == 3 || interp == 4) {
+    const double steps = interp == 3 ? 2048.0 : 256.0;
+    a = rint(a * steps) / steps;
     if (a >= 1.0) {
       o += 1.0;
       a = 0.0;
@@ -150,6 +152,7 @@ hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s) {
                      p->bf_mode == SONAR_BF_TD_NEAREST ? 1
                      : p->bf_mode == SONAR_BF_TD_CUBIC ? 2
                      : p->bf_mode == SONAR_BF_TD_F16   ? 3
+                     : p->bf_mode == SONAR_BF_TD_BF16G ? 4
                                                        : 0,
                      p->d_dtab, p->d_dl);
   return hipGetLastError();

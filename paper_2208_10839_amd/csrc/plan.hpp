@@ -59,7 +59,8 @@ struct sonar_plan_s {
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
   int mt_nwave = 0;     // wavefronts per workgroup (MT_NWAVE_SMALL or MT_NWAVE_LARGE)
   long long mt_flop_per_frame = 0;   // matrix-core flops issued per frame
-  float mt_fir_unscale = 1.f;          // 2^-ts: the two-plane modes' low-pass taps are stored times 2^ts
+  float mt_fir_unscale = 1.f;          // 2^-ts (two-plane modes: taps stored times 2^ts), times 1/M for TD_BF16G
+                                       // (its exact weights leave out the array mean's 1/M)
 
   int device = 0;
   int cu_count = 0;     // compute units of the device
@@ -108,10 +109,17 @@ struct sonar_plan_s {
 // time-domain beamformer: 4 BF16 (re hi, re lo, im hi, im lo) for TD_BF16, 2 (re, im)
 // for TD_BF16X2 (BF16) and TD_F16 (FP16, scaled per frame), 0 for the other modes
 inline int mt_planes(const sonar_plan_s* p) {
-  return p->bf_mode == SONAR_BF_TD_BF16 ? 4 : (p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16 ? 2 : 0);
+  return p->bf_mode == SONAR_BF_TD_BF16 ? 4
+         : (p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16 || p->bf_mode == SONAR_BF_TD_BF16G ? 2 : 0);
 }
 
 inline bool mt_f16(const sonar_plan_s* p) { return p->bf_mode == SONAR_BF_TD_F16; }
+// MFMA TD modes whose interpolation weights are exact in one 16-bit term (delays on a grid):
+// TD_F16 (1/2048 sample, FP16) and TD_BF16G (1/256 sample, BF16); one product per sample plane
+inline bool mt_w1(const sonar_plan_s* p) { return p->bf_mode == SONAR_BF_TD_F16 || p->bf_mode == SONAR_BF_TD_BF16G; }
+inline int mt_grid_steps(const sonar_plan_s* p) {
+  return p->bf_mode == SONAR_BF_TD_F16 ? 2048 : (p->bf_mode == SONAR_BF_TD_BF16G ? 256 : 0);
+}
 // TD_F16 frame header after the planes: complex64 elements (16 bytes, keeps frames 16-byte aligned);
 // float 0 = 2^-e / M, the factor that takes the energyscape of the scaled FP16 samples back
 constexpr int MF_F16_HEADER = 2;

@@ -123,7 +123,8 @@ bool finite_all(const double* v, size_t n) {
 
 bool is_td(const sonar_plan_s* p) {
   return p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_BF16 || p->bf_mode == SONAR_BF_TD_NEAREST ||
-         p->bf_mode == SONAR_BF_TD_CUBIC || p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16;
+         p->bf_mode == SONAR_BF_TD_CUBIC || p->bf_mode == SONAR_BF_TD_BF16X2 || p->bf_mode == SONAR_BF_TD_F16 ||
+         p->bf_mode == SONAR_BF_TD_BF16G;
 }
 
 // Coordinates z_d in which distances between directions equal distances between their
@@ -222,7 +223,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
       ts = std::max(-100, std::min(100, 14 - ex));
     }
   }
-  p->mt_fir_unscale = static_cast<float>(std::ldexp(1.0, -ts));
+  p->mt_fir_unscale = static_cast<float>(std::ldexp(1.0, -ts) / (p->bf_mode == SONAR_BF_TD_BF16G ? p->M : 1));
   const int D = p->D, M = p->M;
   std::vector<int4> dtab(static_cast<size_t>(D) * M);
   hipError_t e = hipMemcpyAsync(dtab.data(), p->d_dtab, dtab.size() * sizeof(int4), hipMemcpyDeviceToHost, stream);
@@ -243,6 +244,8 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   std::vector<int2> kcr(static_cast<size_t>(nt) * nmc * MT_RES);
   int gmax = MT_GROUPS_PER_CHUNK;
   const bool f16 = mt_f16(p);
+  const bool w1 = mt_w1(p);              // gridded delays: one exact 16-bit weight term
+  const double steps = static_cast<double>(mt_grid_steps(p));
   // taps per microphone are allotted in runs of 4 (two planes) or 8 (four planes: the
   // kernel reads a group pair as 8 consecutive samples)
   const int span = mt_planes(p) == 4 ? 2 * MT_GROUP_TAPS : MT_GROUP_TAPS;
@@ -295,18 +298,26 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
           float w = 0.f;
           if (d >= 0 && !pad[li][gi]) {
             const int4 en = dtab[static_cast<size_t>(d) * M + g.x];
-            float w0, w1;
-            std::memcpy(&w0, &en.y, 4);
-            std::memcpy(&w1, &en.z, 4);
-            if (f16) {
-              // gridded delay: alpha = k / 2048 recovered exactly from alpha / M; the weights 1 - alpha
-              // and alpha (without 1/M, applied with the sample scale) are exact in FP16
-              const double a = std::rint(static_cast<double>(w1) * M * 2048.0) / 2048.0;
-              w0 = static_cast<float>(1.0 - a);
-              w1 = static_cast<float>(a);
+            float wa0, wa1;
+            std::memcpy(&wa0, &en.y, 4);
+            std::memcpy(&wa1, &en.z, 4);
+            if (w1) {
+              // gridded delay: alpha = k / steps recovered exactly from alpha / M
+              const double a = std::rint(static_cast<double>(wa1) * M * steps) / steps;
+              // 1 - alpha and alpha are exact in FP16 (1/2048 grid) and in BF16 (1/256 grid); the
+              // 1/M of the array mean is applied in FP32 at the store (with the TD_F16 sample scale,
+              // or with the low-pass scale for TD_BF16G)
+              wa0 = static_cast<float>(1.0 - a);
+              wa1 = static_cast<float>(a);
             }
-            if (tap == en.x) w = w0;
-            else if (tap == en.x + 1) w = w1;
+            if (tap == en.x) w = wa0;
+            else if (tap == en.x + 1) w = wa1;
+          }
+          if (w1 && !f16) {
+            const size_t at = ((static_cast<size_t>(li) * kcmax + kc) * 128 + l) * 8 + j;
+            wtab[at] = to_bf16_bits(w);
+            wtab[at + 64 * 8] = 0;
+            continue;
           }
           if (f16) {
             const _Float16 h = static_cast<_Float16>(w);
@@ -363,7 +374,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   long long chunks = 0;
   for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / MT_GROUPS_PER_CHUNK;
   // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples), 4 (single-term samples) or 2 (FP16)
-  const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : (f16 ? 2 : 4);
+  const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : (w1 ? 2 : 4);
   p->mt_flop_per_frame = chunks * (p->mt_nwave / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   // low-pass: 3 MFMAs per K-step and column block (BF16 hi/lo x hi/lo), 2 with two sample planes
   // (FP16 taps hi + lo times one FP16 term of |b|)
@@ -509,7 +520,7 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   if (d.max_frames < 1) return fail(SONAR_E_INVALID, "max_frames must be >= 1");
   if (d.sample_dtype < SONAR_F32 || d.sample_dtype > SONAR_BF16)
     return fail(SONAR_E_INVALID, "unknown sample_dtype %d", d.sample_dtype);
-  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_F16)
+  if (d.bf_mode < SONAR_BF_TD_LINEAR || d.bf_mode > SONAR_BF_TD_BF16G)
     return fail(SONAR_E_INVALID, "unknown bf_mode %d", d.bf_mode);
   if (!finite_all(d.mic_pos, 3 * static_cast<size_t>(d.n_mics)) ||
       !finite_all(d.dirs, 3 * static_cast<size_t>(d.n_dirs)) ||
@@ -1219,7 +1230,9 @@ int create_with_choice(const sonar_plan_desc* desc, const tune_choice& c, hipStr
   return st;
 }
 
-bool is_mt_mode(int m) { return m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2 || m == SONAR_BF_TD_F16; }
+bool is_mt_mode(int m) {
+  return m == SONAR_BF_TD_BF16 || m == SONAR_BF_TD_BF16X2 || m == SONAR_BF_TD_F16 || m == SONAR_BF_TD_BF16G;
+}
 bool is_fd_mode(int m) { return m == SONAR_BF_FD_FP32 || m == SONAR_BF_FD_BF16 || m == SONAR_BF_FD_BF16X3; }
 
 }  // namespace
@@ -1259,6 +1272,7 @@ int sonar_plan_create_tuned(const sonar_plan_desc* desc, int32_t precision, hipS
     if (desc->n_mics >= 32) {
       modes.push_back(SONAR_BF_FD_BF16);
       modes.push_back(SONAR_BF_TD_BF16X2);
+      modes.push_back(SONAR_BF_TD_BF16G);
     }
   }
   // candidates: the MFMA time-domain modes with both workgroup shapes; the frequency-domain modes
@@ -1422,8 +1436,8 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
   if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
-  if (dpos_out && p->bf_mode == SONAR_BF_TD_F16)
-    return fail(SONAR_E_UNSUPPORTED, "TD_F16: gridded delays are piecewise constant in the positions");
+  if (dpos_out && (p->bf_mode == SONAR_BF_TD_F16 || p->bf_mode == SONAR_BF_TD_BF16G))
+    return fail(SONAR_E_UNSUPPORTED, "TD_F16 / TD_BF16G: gridded delays are piecewise constant in the positions");
   if (dx_out && p->NF > (1 << 14))
     return fail(SONAR_E_UNSUPPORTED, "dx_out: FFT length %d above 32768 is not supported for gradients", p->P);
   const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),

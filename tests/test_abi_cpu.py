@@ -77,7 +77,7 @@ def _desc(**over):
     ("fft_len", 1048576, binding.SONAR_E_UNSUPPORTED),  # above 2 x 16 x 16384
     ("gate_begin", 50, binding.SONAR_E_INVALID),      # gate_end 0 -> n0 >= n1
     ("lpf_len", 4, binding.SONAR_E_INVALID),          # even, and no taps
-    ("bf_mode", 9, binding.SONAR_E_INVALID),
+    ("bf_mode", 10, binding.SONAR_E_INVALID),
     ("sample_dtype", 9, binding.SONAR_E_INVALID),
 ])
 def test_bad_descriptor_rejected_on_host(field, value, status):

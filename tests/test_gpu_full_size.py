@@ -11,6 +11,8 @@ Bars, relative L2 over the whole energyscape [D][Q] of a frame: FP32 modes and F
 against plain linear interpolation.  A fault confined to a few directions (one tile of 32, say)
 could hide inside a whole-frame figure, so each direction is also held to ten times its
 mode's bar relative to the frame's RMS direction norm (||E_d - Eo_d|| <= 10 bar ||Eo|| / sqrt(D)).
+TD_BF16G (delays on a 1/256-sample grid) is held to 1e-3 against both its gridded reading and plain
+linear interpolation.
 """
 
 import sys
@@ -31,6 +33,7 @@ MODES = {
     "td_bf16": [("td", 1e-3)],
     "td_bf16x2": [("td", 1e-3)],
     "td_f16": [("td_grid2048", 2e-4), ("td", 3e-4)],
+    "td_bf16g": [("td_grid256", 1e-3), ("td", 1e-3)],
     "fd_fp32": [("fd", 1e-5)],
     "fd_bf16": [("fd", 1e-3)],
     "fd_bf16x3": [("fd", 1e-5)],
@@ -63,7 +66,7 @@ class _OracleCache:
     def get(self, reading):
         if reading not in self.cache:
             w = self.w
-            mode, steps = ("td", 2048) if reading == "td_grid2048" else (reading, None)
+            mode, steps = ("td", int(reading[7:])) if reading.startswith("td_grid") else (reading, None)
             jobs = [pool.Job(x=w.x[f], chirp=w.chirp, mic_pos=w.mic_pos, dirs=w.dirs, fs=w.fs, c=w.c, P=32768,
                              R=w.cfg.decim, band=w.cfg.band, mode=mode, alpha_steps=steps) for f in FRAMES]
             nw = pool.default_workers()

@@ -14,7 +14,8 @@ from workloads import synth
 
 pytestmark = pytest.mark.gpu
 
-BARS = {"td": 1e-5, "td_bf16": 1e-3, "td_bf16x2": 1e-3, "td_f16": 3e-4, "fd_fp32": 1e-5, "fd_bf16x3": 1e-5, "fd_bf16": 1e-3}
+BARS = {"td": 1e-5, "td_bf16": 1e-3, "td_bf16x2": 1e-3, "td_f16": 3e-4, "fd_fp32": 1e-5, "fd_bf16x3": 1e-5, "fd_bf16": 1e-3,
+        "td_bf16g": 1e-3}
 
 
 def rel_l2(a, b):
@@ -61,7 +62,7 @@ def _check_against_oracle(w, E, P, mode, label):
     assert max(errs) <= BARS[mode]
 
 
-@pytest.mark.parametrize("mode", ["td", "td_bf16", "td_bf16x2", "td_f16"])
+@pytest.mark.parametrize("mode", ["td", "td_bf16", "td_bf16x2", "td_f16", "td_bf16g"])
 def test_network_multi(gpu, torch_mod, network, mode):
     torch = torch_mod
     _say(f"case network multi {mode}: 8 sensors x 4 frames")
@@ -92,7 +93,7 @@ def test_network_multi_shared_plan(gpu, torch_mod, network):
         assert torch.equal(E, E1)
 
 
-@pytest.mark.parametrize("mode", ["td_bf16", "td_bf16x2", "td_f16"])
+@pytest.mark.parametrize("mode", ["td_bf16", "td_bf16x2", "td_f16", "td_bf16g"])
 def test_network_graph_replay(gpu, torch_mod, network, mode):
     """The multi call captured once in a graph, replayed on new inputs: every replay equals the
     eager result for the same inputs."""
@@ -128,11 +129,13 @@ def test_tuned_plan(gpu, torch_mod, network, tune):
     torch = torch_mod
     w = network[3]                                     # 16384 samples, 1500 directions
     pl = _plan(gpu, w, tune=tune)
-    allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16", "td_bf16x2", "td_f16"}}
+    allowed = {"fp32": {"td", "fd_fp32", "fd_bf16x3"}, "bf16": {"td", "fd_fp32", "fd_bf16x3", "td_bf16", "fd_bf16", "td_bf16x2", "td_f16", "td_bf16g"}}
     waves = pl.query(gpu.Q_MT_WAVES)
     _say(f"case tuned {tune}: chose {pl.mode} (MFMA workgroup waves: {waves})")
     assert pl.mode in allowed[tune]
     assert waves in ((4, 8) if pl.mode.startswith("td_bf16") or pl.mode == "td_f16" else (0,))
+    if pl.mode.startswith("fd"):
+        assert pl.query(gpu.Q_FD_PHASE_LEN) >= 16
     E = pl.energyscape(torch.from_numpy(w.x).cuda()).cpu().numpy()
     _check_against_oracle(w, E, pl.P, pl.mode, f"tuned {tune}")
 
@@ -207,7 +210,7 @@ def test_tune_cache_persists_the_choice(gpu, torch_mod, network, tmp_path):
 C3_SUBSET = 250   # directions of each 1500-direction energyscape checked against the oracle (all of the 2D grids)
 
 
-@pytest.mark.parametrize("mode", ["td_bf16x2", "fd_bf16"])
+@pytest.mark.parametrize("mode", ["td_bf16x2", "td_bf16g", "fd_bf16"])
 def test_network_fp16_samples(gpu, torch_mod, network, mode):
     """The sensor network as configured: FP16 samples, BF16 matrix-core beamforming (the persistent
     time-domain launch, or the per-bin GEMM with each sensor's 4 frames as its N dimension).  All 32

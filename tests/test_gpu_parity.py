@@ -139,7 +139,8 @@ def test_odd_shapes_match_oracle(gpu, torch_mod, case):
 
 # compute-only bar per mode (against the oracle on the rounded samples) and its oracle reading
 HALF_MODES = {"td": (1e-5, "td", None), "td_bf16x2": (1e-3, "td", None), "td_f16": (3e-4, "td", None),
-              "fd_bf16": (1e-3, "fd", None), "fd_bf16x3": (1e-5, "fd", None), "td_bf16": (1e-3, "td", None)}
+              "fd_bf16": (1e-3, "fd", None), "fd_bf16x3": (1e-5, "fd", None), "td_bf16": (1e-3, "td", None),
+              "td_bf16g": (1e-3, "td", None)}
 
 
 @pytest.mark.parametrize("mode", list(HALF_MODES))

@@ -1,6 +1,7 @@
 """Pins of the oracle's variant readings (CPU): integer-delay delay-and-sum."""
 
 import numpy as np
+import pytest
 
 import oracle as O
 
@@ -144,9 +145,10 @@ def test_gridded_with_one_step_is_nearest():
     assert np.array_equal(O.das_td(y, Dl, n_idx, alpha_steps=1), O.das_td_nearest(y, Dl, n_idx))
 
 
-def test_gridded_equals_linear_for_delays_on_the_grid():
+@pytest.mark.parametrize("steps", [256, 2048])
+def test_gridded_equals_linear_for_delays_on_the_grid(steps):
     rng = np.random.default_rng(32)
-    M, P, D, steps = 4, 128, 6, 2048
+    M, P, D = 4, 128, 6
     y = _analytic_rows(rng, M, P)
     Dl = -(rng.integers(-6, 7, size=(D, M)) + rng.integers(0, steps, size=(D, M)) / steps)
     n_idx = np.arange(-10, 100)
