@@ -16,6 +16,11 @@ from workloads import synth
 pytestmark = pytest.mark.gpu
 
 BARS = {"fd_fp32": 1e-5, "fd_bf16x3": 1e-5, "fd_bf16": 1e-3}
+# The beam spectrum before the envelope: FD_BF16 rounds each steering component to one BF16 term
+# (relative error at most u = 2^-8, RMS at most u / sqrt(3)); away from the steered reflectors the
+# sum over microphones is incoherent, so that relative error carries over to the spectrum instead of
+# averaging down (the envelope's low-pass does average it: 1e-3 per energyscape)
+STAGE_BARS = {"fd_fp32": 1e-5, "fd_bf16x3": 1e-5, "fd_bf16": 2.0 ** -8 / np.sqrt(3.0)}
 
 
 def rel_l2(a, b):
@@ -66,8 +71,8 @@ def test_fd_beam_spectrum_stage(gpu, torch_mod, mode):
         Y = O.matched_filter_spectrum(w.x[f].astype(np.float64), w.chirp, plan.P, w.fs, w.cfg.band)
         Bo = np.fft.fft(O.das_fd(Y, Dl, np.arange(plan.P)), axis=1)[:, k_lo:k_lo + kb]
         err = rel_l2(B[f][:, :kb], Bo)
-        _say(f"  frame {f}: beam spectrum rel L2 = {err:.3e}")
-        assert err <= BARS[mode]
+        _say(f"  frame {f}: beam spectrum rel L2 = {err:.3e} (bar {STAGE_BARS[mode]:.2e})")
+        assert err <= STAGE_BARS[mode]
     # the energyscape from the same plan is the spectrum's inverse + envelope
     assert torch.equal(plan.beamform_envelope(mf), plan.beamform_envelope(mf))
 
