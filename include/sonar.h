@@ -308,7 +308,7 @@ int sonar_energyscape_batch_static(sonar_plan plan, const void* x, int32_t F, fl
  * This is the sensor network's batch (§3: many sensors' measurements are
  * processed by the same GPU service; §5).  All items are validated before any
  * work is enqueued.  Items whose plans are MFMA time-domain modes (TD_BF16,
- * TD_BF16X2, TD_F16) with the FIR envelope, each plan once in the call, run
+ * TD_BF16X2, TD_F16, TD_BF16G) with the FIR envelope, each plan once in the call, run
  * first, on `stream`: their matched filters, then ONE persistent
  * beamformer + envelope launch per group of up to 16 items with the same mode
  * and workgroup shape (a fixed grid of workgroups walks a work list of every
@@ -341,7 +341,7 @@ int sonar_energyscape_multi(const sonar_plan* plans, const void* const* x, const
 /* Precision classes for sonar_plan_create_tuned. */
 enum sonar_precision {
   SONAR_PREC_FP32 = 0,   /* modes within 1e-5 of the definition: TD_LINEAR, FD_FP32, FD_BF16X3  */
-  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, TD_F16, and FD_BF16 and TD_BF16X2 for >= 32 mics */
+  SONAR_PREC_BF16 = 1    /* modes within 1e-3: the above, TD_BF16, TD_F16, and FD_BF16, TD_BF16X2 and TD_BF16G for >= 32 mics */
 };
 
 /*
