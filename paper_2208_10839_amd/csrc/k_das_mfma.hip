@@ -111,6 +111,13 @@ __device__ __forceinline__ void mt_tile(
   const int s0a = s0 & ~7;                   // staged from here: 16-byte aligned rows
   // first sample of the wavefront, as an index into the staged rows
   const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
+  const int sbl = sb + 4 * (lane & 31);      // this lane's first sample (column) in a staged row
+  // Offsets of output tiles 1-3 (128 samples apart), opaque to the compiler: with constant offsets it
+  // pairs the reads of tiles nt and nt + 1 into one two-address LDS read whose registers then have to
+  // be moved into the fragment order (four moves per product); separate reads land in place.
+  int ntoff1 = 128, ntoff2 = 256, ntoff3 = 384;
+  asm volatile("" : "+v"(ntoff1), "+v"(ntoff2), "+v"(ntoff3));
+  auto ntoff = [&](int nt) { return nt == 0 ? 0 : (nt == 1 ? ntoff1 : (nt == 2 ? ntoff2 : ntoff3)); };
   const int plane = MICS * wrow;
   const int bufsz = NPL * plane;             // one staging buffer: NPL planes x MICS rows
   const unsigned short* src = planes + f * fstride + s0a;
@@ -180,32 +187,31 @@ __device__ __forceinline__ void mt_tile(
   // wave-uniform), so only the weight fragments use vector loads.
   const int li = tile * MT_RES + rho;
   const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-  // K-chunk kc: groups 4 kc .. 4 kc + 3 as {mic, first tap} x 4; lanes 0-31 read the first two,
-  // lanes 32-63 the others
-  const int* gs = reinterpret_cast<const int*>(gtab) + static_cast<long long>(li) * gmax * 2;
-  const bool upper = lane >= 32;
+  // K-chunk kc: groups 4 kc .. 4 kc + 3 as {row offset, first tap} x 4, the row offset being the
+  // group's first sample in its staging buffer, (mic - first mic of its group) * wrow + first tap;
+  // lanes 0-31 use the first two groups, lanes 32-63 the others, each lane reading its pair with
+  // one 16-byte vector load
+  const int2* gs = reinterpret_cast<const int2*>(gtab) + static_cast<long long>(li) * gmax + 2 * (lane >> 5);
   const int kend = kcr[(tile * nmc + nmc - 1) * MT_RES + rho].y;
   int kfirst = kcr[tile * nmc * MT_RES + rho].x;
   if (kfirst >= kend) kfirst = 0;            // no chunks at all: harmless in-table prefetch
   struct Operands {
     uint4 ah, al;                            // weight fragments: BF16 hi and lo terms, or one FP16 term
-    int4 glo, ghi;                           // groups of lanes 0-31 and of lanes 32-63 (uniform)
+    int2 g;                                  // row offsets of this lane half's two groups
   };
   // every body issues the same loads (past the last chunk, an in-table one)
   auto load_ops = [&](Operands& o, int kc) {
     const int kl = kc < kend ? kc : kfirst;
     o.ah = wt[kl * 128];
     if constexpr (!W1) o.al = wt[kl * 128 + 64];
-    const int* q = gs + 8 * kl;
-    o.glo = make_int4(q[0], q[1], q[2], q[3]);
-    o.ghi = make_int4(q[4], q[5], q[6], q[7]);
+    const int4 q = *reinterpret_cast<const int4*>(gs + 4 * kl);
+    o.g = make_int2(q.x, q.z);
   };
   Operands op0, op1;
   op0.al = op1.al = make_uint4(0, 0, 0, 0);
   load_ops(op0, kfirst);
   load_ops(op1, kfirst + 1);
   for (int mc = 0; mc < nmc; ++mc) {
-    const int m0 = mc * MICS;
     unsigned short* buf = sm + (mc & 1) * bufsz;
     unsigned short* nbuf = sm + ((mc + 1) & 1) * bufsz;
     const bool next = mc + 1 < nmc;
@@ -215,10 +221,9 @@ __device__ __forceinline__ void mt_tile(
     const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
     const int kmid = (kr.x + kr.y) >> 1;
     auto kbody = [&](int kc, Operands& o) {
-      const int4 g = upper ? o.ghi : o.glo;
-      const unsigned short* p = buf + (g.x - m0) * wrow + g.y + sb + 4 * (lane & 31);
+      const unsigned short* p = buf + o.g.x + sbl;
       // four planes: the two groups are always taps t, t + 4 of one microphone (registers are short)
-      const unsigned short* p2 = NPL == 4 ? p + 4 : buf + (g.z - m0) * wrow + g.w + sb + 4 * (lane & 31);
+      const unsigned short* p2 = NPL == 4 ? p + 4 : buf + o.g.y + sbl;
       if constexpr (NPL == 4) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -236,8 +241,8 @@ __device__ __forceinline__ void mt_tile(
       } else if constexpr (F16) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
-          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
+          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
           cre[nt] = mfma_f16(o.ah, br, cre[nt]);
           cim[nt] = mfma_f16(o.ah, bi, cim[nt]);
         }
@@ -245,16 +250,16 @@ __device__ __forceinline__ void mt_tile(
         // exact single-term BF16 weights (delays on a 1/256 grid): one product per plane
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
-          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
+          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
           cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
           cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
         }
       } else {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + 128 * nt, p2 + 128 * nt);
-          const uint4 bi = lds_frag(p + plane + 128 * nt, p2 + plane + 128 * nt);
+          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
+          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
           cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
           cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
           cre[nt] = mfma_bf16(o.al, br, cre[nt]);

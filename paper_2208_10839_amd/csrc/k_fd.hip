@@ -272,6 +272,14 @@ __device__ __forceinline__ void load_phase(const float2* __restrict__ in, int kb
 // to its own outputs q = t + T i (registers) the low-pass taps j that read phase r:
 //   E[q] = sum_j h[j] |b[n_start + qR + K - 1 - j]|,   tap j reads phase (n_start + qR + K - 1 - j) mod R'.
 // No copy of the whole beam window is kept, so the window length is not bounded by LDS.
+//
+// Costs kept off the vector ALUs:
+//  * the phase rotation exp(+2 pi i k r / P) of slot s, fold f is A_t exp(+2 pi i (s + 16 f) r / (16 R'))
+//    with A_t = exp(+2 pi i t r / P) (one lookup per thread and phase) and the second factor from an
+//    LDS table of 16 R' entries;
+//  * the taps are rearranged by phase class, hc[c][u] = h[c + R' u] (zero past K), and the phase's
+//    magnitudes carry a circular halo of H entries on both sides, so output q reads its taps and
+//    samples as two runs, hc[c_q][u] and mag[a_q - u] for u < ceil(K / R'), with no index wrapping.
 template <int LOGL, int NFOLD>
 __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
     const float2* __restrict__ bspec, const float2* __restrict__ tw_g, const float* __restrict__ taps,
@@ -282,13 +290,21 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   constexpr int LH = FdTw<LOGL>::LH;
   __shared__ float2 buf[S::LDS_ELEMS];
   __shared__ float2 tw[LH + 64];
-  extern __shared__ float hs[];               // K taps
+  extern __shared__ float2 dyn[];             // 16 R' phase factors, then the classed taps
+  float2* tws = dyn;
+  const int nu = (K + Rp - 1) >> logRp;      // taps per phase class
+  float* hc = reinterpret_cast<float*>(dyn + 16 * Rp);
+  const int H = ((K - 1) / 2 >> logRp) + 2;  // halo of the phase magnitudes (samples read past [0, L))
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
   for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
-  for (int j = tid; j < K; j += T) hs[j] = taps[j];
   const float2* twp_hi = tw_g + LH + 64;
   const float2* twp_lo = twp_hi + P / 64 + 1;
+  for (int i = tid; i < 16 * Rp; i += T) tws[i] = cconj(twp(twp_hi, twp_lo, i * (L / 16)));   // exp(+2 pi i i / (16 R'))
+  for (int i = tid; i < Rp * nu; i += T) {
+    const int c = i / nu, u = i - c * nu, j = c + Rp * u;
+    hc[i] = j < K ? taps[j] : 0.f;
+  }
   const float2* in = bspec + fd * kb_pad;
   float2 bin[NFOLD][16];
 #pragma unroll
@@ -302,36 +318,59 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
 #pragma unroll
   for (int i = 0; i < FD_NQ; ++i) acc[i] = 0.f;
   const float invP = 1.0f / static_cast<float>(P);
-  float* mr = reinterpret_cast<float*>(buf);   // |b| of the current phase, index a
+  float* mr = reinterpret_cast<float*>(buf) + H;   // |b| of the current phase, index a in [-H, L + H)
+  __syncthreads();                                  // tables in LDS
 
   for (int r = 0; r < Rp; ++r) {
     float2 v[16];
+    if (r == 0) {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      float2 x = make_float2(0.f, 0.f);
+      for (int s = 0; s < 16; ++s) {
+        float2 x = bin[0][s];
 #pragma unroll
-      for (int f = 0; f < NFOLD; ++f) {
-        const int k = tid + s * (L / 16) + f * L;
-        x = cadd(x, r == 0 ? bin[f][s] : cmul(bin[f][s], cconj(twp(twp_hi, twp_lo, (k * r) & (P - 1)))));
+        for (int f = 1; f < NFOLD; ++f) x = cadd(x, bin[f][s]);
+        v[s] = x;
       }
-      v[s] = x;
+    } else {
+      const float2 at = cconj(twp(twp_hi, twp_lo, (tid * r) & (P - 1)));   // exp(+2 pi i t r / P)
+      const int m16 = 16 * Rp - 1;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        float2 x = cmul(bin[0][s], cmul(at, tws[(s * r) & m16]));
+#pragma unroll
+        for (int f = 1; f < NFOLD; ++f) x = cadd(x, cmul(bin[f][s], cmul(at, tws[((s + 16 * f) * r) & m16])));
+        v[s] = x;
+      }
     }
     fft_lds<LOGL, true>(v, buf, tw, tw + LH, tid);   // starts with a barrier
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < 16; ++i) mr[S::out_index(tid, i)] = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+    for (int i = 0; i < 16; ++i) {
+      const int oi = S::out_index(tid, i);
+      const float m = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+      mr[oi] = m;
+      if (oi < H) mr[oi + L] = m;
+      if (oi >= L - H) mr[oi - L] = m;
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < FD_NQ; ++i) {
       const int q = tid + T * i;
       if (q < Q) {
         const int base = n_start + q * R + K - 1;        // sample read by tap j = 0
-        float a = acc[i];
-        for (int j = (base - r) & (Rp - 1); j < K; j += Rp) {
-          // sample base - j lies in phase r: its index within the phase, modulo L (circular in P)
-          a = fmaf(hs[j], mr[((base - j - r) >> logRp) & (L - 1)], a);
+        const int c = (base - r) & (Rp - 1);               // taps j = c + R' u read this phase
+        const float* hp = hc + c * nu;
+        const float* mp = mr + ((base - c - r) >> logRp);  // sample of tap c, then one back per u
+        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        int u = 0;
+        for (; u + 4 <= nu; u += 4) {
+          s0 = fmaf(hp[u], mp[-u], s0);
+          s1 = fmaf(hp[u + 1], mp[-u - 1], s1);
+          s2 = fmaf(hp[u + 2], mp[-u - 2], s2);
+          s3 = fmaf(hp[u + 3], mp[-u - 3], s3);
         }
-        acc[i] = a;
+        for (; u < nu; ++u) s0 = fmaf(hp[u], mp[-u], s0);
+        acc[i] += (s0 + s1) + (s2 + s3);
       }
     }
   }
@@ -342,8 +381,80 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   }
 }
 
-// Beam window of one phase of one direction: b at n = R' a + r, written to
-// beam[f][d][n - (n0 - hk) mod P] for window positions below G.
+// The same result with the whole beam window in LDS, where it fits (G floats beside the transform):
+// each phase's magnitudes land at their window positions w = (R' a + r - n_start) mod P, w < G, and
+// the low-pass runs once over the window at the end (contiguous taps per range bin, no per-phase
+// work).  Rotations as above.
+template <int LOGL, int NFOLD>
+__global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_envw_kernel(
+    const float2* __restrict__ bspec, const float2* __restrict__ tw_g, const float* __restrict__ taps,
+    float* __restrict__ E, int kb, int kb_pad, int Rp, int P, int n_start, int G, int Q, int R, int K) {
+  using S = FftShape<LOGL>;
+  constexpr int L = S::NF;
+  constexpr int T = S::T;
+  constexpr int LH = FdTw<LOGL>::LH;
+  __shared__ float2 buf[S::LDS_ELEMS];
+  __shared__ float2 tw[LH + 64];
+  extern __shared__ float2 dyn[];             // 16 R' phase factors, K taps, the G-sample window
+  float2* tws = dyn;
+  float* hs = reinterpret_cast<float*>(dyn + 16 * Rp);
+  float* mag = hs + ((K + 3) & ~3);
+  const int tid = threadIdx.x;
+  const long long fd = blockIdx.x;            // f * D + d
+  for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
+  const float2* twp_hi = tw_g + LH + 64;
+  const float2* twp_lo = twp_hi + P / 64 + 1;
+  for (int i = tid; i < 16 * Rp; i += T) tws[i] = cconj(twp(twp_hi, twp_lo, i * (L / 16)));   // exp(+2 pi i i / (16 R'))
+  for (int j = tid; j < K; j += T) hs[j] = taps[j];
+  const float2* in = bspec + fd * kb_pad;
+  float2 bin[NFOLD][16];
+#pragma unroll
+  for (int f = 0; f < NFOLD; ++f)
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k = tid + s * (L / 16) + f * L;
+      bin[f][s] = k < kb ? in[k] : make_float2(0.f, 0.f);
+    }
+  const float invP = 1.0f / static_cast<float>(P);
+  __syncthreads();                            // tables in LDS
+
+  for (int r = 0; r < Rp; ++r) {
+    float2 v[16];
+    if (r == 0) {
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        float2 x = bin[0][s];
+#pragma unroll
+        for (int f = 1; f < NFOLD; ++f) x = cadd(x, bin[f][s]);
+        v[s] = x;
+      }
+    } else {
+      const float2 at = cconj(twp(twp_hi, twp_lo, (tid * r) & (P - 1)));   // exp(+2 pi i t r / P)
+      const int m16 = 16 * Rp - 1;
+#pragma unroll
+      for (int s = 0; s < 16; ++s) {
+        float2 x = cmul(bin[0][s], cmul(at, tws[(s * r) & m16]));
+#pragma unroll
+        for (int f = 1; f < NFOLD; ++f) x = cadd(x, cmul(bin[f][s], cmul(at, tws[((s + 16 * f) * r) & m16])));
+        v[s] = x;
+      }
+    }
+    fft_lds<LOGL, true>(v, buf, tw, tw + LH, tid);   // starts with a barrier
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int w = (Rp * S::out_index(tid, i) + r - n_start) & (P - 1);   // window position of the sample
+      if (w < G) mag[w] = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < Q; q += T) {
+    const float* a = mag + q * R + K - 1;
+    float acc = 0.f;
+    for (int j = 0; j < K; ++j) acc = fmaf(hs[j], a[-j], acc);
+    E[fd * Q + q] = acc;
+  }
+}
+
 template <int LOGL>
 __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_beam_kernel(
     const float2* __restrict__ bspec, const float2* __restrict__ tw_g, float2* __restrict__ beam,
@@ -404,15 +515,30 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
 
 template <int LOGL, int NFOLD>
 hipError_t launch_env_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
-  const size_t smem = static_cast<size_t>(p->K) * sizeof(float);
+  const int nu = (p->K + p->fd_R - 1) / p->fd_R;
+  const size_t smem = static_cast<size_t>(16) * p->fd_R * sizeof(float2) + static_cast<size_t>(p->fd_R) * nu * sizeof(float);
   hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL, NFOLD>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
                      smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, ilog2_host(p->fd_R), p->P,
                      p->n0 - p->hk, p->Q, p->R, p->K);
   return hipGetLastError();
 }
 
+template <int LOGL, int NFOLD>
+hipError_t launch_envw_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  const size_t smem = fd_envw_dyn_lds(p);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fd_ifft_envw_kernel<LOGL, NFOLD>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((fd_ifft_envw_kernel<LOGL, NFOLD>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
+                     smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, p->P, p->n0 - p->hk, p->G,
+                     p->Q, p->R, p->K);
+  return hipGetLastError();
+}
+
 template <int LOGL>
 hipError_t launch_env_f(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
+  if (p->fd_win)
+    return p->fd_nfold == 1 ? launch_envw_t<LOGL, 1>(p, bspec, F, E, s) : launch_envw_t<LOGL, 2>(p, bspec, F, E, s);
   return p->fd_nfold == 1 ? launch_env_t<LOGL, 1>(p, bspec, F, E, s) : launch_env_t<LOGL, 2>(p, bspec, F, E, s);
 }
 
@@ -457,4 +583,15 @@ hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F
     case 14: return launch_beam_t<14>(p, bspec, F, beam, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+// LDS of the window variant of the fused inverse: static (transform buffer, transform twiddles) and
+// dynamic (16 R' phase factors, taps, the beam window)
+size_t fd_envw_static_lds(int logL) {
+  const int L = 1 << logL;
+  return static_cast<size_t>(L + L / 16 + (L / 64 > 0 ? L / 64 : 1) + 64) * sizeof(float2);
+}
+size_t fd_envw_dyn_lds(const sonar_plan_s* p) {
+  return static_cast<size_t>(16) * p->fd_R * sizeof(float2) + static_cast<size_t>((p->K + 3) & ~3) * sizeof(float) +
+         static_cast<size_t>(p->G) * sizeof(float);
 }

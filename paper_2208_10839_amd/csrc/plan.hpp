@@ -54,6 +54,7 @@ struct sonar_plan_s {
   int kb_pad = 0;       // row stride (bins) of the per-direction spectra
   int fd_L = 0, fd_logL = 0, fd_R = 0, fd_nfold = 0;
   bool fd_fused = false;   // the fused inverse + envelope kernel serves this plan (else beam window + envelope)
+  bool fd_win = false;     // fused, with the whole beam window in LDS (the window fits beside the transform)
 
   // time-domain BF16-MFMA beamformer tiling (see k_das_mfma.hip)
   int mt_ntiles = 0, mt_nmc = 0, mt_qc = 0, mt_nqt = 0, mt_wrow = 0, mt_gmax = 0, mt_kcmax = 0;
@@ -85,7 +86,7 @@ struct sonar_plan_s {
   float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
   float2* d_beam = nullptr;    // beam window [max_frames][D][G'] (unfused FD plans, IIR envelope), else a placeholder
   size_t beam_cap = 0;         // complex elements d_beam holds
-  int2* d_mt_g = nullptr;      // TD BF16: tap groups {mic, first tap offset}, [tiles][MT_RES][gmax]
+  int2* d_mt_g = nullptr;      // TD BF16: tap groups {row offset in the staging buffer, first tap}, [tiles][MT_RES][gmax]
   unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][MT_RES][kcmax][hi, lo][64 lanes][8] BF16
   int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][MT_RES]
   int* d_mt_perm = nullptr;    // TD BF16: tile slot -> direction (-1: empty), [tiles][32]
@@ -223,6 +224,7 @@ constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 p
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
 constexpr int FD_XCDS = 8;             // accelerator dies the FD GEMM's sample tiles are grouped by
 constexpr int FD_MAX_TAPS = 4096;       // low-pass taps of the fused FD inverse (LDS)
+constexpr int FD_MAX_PHASES = 64;       // phases R' = P / L of the fused FD inverse (16 R' rotations in LDS)
 
 hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t init_mt_kernel_attributes();
@@ -237,6 +239,8 @@ hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const flo
 hipError_t launch_build_fd_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);
+size_t fd_envw_static_lds(int logL);
+size_t fd_envw_dyn_lds(const sonar_plan_s* p);
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
 // rows = false skips the complex64 rows (MFMA modes whose beamformer reads only the 16-bit planes)

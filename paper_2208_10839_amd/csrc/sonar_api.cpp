@@ -286,7 +286,11 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   std::vector<uint16_t> wtab(static_cast<size_t>(nlist) * kcmax * 2 * 64 * 8, 0);
   for (int li = 0; li < nlist; ++li) {
     const int t = li / MT_RES;
-    for (size_t g = 0; g < groups[li].size(); ++g) gtab[static_cast<size_t>(li) * gmax + g] = groups[li][g];
+    // {row offset in the staging buffer of the group's microphones, first tap}
+    for (size_t g = 0; g < groups[li].size(); ++g) {
+      const int2 gr = groups[li][g];
+      gtab[static_cast<size_t>(li) * gmax + g] = make_int2((gr.x % mics) * p->mt_wrow + gr.y, gr.y);
+    }
     for (int kc = 0; kc < static_cast<int>(groups[li].size()) / MT_GROUPS_PER_CHUNK; ++kc) {
       for (int l = 0; l < 64; ++l) {
         const int d = perm[t * 32 + (l & 31)];
@@ -723,12 +727,19 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     long long L = hard;
     if (pow2_at_least(p->kb) <= FD_FOLD1_MAX_L) L = std::max(L, pow2_at_least(p->kb));
     if (g_fd_logl_hint > 0) L = std::max(hard, 1LL << g_fd_logl_hint);
-    p->fd_fused = L <= (1LL << FD_MAX_LOGL) && L <= p->P && p->K <= FD_MAX_TAPS;
+    // the fused kernel keeps one phase's magnitudes with a circular halo of hk / R' + 2 entries on each
+    // side inside its L-point transform buffer (2 (L + L / 16) floats)
+    const long long halo = L <= p->P ? (p->K - 1) / 2 / (p->P / L) + 2 : 0;
+    p->fd_fused = L <= (1LL << FD_MAX_LOGL) && L <= p->P && p->K <= FD_MAX_TAPS && p->P / L <= FD_MAX_PHASES &&
+                  2 * halo + L <= 2 * (L + L / 16);
     if (!p->fd_fused) L = std::min<long long>(pow2_at_least(need_fold), std::min<long long>(1LL << FD_MAX_LOGL, p->P));
     p->fd_L = static_cast<int>(L);
     p->fd_logL = ilog2(p->fd_L);
     p->fd_R = p->P / p->fd_L;
     p->fd_nfold = (p->kb + p->fd_L - 1) / p->fd_L;
+    // where the beam window fits in LDS beside the transform, the fused kernel keeps it there and runs
+    // the low-pass once at the end; otherwise it adds each phase's taps as the phase is transformed
+    p->fd_win = p->fd_fused && fd_envw_static_lds(p->fd_logL) + fd_envw_dyn_lds(p) <= 160 * 1024;
   }
   const bool fd = !is_td(p);
 
