@@ -8,17 +8,18 @@
 // dense product.  Directions are grouped into tiles of 32 neighbours (plan
 // time, compact in delay space), so within a tile the
 // integer offsets o[d][m] of one microphone span only a few samples.  For
-// each microphone the tile covers that span with groups of 4 consecutive
-// taps; the tap weights form a sparse 32 x K matrix W (two nonzeros per
-// direction and microphone) and the samples a Hankel matrix
+// each microphone the tile covers that span with groups of GT consecutive
+// taps (GT = 2 with two sample planes, 4 with four); the tap weights form a
+// sparse 32 x K matrix W (two nonzeros per direction and microphone) and the
+// samples a Hankel matrix
 //   Y[(m, toff + j)][n] = yhat_m[n + toff + j],
 // so b = W Y runs on v_mfma_f32_32x32x16_bf16 with FP32 accumulation.  A
-// B-operand fragment (8 consecutive K rows of one sample) is two groups:
-// 4 consecutive samples of one row each (with four planes, 8 consecutive
-// samples of one row: the groups come in pairs).  The 32 columns of an output tile
-// are samples 4c + rho of one residue rho, and the tap groups used for
-// residue rho start at t0 with t0 + rho = 0 mod 4, so every group read is
-// one aligned 8-byte load.
+// B-operand fragment (8 consecutive K rows of one sample) is 8 / GT groups of
+// GT consecutive samples of one row each (with four planes, 8 consecutive
+// samples of one row: the groups come in pairs).  The 32 columns of an output
+// tile are samples GT c + rho of one residue rho, and the tap groups used for
+// residue rho start at t0 with t0 + rho = 0 mod GT, so every group read is
+// one aligned 2 GT-byte load.
 //
 // Precision: weights and samples are each carried as two BF16 terms
 // (hi = bf16(v), lo = bf16(v - hi)); the product keeps hi*hi + hi*lo + lo*hi
@@ -75,8 +76,8 @@ __device__ __forceinline__ f32x16 mfma_f16(uint4 a, uint4 b, f32x16 c) {
 }
 
 // Workgroup: one tile of 32 directions x NWAVE * 128 beam samples of one frame.
-// Wavefront wv owns residue rho = wv % MT_RES of the 512-sample block
-// wv / MT_RES: 4 output tiles of 32 samples (4c + rho).  `block` is the tile's index in the
+// Wavefront wv owns residue rho = wv % GT of the 128 GT-sample block wv / GT: 4 output
+// tiles of 32 samples (GT c + rho).  `block` is the tile's index in the
 // plan's grid (the workgroup index of a one-plan launch, a work-list position of the persistent one).
 template <int NWAVE, int NPL, bool F16, bool W1>
 __device__ __forceinline__ void mt_tile(
@@ -89,14 +90,17 @@ __device__ __forceinline__ void mt_tile(
   extern __shared__ unsigned short sm[];    // NPL planes x MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
   constexpr int NS = NWAVE * 128;            // beam samples per workgroup
   constexpr int NT = NWAVE * 64;
-  static_assert(NWAVE % MT_RES == 0, "wavefronts come in groups of MT_RES residues");
+  constexpr int GT = mt_gt_of(NPL);          // taps per group = sample residues per block
+  constexpr int RES = GT;
+  constexpr int GPC = 16 / GT;               // groups per K-chunk
+  static_assert(NWAVE % RES == 0, "wavefronts come in groups of RES residues");
   static_assert(NPL == 4 || NPL == 2, "four split planes or two single ones");
   static_assert(!F16 || NPL == 2, "FP16 samples come as two planes");
   static_assert(!F16 || W1, "FP16 weights are single terms");
   static_assert(!W1 || NPL == 2, "single-term weights go with single-term samples");
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-  const int rho = wv % MT_RES;
+  const int rho = wv % RES;
   // Workgroups are handed to the XCDs round-robin by index: XCD x = index % nx
   // keeps the weights of its own tpx direction tiles in its L2 and runs them
   // back to back on each staged window (frame f, range tile qt).
@@ -110,12 +114,14 @@ __device__ __forceinline__ void mt_tile(
   const int s0 = qt * qc * R;                // first window sample of the tile (a multiple of 4)
   const int s0a = s0 & ~7;                   // staged from here: 16-byte aligned rows
   // first sample of the wavefront, as an index into the staged rows
-  const int sb = (wv / MT_RES) * (32 * 4 * MT_RES) + rho + (s0 - s0a);
-  const int sbl = sb + 4 * (lane & 31);      // this lane's first sample (column) in a staged row
-  // Offsets of output tiles 1-3 (128 samples apart), opaque to the compiler: with constant offsets it
-  // pairs the reads of tiles nt and nt + 1 into one two-address LDS read whose registers then have to
-  // be moved into the fragment order (four moves per product); separate reads land in place.
-  int ntoff1 = 128, ntoff2 = 256, ntoff3 = 384;
+  // (a block of 128 RES samples holds RES residues x 4 output tiles of 32 columns, column c of tile
+  // nt being sample 32 RES nt + RES c + rho)
+  const int sb = (wv / RES) * (32 * 4 * RES) + rho + (s0 - s0a);
+  const int sbl = sb + RES * (lane & 31);    // this lane's first sample (column) in a staged row
+  // Offsets of output tiles 1-3 (32 RES samples apart), opaque to the compiler: with constant offsets
+  // it pairs the reads of tiles nt and nt + 1 into one two-address LDS read whose registers then have
+  // to be moved into the fragment order (four moves per product); separate reads land in place.
+  int ntoff1 = 32 * RES, ntoff2 = 64 * RES, ntoff3 = 96 * RES;
   asm volatile("" : "+v"(ntoff1), "+v"(ntoff2), "+v"(ntoff3));
   auto ntoff = [&](int nt) { return nt == 0 ? 0 : (nt == 1 ? ntoff1 : (nt == 2 ? ntoff2 : ntoff3)); };
   const int plane = MICS * wrow;
@@ -185,27 +191,30 @@ __device__ __forceinline__ void mt_tile(
   // reads that set, so no register copy has to wait for a load (a one-ahead prefetch into a
   // single set needed one).  The group table is read through the scalar cache (its address is
   // wave-uniform), so only the weight fragments use vector loads.
-  const int li = tile * MT_RES + rho;
+  const int li = tile * RES + rho;
   const uint4* wt = wtab + static_cast<long long>(li) * kcmax * 128 + lane;
-  // K-chunk kc: groups 4 kc .. 4 kc + 3 as {row offset, first tap} x 4, the row offset being the
-  // group's first sample in its staging buffer, (mic - first mic of its group) * wrow + first tap;
-  // lanes 0-31 use the first two groups, lanes 32-63 the others, each lane reading its pair with
-  // one 16-byte vector load
-  const int2* gs = reinterpret_cast<const int2*>(gtab) + static_cast<long long>(li) * gmax + 2 * (lane >> 5);
-  const int kend = kcr[(tile * nmc + nmc - 1) * MT_RES + rho].y;
-  int kfirst = kcr[tile * nmc * MT_RES + rho].x;
+  // K-chunk kc: groups GPC kc .. GPC kc + GPC - 1, each as its first sample's offset in the staging
+  // buffer, (mic - first mic of its group) * wrow + first tap; lanes 0-31 use the first half of the
+  // groups, lanes 32-63 the others, each lane reading its half with one vector load
+  const int* gs = reinterpret_cast<const int*>(gtab) + static_cast<long long>(li) * gmax + (GPC / 2) * (lane >> 5);
+  const int kend = kcr[(tile * nmc + nmc - 1) * RES + rho].y;
+  int kfirst = kcr[tile * nmc * RES + rho].x;
   if (kfirst >= kend) kfirst = 0;            // no chunks at all: harmless in-table prefetch
   struct Operands {
     uint4 ah, al;                            // weight fragments: BF16 hi and lo terms, or one FP16 term
-    int2 g;                                  // row offsets of this lane half's two groups
+    int4 g;                                  // offsets of this lane half's groups (two or four)
   };
   // every body issues the same loads (past the last chunk, an in-table one)
   auto load_ops = [&](Operands& o, int kc) {
     const int kl = kc < kend ? kc : kfirst;
     o.ah = wt[kl * 128];
     if constexpr (!W1) o.al = wt[kl * 128 + 64];
-    const int4 q = *reinterpret_cast<const int4*>(gs + 4 * kl);
-    o.g = make_int2(q.x, q.z);
+    if constexpr (GPC == 8) {
+      o.g = *reinterpret_cast<const int4*>(gs + 8 * kl);
+    } else {
+      const int2 q = *reinterpret_cast<const int2*>(gs + 4 * kl);
+      o.g = make_int4(q.x, q.y, 0, 0);
+    }
   };
   Operands op0, op1;
   op0.al = op1.al = make_uint4(0, 0, 0, 0);
@@ -218,12 +227,19 @@ __device__ __forceinline__ void mt_tile(
     __syncthreads();                         // group mc staged; group mc - 1 no longer read
     sgh = sg0;
     kh = k0;
-    const int2 kr = kcr[(tile * nmc + mc) * MT_RES + rho];
+    const int2 kr = kcr[(tile * nmc + mc) * RES + rho];
     const int kmid = (kr.x + kr.y) >> 1;
     auto kbody = [&](int kc, Operands& o) {
       const unsigned short* p = buf + o.g.x + sbl;
       // four planes: the two groups are always taps t, t + 4 of one microphone (registers are short)
       const unsigned short* p2 = NPL == 4 ? p + 4 : buf + o.g.y + sbl;
+      // two planes: four groups of 2 taps, one 4-byte read each
+      const unsigned short* p3 = buf + o.g.z + sbl;
+      const unsigned short* p4 = buf + o.g.w + sbl;
+      auto frag = [&](int off) {
+        return make_uint4(*reinterpret_cast<const unsigned*>(p + off), *reinterpret_cast<const unsigned*>(p2 + off),
+                          *reinterpret_cast<const unsigned*>(p3 + off), *reinterpret_cast<const unsigned*>(p4 + off));
+      };
       if constexpr (NPL == 4) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
@@ -241,8 +257,8 @@ __device__ __forceinline__ void mt_tile(
       } else if constexpr (F16) {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
-          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
+          const uint4 br = frag(ntoff(nt));
+          const uint4 bi = frag(plane + ntoff(nt));
           cre[nt] = mfma_f16(o.ah, br, cre[nt]);
           cim[nt] = mfma_f16(o.ah, bi, cim[nt]);
         }
@@ -250,16 +266,16 @@ __device__ __forceinline__ void mt_tile(
         // exact single-term BF16 weights (delays on a 1/256 grid): one product per plane
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
-          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
+          const uint4 br = frag(ntoff(nt));
+          const uint4 bi = frag(plane + ntoff(nt));
           cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
           cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
         }
       } else {
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
-          const uint4 br = lds_frag(p + ntoff(nt), p2 + ntoff(nt));
-          const uint4 bi = lds_frag(p + plane + ntoff(nt), p2 + plane + ntoff(nt));
+          const uint4 br = frag(ntoff(nt));
+          const uint4 bi = frag(plane + ntoff(nt));
           cre[nt] = mfma_bf16(o.ah, br, cre[nt]);
           cim[nt] = mfma_bf16(o.ah, bi, cim[nt]);
           cre[nt] = mfma_bf16(o.al, br, cre[nt]);
@@ -293,7 +309,7 @@ __device__ __forceinline__ void mt_tile(
   __syncthreads();
 
   // |b| of the tile into LDS: lane holds rows 8(v/4) + 4(lane/32) + v%4 (directions) of
-  // column lane%32 (window sample sw + 128 nt + 4 column) for each output tile.
+  // column lane%32 (window sample sw + 32 RES nt + RES column) for each output tile.
   //  * two sample planes (FIR16): [32][NSP16] FP16 of 2^e |b|, e per workgroup from the tile's
   //    largest |b| (so every scaled value is below 2^14); the low-pass runs on FP16 MFMA with
   //    the taps (scaled by the plan's power of two) as two FP16 terms, and E is scaled back by
@@ -305,7 +321,7 @@ __device__ __forceinline__ void mt_tile(
   unsigned int* bw = reinterpret_cast<unsigned int*>(sm);
   unsigned short* b16 = reinterpret_cast<unsigned short*>(sm);
   float* wmax = reinterpret_cast<float*>(permL + 32);   // [NWAVE] largest |b| per wavefront
-  const int sw = (wv / MT_RES) * (32 * 4 * MT_RES) + rho;
+  const int sw = (wv / RES) * (32 * 4 * RES) + rho;
   float inv_scale = 1.f;
   if constexpr (FIR16) {
     float mx = 0.f;
@@ -331,7 +347,7 @@ __device__ __forceinline__ void mt_tile(
     inv_scale = ldexpf(1.0f, -e);
 #pragma unroll
     for (int nt = 0; nt < 4; ++nt) {
-      const int s = sw + 128 * nt + 4 * (lane & 31);
+      const int s = sw + 32 * RES * nt + RES * (lane & 31);
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
         const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
@@ -348,7 +364,7 @@ __device__ __forceinline__ void mt_tile(
   } else {
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
-    const int s = sw + 128 * nt + 4 * (lane & 31);
+    const int s = sw + 32 * RES * nt + RES * (lane & 31);
 #pragma unroll
     for (int v = 0; v < 16; v += 2) {
       const int dl = 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);   // dl + 1 for v + 1

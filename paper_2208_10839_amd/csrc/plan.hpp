@@ -86,9 +86,9 @@ struct sonar_plan_s {
   float2* d_fdstep = nullptr;  // FD: per-bin steering rotation exp(-2 pi i Dl / P), [D][M]
   float2* d_beam = nullptr;    // beam window [max_frames][D][G'] (unfused FD plans, IIR envelope), else a placeholder
   size_t beam_cap = 0;         // complex elements d_beam holds
-  int2* d_mt_g = nullptr;      // TD BF16: tap groups {row offset in the staging buffer, first tap}, [tiles][MT_RES][gmax]
-  unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][MT_RES][kcmax][hi, lo][64 lanes][8] BF16
-  int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][MT_RES]
+  int* d_mt_g = nullptr;       // TD BF16: tap groups as their first sample's offset in the staging buffer, [tiles][GT][gmax]
+  unsigned short* d_mt_w = nullptr;   // TD BF16: weight fragments, [tiles][GT][kcmax][hi, lo][64 lanes][8] BF16
+  int2* d_mt_kcr = nullptr;    // TD BF16: K-chunk range per microphone group, [tiles][nmc][GT]
   int* d_mt_perm = nullptr;    // TD BF16: tile slot -> direction (-1: empty), [tiles][32]
   unsigned short* d_mt_fir = nullptr;   // TD BF16: low-pass B fragments, [K-steps][hi, lo][64 lanes][8] BF16
   void* d_aux = nullptr;       // plan-build scratch
@@ -191,7 +191,7 @@ __host__ __device__ inline int fd_tw_len(int L, int P) { return (L / 64 > 0 ? L 
 
 // time-domain beamformer on BF16 MFMA: tiles of 32 directions x nwave * 128
 // beam samples per workgroup; wavefront w computes the samples of residue
-// w % MT_RES (mod MT_RES) in block w / MT_RES; MT_MICS microphones staged at a time.
+// w % GT (mod GT, the tap-group width below) in block w / GT; MT_MICS microphones staged at a time.
 // Plans take 4-wave workgroups (two share a CU) and fall back to 8 waves when the
 // staged window of a wide aperture does not fit the 4-wave staging budget.
 constexpr int DELAY_MARGIN = 3;   // samples of delay range kept beyond the geometry's bound
@@ -205,9 +205,14 @@ constexpr int MT_MICS = 8;      // microphones staged per group with four planes
 // microphones staged per group: the staged bytes per group stay the same for both plane counts
 inline int mt_mics(const sonar_plan_s* p) { return mt_planes(p) == 2 ? 2 * MT_MICS : MT_MICS; }
 constexpr int MT_SPT = 10;   // 16-byte staging chunks per thread: planes x MT_MICS rows x wrow / 8 <= MT_SPT x threads
-constexpr int MT_RES = 4;
-constexpr int MT_GROUP_TAPS = 4;         // consecutive taps of one microphone per tap group (one 8-byte read)
-constexpr int MT_GROUPS_PER_CHUNK = 4;   // tap groups per 16-row K-chunk of the MFMA
+// Tap groups of the MFMA beamformer: GT consecutive taps of one microphone per group (one 2 GT-byte
+// LDS read per output column), GT sample residues per block (a column reads its group where sample +
+// first tap = 0 mod GT, so every read is aligned), 16 / GT groups per 16-row K-chunk.  Two sample
+// planes take groups of 2 (fewer taps issued past each microphone's span: about 4.1x the two taps a
+// direction needs instead of 5.0x with groups of 4 at 32 x 16384 x 1500); four planes keep groups of
+// 4 in pairs (taps t, t + 4 read as 8 consecutive samples).
+__host__ __device__ constexpr int mt_gt_of(int npl) { return npl == 2 ? 2 : 4; }
+inline int mt_gt(const sonar_plan_s* p) { return mt_gt_of(mt_planes(p)); }
 constexpr int MT_XCDS = 8;      // accelerator dies (each with its own L2) that workgroups are spread over
 // |b| rows in LDS for the matrix-core low-pass (one 32-bit word per sample): nwave * 128
 // samples + a zeroed tail, padded so that a row is 16 bytes past a multiple of 256 (bank spread)

@@ -201,12 +201,13 @@ uint16_t to_bf16_bits(float v) {
 // Tiles of the BF16-MFMA time-domain beamformer, built from the device's FP64
 // delay table: directions cut into tiles of 32 that are compact in delay space
 // (a k-d split of the coordinates of delay_space_coords).  Beam samples are
-// split by residue mod MT_RES; for residue rho, per tile and microphone the
-// span of integer offsets is covered by groups of 4 taps whose first tap t0
-// has t0 + rho = 0 mod MT_RES, so every sample group read by the kernel
-// is one 8-byte aligned load (four planes: groups in pairs, one microphone's
-// taps t, t + 4, read as 8 consecutive samples).  Four groups are one K-chunk of
-// v_mfma_f32_32x32x16_bf16 (K rows 4 i .. 4 i + 3 from group i), whose A
+// split by residue mod GT (the group width: 2 taps with two sample planes, 4
+// with four); for residue rho, per tile and microphone the span of integer
+// offsets is covered by groups of GT taps whose first tap t0 has
+// t0 + rho = 0 mod GT, so every sample group read by the kernel is one aligned
+// 2 GT-byte load (four planes: groups in pairs, one microphone's taps t, t + 4,
+// read as 8 consecutive samples).  16 / GT groups are one K-chunk of
+// v_mfma_f32_32x32x16_bf16 (K rows GT i .. GT i + GT - 1 from group i), whose A
 // fragments (tap weights as BF16 hi and lo terms) are stored in lane order.
 int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, const std::vector<double>& taps,
                     hipStream_t stream, size_t* total) {
@@ -238,21 +239,22 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   const int nt = (D + 31) / 32, nmc = (M + mics - 1) / mics;
   std::vector<int> perm(static_cast<size_t>(nt) * 32, -1);
   for (int i = 0; i < D; ++i) perm[i] = order[i];
-  const int nlist = nt * MT_RES;   // group list per (tile, residue)
+  const int res = mt_gt(p), gtaps = mt_gt(p), gpc = 16 / mt_gt(p);   // residues, taps per group, groups per chunk
+  const int nlist = nt * res;   // group list per (tile, residue)
   std::vector<std::vector<int2>> groups(nlist);
   std::vector<std::vector<char>> pad(nlist);   // zero-weight group completing a K-chunk
-  std::vector<int2> kcr(static_cast<size_t>(nt) * nmc * MT_RES);
-  int gmax = MT_GROUPS_PER_CHUNK;
+  std::vector<int2> kcr(static_cast<size_t>(nt) * nmc * res);
+  int gmax = gpc;
   const bool f16 = mt_f16(p);
   const bool w1 = mt_w1(p);              // gridded delays: one exact 16-bit weight term
   const double steps = static_cast<double>(mt_grid_steps(p));
   // taps per microphone are allotted in runs of 4 (two planes) or 8 (four planes: the
   // kernel reads a group pair as 8 consecutive samples)
-  const int span = mt_planes(p) == 4 ? 2 * MT_GROUP_TAPS : MT_GROUP_TAPS;
+  const int span = mt_planes(p) == 4 ? 2 * gtaps : gtaps;
   for (int t = 0; t < nt; ++t) {
-    for (int rho = 0; rho < MT_RES; ++rho) {
-      std::vector<int2>& gl = groups[t * MT_RES + rho];
-      std::vector<char>& pl = pad[t * MT_RES + rho];
+    for (int rho = 0; rho < res; ++rho) {
+      std::vector<int2>& gl = groups[t * res + rho];
+      std::vector<char>& pl = pad[t * res + rho];
       for (int mc = 0; mc < nmc; ++mc) {
         const int m0 = mc * mics, m1 = std::min(M, m0 + mics);
         const int g0 = static_cast<int>(gl.size());
@@ -264,41 +266,41 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
             rmin = std::min(rmin, dtab[static_cast<size_t>(d) * M + m].x);
             rmax = std::max(rmax, dtab[static_cast<size_t>(d) * M + m].x);
           }
-          const int t0 = rmin - (rmin + rho) % MT_RES;   // rmin >= 0, so t0 + rho >= 0
+          const int t0 = rmin - (rmin + rho) % res;   // rmin >= 0, so t0 + rho >= 0
           const int ng = (rmax + 2 - t0 + span - 1) / span;   // taps t0 .. rmax + 1
-          for (int g = 0; g < ng * (span / MT_GROUP_TAPS); ++g) {
-            gl.push_back(make_int2(m, t0 + MT_GROUP_TAPS * g));
+          for (int g = 0; g < ng * (span / gtaps); ++g) {
+            gl.push_back(make_int2(m, t0 + gtaps * g));
             pl.push_back(0);
           }
         }
-        while ((gl.size() - g0) % MT_GROUPS_PER_CHUNK) {
-          gl.push_back(make_int2(m0, (MT_RES - rho) % MT_RES));
+        while ((gl.size() - g0) % gpc) {
+          gl.push_back(make_int2(m0, (res - rho) % res));
           pl.push_back(1);
         }
-        kcr[(static_cast<size_t>(t) * nmc + mc) * MT_RES + rho] =
-            make_int2(g0 / MT_GROUPS_PER_CHUNK, static_cast<int>(gl.size()) / MT_GROUPS_PER_CHUNK);
+        kcr[(static_cast<size_t>(t) * nmc + mc) * res + rho] =
+            make_int2(g0 / gpc, static_cast<int>(gl.size()) / gpc);
       }
       gmax = std::max(gmax, static_cast<int>(gl.size()));
     }
   }
-  const int kcmax = gmax / MT_GROUPS_PER_CHUNK;
-  std::vector<int2> gtab(static_cast<size_t>(nlist) * gmax, make_int2(0, 0));
+  const int kcmax = gmax / gpc;
+  std::vector<int> gtab(static_cast<size_t>(nlist) * gmax, 0);
   std::vector<uint16_t> wtab(static_cast<size_t>(nlist) * kcmax * 2 * 64 * 8, 0);
   for (int li = 0; li < nlist; ++li) {
-    const int t = li / MT_RES;
-    // {row offset in the staging buffer of the group's microphones, first tap}
+    const int t = li / res;
+    // the group's first sample: its microphone's row in the staging buffer, plus the first tap
     for (size_t g = 0; g < groups[li].size(); ++g) {
       const int2 gr = groups[li][g];
-      gtab[static_cast<size_t>(li) * gmax + g] = make_int2((gr.x % mics) * p->mt_wrow + gr.y, gr.y);
+      gtab[static_cast<size_t>(li) * gmax + g] = (gr.x % mics) * p->mt_wrow + gr.y;
     }
-    for (int kc = 0; kc < static_cast<int>(groups[li].size()) / MT_GROUPS_PER_CHUNK; ++kc) {
+    for (int kc = 0; kc < static_cast<int>(groups[li].size()) / gpc; ++kc) {
       for (int l = 0; l < 64; ++l) {
         const int d = perm[t * 32 + (l & 31)];
         for (int j = 0; j < 8; ++j) {
-          // K row 8 (l / 32) + j: tap j % 4 of group 4 kc + 2 (l / 32) + j / 4
-          const int gi = MT_GROUPS_PER_CHUNK * kc + 2 * (l >> 5) + j / MT_GROUP_TAPS;
+          // K row 8 (l / 32) + j: tap j % GT of group (16 / GT) kc + (8 / GT) (l / 32) + j / GT
+          const int gi = gpc * kc + (gpc / 2) * (l >> 5) + j / gtaps;
           const int2 g = groups[li][gi];
-          const int tap = g.y + j % MT_GROUP_TAPS;
+          const int tap = g.y + j % gtaps;
           float w = 0.f;
           if (d >= 0 && !pad[li][gi]) {
             const int4 en = dtab[static_cast<size_t>(d) * M + g.x];
@@ -374,12 +376,12 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   }
   p->mt_gmax = gmax;
   p->mt_kcmax = kcmax;
-  // every (tile, residue) K-chunk runs on nwave / MT_RES wavefronts x 4 output tiles
+  // every (tile, residue) K-chunk runs on nwave / GT wavefronts x 4 output tiles
   long long chunks = 0;
-  for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / MT_GROUPS_PER_CHUNK;
+  for (int li = 0; li < nlist; ++li) chunks += static_cast<long long>(groups[li].size()) / gpc;
   // per K-chunk and 32 x 32 output tile: 6 MFMAs (split samples), 4 (single-term samples) or 2 (FP16)
   const int mfma_per_chunk = mt_planes(p) == 4 ? 6 : (w1 ? 2 : 4);
-  p->mt_flop_per_frame = chunks * (p->mt_nwave / MT_RES) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
+  p->mt_flop_per_frame = chunks * (p->mt_nwave / res) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   // low-pass: 3 MFMAs per K-step and column block (BF16 hi/lo x hi/lo), 2 with two sample planes
   // (FP16 taps hi + lo times one FP16 term of |b|)
   const int fir_mfma = mt_planes(p) == 2 ? 2 : 3;
@@ -397,7 +399,7 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
     (void)hipGetLastError();
     return fail(SONAR_E_NOMEM, "device allocation of the MFMA beamformer tables failed");
   }
-  e = hipMemcpy(p->d_mt_g, gtab.data(), gtab.size() * sizeof(int2), hipMemcpyHostToDevice);
+  e = hipMemcpy(p->d_mt_g, gtab.data(), gtab.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_w, wtab.data(), wtab.size() * sizeof(uint16_t), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_kcr, kcr.data(), kcr.size() * sizeof(int2), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(p->d_mt_perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice);
