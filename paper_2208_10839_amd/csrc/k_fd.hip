@@ -79,13 +79,21 @@ __device__ __forceinline__ void split_bf16x8(const float (&v)[8], bf16x8& hi, bf
 // exp(-2 pi i Dl / P) taken from the plan table (at most 7 FP32 rotations).
 constexpr int CHB = 8;                  // bins per chunk
 constexpr int YS_FRAME = CHB * 32 + 2;  // float2 per frame row in LDS (padded)
+// BF16 modes: the staged samples are split once into four BF16 planes (re hi, re lo, im hi, im lo),
+// [plane][frame][bin][mic] with a 16-byte pad per frame row, so every wavefront reads its operands as
+// 16-byte fragments instead of converting them itself
+constexpr int YB_FRAME = CHB * 32 + 8;  // 16-bit words per frame row
+constexpr int YB_PLANE = FD_GEMM_FRAMES * YB_FRAME;
 
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fd_gemm_kernel(
     const float2* __restrict__ band, const double* __restrict__ dl, const float2* __restrict__ step,
     float2* __restrict__ bspec, int F, int D, int M, int kb, int kb_pad, int k_lo, int P, int nbt, int ndt,
     int nyt) {
-  __shared__ float2 ys[FD_GEMM_FRAMES * YS_FRAME];
+  constexpr bool SPLIT = MODE != MODE_FP32;   // samples as BF16 hi + lo terms
+  __shared__ float2 ys[SPLIT ? 1 : FD_GEMM_FRAMES * YS_FRAME];
+  __shared__ uint4 ybv[SPLIT ? 4 * YB_PLANE / 8 : 1];
+  unsigned short* yb = reinterpret_cast<unsigned short*>(ybv);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
   // Workgroups go to the XCDs round-robin by index.  All ndt direction tiles of one sample tile
@@ -102,6 +110,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const int d_st = dt * FD_GEMM_DIRS + wv * 16 + r16;    // direction this lane steers
   const bool d_ok = d_st < D;
   const double invP = 1.0 / static_cast<double>(P);
+  const float invM = 1.0f / static_cast<float>(M);   // the array mean's 1/M (one rounding, as the steering's)
   const int f_out = ft * FD_GEMM_FRAMES + r16;
 
   for (int k0 = bt * FD_GEMM_BINS; k0 < (bt + 1) * FD_GEMM_BINS && k0 < kb; k0 += CHB) {
@@ -133,27 +142,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int i = 0; i < 16; ++i) {
           const int e = threadIdx.x + 256 * i;
           const int f = e / (CHB * 32), b = (e / 32) % CHB, m = e % 32;
-          ys[f * YS_FRAME + b * 32 + m] = y[i];
+          if constexpr (SPLIT) {
+            const __bf16 rh = static_cast<__bf16>(y[i].x), ih = static_cast<__bf16>(y[i].y);
+            const __bf16 rl = static_cast<__bf16>(y[i].x - static_cast<float>(rh));
+            const __bf16 il = static_cast<__bf16>(y[i].y - static_cast<float>(ih));
+            const int at = f * YB_FRAME + b * 32 + m;
+            yb[at] = __builtin_bit_cast(unsigned short, rh);
+            yb[YB_PLANE + at] = __builtin_bit_cast(unsigned short, rl);
+            yb[2 * YB_PLANE + at] = __builtin_bit_cast(unsigned short, ih);
+            yb[3 * YB_PLANE + at] = __builtin_bit_cast(unsigned short, il);
+          } else {
+            ys[f * YS_FRAME + b * 32 + m] = y[i];
+          }
         }
       }
       __syncthreads();
+      // the delays and rotations of this lane's 8 microphones, all loads issued before any is used
+      // (a slot outside the array reads a valid entry and is zeroed)
       float phr[8], phi[8], str[8], sti[8];
+      double dlv[8];
+      float2 stv[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
-        phr[j] = phi[j] = str[j] = sti[j] = 0.f;
-        if (d_ok && m < M) {
-          const double Dl = dl[static_cast<long long>(d_st) * M + m];
-          const double tt = static_cast<double>(k_lo + k0) * Dl * invP;
-          const float fr = static_cast<float>(tt - floor(tt));
-          float s, c;
-          sincospif(-2.0f * fr, &s, &c);
-          phr[j] = c / static_cast<float>(M);
-          phi[j] = s / static_cast<float>(M);
-          const float2 st = step[static_cast<long long>(d_st) * M + m];
-          str[j] = st.x;
-          sti[j] = st.y;
-        }
+        const long long at = static_cast<long long>(d_ok ? d_st : 0) * M + (m < M ? m : 0);
+        dlv[j] = dl[at];
+        stv[j] = step[at];
+      }
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = mc + (MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j);
+        const double tt = static_cast<double>(k_lo + k0) * dlv[j] * invP;
+        const float fr = static_cast<float>(tt - floor(tt));
+        float s, c;
+        sincospif(-2.0f * fr, &s, &c);
+        const bool ok = d_ok && m < M;
+        phr[j] = ok ? c * invM : 0.f;
+        phi[j] = ok ? s * invM : 0.f;
+        str[j] = ok ? stv[j].x : 0.f;
+        sti[j] = ok ? stv[j].y : 0.f;
       }
 #pragma unroll
       for (int b = 0; b < CHB; ++b) {
@@ -167,11 +194,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           const float ni = phr[j] * sti[j] + phi[j] * str[j];
           phr[j] = nr;
           phi[j] = ni;
-          const int m = MODE == MODE_FP32 ? 4 * j + grp : 8 * grp + j;
-          const float2 y = ys[r16 * YS_FRAME + b * 32 + m];
-          yr[j] = y.x;
-          yi[j] = y.y;
+          if constexpr (!SPLIT) {
+            const float2 y = ys[r16 * YS_FRAME + b * 32 + 4 * j + grp];
+            yr[j] = y.x;
+            yi[j] = y.y;
+          }
         }
+        // BF16 modes: this lane's 8 microphones of frame r16, bin b, from each plane
+        const unsigned short* yp = yb + r16 * YB_FRAME + b * 32 + 8 * grp;
+        auto yfrag = [&](int plane) { return *reinterpret_cast<const bf16x8*>(yp + plane * YB_PLANE); };
         if constexpr (MODE == MODE_FP32) {
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
@@ -183,9 +214,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         } else if constexpr (MODE == MODE_BF16) {
           // steering in one BF16 term, samples in two (hi + lo): two products
           const bf16x8 Ar = to_bf16x8(ar), Ai = to_bf16x8(ai), nAi = to_bf16x8(nai);
-          bf16x8 Yrh, Yrl, Yih, Yil;
-          split_bf16x8(yr, Yrh, Yrl);
-          split_bf16x8(yi, Yih, Yil);
+          const bf16x8 Yrh = yfrag(0), Yrl = yfrag(1), Yih = yfrag(2), Yil = yfrag(3);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrh, cr[b], 0, 0, 0);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yrl, cr[b], 0, 0, 0);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(nAi, Yih, cr[b], 0, 0, 0);
@@ -195,12 +224,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yih, ci[b], 0, 0, 0);
           ci[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ar, Yil, ci[b], 0, 0, 0);
         } else {
-          bf16x8 Arh, Arl, Aih, Ail, nAih, nAil, Yrh, Yrl, Yih, Yil;
+          bf16x8 Arh, Arl, Aih, Ail, nAih, nAil;
           split_bf16x8(ar, Arh, Arl);
           split_bf16x8(ai, Aih, Ail);
           split_bf16x8(nai, nAih, nAil);
-          split_bf16x8(yr, Yrh, Yrl);
-          split_bf16x8(yi, Yih, Yil);
+          const bf16x8 Yrh = yfrag(0), Yrl = yfrag(1), Yih = yfrag(2), Yil = yfrag(3);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrh, cr[b], 0, 0, 0);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arh, Yrl, cr[b], 0, 0, 0);
           cr[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Arl, Yrh, cr[b], 0, 0, 0);
