@@ -141,9 +141,26 @@ struct FftShape {
 // Full transform.  v holds the input in the contract layout and receives the
 // output; lds must hold LDS_ELEMS float2 and is clobbered.  Starts with a
 // barrier, so the caller may still be reading lds when it calls this.
-template <int LOGNF, bool INV>
+// With TW1 (NF >= 256), the twiddles of the second pass (Ns = 16), which
+// depend only on k = tid mod 16 and r, are read from tw1[16 r + k] (the same
+// products, precomputed by the caller, see pass1_twiddles) instead of being
+// rebuilt from the two-level table; k runs fastest, so the 16 values of k a
+// wavefront reads lie in consecutive banks.
+// With TWR, the twiddles of the third radix-16 pass (Ns = 256) and of the final
+// radix-2/4/8 pass, which depend only on the thread, come from twr (filled by
+// fft_thread_twiddles, e.g. once for many transforms and kept in registers).
+template <int LOGNF>
+struct FftTwr {
+  using S = FftShape<LOGNF>;
+  static constexpr int N_P2 = S::N16 >= 3 ? 15 : 0;
+  static constexpr int N_LAST = S::RL > 1 ? (16 / S::RL) * (S::RL - 1) : 0;
+  static constexpr int N = N_P2 + N_LAST > 0 ? N_P2 + N_LAST : 1;
+};
+
+template <int LOGNF, bool INV, bool TW1 = false, bool TWR = false>
 __device__ __forceinline__ void fft_lds(float2 (&v)[16], float2* lds, const float2* tw_hi,
-                                        const float2* tw_lo, int tid) {
+                                        const float2* tw_lo, int tid, const float2* tw1 = nullptr,
+                                        const float2* twr = nullptr) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -162,8 +179,16 @@ __device__ __forceinline__ void fft_lds(float2 (&v)[16], float2* lds, const floa
       for (int r = 0; r < 16; ++r) v[r] = lds[padi(tid + r * (NF / 16))];
       const int k = tid & (Ns - 1);
       const int estep = k * (NF / (Ns * 16));
+      if (TW1 && p == 1) {
 #pragma unroll
-      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<INV>(tw_hi, tw_lo, estep * r));
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw1[16 * r + k]);
+      } else if (TWR && p == 2) {
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twr[r - 1]);
+      } else {
+#pragma unroll
+        for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], twiddle<INV>(tw_hi, tw_lo, estep * r));
+      }
       dft16<INV>(v);
       if (S::RL == 1 && p == S::N16 - 1) return;   // last pass: outputs stay in registers
       __syncthreads();
@@ -185,10 +210,48 @@ __device__ __forceinline__ void fft_lds(float2 (&v)[16], float2* lds, const floa
       for (int b = 0; b < 16 / R; ++b) {
         const int j = tid + b * T;                // Ns * R == NF, so k == j
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[b * R + r] = cmul(v[b * R + r], twiddle<INV>(tw_hi, tw_lo, j * r));
+        for (int r = 1; r < R; ++r) {
+          if constexpr (TWR)
+            v[b * R + r] = cmul(v[b * R + r], twr[FftTwr<LOGNF>::N_P2 + b * (R - 1) + r - 1]);
+          else
+            v[b * R + r] = cmul(v[b * R + r], twiddle<INV>(tw_hi, tw_lo, j * r));
+        }
         dftR<R, INV>(&v[b * R]);
       }
     }
+  }
+}
+
+// The table fft_lds<LOGNF, INV, true> reads: entry 16 r + k is the twiddle of
+// pass 1 (Ns = 16) for k = tid mod 16 and r, exactly as that pass would build
+// it from the two-level table (tw_hi, tw_lo may be the global copies).
+template <int LOGNF, bool INV>
+__device__ __forceinline__ void pass1_twiddles(float2* tw1, const float2* tw_hi, const float2* tw_lo, int tid,
+                                               int nthreads) {
+  constexpr int NF = 1 << LOGNF;
+  static_assert(NF >= 256, "pass 1 exists for NF >= 256");
+  for (int i = tid; i < 256; i += nthreads) tw1[i] = twiddle<INV>(tw_hi, tw_lo, (i & 15) * (NF / 256) * (i >> 4));
+}
+
+// The per-thread twiddles fft_lds<LOGNF, INV, TW1, true> reads, exactly as the
+// passes would build them.
+template <int LOGNF, bool INV>
+__device__ __forceinline__ void fft_thread_twiddles(float2 (&twr)[FftTwr<LOGNF>::N], const float2* tw_hi,
+                                                    const float2* tw_lo, int tid) {
+  using S = FftShape<LOGNF>;
+  constexpr int NF = S::NF;
+  if constexpr (S::N16 >= 3) {
+    const int estep = (tid & 255) * (NF / 4096);
+#pragma unroll
+    for (int r = 1; r < 16; ++r) twr[r - 1] = twiddle<INV>(tw_hi, tw_lo, estep * r);
+  }
+  if constexpr (S::RL > 1) {
+    constexpr int R = S::RL;
+#pragma unroll
+    for (int b = 0; b < 16 / R; ++b)
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        twr[FftTwr<LOGNF>::N_P2 + b * (R - 1) + r - 1] = twiddle<INV>(tw_hi, tw_lo, (tid + b * S::T) * r);
   }
 }
 

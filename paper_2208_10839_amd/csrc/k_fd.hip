@@ -25,6 +25,7 @@
 #include "fft_lds.hpp"
 #include "plan.hpp"
 
+
 using namespace fftk;
 
 namespace {
@@ -43,7 +44,7 @@ constexpr int MODE_BF16 = SONAR_BF_FD_BF16;
 constexpr int MODE_BF16X3 = SONAR_BF_FD_BF16X3;
 
 // ---------------------------------------------------------------------------
-// Per-bin GEMM.  Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS bins,
+// Per-bin GEMM.  Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS_WG bins,
 // up to 16 frames.  Lane l builds the steering values of direction l % 16 of
 // its wavefront for 8 microphones and supplies the samples of frame l % 16 for
 // the same 8 microphones, matching the MFMA operand layouts:
@@ -71,13 +72,52 @@ __device__ __forceinline__ void split_bf16x8(const float (&v)[8], bf16x8& hi, bf
   }
 }
 
-// Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS bins in chunks of 8,
+// Lane exchanges inside a quad (4 consecutive lanes) by DPP: the value of lane q ^ 1, resp. q ^ 2.
+__device__ __forceinline__ float dpp_xor1(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_xor2(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x4E, 0xF, 0xF, true));
+}
+
+// 4 x 4 transpose of 16-byte elements over the lanes of a quad: afterwards lane q holds in e[j] what
+// lane j held in e[q].  Two butterfly steps; in step b a lane takes from lane q ^ b the element p ^ b
+// for every p whose bit b differs from q's.  All four lanes of every quad must be active.
+__device__ __forceinline__ void quad_transpose(f32x4 (&e)[4], int q) {
+  const bool o1 = (q & 1) != 0, o2 = (q & 2) != 0;
+#pragma unroll
+  for (int p = 0; p < 4; p += 2) {
+    f32x4 lo = e[p], hi = e[p + 1];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float plo = dpp_xor1(lo[c]), phi = dpp_xor1(hi[c]);
+      e[p][c] = o1 ? phi : lo[c];
+      e[p + 1][c] = o1 ? hi[c] : plo;
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    f32x4 lo = e[p], hi = e[p + 2];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const float plo = dpp_xor2(lo[c]), phi = dpp_xor2(hi[c]);
+      e[p][c] = o2 ? phi : lo[c];
+      e[p + 2][c] = o2 ? hi[c] : plo;
+    }
+  }
+}
+
+// Workgroup: 4 wavefronts x 16 directions, FD_GEMM_BINS_WG bins in chunks of 8,
 // 16 frames.  The samples of a chunk (16 frames x 8 bins x 32 microphones)
 // are staged once in LDS and shared by the four wavefronts.  Steering values
 // restart at every chunk from an anchor exp(-2 pi i k Dl / P) whose phase is
 // reduced in FP64, then advance bin by bin with the per-(d, m) rotation
 // exp(-2 pi i Dl / P) taken from the plan table (at most 7 FP32 rotations).
 constexpr int CHB = 8;                  // bins per chunk
+// bins per workgroup: one chunk, so a workgroup's stores drain while other workgroups compute (a
+// workgroup that looped over chunks would wait for its stores before loading the next chunk's samples,
+// since loads and stores retire in issue order)
+constexpr int FD_GEMM_BINS_WG = CHB;
 constexpr int YS_FRAME = CHB * 32 + 2;  // float2 per frame row in LDS (padded)
 // BF16 modes: the staged samples are split once into four BF16 planes (re hi, re lo, im hi, im lo),
 // [plane][frame][bin][mic] with a 16-byte pad per frame row, so every wavefront reads its operands as
@@ -111,9 +151,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const bool d_ok = d_st < D;
   const double invP = 1.0 / static_cast<double>(P);
   const float invM = 1.0f / static_cast<float>(M);   // the array mean's 1/M (one rounding, as the steering's)
-  const int f_out = ft * FD_GEMM_FRAMES + r16;
 
-  for (int k0 = bt * FD_GEMM_BINS; k0 < (bt + 1) * FD_GEMM_BINS && k0 < kb; k0 += CHB) {
+  for (int k0 = bt * FD_GEMM_BINS_WG; k0 < (bt + 1) * FD_GEMM_BINS_WG && k0 < kb; k0 += CHB) {
     f32x4 cr[CHB], ci[CHB];
 #pragma unroll
     for (int b = 0; b < CHB; ++b) {
@@ -244,16 +283,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
       }
     }
-    // lane holds (direction 4 grp + i, frame r16) for the chunk's bins: CHB
-    // consecutive bins of one output row, written as 16-byte pairs
-    if (f_out < F) {
+    // Lane holds (direction 4 grp + i, frame r16) for the chunk's CHB = 8 bins: one 64-byte segment of
+    // each of 4 output rows.  A quad transpose gives lane q of each quad the bins 2q, 2q + 1 of the
+    // quad's rows (its 4 frames x the same direction), so each store writes 16 whole 64-byte segments
+    // (4 lanes each) instead of 64 scattered 16-byte pieces.
+    static_assert(CHB == 8, "one 16-byte bin pair per quad lane");
+    const int q = lane & 3;
+    const int f_quad = ft * FD_GEMM_FRAMES + (r16 & ~3);   // frame held by lane 0 of the quad
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int d_out = dt * FD_GEMM_DIRS + wv * 16 + 4 * grp + i;
-        if (d_out < D) {
-          float4* dst = reinterpret_cast<float4*>(bspec + (static_cast<long long>(f_out) * D + d_out) * kb_pad + k0);
+    for (int i = 0; i < 4; ++i) {
+      f32x4 e[4];
 #pragma unroll
-          for (int b = 0; b < CHB; b += 2) dst[b / 2] = make_float4(cr[b][i], ci[b][i], cr[b + 1][i], ci[b + 1][i]);
+      for (int b = 0; b < 4; ++b) e[b] = f32x4{cr[2 * b][i], ci[2 * b][i], cr[2 * b + 1][i], ci[2 * b + 1][i]};
+      quad_transpose(e, q);                                  // e[j]: frame f_quad + j, bins 2q, 2q + 1
+      const int d_out = dt * FD_GEMM_DIRS + wv * 16 + 4 * grp + i;
+      if (d_out < D) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int f = f_quad + j;
+          if (f < F)
+            *reinterpret_cast<f32x4*>(bspec + (static_cast<long long>(f) * D + d_out) * kb_pad + k0 + 2 * q) = e[j];
         }
       }
     }
@@ -316,8 +365,10 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   constexpr int L = S::NF;
   constexpr int T = S::T;
   constexpr int LH = FdTw<LOGL>::LH;
+  constexpr bool TW1 = L >= 256;              // pass-1 twiddles from a table (built once per workgroup)
   __shared__ float2 buf[S::LDS_ELEMS];
   __shared__ float2 tw[LH + 64];
+  __shared__ float2 tw1[TW1 ? 256 : 1];
   extern __shared__ float2 dyn[];             // 16 R' phase factors, then the classed taps
   float2* tws = dyn;
   const int nu = (K + Rp - 1) >> logRp;      // taps per phase class
@@ -326,6 +377,7 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
   for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
+  if constexpr (TW1) pass1_twiddles<LOGL, true>(tw1, tw_g, tw_g + LH, tid, T);
   const float2* twp_hi = tw_g + LH + 64;
   const float2* twp_lo = twp_hi + P / 64 + 1;
   for (int i = tid; i < 16 * Rp; i += T) tws[i] = cconj(twp(twp_hi, twp_lo, i * (L / 16)));   // exp(+2 pi i i / (16 R'))
@@ -370,7 +422,7 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
         v[s] = x;
       }
     }
-    fft_lds<LOGL, true>(v, buf, tw, tw + LH, tid);   // starts with a barrier
+    fft_lds<LOGL, true, TW1>(v, buf, tw, tw + LH, tid, tw1);   // starts with a barrier
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -421,19 +473,24 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_envw_kernel(
   constexpr int L = S::NF;
   constexpr int T = S::T;
   constexpr int LH = FdTw<LOGL>::LH;
+  constexpr bool TW1 = L >= 256;              // pass-1 twiddles from a table (built once per workgroup)
   __shared__ float2 buf[S::LDS_ELEMS];
   __shared__ float2 tw[LH + 64];
-  extern __shared__ float2 dyn[];             // 16 R' phase factors, K taps, the G-sample window
+  __shared__ float2 tw1[TW1 ? 256 : 1];
+  extern __shared__ float2 dyn[];             // 16 R' phase factors, K taps / P, the G-sample window
   float2* tws = dyn;
   float* hs = reinterpret_cast<float*>(dyn + 16 * Rp);
   float* mag = hs + ((K + 3) & ~3);
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
   for (int i = tid; i < LH + 64; i += T) tw[i] = tw_g[i];
+  if constexpr (TW1) pass1_twiddles<LOGL, true>(tw1, tw_g, tw_g + LH, tid, T);
   const float2* twp_hi = tw_g + LH + 64;
   const float2* twp_lo = twp_hi + P / 64 + 1;
   for (int i = tid; i < 16 * Rp; i += T) tws[i] = cconj(twp(twp_hi, twp_lo, i * (L / 16)));   // exp(+2 pi i i / (16 R'))
-  for (int j = tid; j < K; j += T) hs[j] = taps[j];
+  // the taps carry the transform's 1/P (a power of two: the products are exactly those of h[j] |b| / P)
+  const float invP = 1.0f / static_cast<float>(P);
+  for (int j = tid; j < K; j += T) hs[j] = taps[j] * invP;
   const float2* in = bspec + fd * kb_pad;
   float2 bin[NFOLD][16];
 #pragma unroll
@@ -443,8 +500,12 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_envw_kernel(
       const int k = tid + s * (L / 16) + f * L;
       bin[f][s] = k < kb ? in[k] : make_float2(0.f, 0.f);
     }
-  const float invP = 1.0f / static_cast<float>(P);
   __syncthreads();                            // tables in LDS
+  // the twiddles of the later passes depend only on the thread: built once, kept across the phases
+  // (one bin per slot leaves the registers for them)
+  constexpr bool TWR = NFOLD == 1;
+  float2 twr[FftTwr<LOGL>::N];
+  if constexpr (TWR) fft_thread_twiddles<LOGL, true>(twr, tw, tw + LH, tid);
 
   for (int r = 0; r < Rp; ++r) {
     float2 v[16];
@@ -467,11 +528,11 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_envw_kernel(
         v[s] = x;
       }
     }
-    fft_lds<LOGL, true>(v, buf, tw, tw + LH, tid);   // starts with a barrier
+    fft_lds<LOGL, true, TW1, TWR>(v, buf, tw, tw + LH, tid, tw1, twr);   // starts with a barrier
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int w = (Rp * S::out_index(tid, i) + r - n_start) & (P - 1);   // window position of the sample
-      if (w < G) mag[w] = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+      if (w < G) mag[w] = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y);
     }
   }
   __syncthreads();
@@ -516,7 +577,7 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_beam_kernel(
 }  // namespace
 
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s) {
-  const int nbt = (p->kb_pad + FD_GEMM_BINS - 1) / FD_GEMM_BINS;
+  const int nbt = (p->kb_pad + FD_GEMM_BINS_WG - 1) / FD_GEMM_BINS_WG;
   const int ndt = (p->D + FD_GEMM_DIRS - 1) / FD_GEMM_DIRS;
   const int nft = (F + FD_GEMM_FRAMES - 1) / FD_GEMM_FRAMES;
   const int nyt = nbt * nft;                                  // sample tiles
@@ -617,7 +678,7 @@ hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F
 // dynamic (16 R' phase factors, taps, the beam window)
 size_t fd_envw_static_lds(int logL) {
   const int L = 1 << logL;
-  return static_cast<size_t>(L + L / 16 + (L / 64 > 0 ? L / 64 : 1) + 64) * sizeof(float2);
+  return static_cast<size_t>(L + L / 16 + (L / 64 > 0 ? L / 64 : 1) + 64 + (L >= 256 ? 256 : 1)) * sizeof(float2);
 }
 size_t fd_envw_dyn_lds(const sonar_plan_s* p) {
   return static_cast<size_t>(16) * p->fd_R * sizeof(float2) + static_cast<size_t>((p->K + 3) & ~3) * sizeof(float) +

@@ -224,7 +224,6 @@ constexpr int FD_MAX_LOGL = 14;        // largest per-phase transform of the FD 
 constexpr int FD_MAX_FOLD = 2;         // stored bins per slot held in registers by the fused FD inverse
 constexpr int FD_FOLD1_MAX_L = 8192;   // the default layout keeps one bin per slot up to this transform length
 constexpr int FD_NQ = 8;               // range bins per thread of the fused FD inverse: Q <= FD_NQ * fd_L / 16
-constexpr int FD_GEMM_BINS = 64;       // bins per FD GEMM workgroup (multiple of 16)
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
 constexpr int FD_XCDS = 8;             // accelerator dies the FD GEMM's sample tiles are grouped by
