@@ -435,11 +435,18 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
 /*
  * sonar_plan_set_positions -- new microphone positions [M][3] (metres): the
  * delay tables (§4.1 delays) are rebuilt on `stream` without reallocating,
- * ordered after the work already queued there.  TD_LINEAR and FD modes;
- * SONAR_E_UNSUPPORTED for the MFMA TD modes (their tiles are built for one geometry) and for
- * a TD_LINEAR plan whose new geometry needs delays outside the plan's range
- * (the plan keeps 3 samples of slack on each side of the geometry it was
- * created with).
+ * ordered after the work already queued there.  A time-domain plan whose new
+ * geometry needs delays outside the plan's range returns SONAR_E_UNSUPPORTED
+ * and keeps its old positions (the plan keeps 3 samples of slack on each side
+ * of the geometry it was created with).
+ * MFMA TD modes (TD_BF16, TD_BF16X2, TD_F16, TD_BF16G): their direction tiles,
+ * tap groups and weight fragments follow the geometry, so the call also
+ * synchronizes `stream`, rebuilds those tables on the host and replaces them
+ * (device allocations: not for graph capture or no-allocation callers).  The
+ * plan must not be in use on another stream meanwhile.  If the rebuild fails
+ * (SONAR_E_NOMEM, SONAR_E_HIP), the delay table already holds the new
+ * positions while the tiles keep the old ones: set the positions again or
+ * create a new plan.
  */
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
 /* (TD_NEAREST and TD_CUBIC plans move like TD_LINEAR ones.  TD_NEAREST's dL/dp is zero

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <vector>
 
 #include "sonar.h"
 
@@ -62,6 +63,8 @@ struct sonar_plan_s {
   long long mt_flop_per_frame = 0;   // matrix-core flops issued per frame
   float mt_fir_unscale = 1.f;          // 2^-ts (two-plane modes: taps stored times 2^ts), times 1/M for TD_BF16G
                                        // (its exact weights leave out the array mean's 1/M)
+  std::vector<double> h_dirs;          // [D][3] and [K] host copies of the directions and FP64 taps: the
+  std::vector<double> h_taps;          // MFMA tiles are rebuilt from them when the positions change
 
   int device = 0;
   int cu_count = 0;     // compute units of the device

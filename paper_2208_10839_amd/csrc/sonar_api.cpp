@@ -817,6 +817,8 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   e = launch_build_tables(p, stream);
   if (e == hipSuccess && fd) e = launch_build_fd_tables(p, stream);
   if (e == hipSuccess && mt_planes(p)) {
+    p->h_dirs.assign(d.dirs, d.dirs + 3 * static_cast<size_t>(p->D));
+    p->h_taps = taps;
     const int st = build_mt_tables(p, d.mic_pos, d.dirs, taps, stream, &total);
     if (st != SONAR_OK) {
       free_plan(p);
@@ -1481,11 +1483,9 @@ int sonar_energyscape_backward(sonar_plan p, const void* x, const float* dE, int
 
 int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t stream) {
   if (!p || !mic_pos) return fail(SONAR_E_INVALID, "plan and mic_pos must not be NULL");
-  if (mt_planes(p))
-    return fail(SONAR_E_UNSUPPORTED, "MFMA TD tiles are built for one geometry: create a new plan");
   for (int i = 0; i < 3 * p->M; ++i)
     if (!std::isfinite(mic_pos[i])) return fail(SONAR_E_INVALID, "mic_pos must be finite");
-  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC) {
+  if (is_td(p)) {
     // offsets o in [floor(-bmax), floor(bmax) + 1] (nearest rounds up by one at most); the taps read
     // o .. o + 1 (linear), o - 1 .. o + 2 (cubic)
     const double bmax = delay_bound(mic_pos, p->M, p->fs, p->c);
@@ -1496,7 +1496,51 @@ int sonar_plan_set_positions(sonar_plan p, const double* mic_pos, hipStream_t st
   hipError_t e = hipMemcpyAsync(p->d_pos, mic_pos, 3 * sizeof(double) * p->M, hipMemcpyHostToDevice, stream);
   if (e == hipSuccess) e = launch_delay_tables(p, stream);
   if (e == hipSuccess && !is_td(p)) e = launch_fd_step_table(p, stream);
-  return e == hipSuccess ? SONAR_OK : hip_fail(e, "position update");
+  if (e != hipSuccess) return hip_fail(e, "position update");
+  if (!mt_planes(p)) return SONAR_OK;
+  // MFMA time-domain modes: the direction tiles, tap groups and weights follow the geometry and are
+  // rebuilt on the host from the new delay table (the staged window already spans the plan's whole
+  // delay range).  The new tables replace the old ones only once they are complete; on failure the
+  // plan keeps the old tables, which then no longer match the delay table.
+  e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "position update");
+  int* old_g = p->d_mt_g;
+  unsigned short* old_w = p->d_mt_w;
+  int2* old_kcr = p->d_mt_kcr;
+  int* old_perm = p->d_mt_perm;
+  unsigned short* old_fir = p->d_mt_fir;
+  const int old_gmax = p->mt_gmax, old_kcmax = p->mt_kcmax;
+  const long long old_flop = p->mt_flop_per_frame;
+  const float old_unscale = p->mt_fir_unscale;
+  p->d_mt_g = nullptr;
+  p->d_mt_w = nullptr;
+  p->d_mt_kcr = nullptr;
+  p->d_mt_perm = nullptr;
+  p->d_mt_fir = nullptr;
+  size_t total = 0;
+  const int st = build_mt_tables(p, mic_pos, p->h_dirs.data(), p->h_taps, stream, &total);
+  int* const fr_g = st == SONAR_OK ? old_g : p->d_mt_g;
+  unsigned short* const fr_w = st == SONAR_OK ? old_w : p->d_mt_w;
+  int2* const fr_kcr = st == SONAR_OK ? old_kcr : p->d_mt_kcr;
+  int* const fr_perm = st == SONAR_OK ? old_perm : p->d_mt_perm;
+  unsigned short* const fr_fir = st == SONAR_OK ? old_fir : p->d_mt_fir;
+  (void)hipFree(fr_g);
+  (void)hipFree(fr_w);
+  (void)hipFree(fr_kcr);
+  (void)hipFree(fr_perm);
+  (void)hipFree(fr_fir);
+  if (st != SONAR_OK) {
+    p->d_mt_g = old_g;
+    p->d_mt_w = old_w;
+    p->d_mt_kcr = old_kcr;
+    p->d_mt_perm = old_perm;
+    p->d_mt_fir = old_fir;
+    p->mt_gmax = old_gmax;
+    p->mt_kcmax = old_kcmax;
+    p->mt_flop_per_frame = old_flop;
+    p->mt_fir_unscale = old_unscale;
+  }
+  return st;
 }
 
 namespace {

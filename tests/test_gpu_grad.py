@@ -165,6 +165,39 @@ def test_set_positions_matches_a_new_plan(gpu, torch_mod, mode):
         plan.set_positions(w.mic_pos * 4.0)       # exact phases: any geometry
 
 
+@pytest.mark.parametrize("mode,bar", [("td_bf16", 1e-3), ("td_bf16x2", 1e-3), ("td_f16", 3e-4), ("td_bf16g", 1e-3)])
+def test_set_positions_rebuilds_mfma_tiles(gpu, torch_mod, mode, bar):
+    """MFMA TD modes: new positions rebuild the direction tiles, tap groups and weights.  The result
+    matches the oracle at the new positions and a plan created there; going back to the old
+    positions gives the old energyscape bit for bit; positions beyond the plan's delay range are
+    refused and leave the plan as it was."""
+    torch = torch_mod
+    w = synth.make_workload("c1", n_dirs=97)          # 4 direction tiles
+    _say(f"case set_positions {mode}: c1 D=97")
+    rng = np.random.default_rng(np.random.SeedSequence([4, 0, 0, 7]))
+    pos2 = w.mic_pos + rng.normal(0.0, 0.5e-3, size=w.mic_pos.shape)
+    N = w.x.shape[2]
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, N, fs=w.fs, c=w.c, mode=mode)
+    x = torch.from_numpy(w.x).cuda()
+    E0 = plan.energyscape(x).cpu().numpy()
+    plan.set_positions(pos2)
+    E1 = plan.energyscape(x).cpu().numpy()[0]
+    E2 = gpu.Plan(pos2, w.chirp, w.dirs, N, fs=w.fs, c=w.c, mode=mode).energyscape(x).cpu().numpy()[0]
+    Eo = O.energyscape(w.x[0].astype(np.float64), w.chirp, pos2, w.dirs, fs=w.fs, c=w.c, P=plan.P, R=10,
+                       mode="td")
+    e_new, e_or = rel_l2(E1, E2), rel_l2(E1, Eo)
+    _say(f"  moved plan vs new plan {e_new:.2e}, vs oracle {e_or:.2e} (bar {bar:.0e})")
+    # the two plans sum the same products; their K-chunks may group the taps differently
+    assert e_new <= 1e-5
+    assert e_or <= bar
+    plan.set_positions(w.mic_pos)
+    assert np.array_equal(plan.energyscape(x).cpu().numpy(), E0)
+    with pytest.raises(gpu.SonarError) as ei:
+        plan.set_positions(w.mic_pos * 4.0)           # beyond the plan's delay range
+    assert ei.value.status == gpu.SONAR_E_UNSUPPORTED
+    assert np.array_equal(plan.energyscape(x).cpu().numpy(), E0)
+
+
 def test_autograd_function_matches_vjp(gpu, torch_mod):
     """Energyscape.apply: backward gives the sonar_energyscape_vjp results for x and positions."""
     torch = torch_mod
