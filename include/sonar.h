@@ -451,9 +451,10 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
 int sonar_plan_set_positions(sonar_plan plan, const double* mic_pos, hipStream_t stream);
 /* (TD_NEAREST and TD_CUBIC plans move like TD_LINEAR ones.  TD_NEAREST's dL/dp is zero
  * almost everywhere, so sonar_energyscape_vjp returns SONAR_E_UNSUPPORTED for dpos_out on
- * it, and on TD_F16, whose delays lie on a 1/2048-sample grid; dx_out of a TD_F16 plan is the
- * adjoint of TD_LINEAR on the gridded delays; TD_CUBIC has no gradient kernels
- * (SONAR_E_UNSUPPORTED).) */
+ * it, and on TD_F16 and TD_BF16G, whose delays lie on a 1/2048- or 1/256-sample grid; dx_out
+ * of those plans is the adjoint of TD_LINEAR on the gridded delays.  TD_CUBIC's gradients are
+ * those of its 4-point Lagrange reading: dx from the four taps' weights, dpos from their
+ * slopes in the fractional delay.) */
 
 /*
  * PDM front end (§2: the microphones deliver 1-bit sigma-delta pulse-density

@@ -18,6 +18,7 @@ from .sonar_oracle import (  # noqa: F401
     das_fd_vjp,
     das_td,
     das_td_cubic,
+    das_td_cubic_vjp,
     das_td_nearest,
     das_td_vjp,
     default_lowpass,
@@ -27,6 +28,7 @@ from .sonar_oracle import (  # noqa: F401
     energyscape_vjp_fd,
     energyscape_vjp_td,
     gridded_offsets,
+    lagrange4_weight_slopes,
     lagrange4_weights,
     lfilter,
     envelope,

@@ -196,6 +196,30 @@ def lagrange4_weights(alpha):
     return np.stack(out, axis=-1)
 
 
+def lagrange4_weight_slopes(alpha):
+    """d L_k / d alpha of lagrange4_weights (nodes -1, 0, 1, 2): by the product rule,
+    L_k'(alpha) = sum_{i != k} prod_{j != k, i} (alpha - j) / prod_{j != k} (k - j).  Returns [..., 4]."""
+    a = np.asarray(alpha, dtype=np.float64)
+    nodes = (-1, 0, 1, 2)
+    out = []
+    for k in nodes:
+        den = 1.0
+        for j in nodes:
+            if j != k:
+                den *= (k - j)
+        s = np.zeros_like(a)
+        for i in nodes:
+            if i == k:
+                continue
+            t = np.ones_like(a)
+            for j in nodes:
+                if j != k and j != i:
+                    t = t * (a - j)
+            s = s + t
+        out.append(s / den)
+    return np.stack(out, axis=-1)
+
+
 def das_td_cubic(yhat, Dl, n_idx) -> np.ndarray:
     """Fractional-delay DAS with 4-point (cubic) Lagrange interpolation, circular in P:
     o = floor(-Dl), alpha = -Dl - o,
@@ -497,6 +521,35 @@ def das_td_vjp(yhat, Dl, n_idx, G_b):
     return G_y, dDl
 
 
+def das_td_cubic_vjp(yhat, Dl, n_idx, G_b):
+    """Gradients of b = das_td_cubic(yhat, Dl, n_idx) given G_b [D][len(n_idx)].
+
+    Returns (G_y [M][P] complex, dDl [D][M] real):
+      G_y[m][(n+o+k) mod P] += L_k(alpha)/M * G_b[d][n]                   (k = -1 .. 2)
+      dDl[d][m] = -(1/M) sum_n Re(conj(G_b[d][n]) sum_k L_k'(alpha) yhat_m[n+o+k])
+    (alpha = -Dl - o has slope -1 in Dl inside a sample cell; o is piecewise constant, so this
+    is the derivative almost everywhere.)"""
+    yhat = np.asarray(yhat)
+    M, P = yhat.shape
+    o, alpha = td_offsets(Dl)
+    Lw = lagrange4_weights(alpha)
+    Ls = lagrange4_weight_slopes(alpha)
+    n_idx = np.asarray(n_idx, dtype=np.int64)
+    G_b = np.asarray(G_b)
+    D = o.shape[0]
+    G_y = np.zeros((M, P), dtype=np.complex128)
+    dDl = np.zeros((D, M))
+    for d in range(D):
+        for m in range(M):
+            acc = np.zeros(n_idx.size, dtype=np.complex128)
+            for i, k in enumerate((-1, 0, 1, 2)):
+                idx = np.mod(n_idx + o[d, m] + k, P)
+                np.add.at(G_y[m], idx, Lw[d, m, i] / M * G_b[d])
+                acc += Ls[d, m, i] * yhat[m, idx]
+            dDl[d, m] = -np.sum(np.real(np.conj(G_b[d]) * acc)) / M
+    return G_y, dDl
+
+
 def matched_filter_vjp(G_y, chirp, P: int, N: int, fs: float, band=None) -> np.ndarray:
     """dx [M][N] for yhat = matched_filter(x) (x real, zero-padded to P): the filter is
     yhat = IDFT(C . DFT(x)), so its adjoint is dx = Re IDFT(conj(C) . DFT(G_y)), cut to N."""
@@ -575,9 +628,12 @@ def energyscape_vjp_fd(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: i
 
 
 def energyscape_vjp_td(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: int | None = None,
-                       gate=None, R: int = 10, taps=None, band=None):
-    """(dx [M][N], dpos [M][3]) of L = sum(dE * energyscape(..., mode='td')) by the chain rule:
-    envelope -> delay-and-sum -> matched filter and delays."""
+                       gate=None, R: int = 10, taps=None, band=None, interp: str = "linear"):
+    """(dx [M][N], dpos [M][3]) of L = sum(dE * energyscape(..., mode='td')) (interp 'linear') or
+    of mode='td_cubic' (interp 'cubic') by the chain rule: envelope -> delay-and-sum -> matched
+    filter and delays."""
+    if interp not in ("linear", "cubic"):
+        raise ValueError("interp must be 'linear' or 'cubic'")
     x = np.asarray(x, dtype=np.float64)
     M, N = x.shape
     L = len(chirp)
@@ -592,9 +648,9 @@ def energyscape_vjp_td(x, chirp, mic_pos, dirs, dE, *, fs: float, c: float, P: i
     Dl = delays(mic_pos, dirs, fs, c)
     n_idx = beam_window_indices(n0, Q, R, K)
     yhat = matched_filter(x, chirp, P, fs, band)
-    b = das_td(yhat, Dl, n_idx)
+    b = das_td(yhat, Dl, n_idx) if interp == "linear" else das_td_cubic(yhat, Dl, n_idx)
     G_b = envelope_vjp(b, h, dE, Q, R)
-    G_y, dDl = das_td_vjp(yhat, Dl, n_idx, G_b)
+    G_y, dDl = (das_td_vjp if interp == "linear" else das_td_cubic_vjp)(yhat, Dl, n_idx, G_b)
     dx = matched_filter_vjp(G_y, chirp, P, N, fs, band)
     dpos = delays_vjp(dDl, dirs, fs, c)
     return dx, dpos

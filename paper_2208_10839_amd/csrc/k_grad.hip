@@ -7,6 +7,8 @@
 //   envelope      G_b[w]   = (sum_{q, j: qR + K-1-j = w} dE[q] h[j]) * b[w] / |b[w]|
 //   delay-and-sum dDl[d][m] = sum_w Re(conj(G_b[w]) (y_m[w+rel] - y_m[w+rel+1])) / M
 //                 G_y[m][r] = sum_d w0[d][m] G_b[d][r-rel] + w1[d][m] G_b[d][r-rel-1]
+//   (4-point Lagrange reading, TD_CUBIC: taps k = -1 .. 2 with weights L_k(alpha) / M, so
+//    G_y collects all four and dDl[d][m] = -sum_w Re(conj(G_b[w]) sum_k L_k'(alpha) y_m[w+rel_k]) / M)
 //   delays        dpos[m]   = fs/c * sum_{f,d} dDl[f][d][m] u_d
 //   matched filter dx       = Re IDFT_P(conj(C) . DFT_P(G_yhat)), cut to N
 //
@@ -50,23 +52,54 @@ __global__ void env_vjp_kernel(float2* __restrict__ beam, const float* __restric
   beam[fd * G + w] = make_float2(s * b.x, s * b.y);
 }
 
-// dDl[f][d][m]: one workgroup per (frame, direction), a block reduction per microphone
+// dDl[f][d][m]: one workgroup per (frame, direction), a block reduction per microphone.  Linear
+// readings: one table entry {rel, w0, w1} per microphone, slopes (1, -1) on y[rel], y[rel + 1].
+// Cubic: two entries {o - 1 - omin, ..}, {o + 1 - omin, ..} per microphone; the slopes -L_k'(alpha)
+// of the four taps come from the FP64 delay dl (alpha = -Dl - floor(-Dl)).
 __global__ __launch_bounds__(256) void dl_vjp_kernel(const float2* __restrict__ gb, const float2* __restrict__ yext,
-                                                     const int4* __restrict__ dtab, float* __restrict__ ddl,
-                                                     long long fstride, int M, int D, int G, int row) {
+                                                     const int4* __restrict__ dtab, const double* __restrict__ dl,
+                                                     float* __restrict__ ddl, long long fstride, int M, int D, int G,
+                                                     int row, int cubic) {
   __shared__ float red[256 / 64];
   const int d = blockIdx.x % D;
   const long long f = blockIdx.x / D;
   const float2* g = gb + (f * D + d) * G;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int m = 0; m < M; ++m) {
-    const int rel = dtab[static_cast<long long>(d) * M + m].x;
-    const float2* y = yext + f * fstride + static_cast<long long>(m) * row + rel;
+    const long long i = static_cast<long long>(d) * M + m;
+    // taps y[rel_k + w] with slopes s_k (k = 0 .. 3); the linear readings use the first two
+    int rel0, rel2 = 0;
+    float s0 = 1.f, s1 = -1.f, s2 = 0.f, s3 = 0.f;
+    if (cubic) {
+      rel0 = dtab[2 * i].x;
+      rel2 = dtab[2 * i + 1].x;
+      const double Dl = dl[i];
+      const double a = -Dl - floor(-Dl), a2 = a * a;
+      // -L_k'(a) for the nodes -1, 0, 1, 2
+      s0 = static_cast<float>((3.0 * a2 - 6.0 * a + 2.0) / 6.0);
+      s1 = static_cast<float>(-(3.0 * a2 - 4.0 * a - 1.0) / 2.0);
+      s2 = static_cast<float>((3.0 * a2 - 2.0 * a - 2.0) / 2.0);
+      s3 = static_cast<float>(-(3.0 * a2 - 1.0) / 6.0);
+    } else {
+      rel0 = dtab[i].x;
+    }
+    const float2* y = yext + f * fstride + static_cast<long long>(m) * row + rel0;
+    const float2* y2 = yext + f * fstride + static_cast<long long>(m) * row + rel2;
     float acc = 0.f;
-    for (int w = threadIdx.x; w < G; w += 256) {
-      const float2 gw = g[w], a = y[w], b = y[w + 1];
-      acc = fmaf(gw.x, a.x - b.x, acc);
-      acc = fmaf(gw.y, a.y - b.y, acc);
+    if (cubic) {
+      for (int w = threadIdx.x; w < G; w += 256) {
+        const float2 gw = g[w], a = y[w], b = y[w + 1], c = y2[w], e = y2[w + 1];
+        const float tx = s0 * a.x + s1 * b.x + s2 * c.x + s3 * e.x;
+        const float ty = s0 * a.y + s1 * b.y + s2 * c.y + s3 * e.y;
+        acc = fmaf(gw.x, tx, acc);
+        acc = fmaf(gw.y, ty, acc);
+      }
+    } else {
+      for (int w = threadIdx.x; w < G; w += 256) {
+        const float2 gw = g[w], a = y[w], b = y[w + 1];
+        acc = fmaf(gw.x, a.x - b.x, acc);
+        acc = fmaf(gw.y, a.y - b.y, acc);
+      }
     }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (lane == 0) red[wv] = acc;
@@ -104,19 +137,22 @@ __global__ __launch_bounds__(256) void pos_vjp_kernel(const float* __restrict__ 
 
 // G_yhat[f][m][n], n in Z_P: every row position r = (n - origin) mod P, r + P, ... below row
 // collects the taps that read it
+// (TD_CUBIC: 1 << vshift = 2 two-tap table entries per microphone, each handled as a linear one)
 __global__ __launch_bounds__(256) void yhat_vjp_kernel(const float2* __restrict__ gb, const int4* __restrict__ dtab,
                                                        float2* __restrict__ gy, int M, int D, int G, int row, int P,
-                                                       int origin) {
+                                                       int origin, int vshift) {
   const int n = blockIdx.y * 256 + threadIdx.x;
   const long long fm = blockIdx.x;
   if (n >= P) return;
   const long long f = fm / M;
   const int m = static_cast<int>(fm - f * M);
   const float2* g = gb + f * D * G;
+  const int ne = 1 << vshift;
   float2 acc = make_float2(0.f, 0.f);
   for (int r = (n - origin) & (P - 1); r < row; r += P) {
-    for (int d = 0; d < D; ++d) {
-      const int4 e = dtab[static_cast<long long>(d) * M + m];
+    for (int de = 0; de < D * ne; ++de) {
+      const int d = de >> vshift;
+      const int4 e = dtab[((static_cast<long long>(d) * M + m) << vshift) + (de & (ne - 1))];
       const int w = r - e.x;
       const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.z);
       if (w >= 0 && w < G) {
@@ -461,11 +497,13 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (p->bf_mode != SONAR_BF_TD_LINEAR && p->bf_mode != SONAR_BF_TD_BF16 && p->bf_mode != SONAR_BF_TD_NEAREST &&
-      p->bf_mode != SONAR_BF_TD_BF16X2 && p->bf_mode != SONAR_BF_TD_F16 && p->bf_mode != SONAR_BF_TD_BF16G)
+      p->bf_mode != SONAR_BF_TD_BF16X2 && p->bf_mode != SONAR_BF_TD_F16 && p->bf_mode != SONAR_BF_TD_BF16G &&
+      p->bf_mode != SONAR_BF_TD_CUBIC)
     return vjp_fd(p, mf, beam_grad, F, dyhat, dx, dpos, s);
+  const int cubic = p->bf_mode == SONAR_BF_TD_CUBIC ? 1 : 0;
   if (dpos) {
     hipLaunchKernelGGL(dl_vjp_kernel, dim3(static_cast<unsigned>(rows)), dim3(256), 0, s, beam_grad, mf, p->d_dtab,
-                       p->d_gdl, p->mf_fstride, p->M, p->D, p->G, p->row);
+                       p->d_dl, p->d_gdl, p->mf_fstride, p->M, p->D, p->G, p->row, cubic);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(pos_vjp_kernel, dim3(p->M), dim3(256), 0, s, p->d_gdl, p->d_dirs, dpos, F, p->M, p->D,
                        p->fs / p->c);
@@ -473,7 +511,7 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
   }
   if (dyhat) {
     hipLaunchKernelGGL(yhat_vjp_kernel, dim3(F * p->M, (p->P + 255) / 256), dim3(256), 0, s, beam_grad, p->d_dtab,
-                       dyhat, p->M, p->D, p->G, p->row, p->P, static_cast<int>(p->origin));
+                       dyhat, p->M, p->D, p->G, p->row, p->P, static_cast<int>(p->origin), cubic);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (dx) return mfadj(p, dyhat, F, dx, s);
   }

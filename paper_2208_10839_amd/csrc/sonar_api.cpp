@@ -1447,7 +1447,6 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   if (!beam_inout) return fail(SONAR_E_INVALID, "beam_inout is NULL");
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
   if (p->iir_ns > 0) return fail(SONAR_E_UNSUPPORTED, "gradients are built for the FIR envelope only");
-  if (p->bf_mode == SONAR_BF_TD_CUBIC) return fail(SONAR_E_UNSUPPORTED, "TD_CUBIC has no gradient kernels");
   if (dx_out && !dyhat_out) return fail(SONAR_E_INVALID, "dx_out needs dyhat_out (the matched filter's gradient)");
   if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");

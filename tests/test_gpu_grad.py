@@ -46,7 +46,7 @@ def torch_mod():
 
 def _plan(gpu, w, mode, **kw):
     return gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, band=w.cfg.band,
-                    decim=w.cfg.decim, mode={"td": "td", "fd": "fd_fp32"}[mode], **kw)
+                    decim=w.cfg.decim, mode={"td": "td", "fd": "fd_fp32", "cubic": "td_cubic"}[mode], **kw)
 
 
 def _oracle_steps(w, frame, plan, mode):
@@ -57,9 +57,9 @@ def _oracle_steps(w, frame, plan, mode):
     Q = O.num_range_bins(0, x.shape[1], R)
     Dl = O.delays(w.mic_pos, w.dirs, w.fs, w.c)
     n_idx = O.beam_window_indices(0, Q, R, h.size)
-    if mode == "td":
+    if mode in ("td", "cubic"):
         y = O.matched_filter(x, w.chirp, P, w.fs, w.cfg.band)
-        b = O.das_td(y, Dl, n_idx)
+        b = O.das_td(y, Dl, n_idx) if mode == "td" else O.das_td_cubic(y, Dl, n_idx)
     else:
         y = O.matched_filter_spectrum(x, w.chirp, P, w.fs, w.cfg.band)
         b = O.das_fd(y, Dl, n_idx)
@@ -70,8 +70,8 @@ def _oracle_back(w, plan, mode, steps, G_b):
     """Oracle backward from G_b: (G_mf over Z_P, dx, dpos)."""
     R, h, Q, Dl, n_idx, y, b = steps
     N = w.x.shape[2]
-    if mode == "td":
-        G_y, dDl = O.das_td_vjp(y, Dl, n_idx, G_b)
+    if mode in ("td", "cubic"):
+        G_y, dDl = (O.das_td_vjp if mode == "td" else O.das_td_cubic_vjp)(y, Dl, n_idx, G_b)
         dx = O.matched_filter_vjp(G_y, w.chirp, plan.P, N, w.fs, w.cfg.band)
     else:
         G_y, dDl = O.das_fd_vjp(y, Dl, n_idx, G_b)
@@ -79,7 +79,7 @@ def _oracle_back(w, plan, mode, steps, G_b):
     return G_y, dx, O.delays_vjp(dDl, w.dirs, w.fs, w.c)
 
 
-@pytest.mark.parametrize("mode", ["td", "fd"])
+@pytest.mark.parametrize("mode", ["td", "fd", "cubic"])
 def test_vjp_matches_oracle(gpu, torch_mod, mode):
     """Each step against the oracle applied to the GPU's own input of that step (the
     envelope derivative b/|b| is ill-conditioned where |b| is small, so G_b is checked on
@@ -252,7 +252,7 @@ def test_autograd_backward_uses_its_own_forward_geometry(gpu, torch_mod):
     assert not np.array_equal(dpos, dpos2)
 
 
-@pytest.mark.parametrize("mode", ["td", "fd"])
+@pytest.mark.parametrize("mode", ["td", "fd", "cubic"])
 def test_backward_from_samples_matches_vjp(gpu, torch_mod, mode):
     """sonar_energyscape_backward (x -> dx, dp in one call) equals matched filter + beamform + VJP."""
     torch = torch_mod

@@ -139,8 +139,9 @@ def test_td_cubic_matches_oracle(gpu, torch_mod, cfg, n_samples, n_dirs, frames)
     mf = plan.matched_filter(x)
     beam = plan.beamform(mf)
     assert rel_l2(plan.envelope(beam).cpu().numpy(), E) <= 1e-6
-    with pytest.raises(gpu.SonarError):
-        plan.vjp(mf, beam, torch.zeros((frames, plan.D, plan.Q), dtype=torch.float32, device="cuda"))
+    # gradients of the cubic reading exist (their parity is in test_gpu_grad.py)
+    _, dx, dpos = plan.vjp(mf, beam, torch.ones((frames, plan.D, plan.Q), dtype=torch.float32, device="cuda"))
+    assert bool(torch.isfinite(dx).all()) and np.all(np.isfinite(dpos))
 
 
 def test_td_cubic_positions_and_limits(gpu, torch_mod):
