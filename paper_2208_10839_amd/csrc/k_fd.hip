@@ -345,17 +345,19 @@ __device__ __forceinline__ void load_phase(const float2* __restrict__ in, int kb
 // One direction of one frame per workgroup: the fused inverse transform and envelope.
 // The stored bins are read once into registers (NFOLD per slot, k' = t + s L/16 + f L).  For each
 // phase r the folded, rotated spectrum goes through one L-point inverse transform in LDS; the
-// magnitudes |b[R' a + r]| of that phase replace the transform's data in LDS, and every thread adds
-// to its own outputs q = t + T i (registers) the low-pass taps j that read phase r:
+// magnitudes |b[R' a + r]| of that phase replace the transform's data in LDS, and each range bin q
+// (owned by thread q mod T, its sum kept in LDS) adds the low-pass taps j that read phase r:
 //   E[q] = sum_j h[j] |b[n_start + qR + K - 1 - j]|,   tap j reads phase (n_start + qR + K - 1 - j) mod R'.
-// No copy of the whole beam window is kept, so the window length is not bounded by LDS.
+// No copy of the whole beam window is kept, so the window length is not bounded by LDS (Q floats
+// are: the range-bin sums).
 //
 // Costs kept off the vector ALUs:
-//  * the phase rotation exp(+2 pi i k r / P) of slot s, fold f is A_t exp(+2 pi i (s + 16 f) r / (16 R'))
-//    with A_t = exp(+2 pi i t r / P) (one lookup per thread and phase) and the second factor from an
-//    LDS table of 16 R' entries;
+//  * the phase rotation exp(+2 pi i k r / P) of slot s, fold f is A_t exp(+2 pi i s r / (16 R'))
+//    exp(+2 pi i f r / R'), with A_t = exp(+2 pi i t r / P) (one lookup per thread and phase), the
+//    second factor from an LDS table of 16 R' entries and the third the same for every thread, so the
+//    folds are combined first (a short DFT over f with uniform factors) and rotated once;
 //  * the taps are rearranged by phase class, hc[c][u] = h[c + R' u] (zero past K), and the phase's
-//    magnitudes carry a circular halo of H entries on both sides, so output q reads its taps and
+//    magnitudes carry a circular halo of H entries on both sides, so range bin q reads its taps and
 //    samples as two runs, hc[c_q][u] and mag[a_q - u] for u < ceil(K / R'), with no index wrapping.
 template <int LOGL, int NFOLD>
 __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
@@ -369,10 +371,11 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   __shared__ float2 buf[S::LDS_ELEMS];
   __shared__ float2 tw[LH + 64];
   __shared__ float2 tw1[TW1 ? 256 : 1];
-  extern __shared__ float2 dyn[];             // 16 R' phase factors, then the classed taps
+  extern __shared__ float2 dyn[];             // 16 R' phase factors, the classed taps / P, the Q range-bin sums
   float2* tws = dyn;
   const int nu = (K + Rp - 1) >> logRp;      // taps per phase class
   float* hc = reinterpret_cast<float*>(dyn + 16 * Rp);
+  float* accq = hc + Rp * nu;
   const int H = ((K - 1) / 2 >> logRp) + 2;  // halo of the phase magnitudes (samples read past [0, L))
   const int tid = threadIdx.x;
   const long long fd = blockIdx.x;            // f * D + d
@@ -381,10 +384,13 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
   const float2* twp_hi = tw_g + LH + 64;
   const float2* twp_lo = twp_hi + P / 64 + 1;
   for (int i = tid; i < 16 * Rp; i += T) tws[i] = cconj(twp(twp_hi, twp_lo, i * (L / 16)));   // exp(+2 pi i i / (16 R'))
+  // the taps carry the transform's 1/P (a power of two: the products are exactly those of h[j] |b| / P)
+  const float invP = 1.0f / static_cast<float>(P);
   for (int i = tid; i < Rp * nu; i += T) {
     const int c = i / nu, u = i - c * nu, j = c + Rp * u;
-    hc[i] = j < K ? taps[j] : 0.f;
+    hc[i] = j < K ? taps[j] * invP : 0.f;
   }
+  for (int q = tid; q < Q; q += T) accq[q] = 0.f;
   const float2* in = bspec + fd * kb_pad;
   float2 bin[NFOLD][16];
 #pragma unroll
@@ -394,10 +400,6 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
       const int k = tid + s * (L / 16) + f * L;
       bin[f][s] = k < kb ? in[k] : make_float2(0.f, 0.f);
     }
-  float acc[FD_NQ];
-#pragma unroll
-  for (int i = 0; i < FD_NQ; ++i) acc[i] = 0.f;
-  const float invP = 1.0f / static_cast<float>(P);
   float* mr = reinterpret_cast<float*>(buf) + H;   // |b| of the current phase, index a in [-H, L + H)
   __syncthreads();                                  // tables in LDS
 
@@ -414,12 +416,15 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
     } else {
       const float2 at = cconj(twp(twp_hi, twp_lo, (tid * r) & (P - 1)));   // exp(+2 pi i t r / P)
       const int m16 = 16 * Rp - 1;
+      float2 om[NFOLD];                                                    // exp(+2 pi i f r / R')
+#pragma unroll
+      for (int f = 1; f < NFOLD; ++f) om[f] = tws[(16 * f * r) & m16];
 #pragma unroll
       for (int s = 0; s < 16; ++s) {
-        float2 x = cmul(bin[0][s], cmul(at, tws[(s * r) & m16]));
+        float2 x = bin[0][s];
 #pragma unroll
-        for (int f = 1; f < NFOLD; ++f) x = cadd(x, cmul(bin[f][s], cmul(at, tws[((s + 16 * f) * r) & m16])));
-        v[s] = x;
+        for (int f = 1; f < NFOLD; ++f) x = cadd(x, cmul(bin[f][s], om[f]));
+        v[s] = cmul(x, cmul(at, tws[(s * r) & m16]));
       }
     }
     fft_lds<LOGL, true, TW1>(v, buf, tw, tw + LH, tid, tw1);   // starts with a barrier
@@ -427,38 +432,30 @@ __global__ __launch_bounds__((1 << LOGL) / 16) void fd_ifft_env_kernel(
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int oi = S::out_index(tid, i);
-      const float m = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y) * invP;
+      const float m = __builtin_amdgcn_sqrtf(v[i].x * v[i].x + v[i].y * v[i].y);
       mr[oi] = m;
       if (oi < H) mr[oi + L] = m;
       if (oi >= L - H) mr[oi - L] = m;
     }
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < FD_NQ; ++i) {
-      const int q = tid + T * i;
-      if (q < Q) {
-        const int base = n_start + q * R + K - 1;        // sample read by tap j = 0
-        const int c = (base - r) & (Rp - 1);               // taps j = c + R' u read this phase
-        const float* hp = hc + c * nu;
-        const float* mp = mr + ((base - c - r) >> logRp);  // sample of tap c, then one back per u
-        float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-        int u = 0;
-        for (; u + 4 <= nu; u += 4) {
-          s0 = fmaf(hp[u], mp[-u], s0);
-          s1 = fmaf(hp[u + 1], mp[-u - 1], s1);
-          s2 = fmaf(hp[u + 2], mp[-u - 2], s2);
-          s3 = fmaf(hp[u + 3], mp[-u - 3], s3);
-        }
-        for (; u < nu; ++u) s0 = fmaf(hp[u], mp[-u], s0);
-        acc[i] += (s0 + s1) + (s2 + s3);
+    for (int q = tid; q < Q; q += T) {
+      const int base = n_start + q * R + K - 1;        // sample read by tap j = 0
+      const int c = (base - r) & (Rp - 1);               // taps j = c + R' u read this phase
+      const float* hp = hc + c * nu;
+      const float* mp = mr + ((base - c - r) >> logRp);  // sample of tap c, then one back per u
+      float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+      int u = 0;
+      for (; u + 4 <= nu; u += 4) {
+        s0 = fmaf(hp[u], mp[-u], s0);
+        s1 = fmaf(hp[u + 1], mp[-u - 1], s1);
+        s2 = fmaf(hp[u + 2], mp[-u - 2], s2);
+        s3 = fmaf(hp[u + 3], mp[-u - 3], s3);
       }
+      for (; u < nu; ++u) s0 = fmaf(hp[u], mp[-u], s0);
+      accq[q] += (s0 + s1) + (s2 + s3);                  // this thread's own range bin
     }
   }
-#pragma unroll
-  for (int i = 0; i < FD_NQ; ++i) {
-    const int q = tid + T * i;
-    if (q < Q) E[fd * Q + q] = acc[i];
-  }
+  for (int q = tid; q < Q; q += T) E[fd * Q + q] = accq[q];
 }
 
 // The same result with the whole beam window in LDS, where it fits (G floats beside the transform):
@@ -604,8 +601,10 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
 
 template <int LOGL, int NFOLD>
 hipError_t launch_env_t(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
-  const int nu = (p->K + p->fd_R - 1) / p->fd_R;
-  const size_t smem = static_cast<size_t>(16) * p->fd_R * sizeof(float2) + static_cast<size_t>(p->fd_R) * nu * sizeof(float);
+  const size_t smem = fd_env_dyn_lds(p);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fd_ifft_env_kernel<LOGL, NFOLD>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((fd_ifft_env_kernel<LOGL, NFOLD>), dim3(static_cast<unsigned>(F) * p->D), dim3((1 << LOGL) / 16),
                      smem, s, bspec, p->d_fdtw, p->d_taps, E, p->kb, p->kb_pad, p->fd_R, ilog2_host(p->fd_R), p->P,
                      p->n0 - p->hk, p->Q, p->R, p->K);
@@ -626,9 +625,12 @@ hipError_t launch_envw_t(const sonar_plan_s* p, const float2* bspec, int F, floa
 
 template <int LOGL>
 hipError_t launch_env_f(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
-  if (p->fd_win)
-    return p->fd_nfold == 1 ? launch_envw_t<LOGL, 1>(p, bspec, F, E, s) : launch_envw_t<LOGL, 2>(p, bspec, F, E, s);
-  return p->fd_nfold == 1 ? launch_env_t<LOGL, 1>(p, bspec, F, E, s) : launch_env_t<LOGL, 2>(p, bspec, F, E, s);
+  if (p->fd_win) {
+    if (p->fd_nfold == 1) return launch_envw_t<LOGL, 1>(p, bspec, F, E, s);
+    return p->fd_nfold == 2 ? launch_envw_t<LOGL, 2>(p, bspec, F, E, s) : launch_envw_t<LOGL, 3>(p, bspec, F, E, s);
+  }
+  if (p->fd_nfold == 1) return launch_env_t<LOGL, 1>(p, bspec, F, E, s);
+  return p->fd_nfold == 2 ? launch_env_t<LOGL, 2>(p, bspec, F, E, s) : launch_env_t<LOGL, 3>(p, bspec, F, E, s);
 }
 
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s) {
@@ -676,6 +678,11 @@ hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F
 
 // LDS of the window variant of the fused inverse: static (transform buffer, transform twiddles) and
 // dynamic (16 R' phase factors, taps, the beam window)
+size_t fd_env_dyn_lds(const sonar_plan_s* p) {
+  const int nu = (p->K + p->fd_R - 1) / p->fd_R;
+  return static_cast<size_t>(16) * p->fd_R * sizeof(float2) + static_cast<size_t>(p->fd_R) * nu * sizeof(float) +
+         static_cast<size_t>(p->Q) * sizeof(float);
+}
 size_t fd_envw_static_lds(int logL) {
   const int L = 1 << logL;
   return static_cast<size_t>(L + L / 16 + (L / 64 > 0 ? L / 64 : 1) + 64 + (L >= 256 ? 256 : 1)) * sizeof(float2);

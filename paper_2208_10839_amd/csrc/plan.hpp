@@ -224,9 +224,8 @@ constexpr int MT_FIR_TAIL = 64;   // zero words after the last |b| row
 constexpr int MT_MULTI_MAX_ITEMS = 16;   // items of one persistent multi launch (descriptors travel as kernel arguments)
 
 constexpr int FD_MAX_LOGL = 14;        // largest per-phase transform of the FD inverse (LDS): 16384 points
-constexpr int FD_MAX_FOLD = 2;         // stored bins per slot held in registers by the fused FD inverse
+constexpr int FD_MAX_FOLD = 3;         // stored bins per slot held in registers by the fused FD inverse
 constexpr int FD_FOLD1_MAX_L = 8192;   // the default layout keeps one bin per slot up to this transform length
-constexpr int FD_NQ = 8;               // range bins per thread of the fused FD inverse: Q <= FD_NQ * fd_L / 16
 constexpr int FD_GEMM_DIRS = 64;       // directions per FD GEMM workgroup (16 per wavefront)
 constexpr int FD_GEMM_FRAMES = 16;     // frames per FD GEMM workgroup
 constexpr int FD_XCDS = 8;             // accelerator dies the FD GEMM's sample tiles are grouped by
@@ -248,6 +247,7 @@ hipError_t launch_mf_fd(const sonar_plan_s* p, const void* x, int F, float2* ban
 hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, float2* bspec, hipStream_t s);
 size_t fd_envw_static_lds(int logL);
 size_t fd_envw_dyn_lds(const sonar_plan_s* p);
+size_t fd_env_dyn_lds(const sonar_plan_s* p);     // per-phase variant: 16 R' factors, classed taps, Q range-bin sums
 hipError_t launch_fd_ifft_env(const sonar_plan_s* p, const float2* bspec, int F, float* E, hipStream_t s);
 hipError_t launch_fd_ifft_beam(const sonar_plan_s* p, const float2* bspec, int F, float2* beam, hipStream_t s);
 // rows = false skips the complex64 rows (MFMA modes whose beamformer reads only the 16-bit planes)

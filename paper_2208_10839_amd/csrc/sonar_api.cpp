@@ -715,32 +715,35 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
   p->kb_pad = (p->kb + 15) / 16 * 16;
   {
     // Inverse layout: phases of L points with the stored bins folded modulo L.  The fused inverse +
-    // envelope keeps at most FD_MAX_FOLD bins per slot in registers and FD_NQ range bins per thread,
-    // so L >= kb / FD_MAX_FOLD and L >= 16 Q / FD_NQ; by default one bin per slot (L >= kb) while
-    // L <= FD_FOLD1_MAX_L.  The tuner may ask for another L (g_fd_logl_hint).
+    // envelope keeps at most FD_MAX_FOLD bins per slot in registers, so L >= kb / FD_MAX_FOLD; by
+    // default the fewest folds whose L is at most FD_FOLD1_MAX_L (512-thread transforms).  The tuner
+    // may ask for another L (g_fd_logl_hint).
     auto pow2_at_least = [](long long v) {
       long long l = 16;
       while (l < v) l *= 2;
       return l;
     };
-    const long long need_q = 16LL * ((p->Q + FD_NQ - 1) / FD_NQ);
-    const long long need_fold = (p->kb + FD_MAX_FOLD - 1) / FD_MAX_FOLD;
-    const long long hard = pow2_at_least(std::max({need_q, need_fold}));
-    long long L = hard;
-    if (pow2_at_least(p->kb) <= FD_FOLD1_MAX_L) L = std::max(L, pow2_at_least(p->kb));
+    const long long hard = pow2_at_least((p->kb + FD_MAX_FOLD - 1) / FD_MAX_FOLD);
+    long long L = 0;
+    for (int nf = 1; nf <= FD_MAX_FOLD && L == 0; ++nf) {
+      const long long l = pow2_at_least((p->kb + nf - 1) / nf);
+      if (l <= FD_FOLD1_MAX_L) L = l;
+    }
+    if (L == 0) L = hard;
     if (g_fd_logl_hint > 0) L = std::max(hard, 1LL << g_fd_logl_hint);
     // the fused kernel keeps one phase's magnitudes with a circular halo of hk / R' + 2 entries on each
     // side inside its L-point transform buffer (2 (L + L / 16) floats)
     const long long halo = L <= p->P ? (p->K - 1) / 2 / (p->P / L) + 2 : 0;
     p->fd_fused = L <= (1LL << FD_MAX_LOGL) && L <= p->P && p->K <= FD_MAX_TAPS && p->P / L <= FD_MAX_PHASES &&
                   2 * halo + L <= 2 * (L + L / 16);
-    if (!p->fd_fused) L = std::min<long long>(pow2_at_least(need_fold), std::min<long long>(1LL << FD_MAX_LOGL, p->P));
+    if (!p->fd_fused) L = std::min<long long>(hard, std::min<long long>(1LL << FD_MAX_LOGL, p->P));
     p->fd_L = static_cast<int>(L);
     p->fd_logL = ilog2(p->fd_L);
     p->fd_R = p->P / p->fd_L;
     p->fd_nfold = (p->kb + p->fd_L - 1) / p->fd_L;
-    // where the beam window fits in LDS beside the transform, the fused kernel keeps it there and runs
-    // the low-pass once at the end; otherwise it adds each phase's taps as the phase is transformed
+    // LDS: the per-phase variant holds the Q range-bin sums beside the transform; where the whole beam
+    // window fits there too, the fused kernel keeps it and runs the low-pass once at the end instead
+    p->fd_fused = p->fd_fused && fd_envw_static_lds(p->fd_logL) + fd_env_dyn_lds(p) <= 160 * 1024;
     p->fd_win = p->fd_fused && fd_envw_static_lds(p->fd_logL) + fd_envw_dyn_lds(p) <= 160 * 1024;
   }
   const bool fd = !is_td(p);
