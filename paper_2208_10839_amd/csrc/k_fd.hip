@@ -136,13 +136,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   unsigned short* yb = reinterpret_cast<unsigned short*>(ybv);
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  // Workgroups go to the XCDs round-robin by index.  All ndt direction tiles of one sample tile
-  // (bin tile bt, frame tile ft) are given to one XCD back to back, so that XCD reads the tile
-  // from HBM once and its other ndt - 1 readers find it in the XCD's L2.
+  // Workgroups go to the XCDs round-robin by index.  Each XCD takes a contiguous block of sample
+  // tiles (bin tile bt, frame tile ft) in pairs of neighbouring bin tiles, and runs every direction
+  // tile of a pair back to back, the two sample tiles alternating: the XCD reads each sample tile
+  // from HBM once (its other ndt - 1 readers find it in the XCD's L2), and the two 64-byte halves of
+  // each 128-byte line of the beam spectra are written by consecutive workgroups of one L2, so whole
+  // lines reach HBM (a lone half costs a fill read).
   const int xcd = blockIdx.x % FD_XCDS;
   const int jx = blockIdx.x / FD_XCDS;       // position in this XCD's sequence
-  const int dt = jx % ndt;
-  const int yt = xcd + FD_XCDS * (jx / ndt);
+  const int pr = jx % (2 * ndt);             // position within the pair's run
+  const int dt = pr >> 1;
+  const int yt = xcd * (static_cast<int>(gridDim.x) / ndt / FD_XCDS) + 2 * (jx / (2 * ndt)) + (pr & 1);
   if (yt >= nyt) return;
   const int bt = yt % nbt;
   const int ft = yt / nbt;
@@ -286,7 +290,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // Lane holds (direction 4 grp + i, frame r16) for the chunk's CHB = 8 bins: one 64-byte segment of
     // each of 4 output rows.  A quad transpose gives lane q of each quad the bins 2q, 2q + 1 of the
     // quad's rows (its 4 frames x the same direction), so each store writes 16 whole 64-byte segments
-    // (4 lanes each) instead of 64 scattered 16-byte pieces.
+    // (4 lanes each) instead of 64 scattered 16-byte pieces.  The stores are non-temporal: the beam
+    // spectra stream out without evicting the band spectra that the sample tile's other direction
+    // tiles still read from L2.
     static_assert(CHB == 8, "one 16-byte bin pair per quad lane");
     const int q = lane & 3;
     const int f_quad = ft * FD_GEMM_FRAMES + (r16 & ~3);   // frame held by lane 0 of the quad
@@ -302,7 +308,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         for (int j = 0; j < 4; ++j) {
           const int f = f_quad + j;
           if (f < F)
-            *reinterpret_cast<f32x4*>(bspec + (static_cast<long long>(f) * D + d_out) * kb_pad + k0 + 2 * q) = e[j];
+            __builtin_nontemporal_store(e[j], reinterpret_cast<f32x4*>(bspec + (static_cast<long long>(f) * D + d_out) * kb_pad + k0 + 2 * q));
         }
       }
     }
@@ -578,7 +584,7 @@ hipError_t launch_fd_gemm(const sonar_plan_s* p, const float2* band, int F, floa
   const int ndt = (p->D + FD_GEMM_DIRS - 1) / FD_GEMM_DIRS;
   const int nft = (F + FD_GEMM_FRAMES - 1) / FD_GEMM_FRAMES;
   const int nyt = nbt * nft;                                  // sample tiles
-  const int nyt8 = (nyt + FD_XCDS - 1) / FD_XCDS * FD_XCDS;   // padded to whole rounds over the XCDs
+  const int nyt8 = (nyt + 2 * FD_XCDS - 1) / (2 * FD_XCDS) * (2 * FD_XCDS);   // whole pairs on every XCD
   const dim3 grid(static_cast<unsigned>(nyt8) * ndt);
   switch (p->bf_mode) {
     case SONAR_BF_FD_FP32:
