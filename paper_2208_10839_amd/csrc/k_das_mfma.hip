@@ -43,7 +43,8 @@
 // the four residue wavefronts) and the low-pass + decimation runs as a banded
 // Toeplitz product on MFMA: with four planes on BF16 (|b| and taps as hi + lo
 // terms, three products), with two planes on FP16 (|b| as one FP16 term scaled
-// per workgroup by a power of two, taps as hi + lo, two products).
+// per workgroup by a power of two, taps as hi + lo, two products; TD_BF16G: the taps
+// as one FP16 term, one product).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -395,23 +396,28 @@ __device__ __forceinline__ void mt_tile(
   // The product is taken as E^T = H^T |b|^T: the same fragments with the operands swapped,
   // so lane l receives range bins 8 g + 4 (l / 32) + 0..3 (g = v / 4) of direction l % 32
   // and writes them with one 16-byte store per g.
+  // TD_BF16G: the taps as one FP16 term (the largest scaled into [2^13, 2^14), so every tap keeps 11
+  // significant bits): one product per K-step instead of the hi + lo pair
+  constexpr bool FIR1 = W1 && !F16;
 #define MT_FIR_LOAD(H0, L0, H1, L1, H2, L2, H3, L3, KB)                                               \
   {                                                                                                    \
     const uint4* fp = ftab + 2 * (KB) * 64 + lane;                                                     \
     H0 = fp[0];                                                                                        \
-    L0 = fp[64];                                                                                       \
     H1 = fp[128];                                                                                      \
-    L1 = fp[192];                                                                                      \
     H2 = fp[256];                                                                                      \
-    L2 = fp[320];                                                                                      \
     H3 = fp[384];                                                                                      \
-    L3 = fp[448];                                                                                      \
+    if constexpr (!FIR1) {                                                                             \
+      L0 = fp[64];                                                                                     \
+      L1 = fp[192];                                                                                    \
+      L2 = fp[320];                                                                                    \
+      L3 = fp[448];                                                                                    \
+    }                                                                                                  \
   }
 #define MT_FIR_STEP16(H, L, KS, ACC)                                                                   \
   {                                                                                                    \
     const uint4 bb = *reinterpret_cast<const uint4*>(bh + 16 * (KS));                                  \
     ACC = mfma_f16(H, bb, ACC);                                                                        \
-    ACC = mfma_f16(L, bb, ACC);                                                                        \
+    if constexpr (!FIR1) ACC = mfma_f16(L, bb, ACC);                                                   \
   }
 #define MT_FIR_STEP(H, L, KS, ACC)                                                                     \
   if constexpr (FIR16) MT_FIR_STEP16(H, L, KS, ACC) else                                               \
@@ -439,8 +445,8 @@ __device__ __forceinline__ void mt_tile(
     const unsigned short* bh = b16 + (lane & 31) * NSP16 + 32 * cb * R + 8 * (lane >> 5);
     (void)ah;
     (void)bh;
-    uint4 ah0, al0, ah1, al1, ah2, al2, ah3, al3;   // tap fragments, batch A
-    uint4 bh0, bl0, bh1, bl1, bh2, bl2, bh3, bl3;   // batch B
+    uint4 ah0, al0 = {}, ah1, al1 = {}, ah2, al2 = {}, ah3, al3 = {};   // tap fragments, batch A
+    uint4 bh0, bl0 = {}, bh1, bl1 = {}, bh2, bl2 = {}, bh3, bl3 = {};   // batch B
     MT_FIR_LOAD(ah0, al0, ah1, al1, ah2, al2, ah3, al3, k0)
     for (int kb = k0; kb < k1; kb += 8) {
       const bool more = kb + 4 < k1;

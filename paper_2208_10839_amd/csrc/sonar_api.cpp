@@ -384,7 +384,8 @@ int build_mt_tables(sonar_plan_s* p, const double* pos, const double* dirs, cons
   p->mt_flop_per_frame = chunks * (p->mt_nwave / res) * 4 * mfma_per_chunk * (2LL * 32 * 32 * 16) * p->mt_nqt;
   // low-pass: 3 MFMAs per K-step and column block (BF16 hi/lo x hi/lo), 2 with two sample planes
   // (FP16 taps hi + lo times one FP16 term of |b|)
-  const int fir_mfma = mt_planes(p) == 2 ? 2 : 3;
+  // (TD_BF16G: taps as one FP16 term, one product)
+  const int fir_mfma = p->bf_mode == SONAR_BF_TD_BF16G ? 1 : (mt_planes(p) == 2 ? 2 : 3);
   for (int q0 = 0; q0 < p->mt_qc; q0 += 32) {
     const int nval = std::min(32, p->mt_qc - q0);
     p->mt_flop_per_frame += static_cast<long long>((nval - 1) * p->R + p->K + 15) / 16 * fir_mfma *
