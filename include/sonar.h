@@ -397,8 +397,10 @@ int sonar_tune_cache(const char* path);
  *
  * sonar_plan_enable_gradients -- allocates the gradient workspace of the plan
  * (once; the bytes are added to SONAR_Q_WORKSPACE_BYTES), including the beam
- * window [max_frames][D][G'] that sonar_energyscape_backward fills.  Frequency-domain
- * plans need P <= 32768 (SONAR_E_UNSUPPORTED otherwise).
+ * window [max_frames][D][G'] that sonar_energyscape_backward fills.  Every FFT length
+ * the plan accepts is supported: the P-point transforms of the adjoint run as P / L
+ * phase transforms of L = min(P / 2, 16384) points.  The frequency-domain workspace
+ * holds max_frames * D * P complex64 values (FP32 pairs) for those phase transforms.
  */
 int sonar_plan_enable_gradients(sonar_plan plan);
 
@@ -413,7 +415,7 @@ int sonar_plan_enable_gradients(sonar_plan plan);
  *                complex64 [F][M][P] G_yhat over Z_P (sample n at index n).
  *                FD modes: complex64 [F][Kb][M], G_Yhat on the band bins in
  *                the layout of the FD matched-filter buffer.
- *   dx_out     : float [F][M][N], or NULL (needs dyhat_out; P <= 32768).
+ *   dx_out     : float [F][M][N], or NULL (needs dyhat_out).
  *   dpos_out   : double [M][3] dL/dp_m summed over the F frames, or NULL.
  * SONAR_E_INVALID before sonar_plan_enable_gradients.
  */

@@ -14,9 +14,11 @@
 //
 // (w is the beam-window position, r the position in a matched-filter row, rel
 // the row offset of tap 0; the row layout and weights are those of the forward
-// kernels.)  The complex P-point DFT of G_yhat runs as two NF-point transforms
-// of its even and odd samples; the inverse is the forward matched filter's
-// two-parity inverse.
+// kernels.)  The complex P-point DFTs of G_yhat and G_b run as P / L transforms of
+// L points, one per phase (samples nph a + ph), recombined with exp(-2 pi i k ph / P):
+// L = NF (even and odd samples) while it fits one workgroup's LDS, else the big
+// matched filter's 2^MB_LOGN2-point rows; the inverse is the forward matched
+// filter's two-parity inverse (in LDS, or over global memory for the big rows).
 //
 // The exact-phase (frequency-domain) beamformer b_d = IDFT_P(B_d) on the window,
 // B_d[k] = (1/M) sum_m Y_m[k] exp(-2 pi i k Dl[d][m] / P) over the band bins, has
@@ -179,44 +181,69 @@ __device__ __forceinline__ void load_tw(float2* tw, const float2* __restrict__ t
   for (int i = tid; i < LEN; i += nthreads) tw[i] = tw_g[i];
 }
 
-// S[ch][par][k] = DFT_NF(g[2n + par])[k]
-template <int LOGNF>
-__global__ __launch_bounds__((1 << LOGNF) / 16) void mfadj_fft_kernel(const float2* __restrict__ gy,
-                                                                      const float2* __restrict__ tw_g,
-                                                                      float2* __restrict__ S) {
-  using Sh = FftShape<LOGNF>;
-  constexpr int NF = Sh::NF;
+// Polyphase split of a P-point DFT, P = nph L:
+//   DFT_P(g)[k] = sum_ph exp(-2 pi i k ph / P) S_ph[k mod L],  S_ph = DFT_L(g[nph a + ph]), a < L.
+// S[ch][ph][j] = DFT_L(g[nph a + ph])[j] for the row of channel ch placed on Z_P: row position i
+// (i < G) sits at sample (wstart + i) mod P, every other sample is zero.  twl holds the L-point
+// two-level table (exp(-2 pi i 64 t / L), t < max(L/64, 1), then exp(-2 pi i t / L), t < 64).
+template <int LOGL>
+__global__ __launch_bounds__((1 << LOGL) / 16) void phase_fft_kernel(const float2* __restrict__ g, long long gstride,
+                                                                     const float2* __restrict__ twl,
+                                                                     float2* __restrict__ S, int G, int P, int wstart,
+                                                                     int nph) {
+  using Sh = FftShape<LOGL>;
+  constexpr int L = Sh::NF;
   constexpr int T = Sh::T;
-  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
-  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
+  constexpr int NHI = L / 64 > 0 ? L / 64 : 1;
   __shared__ float2 lds[Sh::LDS_ELEMS];
-  __shared__ float2 tw[TWLEN];
+  __shared__ float2 tw[NHI + 64];
   const int tid = threadIdx.x;
-  const int par = blockIdx.x & 1;
-  const long long ch = blockIdx.x >> 1;
-  load_tw<LOGNF>(tw, tw_g, tid, T);
+  const int ph = blockIdx.x % nph;
+  const long long ch = blockIdx.x / nph;
+  for (int i = tid; i < NHI + 64; i += T) tw[i] = twl[i];
   __syncthreads();
-  const float2* in = gy + ch * 2 * NF;
+  const float2* in = g + ch * gstride;
   float2 v[16];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) v[r] = in[2 * (tid + r * (NF / 16)) + par];
-  fft_lds<LOGNF, false>(v, lds, tw, tw + NHI, tid);
-  float2* out = S + (ch * 2 + par) * NF;
+  for (int r = 0; r < 16; ++r) {
+    const int n = nph * (tid + r * (L / 16)) + ph;
+    const int i = (n - wstart) & (P - 1);
+    v[r] = i < G ? in[i] : make_float2(0.f, 0.f);
+  }
+  fft_lds<LOGL, false>(v, lds, tw, tw + NHI, tid);
+  float2* out = S + (ch * nph + ph) * L;
 #pragma unroll
   for (int i = 0; i < 16; ++i) out[Sh::out_index(tid, i)] = v[i];
 }
 
-// V[ch][k] = conj(C[k]) (E[k mod NF] + exp(-2 pi i k / P) O[k mod NF]), k in [0, NF]
+// exp(-2 pi i e / P), 0 <= e < P, from the plan's table of exp(-2 pi i t / P) for t <= NF + 63
+// (tw_g: the two-level table of d_tw; e > NF by the half-turn symmetry)
+__device__ __forceinline__ float2 tw_p(const float2* __restrict__ tw_g, int NF, int e) {
+  const float2* hi = tw_g + fft_nhi(NF) + 64;          // exp(-2 pi i 64 t / P)
+  const float2* lo = hi + fft_nhp(NF);                 // exp(-2 pi i t / P)
+  if (e <= NF) return cmul(hi[e >> 6], lo[e & 63]);
+  const float2 w = cmul(hi[(e - NF) >> 6], lo[(e - NF) & 63]);
+  return make_float2(-w.x, -w.y);
+}
+
+// DFT_P(g)[k] of channel ch from its nph phase transforms (layout of phase_fft_kernel)
+__device__ __forceinline__ float2 phase_sum(const float2* __restrict__ S, const float2* __restrict__ tw_g,
+                                            long long ch, int nph, int L, int NF, int P, int k) {
+  const int km = k & (L - 1);
+  const float2* s = S + ch * nph * static_cast<long long>(L) + km;
+  float2 acc = s[0];
+  for (int ph = 1; ph < nph; ++ph)
+    acc = cadd(acc, cmul(tw_p(tw_g, NF, (k * ph) & (P - 1)), s[static_cast<long long>(ph) * L]));
+  return acc;
+}
+
+// V[ch][k] = conj(C[k]) DFT_P(G_yhat[ch])[k], k in [0, NF]
 __global__ void mfadj_mul_kernel(const float2* __restrict__ S, const float2* __restrict__ cspec,
-                                 const float2* __restrict__ tw_g, float2* __restrict__ V, int NF) {
+                                 const float2* __restrict__ tw_g, float2* __restrict__ V, int NF, int nph, int L) {
   const int k = blockIdx.y * blockDim.x + threadIdx.x;
   const long long ch = blockIdx.x;
   if (k > NF) return;
-  const float2* twp_hi = tw_g + fft_nhi(NF) + 64;                   // exp(-2 pi i 64 t / P)
-  const float2* twp_lo = tw_g + fft_nhi(NF) + 64 + fft_nhp(NF);     // exp(-2 pi i t / P)
-  const int km = k & (NF - 1);
-  const float2 e = S[ch * 2 * NF + km], o = S[(ch * 2 + 1) * NF + km];
-  const float2 gk = cadd(e, cmul(cmul(twp_hi[k >> 6], twp_lo[k & 63]), o));
+  const float2 gk = phase_sum(S, tw_g, ch, nph, L, NF, 2 * NF, k);
   V[ch * (NF + 1) + k] = cmul(cconj(cspec[k]), gk);
 }
 
@@ -268,51 +295,13 @@ __device__ __forceinline__ float2 steer(int k, double dl_over_p) {
   return make_float2(c, s);
 }
 
-// S[ch][par][k] = DFT_NF(g[2n + par])[k], g = G_b of channel ch = f * D + d placed on Z_P:
-// window position i sits at sample (wstart + i) mod P
-template <int LOGNF>
-__global__ __launch_bounds__((1 << LOGNF) / 16) void gfd_fft_kernel(const float2* __restrict__ gb,
-                                                                     const float2* __restrict__ tw_g,
-                                                                     float2* __restrict__ S, int G, int P,
-                                                                     int wstart) {
-  using Sh = FftShape<LOGNF>;
-  constexpr int NF = Sh::NF;
-  constexpr int T = Sh::T;
-  constexpr int NHI = NF / 64 > 0 ? NF / 64 : 1;
-  constexpr int TWLEN = NHI + 64 + (NF / 64 + 1) + 64;
-  __shared__ float2 lds[Sh::LDS_ELEMS];
-  __shared__ float2 tw[TWLEN];
-  const int tid = threadIdx.x;
-  const int par = blockIdx.x & 1;
-  const long long ch = blockIdx.x >> 1;
-  load_tw<LOGNF>(tw, tw_g, tid, T);
-  __syncthreads();
-  const float2* in = gb + ch * G;
-  float2 v[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int n = 2 * (tid + r * (NF / 16)) + par;
-    const int i = (n - wstart) & (P - 1);
-    v[r] = i < G ? in[i] : make_float2(0.f, 0.f);
-  }
-  fft_lds<LOGNF, false>(v, lds, tw, tw + NHI, tid);
-  float2* out = S + (ch * 2 + par) * NF;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) out[Sh::out_index(tid, i)] = v[i];
-}
-
-// G_B[ch][j] = (E[k mod NF] + exp(-2 pi i k / P) O[k mod NF]) / P, k = k_lo + j
+// G_B[ch][j] = DFT_P(G_b[ch] on its window positions)[k] / P, k = k_lo + j
 __global__ void gfd_band_kernel(const float2* __restrict__ S, const float2* __restrict__ tw_g,
-                                float2* __restrict__ GB, int NF, int P, int k_lo, int kb) {
+                                float2* __restrict__ GB, int NF, int P, int k_lo, int kb, int nph, int L) {
   const int j = blockIdx.y * blockDim.x + threadIdx.x;
   const long long ch = blockIdx.x;
   if (j >= kb) return;
-  const int k = k_lo + j;
-  const float2* twp_hi = tw_g + fft_nhi(NF) + 64;
-  const float2* twp_lo = tw_g + fft_nhi(NF) + 64 + fft_nhp(NF);
-  const int km = k & (NF - 1);
-  const float2 e = S[ch * 2 * NF + km], o = S[(ch * 2 + 1) * NF + km];
-  const float2 g = cadd(e, cmul(cmul(twp_hi[k >> 6], twp_lo[k & 63]), o));
+  const float2 g = phase_sum(S, tw_g, ch, nph, L, NF, P, k_lo + j);
   const float inv_p = 1.0f / static_cast<float>(P);
   GB[ch * kb + j] = make_float2(g.x * inv_p, g.y * inv_p);
 }
@@ -395,28 +384,20 @@ __global__ void gfd_spec_kernel(const float2* __restrict__ GY, const float2* __r
   V[ch * (NF + 1) + k] = v;
 }
 
-template <int LOGNF>
-hipError_t launch_gfd_fft_t(const sonar_plan_s* p, const float2* gb, int F, hipStream_t s) {
-  constexpr int T = (1 << LOGNF) / 16;
-  hipLaunchKernelGGL((gfd_fft_kernel<LOGNF>), dim3(2 * F * p->D), dim3(T), 0, s, gb, p->d_tw, p->d_gscr, p->G,
-                     p->P, p->n0 - p->hk);
+// Transform length of the polyphase split: L = NF (two phases) while an NF-point transform fits
+// one workgroup's LDS, else L = 2^MB_LOGN2 and P / L phases (the big matched filter's row length,
+// whose table is d_tw2)
+int adj_logl(const sonar_plan_s* p) { return p->NF > (1 << MB_LOGN2) ? MB_LOGN2 : p->logNF; }
+
+template <int LOGL>
+hipError_t launch_phase_fft_t(const sonar_plan_s* p, const float2* g, long long gstride, long long chans, int G,
+                              int wstart, hipStream_t s) {
+  constexpr int T = (1 << LOGL) / 16;
+  const int nph = p->P >> LOGL;
+  const float2* twl = LOGL == p->logNF ? p->d_tw : p->d_tw2;
+  hipLaunchKernelGGL((phase_fft_kernel<LOGL>), dim3(static_cast<unsigned>(chans * nph)), dim3(T), 0, s, g, gstride,
+                     twl, p->d_gscr, G, p->P, wstart, nph);
   return hipGetLastError();
-}
-
-template <int LOGNF>
-hipError_t launch_mfinv_t(const sonar_plan_s* p, const float2* V, int F, float* dx, hipStream_t s);
-
-template <int LOGNF>
-hipError_t launch_mfadj_t(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
-  constexpr int T = (1 << LOGNF) / 16;
-  const int chans = F * p->M;
-  hipLaunchKernelGGL((mfadj_fft_kernel<LOGNF>), dim3(2 * chans), dim3(T), 0, s, gy, p->d_tw, p->d_gscr);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(mfadj_mul_kernel, dim3(chans, (p->NF + 1 + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_cspec,
-                     p->d_tw, p->d_spec, p->NF);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  return launch_mfinv_t<LOGNF>(p, p->d_spec, F, dx, s);
 }
 
 template <int LOGNF>
@@ -426,8 +407,8 @@ hipError_t launch_mfinv_t(const sonar_plan_s* p, const float2* V, int F, float* 
   return hipGetLastError();
 }
 
-#define SONAR_LOGNF_DISPATCH(NAME, ...)          \
-  switch (p->logNF) {                             \
+#define SONAR_LOG_DISPATCH(LOG, NAME, ...)       \
+  switch (LOG) {                                  \
     case 4: return NAME<4>(__VA_ARGS__);          \
     case 5: return NAME<5>(__VA_ARGS__);          \
     case 6: return NAME<6>(__VA_ARGS__);          \
@@ -442,25 +423,38 @@ hipError_t launch_mfinv_t(const sonar_plan_s* p, const float2* V, int F, float* 
     default: return hipErrorInvalidValue;         \
   }
 
-hipError_t gfd_fft(const sonar_plan_s* p, const float2* gb, int F, hipStream_t s) {
-  SONAR_LOGNF_DISPATCH(launch_gfd_fft_t, p, gb, F, s)
+// phase transforms of chans rows (stride gstride, G values from window sample wstart) into d_gscr
+hipError_t phase_fft(const sonar_plan_s* p, const float2* g, long long gstride, long long chans, int G, int wstart,
+                     hipStream_t s) {
+  SONAR_LOG_DISPATCH(adj_logl(p), launch_phase_fft_t, p, g, gstride, chans, G, wstart, s)
 }
 
-hipError_t mfadj(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
-  SONAR_LOGNF_DISPATCH(launch_mfadj_t, p, gy, F, dx, s)
-}
-
+// dx = Re IDFT_P(V) cut to N, V one-sided per (frame, microphone)
 hipError_t mfinv(const sonar_plan_s* p, const float2* V, int F, float* dx, hipStream_t s) {
-  SONAR_LOGNF_DISPATCH(launch_mfinv_t, p, V, F, dx, s)
+  if (p->NF > (1 << MB_LOGN2)) return launch_big_inv_real(p, V, F * p->M, dx, s);
+  SONAR_LOG_DISPATCH(p->logNF, launch_mfinv_t, p, V, F, dx, s)
+}
+
+// matched-filter adjoint of the time-domain path: dx from G_yhat over Z_P
+hipError_t mfadj(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
+  const int chans = F * p->M;
+  hipError_t e = phase_fft(p, gy, p->P, chans, p->P, 0, s);
+  if (e != hipSuccess) return e;
+  const int L = 1 << adj_logl(p);
+  hipLaunchKernelGGL(mfadj_mul_kernel, dim3(chans, (p->NF + 1 + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_cspec,
+                     p->d_tw, p->d_spec, p->NF, p->P / L, L);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return mfinv(p, p->d_spec, F, dx, s);
 }
 
 // exact-phase beamformer: G_B, then dDl / dpos and G_Y / dx
 hipError_t vjp_fd(const sonar_plan_s* p, const float2* mf, const float2* gb, int F, float2* dyhat, float* dx,
                   double* dpos, hipStream_t s) {
-  hipError_t e = gfd_fft(p, gb, F, s);
+  hipError_t e = phase_fft(p, gb, p->G, static_cast<long long>(F) * p->D, p->G, p->n0 - p->hk, s);
   if (e != hipSuccess) return e;
+  const int L = 1 << adj_logl(p);
   hipLaunchKernelGGL(gfd_band_kernel, dim3(F * p->D, (p->kb + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_tw,
-                     p->d_gband, p->NF, p->P, p->k_lo, p->kb);
+                     p->d_gband, p->NF, p->P, p->k_lo, p->kb, p->P / L, L);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (dpos) {
     int ms = 1;

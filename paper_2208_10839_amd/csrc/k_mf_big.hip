@@ -17,7 +17,9 @@
 //   inverse  : big_inv_rows (per output parity and k1: parity twiddle,
 //              N2-point inverse FFT -> u), big_inv_radix (twiddle, radix-R
 //              inverse, Nyquist term, 1/P, scatter into the halo'd rows and
-//              the BF16 planes).
+//              the BF16 planes);
+//   real inverse: big_inv_rows, then big_inv_real (the real part cut to N samples:
+//              the adjoint of the matched filter in the gradient path).
 // Scratch (plan workspace): per channel 2 NF complex values; t and Z first,
 // then the two parities of u.
 #include <hip/hip_runtime.h>
@@ -248,6 +250,47 @@ __global__ __launch_bounds__(256) void big_inv_radix(const float2* __restrict__ 
   }
 }
 
+// Real part of the same inverse, cut to n < N: out[ch][n] = Re (y + (-1)^par V[NF]) / P
+// (the matched filter's adjoint, whose one-sided spectrum V is conjugate-symmetric only in
+// what the real part keeps)
+template <int R>
+__global__ __launch_bounds__(256) void big_inv_real(const float2* __restrict__ V, const float2* __restrict__ tw_g,
+                                                    const float2* __restrict__ scratch, float* __restrict__ out,
+                                                    int N, int P) {
+  constexpr int NF = R * N2;
+  const int n2 = blockIdx.x * 256 + threadIdx.x;
+  const int par = blockIdx.y & 1;
+  const long long ch = blockIdx.y >> 1;
+  const BigTw tw = big_tw(tw_g, NF);
+  const float2* u = scratch + ch * 2 * NF + static_cast<long long>(par) * NF;
+  float2 v[R];
+#pragma unroll
+  for (int k1 = 0; k1 < R; ++k1) {
+    const float2 a = u[static_cast<long long>(k1) * N2 + n2];
+    v[k1] = k1 == 0 ? a : cmul(a, cconj(tw.nf(n2 * k1)));
+  }
+  dftR<R, true>(v);
+  const float ny = V[ch * (NF + 1) + NF].x;
+  const float inv_p = 1.0f / static_cast<float>(P);
+  const float sgn = par ? -1.0f : 1.0f;
+  float* o = out + ch * N;
+#pragma unroll
+  for (int n1 = 0; n1 < R; ++n1) {
+    const int n = 2 * (N2 * n1 + n2) + par;
+    if (n < N) o[n] = (v[n1].x + sgn * ny) * inv_p;
+  }
+}
+
+template <int R>
+hipError_t inverse_real_t(const sonar_plan_s* p, const float2* V, int chans, float* out, hipStream_t s) {
+  hipLaunchKernelGGL((big_inv_rows<R>), dim3(chans * 2 * R), dim3(N2 / 16), 0, s, V, p->d_tw, p->d_tw2, p->d_big);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((big_inv_real<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, V, p->d_tw, p->d_big, out, p->N,
+                     p->P);
+  return hipGetLastError();
+}
+
 template <int R, typename TIn>
 hipError_t forward_t(const sonar_plan_s* p, const void* x, int F, float2* spec, float2* band, hipStream_t s) {
   constexpr int NF = R * N2;
@@ -307,6 +350,17 @@ hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2*
     case 4: return inverse_t<4>(p, F, yext, s, rows);
     case 8: return inverse_t<8>(p, F, yext, s, rows);
     case 16: return inverse_t<16>(p, F, yext, s, rows);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_big_inv_real(const sonar_plan_s* p, const float2* V, int chans, float* out, hipStream_t s) {
+  if (!p->d_big || !p->d_tw2) return hipErrorInvalidValue;
+  switch (p->NF / N2) {
+    case 2: return inverse_real_t<2>(p, V, chans, out, s);
+    case 4: return inverse_real_t<4>(p, V, chans, out, s);
+    case 8: return inverse_real_t<8>(p, V, chans, out, s);
+    case 16: return inverse_real_t<16>(p, V, chans, out, s);
     default: return hipErrorInvalidValue;
   }
 }

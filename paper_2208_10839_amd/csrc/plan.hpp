@@ -236,6 +236,8 @@ hipError_t launch_build_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t init_mt_kernel_attributes();
 hipError_t launch_mf_big_td(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows);
 hipError_t launch_mf_big_fd(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s);
+// out[ch][n] = Re IDFT_P(V[ch]) for n < N from one-sided spectra V[ch][0..NF] (chans <= max_frames * M)
+hipError_t launch_big_inv_real(const sonar_plan_s* p, const float2* V, int chans, float* out, hipStream_t s);
 size_t mt_smem_bytes(const sonar_plan_s* p);
 hipError_t launch_das_mfma_env(const sonar_plan_s* p, const float2* yext, int F, float* E, hipStream_t s);
 // persistent beamformer + envelope over n <= MT_MULTI_MAX_ITEMS items of compatible MFMA TD plans

@@ -1410,8 +1410,6 @@ int ensure_beam_workspace(sonar_plan_s* p, size_t* total) {
 int sonar_plan_enable_gradients(sonar_plan p) {
   if (!p) return fail(SONAR_E_INVALID, "plan is NULL");
   const bool td = is_td(p);
-  if (!td && p->NF > (1 << 14))
-    return fail(SONAR_E_UNSUPPORTED, "frequency-domain gradients: FFT length %d above 32768 is not supported", p->P);
   if (p->grad_on) return SONAR_OK;
   const size_t mf = static_cast<size_t>(p->max_frames);
   size_t total = 0;
@@ -1456,8 +1454,6 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
     return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
   if (dpos_out && (p->bf_mode == SONAR_BF_TD_F16 || p->bf_mode == SONAR_BF_TD_BF16G))
     return fail(SONAR_E_UNSUPPORTED, "TD_F16 / TD_BF16G: gridded delays are piecewise constant in the positions");
-  if (dx_out && p->NF > (1 << 14))
-    return fail(SONAR_E_UNSUPPORTED, "dx_out: FFT length %d above 32768 is not supported for gradients", p->P);
   const hipError_t e = launch_energyscape_vjp(p, static_cast<const float2*>(mf_in), static_cast<float2*>(beam_inout),
                                               dE, F, static_cast<float2*>(dyhat_out), dx_out, dpos_out, stream);
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "gradient launch");

@@ -84,10 +84,23 @@ def test_vjp_matches_oracle(gpu, torch_mod, mode):
     """Each step against the oracle applied to the GPU's own input of that step (the
     envelope derivative b/|b| is ill-conditioned where |b| is small, so G_b is checked on
     the GPU's forward beam), and the end results dx, dp against the oracle's whole chain."""
+    _check_vjp(gpu, torch_mod, mode, n_dirs=37, fft_len=0)
+
+
+@pytest.mark.parametrize("mode,fft_len", [("fd", 65536), ("td", 65536), ("fd", 131072)])
+def test_vjp_long_fft_matches_oracle(gpu, torch_mod, mode, fft_len):
+    """FFT lengths above 32768: the adjoint's P-point transforms run as P / 16384 phase
+    transforms of 16384 points and dx through the four-step inverse; same bars as above."""
+    _check_vjp(gpu, torch_mod, mode, n_dirs=11, fft_len=fft_len)
+
+
+def _check_vjp(gpu, torch_mod, mode, n_dirs, fft_len):
     torch = torch_mod
-    w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=37)
-    _say(f"case vjp {mode}: M=32 N=4096 D=37 F=2")
-    plan = _plan(gpu, w, mode, max_frames=2)
+    w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=n_dirs)
+    _say(f"case vjp {mode}: M=32 N=4096 D={n_dirs} F=2 fft_len={fft_len or 'default'}")
+    plan = _plan(gpu, w, mode, max_frames=2, fft_len=fft_len)
+    if fft_len:
+        assert plan.P == fft_len
     x = torch.from_numpy(w.x).cuda()
     mf = plan.matched_filter(x)
     beam = plan.beamform(mf)
