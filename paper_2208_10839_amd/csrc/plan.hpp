@@ -162,16 +162,31 @@ constexpr int PDM_MAX_MICS = 128;
 constexpr int PDM_MAX_TAPS = 513;
 constexpr size_t PDM_LDS_LIMIT = 150 * 1024;
 
+// Matrix-core variant: 16-output x 16-microphone tiles on int8 MFMA (16x16x64), PDM_MT_THREADS
+// threads per workgroup; used where the tile's tap operand (4 PDM_MT_KS_MAX KB at most) fits
+constexpr int PDM_MT_THREADS = 512;
+constexpr int PDM_MT_KS_MAX = 16;   // 64-tick K-steps per tile: 15 D + K <= 1024
+constexpr size_t PDM_MT_LDS_PAIR = 80 * 1024;   // two workgroups per CU below this
+
 struct sonar_pdm_s {
   int M = 0, N = 0, D = 1, K = 0, C = 0, W = 1, max_frames = 1, device = 0;
   int NB = 0, SW = 0;          // outputs per workgroup, staged words per microphone
   float* d_lut = nullptr;      // [C][256] byte tables of the reversed taps (C = 4 ceil(K/32), zero past K)
   float* d_gcum = nullptr;     // [K + 1] prefix sums of the reversed taps (windows at the recording's edges)
+  // matrix-core variant (mt = true): taps as integers r = round(g 2^qshift), |r| < 2^29, split into
+  // four signed base-256 digits
+  bool mt = false;
+  int KS = 0, qshift = 0, rows = 0;   // K-steps per tile, tap scale, staged microphone rows (16 ceil(M/16))
+  unsigned* d_qtab = nullptr;   // [KS][4 digits][64 lanes][4 words]: the Toeplitz tap operand of a tile
+  long long* d_rcum = nullptr;  // [K + 1] prefix sums of r
 };
 
 int pdm_span_words(int NB, int D, int K);
 int pdm_tables(int K);
 size_t pdm_lds_bytes(int M, int SW, int C);
+int pdm_mt_ksteps(int D, int K);
+int pdm_mt_span_words(int NB, int D, int KS);
+size_t pdm_mt_lds_bytes(int rows, int SW, int KS);
 hipError_t launch_pdm_tables(sonar_pdm_s* p, const double* d_taps64, hipStream_t s);
 hipError_t init_pdm_kernel_attributes(const sonar_pdm_s* p, size_t lds);
 hipError_t launch_pdm_demod(const sonar_pdm_s* p, const unsigned* words, int F, float* x, hipStream_t s);

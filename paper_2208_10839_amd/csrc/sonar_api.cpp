@@ -1651,6 +1651,8 @@ int sonar_pdm_destroy(sonar_pdm p) {
   if (!p) return SONAR_OK;
   (void)hipFree(p->d_lut);
   (void)hipFree(p->d_gcum);
+  (void)hipFree(p->d_qtab);
+  (void)hipFree(p->d_rcum);
   delete p;
   return SONAR_OK;
 }
@@ -1699,12 +1701,39 @@ int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* 
     delete p;
     return fail(SONAR_E_HIP, "hipGetDevice failed");
   }
-  for (int nb = 256; nb >= 64; nb /= 2) {
-    const int sw = pdm_span_words(nb, p->D, K);
-    if (pdm_lds_bytes(p->M, sw, p->C) <= PDM_LDS_LIMIT) {
-      p->NB = nb;
-      p->SW = sw;
-      break;
+  // matrix-core variant where a tile's tap operand fits: the largest tile of outputs that
+  // leaves room for two workgroups per CU, else the largest that fits one
+  const int KS = pdm_mt_ksteps(p->D, K);
+  p->rows = 16 * ((p->M + 15) / 16);
+  if (KS <= PDM_MT_KS_MAX) {
+    for (const size_t cap : {PDM_MT_LDS_PAIR, PDM_LDS_LIMIT}) {
+      for (int nb = 512; nb >= 64 && !p->mt; nb /= 2) {
+        const int sw = pdm_mt_span_words(nb, p->D, KS);
+        if (pdm_mt_lds_bytes(p->rows, sw, KS) <= cap) {
+          p->mt = true;
+          p->NB = nb;
+          p->SW = sw;
+          p->KS = KS;
+        }
+      }
+      if (p->mt) break;
+    }
+  }
+  if (p->mt) {
+    // integer taps r = round(g 2^qshift) with |r| <= 2^29: four signed base-256 digits
+    double amax = 0.0;
+    for (double v : taps) amax = std::max(amax, std::fabs(v));
+    int ex = 0;
+    if (amax > 0.0) (void)std::frexp(amax, &ex);
+    p->qshift = amax > 0.0 ? 29 - ex : 0;
+  } else {
+    for (int nb = 256; nb >= 64; nb /= 2) {
+      const int sw = pdm_span_words(nb, p->D, K);
+      if (pdm_lds_bytes(p->M, sw, p->C) <= PDM_LDS_LIMIT) {
+        p->NB = nb;
+        p->SW = sw;
+        break;
+      }
     }
   }
   if (p->NB == 0) {
@@ -1713,14 +1742,18 @@ int sonar_pdm_create(const sonar_pdm_desc* desc, hipStream_t stream, sonar_pdm* 
   }
   size_t total = 0;
   double* d_taps64 = nullptr;
-  bool ok = dev_alloc(&p->d_lut, static_cast<size_t>(p->C) * 256, &total) == hipSuccess &&
-            dev_alloc(&p->d_gcum, static_cast<size_t>(K) + 1, &total) == hipSuccess &&
+  bool ok = (p->mt ? dev_alloc(&p->d_qtab, static_cast<size_t>(p->KS) * 1024, &total) == hipSuccess &&
+                         dev_alloc(&p->d_rcum, static_cast<size_t>(K) + 1, &total) == hipSuccess
+                   : dev_alloc(&p->d_lut, static_cast<size_t>(p->C) * 256, &total) == hipSuccess &&
+                         dev_alloc(&p->d_gcum, static_cast<size_t>(K) + 1, &total) == hipSuccess) &&
             hipMalloc(&d_taps64, sizeof(double) * K) == hipSuccess;
   hipError_t e = ok ? hipMemcpyAsync(d_taps64, taps.data(), sizeof(double) * K, hipMemcpyHostToDevice, stream)
                     : hipErrorOutOfMemory;
   if (e == hipSuccess) e = launch_pdm_tables(p, d_taps64, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e == hipSuccess) e = init_pdm_kernel_attributes(p, pdm_lds_bytes(p->M, p->SW, p->C));
+  if (e == hipSuccess)
+    e = init_pdm_kernel_attributes(p, p->mt ? pdm_mt_lds_bytes(p->rows, p->SW, p->KS)
+                                            : pdm_lds_bytes(p->M, p->SW, p->C));
   (void)hipFree(d_taps64);
   if (e != hipSuccess) {
     (void)hipGetLastError();

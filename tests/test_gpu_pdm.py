@@ -1,11 +1,13 @@
 """PDM front end on the GPU (sonar_pdm_demodulate) against the FP64 oracle.
 
 Bars: every output within 1e-6 sum|h| of the oracle (sum|h| is the full-scale output of
-the +-1 input; the kernel adds 4 ceil(K/32) FP32 table entries, each an FP64 sum of 8 taps
-rounded once, plus, for windows reaching past the recording, an FP32 prefix-sum
-correction of the same scale), and a relative L2 error <= 1e-6 per frame for recordings
-at least one filter long (shorter ones have only edge windows, whose small outputs come
-from that full-scale arithmetic).  Shapes cover one and several words per tick, partial
+the +-1 input), and a relative L2 error <= 1e-6 per frame for recordings at least one
+filter long (shorter ones have only edge windows, whose small outputs come from
+full-scale arithmetic).  Two kernels: where 15 D + K <= 1024 the int8 matrix-core one
+(taps rounded to 29-bit integers, exact integer sums, one rounding at the end), else the
+byte-table one (4 ceil(K/32) FP32 table entries, each an FP64 sum of 8 taps rounded
+once, plus an FP32 prefix-sum correction for windows reaching past the recording; the
+case with D = 64 runs it).  Shapes cover one and several words per tick, partial
 words, ragged last tiles, windows cut by both ends of the recording, custom filters, and
 the full 32 x 16384 x 10 size of the headline workload.
 """
@@ -64,7 +66,7 @@ def test_pdm_sigma_delta_recording_matches_oracle(gpu, torch_mod):
 @pytest.mark.parametrize("M,N,D,K", [
     (1, 1, 10, 0), (6, 7, 10, 0), (32, 1000, 10, 0), (33, 300, 3, 0), (64, 257, 1, 0),
     (100, 129, 16, 0), (128, 513, 10, 0), (32, 500, 10, 1), (32, 500, 10, 9), (5, 333, 7, 161),
-    (32, 64, 4, 513),
+    (32, 64, 4, 513), (8, 100, 64, 161), (40, 200, 64, 129),
 ])
 def test_pdm_shapes_match_oracle(gpu, torch_mod, M, N, D, K):
     torch = torch_mod
