@@ -419,9 +419,29 @@ def adjoint_path(args, stream):
     for _ in range(2):
         step()
     ms = time_calls(step, max(3, args.steps // 10), stream)
+
+    # the same loss read from its cells only (sonar_energyscape_cells): E at the reflector cells and
+    # dL/dp without the beam window
+    cl = [(f, d, q) for f, fc in enumerate(w.cells) for d, q in fc]
+    cells = torch.tensor(cl, dtype=torch.int32, device="cuda")
+    wts = torch.full((len(cl),), -1.0, dtype=torch.float32, device="cuda")
+    Ec = torch.empty((len(cl),), dtype=torch.float32, device="cuda")
+
+    def step_cells():
+        binding._check(lib.sonar_plan_set_positions(plan._h, binding._ptr(pos), sh), "set_positions")
+        binding._check(lib.sonar_energyscape_cells(plan._h, ctypes.c_void_p(mf.data_ptr()),
+                                                   ctypes.c_void_p(cells.data_ptr()), len(cl),
+                                                   ctypes.c_void_p(wts.data_ptr()), F, ctypes.c_void_p(Ec.data_ptr()),
+                                                   ctypes.c_void_p(dpos.data_ptr()), sh), "cells")
+    for _ in range(2):
+        step_cells()
+    ms_c = time_calls(step_cells, max(10, args.steps // 2), stream)
     plan.close()
     return {"what": "set_positions + beamform + envelope + dL/dp (FD exact-phase, FP32), 10 frames",
-            "value": round(F / (ms / 1e3), 2), "unit": "frames/s", "ms_per_step": round(ms, 4)}
+            "value": round(F / (ms / 1e3), 2), "unit": "frames/s", "ms_per_step": round(ms, 4),
+            "cells_path": {"what": f"set_positions + E and dL/dp at the {len(cl)} reflector cells only "
+                                   "(sonar_energyscape_cells), same loss", "value": round(F / (ms_c / 1e3), 2),
+                           "unit": "frames/s", "ms_per_step": round(ms_c, 4)}}
 
 
 def pdm_path(args, stream, x_shape, mode):

@@ -435,6 +435,33 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
                                double* dpos_out, hipStream_t stream);
 
 /*
+ * sonar_energyscape_cells -- selected energyscape cells of a frequency-domain
+ * (exact-phase, section 4.3) plan and the position derivative of a loss that
+ * reads only them, for calibration losses whose dE vanishes elsewhere (a few
+ * reflector cells of a whole energyscape).  Each cell c = (f, d, q) is computed
+ * from the band spectra alone, by the definitions of sonar_energyscape (beamformer
+ * section 4.1 with per-bin steering, envelope and subsampling):
+ *   B[k]  = (1/M) sum_m Y_m[k] e^{-2 pi i k Dl[d][m]/P}  on the band bins,
+ *   b_i   = IDFT_P(B) at the K window samples n_i = n0 - (K-1)/2 + qR + i,
+ *   E_c   = sum_i h[K-1-i] |b_i|,
+ * and for L = sum_c dE[c] E_c the chain of sonar_energyscape_vjp restricted to
+ * the cells' windows gives dL/dp (no beam window, no P-point transform).
+ *   mf_in     : the FD matched-filter buffer of the F frames (sonar_matched_filter),
+ *               complex64 [F][Kb][M].
+ *   cells     : int32 [n_cells][3] (f, d, q) in device memory; a cell outside
+ *               [0, F) x [0, D) x [0, Q) yields E = NaN and adds nothing to dL/dp.
+ *   dE        : float [n_cells] in device memory (the weights dL/dE_c).
+ *   E_out     : float [n_cells], or NULL.
+ *   dpos_out  : double [M][3], or NULL.
+ * Repeated cells count once each.  Needs sonar_plan_enable_gradients (its
+ * workspace holds the per-cell delay derivatives, so n_cells <= max_frames * D),
+ * an FD mode, K <= 256 and M <= 256 (SONAR_E_UNSUPPORTED otherwise).  FP32
+ * arithmetic with the steering phases reduced in FP64, as the dense derivative.
+ */
+int sonar_energyscape_cells(sonar_plan plan, const void* mf_in, const int32_t* cells, int32_t n_cells,
+                            const float* dE, int32_t F, float* E_out, double* dpos_out, hipStream_t stream);
+
+/*
  * sonar_plan_set_positions -- new microphone positions [M][3] (metres): the
  * delay tables (§4.1 delays) are rebuilt on `stream` without reallocating,
  * ordered after the work already queued there.  A time-domain plan whose new

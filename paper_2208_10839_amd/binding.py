@@ -90,6 +90,9 @@ _SIGNATURES = {
     "sonar_plan_set_positions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "sonar_energyscape_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "sonar_energyscape_cells": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                ctypes.c_void_p]),
     "sonar_pdm_create": (ctypes.c_int, [ctypes.POINTER(PdmDesc), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "sonar_pdm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "sonar_pdm_demodulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -372,6 +375,28 @@ class Plan:
                                                  ctypes.c_void_p(dpos.data_ptr() if dpos is not None else 0),
                                                  _stream_handle(stream)), "sonar_energyscape_backward")
         return dx, (dpos.cpu().numpy() if dpos is not None else None)
+
+    def cells(self, mf, cells, dE, want_E=True, want_dpos=True, stream=None):
+        """sonar_energyscape_cells: (E [n] float32 tensor or None, dpos [M][3] float64 numpy or None)
+        for cells int32 [n][3] (f, d, q) and weights dE float32 [n] on the device."""
+        import torch
+        self.enable_gradients()
+        F = self._frames(mf, (self.mf_frame_elems,), "mf")
+        if not (isinstance(cells, torch.Tensor) and cells.is_cuda and cells.dtype == torch.int32 and cells.dim() == 2
+                and cells.shape[1] == 3 and cells.is_contiguous()):
+            raise ValueError("cells must be a contiguous int32 CUDA tensor [n][3]")
+        n = cells.shape[0]
+        if not (isinstance(dE, torch.Tensor) and dE.is_cuda and dE.dtype == torch.float32 and tuple(dE.shape) == (n,)
+                and dE.is_contiguous()):
+            raise ValueError("dE must be a contiguous float32 CUDA tensor [n]")
+        E = torch.empty((n,), dtype=torch.float32, device=mf.device) if want_E else None
+        dpos = torch.empty((self.M, 3), dtype=torch.float64, device=mf.device) if want_dpos else None
+        _check(load().sonar_energyscape_cells(self._h, ctypes.c_void_p(mf.data_ptr()), ctypes.c_void_p(cells.data_ptr()),
+                                              n, ctypes.c_void_p(dE.data_ptr()), F,
+                                              ctypes.c_void_p(E.data_ptr() if E is not None else 0),
+                                              ctypes.c_void_p(dpos.data_ptr() if dpos is not None else 0),
+                                              _stream_handle(stream)), "sonar_energyscape_cells")
+        return E, (dpos.cpu().numpy() if dpos is not None else None)
 
     def beamform_envelope(self, mf, out=None, stream=None):
         """E[F][D][Q] from a matched-filter buffer, beam kept on chip."""

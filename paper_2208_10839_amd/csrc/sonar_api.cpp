@@ -1459,6 +1459,30 @@ int sonar_energyscape_vjp(sonar_plan p, const void* mf_in, void* beam_inout, con
   return e == hipSuccess ? SONAR_OK : hip_fail(e, "gradient launch");
 }
 
+int sonar_energyscape_cells(sonar_plan p, const void* mf_in, const int32_t* cells, int32_t n_cells, const float* dE,
+                            int32_t F, float* E_out, double* dpos_out, hipStream_t stream) {
+  int st = check_exec(p, mf_in, cells, F);
+  if (st != SONAR_OK) return st;
+  if (!dE) return fail(SONAR_E_INVALID, "dE is NULL");
+  if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
+  if (is_td(p)) return fail(SONAR_E_UNSUPPORTED, "energyscape cells: frequency-domain (exact-phase) plans only");
+  if (!cells_supported(p))
+    return fail(SONAR_E_UNSUPPORTED, "energyscape cells: K=%d and M=%d must be at most 256", p->K, p->M);
+  if (n_cells < 0 || static_cast<long long>(n_cells) > static_cast<long long>(p->max_frames) * p->D)
+    return fail(SONAR_E_INVALID, "n_cells=%d outside [0, max_frames * D = %lld]", n_cells,
+                static_cast<long long>(p->max_frames) * p->D);
+  if (n_cells == 0) {
+    if (dpos_out) {
+      const hipError_t e = hipMemsetAsync(dpos_out, 0, sizeof(double) * 3 * p->M, stream);
+      if (e != hipSuccess) return hip_fail(e, "energyscape cells");
+    }
+    return SONAR_OK;
+  }
+  const hipError_t e = launch_energyscape_cells(p, static_cast<const float2*>(mf_in), F, cells, dE, n_cells, E_out,
+                                                dpos_out, stream);
+  return e == hipSuccess ? SONAR_OK : hip_fail(e, "energyscape cells launch");
+}
+
 int sonar_energyscape_backward(sonar_plan p, const void* x, const float* dE, int32_t F, float* dx_out,
                                double* dpos_out, hipStream_t stream) {
   int st = check_exec(p, x, dE, F);

@@ -329,6 +329,74 @@ def _geometry_error(pos, true_pos):
     return float(np.sqrt(np.mean(n * n))), float(n.max())
 
 
+def test_cells_match_oracle(gpu, torch_mod):
+    """sonar_energyscape_cells: E at chosen cells (edges of the range included, one cell
+    repeated, one outside the plan) and dL/dp for random weights, against the oracle's
+    energyscape and its whole derivative chain with dE scattered onto those cells."""
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=37)
+    _say("case cells: M=32 N=4096 D=37 F=2 fd_fp32")
+    plan = _plan(gpu, w, "fd", max_frames=2)
+    x = torch.from_numpy(w.x).cuda()
+    mf = plan.matched_filter(x)
+    rng = np.random.default_rng(np.random.SeedSequence([4, 1, 2, 3]))
+    cells = [(0, 0, 0), (0, 36, plan.Q - 1), (1, 5, 17), (1, 5, 17), (0, 12, plan.Q // 2)]
+    cells += [(int(rng.integers(2)), int(rng.integers(plan.D)), int(rng.integers(plan.Q))) for _ in range(11)]
+    wts = rng.standard_normal(len(cells)).astype(np.float32)
+    bad = (0, plan.D, 3)   # outside the plan: E = NaN, adds nothing
+    ct = torch.tensor(cells + [bad], dtype=torch.int32, device="cuda")
+    E, dpos = plan.cells(mf, ct, torch.from_numpy(np.append(wts, 5.0).astype(np.float32)).cuda())
+    E = E.cpu().numpy()
+    assert np.isnan(E[-1])
+    dpos_o = np.zeros((plan.M, 3))
+    E_o = np.zeros(len(cells))
+    E_scale = 0.0
+    for f in range(2):
+        steps = _oracle_steps(w, f, plan, "fd")
+        R, h, Q = steps[:3]
+        Eo = O.envelope(steps[6], h, Q, R)
+        E_scale = max(E_scale, float(np.max(np.abs(Eo))))
+        dEf = np.zeros((plan.D, Q))
+        for i, (cf, cd, cq) in enumerate(cells):
+            if cf == f:
+                E_o[i] = Eo[cd, cq]
+                dEf[cd, cq] += wts[i]
+        G_b = O.envelope_vjp(steps[6], h, dEf, Q, R)
+        dpos_o += _oracle_back(w, plan, "fd", steps, G_b)[2]
+    # E as the dense tests hold it: relative L2 over the cells, and every cell within 1e-5 of the
+    # energyscape's largest value (a cell in the noise is a sum over the band whose terms cancel, so
+    # its own relative error is larger)
+    errE = rel_l2(E[:-1], E_o)
+    errE_max = float(np.max(np.abs(E[:-1] - E_o))) / E_scale
+    errP = rel_l2(dpos, dpos_o)
+    _say(f"cells: E rel L2 {errE:.2e}, max err / max E {errE_max:.2e}, "
+         f"max rel err per cell {float(np.max(np.abs(E[:-1] - E_o) / np.abs(E_o))):.2e}; dpos rel L2 {errP:.2e}")
+    assert errE <= 1e-5
+    assert errE_max <= 1e-5
+    assert errP <= TOL_GRAD
+
+
+def test_cells_match_dense_calibration(gpu, torch_mod):
+    """The calibration workload (32 mics, 16384 samples, 1500 directions, 10 frames of 5
+    reflectors): the cells path gives the dense path's loss and gradient."""
+    torch = torch_mod
+    w = synth.make_calibration()
+    F, M, N = w.x.shape
+    _say(f"case cells vs dense: M={M} N={N} D={w.dirs.shape[0]} F={F}")
+    plan = gpu.Plan(w.start_pos, w.chirp, w.dirs, N, fs=w.fs, c=w.c, band=w.band, decim=w.decim, mode="fd_fp32",
+                    max_frames=F)
+    x = torch.from_numpy(w.x).cuda()
+    mf = plan.matched_filter(x)
+    cells = _cell_index(w.cells, torch)
+    L, g = _cal_loss_grad(plan, mf, cells, torch)
+    ct = torch.stack(cells, dim=1).to(torch.int32).contiguous()
+    E, g2 = plan.cells(mf, ct, torch.full((ct.shape[0],), -1.0, dtype=torch.float32, device="cuda"))
+    L2 = -float(E.double().sum().item())
+    _say(f"cells vs dense: loss {L2:.9e} vs {L:.9e}, dpos rel L2 {rel_l2(g2, g):.2e}")
+    assert abs(L2 - L) <= 1e-5 * abs(L)
+    assert rel_l2(g2, g) <= TOL_GRAD
+
+
 def test_self_calibration_recovers_positions(gpu, torch_mod):
     torch = torch_mod
     from scipy.optimize import minimize
