@@ -5,10 +5,13 @@
 // s[i+1] = A s[i] + B x[i], y[i] = C s[i] + D x[i] of dimension NS (2 per section),
 // built and raised to powers on the host in FP64.
 //
-// One wavefront per row: lane c owns the chunk [c L, c L + L) of the window (L =
-// ceil(G'/64)).  The row is read in steps of IIR_TB samples per chunk: the wave
-// loads 64 chunks x IIR_TB consecutive samples (16 lanes per 128-byte run) into
-// LDS, then each lane runs its chunk's IIR_TB samples from there.  Pass 1 runs
+// One wavefront per row: lane c owns the chunk [c L - o, c L + L - o) of the window, where
+// L is a multiple of IIR_TB with 64 L >= G' + 15 and o < 16 is the row's offset from a
+// 128-byte boundary in samples, so every chunk starts on a 128-byte boundary (positions
+// below 0 are zero input, which leaves the zero start state as it is).  The row is read
+// in steps of IIR_TB samples per chunk: the wave loads 64 chunks x IIR_TB consecutive
+// samples (16 lanes per aligned 128-byte line) into LDS, then each lane runs its chunk's
+// IIR_TB samples from there, the next step's loads in flight meanwhile.  Pass 1 runs
 // each chunk from zero state to get its end state e_c; a Hillis-Steele scan over the lanes with the tables A^(L 2^k) turns these into the
 // true start state of every chunk (start_c = sum_{j<c} A^(L (c-1-j)) e_j); pass 2 reruns
 // each chunk from its start state and writes the subsampled outputs.
@@ -20,20 +23,22 @@ namespace {
 
 constexpr int IIR_TB = 16;
 
-// |b| of samples [t0, t0 + IIR_TB) of every chunk into seg[chunk][.] (0 past the chunk or the row)
-__device__ __forceinline__ void stage_abs(const float2* __restrict__ b, float (*seg)[IIR_TB + 1], int t0, int L,
-                                          int G, int lane) {
+// samples [t0, t0 + IIR_TB) of every chunk into registers (0 outside the row): value j of
+// lane l is sample t0 + l % 16 of chunk 4 j + l / 16
+__device__ __forceinline__ void load_stage(const float2* __restrict__ b, float2* v, int t0, int L, int G, int off,
+                                           int lane) {
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int c = 4 * j + (lane >> 4), tt = lane & 15;
-    const int i = c * L + t0 + tt;
-    float v = 0.f;
-    if (t0 + tt < L && i < G) {
-      const float2 z = b[i];
-      v = sqrtf(z.x * z.x + z.y * z.y);
-    }
-    seg[c][tt] = v;
+    const int i = c * L - off + t0 + tt;
+    v[j] = (i >= 0 && i < G) ? b[i] : make_float2(0.f, 0.f);
   }
+}
+
+// their magnitudes into seg[chunk][.]
+__device__ __forceinline__ void store_abs(const float2* v, float (*seg)[IIR_TB + 1], int lane) {
+#pragma unroll
+  for (int j = 0; j < 16; ++j) seg[4 * j + (lane >> 4)][lane & 15] = sqrtf(v[j].x * v[j].x + v[j].y * v[j].y);
 }
 
 template <int NS>
@@ -65,17 +70,22 @@ __global__ __launch_bounds__(64) void iir_env_kernel(const float2* __restrict__ 
   const float* Apow = t + IIR_POW_OFFSET;   // [6][NS][NS]
   const long long row = blockIdx.x;
   const float2* b = beam + row * G;
-  const int i0 = lane * L;
+  const int off = static_cast<int>((reinterpret_cast<uintptr_t>(b) >> 3) & 15);
+  const int i0 = lane * L - off;
   const int i1 = i0 + L < G ? i0 + L : G;
 
   float s[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) s[i] = 0.f;
+  // each stage's loads are issued before the previous stage's recurrence runs
+  float2 v[16];
+  load_stage(b, v, 0, L, G, off, lane);
   for (int t0 = 0; t0 < L; t0 += IIR_TB) {
-    stage_abs(b, seg, t0, L, G, lane);
+    store_abs(v, seg, lane);
     __syncthreads();
+    if (t0 + IIR_TB < L) load_stage(b, v, t0 + IIR_TB, L, G, off, lane);
     for (int tt = 0; tt < IIR_TB; ++tt)
-      if (i0 + t0 + tt < i1) step<NS>(A, B, s, seg[lane][tt]);
+      if (i0 + t0 + tt >= 0 && i0 + t0 + tt < i1) step<NS>(A, B, s, seg[lane][tt]);
     __syncthreads();
   }
   // inclusive scan of the chunk end states: V_c = sum_{j<=c} A^(L (c-j)) e_j
@@ -103,9 +113,11 @@ __global__ __launch_bounds__(64) void iir_env_kernel(const float2* __restrict__ 
     s[i] = lane == 0 ? 0.f : v;
   }
   float* e = E + row * Q;
+  load_stage(b, v, 0, L, G, off, lane);
   for (int t0 = 0; t0 < L; t0 += IIR_TB) {
-    stage_abs(b, seg, t0, L, G, lane);
+    store_abs(v, seg, lane);
     __syncthreads();
+    if (t0 + IIR_TB < L) load_stage(b, v, t0 + IIR_TB, L, G, off, lane);
     for (int tt = 0; tt < IIR_TB; ++tt) {
       const int i = i0 + t0 + tt;
       if (i >= i1) break;

@@ -104,7 +104,7 @@ struct sonar_plan_s {
                                // ([max_frames][M][P] TD, [max_frames][kb][M] FD)
   bool grad_on = false;
   int iir_ns = 0;              // IIR envelope: state dimension (2 per section); 0 = the FIR envelope
-  int iir_chunk = 0;           // IIR envelope: window samples per lane, ceil(G'/64)
+  int iir_chunk = 0;           // IIR envelope: window samples per lane (multiple of 16, 64 L >= G' + 15)
   float* d_iir = nullptr;      // IIR envelope tables (layout: IIR_TAB_LEN below)
   float* d_fbound = nullptr;   // TD_F16: per channel bound (1/P) sum_k |Yhat[k]| >= max |yhat|, [max_frames][M]
 };

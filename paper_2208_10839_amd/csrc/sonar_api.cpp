@@ -1631,7 +1631,8 @@ int sonar_plan_set_envelope_iir(sonar_plan p, int32_t n_sections, const double* 
     Cu[r] += 1.0;
     Du *= b0;
   }
-  const int L = (p->G + 63) / 64;
+  // chunk length: a multiple of 16 samples with 64 L >= G' + 15 (chunks start on 128-byte boundaries)
+  const int L = ((p->G + 15 + 63) / 64 + 15) / 16 * 16;
   std::vector<float> tab(IIR_TAB_LEN, 0.0f);
   for (int i = 0; i < ns * ns; ++i) tab[i] = static_cast<float>(A[i]);
   for (int i = 0; i < ns; ++i) {
