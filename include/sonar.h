@@ -454,9 +454,11 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
  *   E_out     : float [n_cells], or NULL.
  *   dpos_out  : double [M][3], or NULL.
  * Repeated cells count once each.  Needs sonar_plan_enable_gradients (its
- * workspace holds the per-cell delay derivatives, so n_cells <= max_frames * D),
- * an FD mode, K <= 256 and M <= 256 (SONAR_E_UNSUPPORTED otherwise).  FP32
- * arithmetic with the steering phases reduced in FP64, as the dense derivative.
+ * workspace holds the per-cell partial sums, so n_cells <= max_frames * D),
+ * an FD mode, K <= 256, M <= 256 and 2K + M <= 2P (SONAR_E_UNSUPPORTED
+ * otherwise).  FP32 arithmetic with the steering phases reduced in FP64, as the
+ * dense derivative.  Uses the same workspace as sonar_energyscape_vjp: calls on
+ * one plan must be ordered (one stream).
  */
 int sonar_energyscape_cells(sonar_plan plan, const void* mf_in, const int32_t* cells, int32_t n_cells,
                             const float* dE, int32_t F, float* E_out, double* dpos_out, hipStream_t stream);

@@ -482,17 +482,20 @@ hipError_t vjp_fd(const sonar_plan_s* p, const float2* mf, const float2* gb, int
 }
 
 // ---------------------------------------------------------------------------
-// Energyscape cells of the exact-phase beamformer and their adjoint, one workgroup per
-// cell c = (f, d, q) with weight w_c (the loss L = sum_c w_c E_c), from the band spectra
-// Y[f][j][m] alone: no beam window and no P-point transform.  With n_i = n0 - hk + qR + i
-// (i < K, window position qR + i, tap K-1-i):
+// Energyscape cells of the exact-phase beamformer and their adjoint, for a loss
+// L = sum_c w_c E_c over cells c = (f, d, q), from the band spectra Y[f][j][m] alone: no
+// beam window and no P-point transform.  With n_i = n0 - hk + qR + i (i < K, window
+// position qR + i, tap K-1-i):
 //   B[k]    = (1/M) sum_m Y_m[k] exp(-2 pi i k Dl[d][m] / P)            (band bins k)
 //   b_i     = (1/P) sum_k B[k] exp(+2 pi i k n_i / P)
 //   E_c     = sum_i h[K-1-i] |b_i|
 //   G_b,i   = w_c h[K-1-i] b_i / |b_i|
 //   G_B[k]  = (1/P) sum_i G_b,i exp(-2 pi i k n_i / P)
 //   dDl[m]  = (1/M) sum_k Re(conj(G_B[k]) Y_m[k] (-2 pi i k / P) exp(-2 pi i k Dl[d][m] / P))
-// (the same chain as the dense derivative restricted to the cells' windows).  B and G_B
+// (the chain of the dense derivative restricted to the cells' windows).  The band bins of a
+// cell are split into S ranges, one workgroup each: cells_b_kernel writes each range's share
+// of the sums b_i, cells_g_kernel adds them up (every range's workgroup the same way), forms
+// E and G_b, and writes its range's share of dDl; pos_cells_kernel adds the shares.  B and G_B
 // go through LDS in chunks of CELL_CHUNK bins.
 constexpr int CELL_THREADS = 1024;
 constexpr int CELL_WAVES = CELL_THREADS / 64;
@@ -500,41 +503,56 @@ constexpr int CELL_CHUNK = 4096;
 constexpr int CELL_SPW = 16;    // window samples per wavefront: K <= CELL_WAVES * CELL_SPW
 constexpr int CELL_MG = 4;      // groups of 64 microphones: M <= 256
 
-__global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
-    const float2* __restrict__ Y, const int* __restrict__ cells, const float* __restrict__ wgt, int n, int F,
-    const double* __restrict__ dl, const float* __restrict__ taps, const float2* __restrict__ tw_g,
-    float* __restrict__ E_out, float* __restrict__ ddl, int M, int D, int Q, int R, int K, int n0, int hk,
-    int k_lo, int kb, int NF, int P) {
-  __shared__ float2 chunk[CELL_CHUNK];
-  __shared__ float2 bw[CELL_WAVES * CELL_SPW], gw[CELL_WAVES * CELL_SPW];
-  __shared__ float red[CELL_THREADS];
-  __shared__ int bad;
-  const int c = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int f = cells[3 * c], d = cells[3 * c + 1], q = cells[3 * c + 2];
-  if (tid == 0) bad = !(f >= 0 && f < F && d >= 0 && d < D && q >= 0 && q < Q);
-  __syncthreads();
-  if (bad) {
-    if (E_out && tid == 0) E_out[c] = __builtin_nanf("");
-    for (int m = tid; m < M; m += CELL_THREADS) ddl[static_cast<long long>(c) * M + m] = 0.f;
-    return;
-  }
-  const float2* y = Y + static_cast<long long>(f) * kb * M;
-  const double* dlr = dl + static_cast<long long>(d) * M;
-  const double inv_pd = 1.0 / static_cast<double>(P);
-  const float inv_m = 1.0f / static_cast<float>(M), inv_p = 1.0f / static_cast<float>(P);
-  const int nbase = n0 - hk + q * R;
+struct CellArgs {
+  const float2* Y;
+  const int* cells;
+  const float* wgt;
+  const double* dl;
+  const float* taps;
+  const float2* tw;
+  float* E_out;
+  float2* bpart;   // [n][S][K]
+  float* dpart;    // [n][S][M]
+  int n, S, F, M, D, Q, R, K, n0, hk, k_lo, kb, NF, P;
+};
 
-  // B on the band bins, chunk by chunk; wavefront wv accumulates the window samples
-  // i = wv + CELL_WAVES s over its lanes' bins
+__device__ __forceinline__ bool cell_valid(const CellArgs& a, int c, int* f, int* d, int* q) {
+  *f = a.cells[3 * c];
+  *d = a.cells[3 * c + 1];
+  *q = a.cells[3 * c + 2];
+  return *f >= 0 && *f < a.F && *d >= 0 && *d < a.D && *q >= 0 && *q < a.Q;
+}
+
+// bins [jb, je) of range sp of the cell
+__device__ __forceinline__ void cell_range(const CellArgs& a, int sp, int* jb, int* je) {
+  const int per = (a.kb + a.S - 1) / a.S;
+  *jb = sp * per < a.kb ? sp * per : a.kb;
+  *je = *jb + per < a.kb ? *jb + per : a.kb;
+}
+
+__global__ __launch_bounds__(CELL_THREADS) void cells_b_kernel(const CellArgs a) {
+  __shared__ float2 chunk[CELL_CHUNK];
+  const int c = blockIdx.x / a.S, sp = blockIdx.x % a.S;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  int f, d, q;
+  if (!cell_valid(a, c, &f, &d, &q)) return;   // uniform: cells_g_kernel handles the cell
+  int jb, je;
+  cell_range(a, sp, &jb, &je);
+  const int M = a.M, P = a.P;
+  const float2* y = a.Y + static_cast<long long>(f) * a.kb * M;
+  const double* dlr = a.dl + static_cast<long long>(d) * M;
+  const double inv_pd = 1.0 / static_cast<double>(P);
+  const float inv_m = 1.0f / static_cast<float>(M);
+  const int nbase = a.n0 - a.hk + q * a.R;
+  // wavefront wv accumulates the window samples i = wv + CELL_WAVES s over its lanes' bins
   float2 bacc[CELL_SPW];
 #pragma unroll
   for (int s = 0; s < CELL_SPW; ++s) bacc[s] = make_float2(0.f, 0.f);
-  for (int c0 = 0; c0 < kb; c0 += CELL_CHUNK) {
-    const int nb = kb - c0 < CELL_CHUNK ? kb - c0 : CELL_CHUNK;
+  for (int c0 = jb; c0 < je; c0 += CELL_CHUNK) {
+    const int nb = je - c0 < CELL_CHUNK ? je - c0 : CELL_CHUNK;
     for (int jj = tid; jj < nb; jj += CELL_THREADS) {
       const int j = c0 + jj;
-      const int k = k_lo + j;
+      const int k = a.k_lo + j;
       float2 acc = make_float2(0.f, 0.f);
       for (int m = 0; m < M; ++m) acc = cadd(acc, cmul(y[static_cast<long long>(j) * M + m], steer(k, dlr[m] * inv_pd)));
       chunk[jj] = make_float2(acc.x * inv_m, acc.y * inv_m);
@@ -543,16 +561,17 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
 #pragma unroll
     for (int s = 0; s < CELL_SPW; ++s) {
       const int i = wv + CELL_WAVES * s;
-      if (i < K) {
+      if (i < a.K) {
         const unsigned ni = static_cast<unsigned>((nbase + i) & (P - 1));
         for (int jj = lane; jj < nb; jj += 64) {
-          const unsigned e = (static_cast<unsigned>(k_lo + c0 + jj) * ni) & static_cast<unsigned>(P - 1);
-          bacc[s] = cadd(bacc[s], cmul(chunk[jj], cconj(tw_p(tw_g, NF, static_cast<int>(e)))));
+          const unsigned e = (static_cast<unsigned>(a.k_lo + c0 + jj) * ni) & static_cast<unsigned>(P - 1);
+          bacc[s] = cadd(bacc[s], cmul(chunk[jj], cconj(tw_p(a.tw, a.NF, static_cast<int>(e)))));
         }
       }
     }
     __syncthreads();
   }
+  float2* out = a.bpart + (static_cast<long long>(c) * a.S + sp) * a.K;
 #pragma unroll
   for (int s = 0; s < CELL_SPW; ++s) {
     float2 v = bacc[s];
@@ -562,24 +581,49 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
       v.y += __shfl_xor(v.y, off);
     }
     const int i = wv + CELL_WAVES * s;
-    if (lane == 0 && i < K) bw[i] = make_float2(v.x * inv_p, v.y * inv_p);
+    if (lane == 0 && i < a.K) out[i] = v;
   }
-  __syncthreads();
+}
 
-  // E and G_b (wavefront 0)
+__global__ __launch_bounds__(CELL_THREADS) void cells_g_kernel(const CellArgs a) {
+  __shared__ float2 chunk[CELL_CHUNK];
+  __shared__ float2 gw[CELL_WAVES * CELL_SPW];
+  __shared__ float red[CELL_THREADS];
+  const int c = blockIdx.x / a.S, sp = blockIdx.x % a.S;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int M = a.M, P = a.P, K = a.K;
+  float* dout = a.dpart + (static_cast<long long>(c) * a.S + sp) * M;
+  int f, d, q;
+  if (!cell_valid(a, c, &f, &d, &q)) {
+    if (a.E_out && sp == 0 && tid == 0) a.E_out[c] = __builtin_nanf("");
+    for (int m = tid; m < M; m += CELL_THREADS) dout[m] = 0.f;
+    return;
+  }
+  int jb, je;
+  cell_range(a, sp, &jb, &je);
+  const float2* y = a.Y + static_cast<long long>(f) * a.kb * M;
+  const double* dlr = a.dl + static_cast<long long>(d) * M;
+  const double inv_pd = 1.0 / static_cast<double>(P);
+  const float inv_m = 1.0f / static_cast<float>(M), inv_p = 1.0f / static_cast<float>(P);
+  const int nbase = a.n0 - a.hk + q * a.R;
+
+  // b from the ranges' shares, E and G_b (wavefront 0; every range's workgroup alike)
   if (wv == 0) {
+    const float wc = a.wgt[c];
     float e = 0.f;
     for (int i = lane; i < K; i += 64) {
-      const float2 b = bw[i];
-      const float a = sqrtf(b.x * b.x + b.y * b.y);
-      const float h = taps[K - 1 - i];
-      e = fmaf(h, a, e);
-      const float g = a > 0.f ? wgt[c] * h / a : 0.f;
+      float2 b = make_float2(0.f, 0.f);
+      for (int r = 0; r < a.S; ++r) b = cadd(b, a.bpart[(static_cast<long long>(c) * a.S + r) * K + i]);
+      b = make_float2(b.x * inv_p, b.y * inv_p);
+      const float am = sqrtf(b.x * b.x + b.y * b.y);
+      const float h = a.taps[K - 1 - i];
+      e = fmaf(h, am, e);
+      const float g = am > 0.f ? wc * h / am : 0.f;
       gw[i] = make_float2(g * b.x, g * b.y);
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
-    if (lane == 0 && E_out) E_out[c] = e;
+    if (lane == 0 && sp == 0 && a.E_out) a.E_out[c] = e;
   }
   __syncthreads();
 
@@ -593,14 +637,14 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
   float dacc[CELL_MG];
 #pragma unroll
   for (int g = 0; g < CELL_MG; ++g) dacc[g] = 0.f;
-  for (int c0 = 0; c0 < kb; c0 += CELL_CHUNK) {
-    const int nb = kb - c0 < CELL_CHUNK ? kb - c0 : CELL_CHUNK;
+  for (int c0 = jb; c0 < je; c0 += CELL_CHUNK) {
+    const int nb = je - c0 < CELL_CHUNK ? je - c0 : CELL_CHUNK;
     for (int jj = tid; jj < nb; jj += CELL_THREADS) {
-      const unsigned k = static_cast<unsigned>(k_lo + c0 + jj);
+      const unsigned k = static_cast<unsigned>(a.k_lo + c0 + jj);
       float2 acc = make_float2(0.f, 0.f);
       for (int i = 0; i < K; ++i) {
         const unsigned e = (k * static_cast<unsigned>((nbase + i) & (P - 1))) & static_cast<unsigned>(P - 1);
-        acc = cadd(acc, cmul(gw[i], tw_p(tw_g, NF, static_cast<int>(e))));
+        acc = cadd(acc, cmul(gw[i], tw_p(a.tw, a.NF, static_cast<int>(e))));
       }
       chunk[jj] = make_float2(acc.x * inv_p, acc.y * inv_p);
     }
@@ -611,7 +655,7 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
       if (64 * g < M && m < M) {
         const double dlp = dlr[m] * inv_pd;
         for (int jj = jsub; jj < nb; jj += jstep) {
-          const int k = k_lo + c0 + jj;
+          const int k = a.k_lo + c0 + jj;
           const float2 t = cmul(cconj(chunk[jj]), cmul(y[static_cast<long long>(c0 + jj) * M + m], steer(k, dlp)));
           dacc[g] = fmaf(two_pi_over_p * static_cast<float>(k), t.y, dacc[g]);
         }
@@ -626,23 +670,25 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_fd_kernel(
     if (tid < ms && m < M) {
       float sum = 0.f;
       for (int i = tid; i < CELL_THREADS; i += ms) sum += red[i];
-      ddl[static_cast<long long>(c) * M + m] = sum * inv_m;
+      dout[m] = sum * inv_m;
     }
     __syncthreads();
   }
 }
 
-// dpos[m] = fs/c sum_cells dDl[c][m] u_{d_c} (cells outside the plan add nothing: their rows are zero)
-__global__ __launch_bounds__(256) void pos_cells_kernel(const float* __restrict__ ddl, const int* __restrict__ cells,
-                                                        int n, const double* __restrict__ dirs, double* __restrict__ dpos,
-                                                        int M, int D, double scale) {
+// dpos[m] = fs/c sum_cells (sum of the ranges' dDl shares)[m] u_{d_c} (cells outside the plan add
+// nothing: their shares are zero)
+__global__ __launch_bounds__(256) void pos_cells_kernel(const float* __restrict__ dpart, const int* __restrict__ cells,
+                                                        int n, int S, const double* __restrict__ dirs,
+                                                        double* __restrict__ dpos, int M, int D, double scale) {
   __shared__ double red[3][256];
   const int m = blockIdx.x;
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) {
     int d = cells[3 * i + 1];
     d = d < 0 ? 0 : (d >= D ? D - 1 : d);
-    const double v = ddl[static_cast<long long>(i) * M + m];
+    double v = 0.0;
+    for (int r = 0; r < S; ++r) v += dpart[(static_cast<long long>(i) * S + r) * M + m];
     a0 += v * dirs[3 * d];
     a1 += v * dirs[3 * d + 1];
     a2 += v * dirs[3 * d + 2];
@@ -690,16 +736,48 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
   return hipSuccess;
 }
 
-bool cells_supported(const sonar_plan_s* p) { return p->K <= CELL_WAVES * CELL_SPW && p->M <= 64 * CELL_MG; }
+bool cells_supported(const sonar_plan_s* p) {
+  return p->K <= CELL_WAVES * CELL_SPW && p->M <= 64 * CELL_MG && 2 * p->K + p->M <= 2 * p->P;
+}
 
 hipError_t launch_energyscape_cells(const sonar_plan_s* p, const float2* mf, int F, const int* cells,
                                     const float* dE, int n, float* E_out, double* dpos, hipStream_t s) {
-  hipLaunchKernelGGL(cells_fd_kernel, dim3(n), dim3(CELL_THREADS), 0, s, mf, cells, dE, n, F, p->d_dl, p->d_taps,
-                     p->d_tw, E_out, p->d_gdl, p->M, p->D, p->Q, p->R, p->K, p->n0, p->hk, p->k_lo, p->kb, p->NF,
-                     p->P);
+  // S bin ranges per cell (about 1024 bins each, at most 8), with the shares of b and dDl in the
+  // plan's transform scratch (P complex values per cell slot: S (K + M) floats must fit 2 P)
+  int S = p->kb / 1024;
+  S = S < 1 ? 1 : (S > 8 ? 8 : S);
+  while (S > 1 && static_cast<long long>(S) * (2 * p->K + p->M) > 2LL * p->P) --S;
+  CellArgs a;
+  a.Y = mf;
+  a.cells = cells;
+  a.wgt = dE;
+  a.dl = p->d_dl;
+  a.taps = p->d_taps;
+  a.tw = p->d_tw;
+  a.E_out = E_out;
+  a.bpart = p->d_gscr;
+  a.dpart = reinterpret_cast<float*>(p->d_gscr + static_cast<long long>(n) * S * p->K);
+  a.n = n;
+  a.S = S;
+  a.F = F;
+  a.M = p->M;
+  a.D = p->D;
+  a.Q = p->Q;
+  a.R = p->R;
+  a.K = p->K;
+  a.n0 = p->n0;
+  a.hk = p->hk;
+  a.k_lo = p->k_lo;
+  a.kb = p->kb;
+  a.NF = p->NF;
+  a.P = p->P;
+  const dim3 grid(static_cast<unsigned>(static_cast<long long>(n) * S));
+  hipLaunchKernelGGL(cells_b_kernel, grid, dim3(CELL_THREADS), 0, s, a);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !dpos) return e;
-  hipLaunchKernelGGL(pos_cells_kernel, dim3(p->M), dim3(256), 0, s, p->d_gdl, cells, n, p->d_dirs, dpos, p->M, p->D,
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cells_g_kernel, grid, dim3(CELL_THREADS), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess || !dpos) return e;
+  hipLaunchKernelGGL(pos_cells_kernel, dim3(p->M), dim3(256), 0, s, a.dpart, cells, n, S, p->d_dirs, dpos, p->M, p->D,
                      p->fs / p->c);
   return hipGetLastError();
 }

@@ -272,7 +272,7 @@ hipError_t launch_mf_td(const sonar_plan_s* p, const void* x, int F, float2* yex
 hipError_t launch_mf_bound(const sonar_plan_s* p, int F, hipStream_t s);
 hipError_t launch_delay_tables(sonar_plan_s* p, hipStream_t s);
 hipError_t launch_fd_step_table(sonar_plan_s* p, hipStream_t s);
-// energyscape cells (f, d, q) of an exact-phase plan and dL/dp for L = sum_c dE[c] E_c (scratch: d_gdl)
+// energyscape cells (f, d, q) of an exact-phase plan and dL/dp for L = sum_c dE[c] E_c (scratch: d_gscr)
 bool cells_supported(const sonar_plan_s* p);
 hipError_t launch_energyscape_cells(const sonar_plan_s* p, const float2* mf, int F, const int* cells,
                                     const float* dE, int n, float* E_out, double* dpos, hipStream_t s);

@@ -1467,7 +1467,8 @@ int sonar_energyscape_cells(sonar_plan p, const void* mf_in, const int32_t* cell
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
   if (is_td(p)) return fail(SONAR_E_UNSUPPORTED, "energyscape cells: frequency-domain (exact-phase) plans only");
   if (!cells_supported(p))
-    return fail(SONAR_E_UNSUPPORTED, "energyscape cells: K=%d and M=%d must be at most 256", p->K, p->M);
+    return fail(SONAR_E_UNSUPPORTED, "energyscape cells: K=%d and M=%d must be at most 256 (and 2K + M <= 2P)", p->K,
+                p->M);
   if (n_cells < 0 || static_cast<long long>(n_cells) > static_cast<long long>(p->max_frames) * p->D)
     return fail(SONAR_E_INVALID, "n_cells=%d outside [0, max_frames * D = %lld]", n_cells,
                 static_cast<long long>(p->max_frames) * p->D);
