@@ -435,19 +435,22 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
                                double* dpos_out, hipStream_t stream);
 
 /*
- * sonar_energyscape_cells -- selected energyscape cells of a frequency-domain
- * (exact-phase, section 4.3) plan and the position derivative of a loss that
- * reads only them, for calibration losses whose dE vanishes elsewhere (a few
- * reflector cells of a whole energyscape).  Each cell c = (f, d, q) is computed
- * from the band spectra alone, by the definitions of sonar_energyscape (beamformer
- * section 4.1 with per-bin steering, envelope and subsampling):
- *   B[k]  = (1/M) sum_m Y_m[k] e^{-2 pi i k Dl[d][m]/P}  on the band bins,
- *   b_i   = IDFT_P(B) at the K window samples n_i = n0 - (K-1)/2 + qR + i,
- *   E_c   = sum_i h[K-1-i] |b_i|,
+ * sonar_energyscape_cells -- selected energyscape cells and the position
+ * derivative of a loss that reads only them, for calibration losses whose dE
+ * vanishes elsewhere (a few reflector cells of a whole energyscape).  Each cell
+ * c = (f, d, q) is computed by the definitions of sonar_energyscape (section 4.1
+ * beamformer, envelope and subsampling) on its K window samples
+ * n_i = n0 - (K-1)/2 + qR + i only:
+ *   frequency-domain plans (FD_FP32, FD_BF16, FD_BF16X3; exact phase, section 4.3):
+ *     B[k] = (1/M) sum_m Y_m[k] e^{-2 pi i k Dl[d][m]/P} on the band bins and
+ *     b_i = IDFT_P(B) at n_i, from the band spectra alone (no P-point transform);
+ *   FP32 time-domain plans (TD_LINEAR, TD_NEAREST, TD_CUBIC): b_i = the plan's
+ *     interpolated delay-and-sum at n_i from the matched-filter rows;
+ *   E_c = sum_i h[K-1-i] |b_i|,
  * and for L = sum_c dE[c] E_c the chain of sonar_energyscape_vjp restricted to
- * the cells' windows gives dL/dp (no beam window, no P-point transform).
- *   mf_in     : the FD matched-filter buffer of the F frames (sonar_matched_filter),
- *               complex64 [F][Kb][M].
+ * the cells' windows gives dL/dp (TD_NEAREST: refused, as in the dense call).
+ *   mf_in     : the matched-filter buffer of the F frames (sonar_matched_filter):
+ *               FD complex64 [F][Kb][M], TD the rows with their halo.
  *   cells     : int32 [n_cells][3] (f, d, q) in device memory; a cell outside
  *               [0, F) x [0, D) x [0, Q) yields E = NaN and adds nothing to dL/dp.
  *   dE        : float [n_cells] in device memory (the weights dL/dE_c).
@@ -455,8 +458,8 @@ int sonar_energyscape_backward(sonar_plan plan, const void* x, const float* dE, 
  *   dpos_out  : double [M][3], or NULL.
  * Repeated cells count once each.  Needs sonar_plan_enable_gradients (its
  * workspace holds the per-cell partial sums, so n_cells <= max_frames * D),
- * an FD mode, K <= 256, M <= 256 and 2K + M <= 2P (SONAR_E_UNSUPPORTED
- * otherwise).  FP32 arithmetic with the steering phases reduced in FP64, as the
+ * K <= 256, and for FD plans M <= 256 and 2K + M <= 2P (SONAR_E_UNSUPPORTED
+ * otherwise, and for the BF16 / FP16 time-domain modes).  FP32 arithmetic with the steering phases reduced in FP64, as the
  * dense derivative.  Uses the same workspace as sonar_energyscape_vjp: calls on
  * one plan must be ordered (one stream).
  */

@@ -676,6 +676,87 @@ __global__ __launch_bounds__(CELL_THREADS) void cells_g_kernel(const CellArgs a)
   }
 }
 
+// Time-domain readings (linear, nearest, cubic) of the same cells, one 256-thread workgroup per
+// cell from the matched-filter rows: b_i = sum over the delay-table entries of the two weighted
+// taps at window position qR + i (the weights carry 1/M), E_c, G_b, and dDl[m] with the slopes of
+// the dense kernel ((1, -1) on the linear pair; -L_k'(alpha) on the four cubic taps)
+__global__ __launch_bounds__(256) void cells_td_kernel(const float2* __restrict__ yext, long long fstride, int row,
+                                                       const int4* __restrict__ dtab, const double* __restrict__ dl,
+                                                       const int* __restrict__ cells, const float* __restrict__ wgt,
+                                                       const float* __restrict__ taps, float* __restrict__ E_out,
+                                                       float* __restrict__ dpart, int F, int M, int D, int Q, int R,
+                                                       int K, int cubic) {
+  __shared__ float2 gw[256];
+  __shared__ float red[4];
+  const int c = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int f = cells[3 * c], d = cells[3 * c + 1], q = cells[3 * c + 2];
+  float* dout = dpart + static_cast<long long>(c) * M;
+  if (!(f >= 0 && f < F && d >= 0 && d < D && q >= 0 && q < Q)) {
+    if (E_out && tid == 0) E_out[c] = __builtin_nanf("");
+    for (int m = tid; m < M; m += 256) dout[m] = 0.f;
+    return;
+  }
+  const float2* yf = yext + static_cast<long long>(f) * fstride;
+  const int ne = cubic ? 2 * M : M;   // table entries of the direction, entry e reading row e / (1 + cubic)
+  const int4* dt = dtab + static_cast<long long>(d) * ne;
+  float e = 0.f;
+  if (tid < K) {
+    const int w = q * R + tid;
+    float2 b = make_float2(0.f, 0.f);
+    for (int en = 0; en < ne; ++en) {
+      const int4 t = dt[en];
+      const float2* y = yf + static_cast<long long>(cubic ? en >> 1 : en) * row + t.x + w;
+      const float w0 = __int_as_float(t.y), w1 = __int_as_float(t.z);
+      const float2 a0 = y[0], a1 = y[1];
+      b.x = fmaf(w0, a0.x, fmaf(w1, a1.x, b.x));
+      b.y = fmaf(w0, a0.y, fmaf(w1, a1.y, b.y));
+    }
+    const float am = sqrtf(b.x * b.x + b.y * b.y);
+    const float h = taps[K - 1 - tid];
+    e = h * am;
+    const float g = am > 0.f ? wgt[c] * h / am : 0.f;
+    gw[tid] = make_float2(g * b.x, g * b.y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+  if (lane == 0) red[wv] = e;
+  __syncthreads();
+  if (tid == 0 && E_out) E_out[c] = red[0] + red[1] + red[2] + red[3];
+  const float inv_m = 1.0f / static_cast<float>(M);
+  for (int m = tid; m < M; m += 256) {
+    const long long i = static_cast<long long>(d) * M + m;
+    int rel0, rel2 = 0;
+    float s0 = 1.f, s1 = -1.f, s2 = 0.f, s3 = 0.f;
+    if (cubic) {
+      rel0 = dtab[2 * i].x;
+      rel2 = dtab[2 * i + 1].x;
+      const double Dl = dl[i];
+      const double a = -Dl - floor(-Dl), a2 = a * a;
+      s0 = static_cast<float>((3.0 * a2 - 6.0 * a + 2.0) / 6.0);
+      s1 = static_cast<float>(-(3.0 * a2 - 4.0 * a - 1.0) / 2.0);
+      s2 = static_cast<float>((3.0 * a2 - 2.0 * a - 2.0) / 2.0);
+      s3 = static_cast<float>(-(3.0 * a2 - 1.0) / 6.0);
+    } else {
+      rel0 = dtab[i].x;
+    }
+    const float2* y = yf + static_cast<long long>(m) * row + rel0 + q * R;
+    const float2* y2 = yf + static_cast<long long>(m) * row + rel2 + q * R;
+    float acc = 0.f;
+    for (int k = 0; k < K; ++k) {
+      const float2 g = gw[k], a = y[k], b = y[k + 1];
+      float tx = s0 * a.x + s1 * b.x, ty = s0 * a.y + s1 * b.y;
+      if (cubic) {
+        const float2 cc = y2[k], ee = y2[k + 1];
+        tx += s2 * cc.x + s3 * ee.x;
+        ty += s2 * cc.y + s3 * ee.y;
+      }
+      acc = fmaf(g.x, tx, acc);
+      acc = fmaf(g.y, ty, acc);
+    }
+    dout[m] = acc * inv_m;
+  }
+}
+
 // dpos[m] = fs/c sum_cells (sum of the ranges' dDl shares)[m] u_{d_c} (cells outside the plan add
 // nothing: their shares are zero)
 __global__ __launch_bounds__(256) void pos_cells_kernel(const float* __restrict__ dpart, const int* __restrict__ cells,
@@ -737,11 +818,25 @@ hipError_t launch_energyscape_vjp(const sonar_plan_s* p, const float2* mf, float
 }
 
 bool cells_supported(const sonar_plan_s* p) {
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC)
+    return p->K <= 256;
+  if (p->bf_mode != SONAR_BF_FD_FP32 && p->bf_mode != SONAR_BF_FD_BF16 && p->bf_mode != SONAR_BF_FD_BF16X3) return false;
   return p->K <= CELL_WAVES * CELL_SPW && p->M <= 64 * CELL_MG && 2 * p->K + p->M <= 2 * p->P;
 }
 
 hipError_t launch_energyscape_cells(const sonar_plan_s* p, const float2* mf, int F, const int* cells,
                                     const float* dE, int n, float* E_out, double* dpos, hipStream_t s) {
+  if (p->bf_mode == SONAR_BF_TD_LINEAR || p->bf_mode == SONAR_BF_TD_NEAREST || p->bf_mode == SONAR_BF_TD_CUBIC) {
+    // the delay-derivative shares go to the plan's [max_frames][D][M] table (n <= max_frames D)
+    hipLaunchKernelGGL(cells_td_kernel, dim3(n), dim3(256), 0, s, mf, p->mf_fstride, p->row, p->d_dtab, p->d_dl, cells,
+                       dE, p->d_taps, E_out, p->d_gdl, F, p->M, p->D, p->Q, p->R, p->K,
+                       p->bf_mode == SONAR_BF_TD_CUBIC ? 1 : 0);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !dpos) return e;
+    hipLaunchKernelGGL(pos_cells_kernel, dim3(p->M), dim3(256), 0, s, p->d_gdl, cells, n, 1, p->d_dirs, dpos, p->M,
+                       p->D, p->fs / p->c);
+    return hipGetLastError();
+  }
   // S bin ranges per cell (about 1024 bins each, at most 8), with the shares of b and dDl in the
   // plan's transform scratch (P complex values per cell slot: S (K + M) floats must fit 2 P)
   int S = p->kb / 1024;

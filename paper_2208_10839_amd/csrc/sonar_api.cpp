@@ -1465,10 +1465,12 @@ int sonar_energyscape_cells(sonar_plan p, const void* mf_in, const int32_t* cell
   if (st != SONAR_OK) return st;
   if (!dE) return fail(SONAR_E_INVALID, "dE is NULL");
   if (!p->grad_on) return fail(SONAR_E_INVALID, "call sonar_plan_enable_gradients first");
-  if (is_td(p)) return fail(SONAR_E_UNSUPPORTED, "energyscape cells: frequency-domain (exact-phase) plans only");
   if (!cells_supported(p))
-    return fail(SONAR_E_UNSUPPORTED, "energyscape cells: K=%d and M=%d must be at most 256 (and 2K + M <= 2P)", p->K,
-                p->M);
+    return fail(SONAR_E_UNSUPPORTED,
+                "energyscape cells: FP32 time-domain (linear, nearest, cubic) or frequency-domain plans with K <= 256 "
+                "(and M <= 256, 2K + M <= 2P for frequency-domain plans)");
+  if (dpos_out && p->bf_mode == SONAR_BF_TD_NEAREST)
+    return fail(SONAR_E_UNSUPPORTED, "TD_NEAREST: integer delays are piecewise constant in the positions");
   if (n_cells < 0 || static_cast<long long>(n_cells) > static_cast<long long>(p->max_frames) * p->D)
     return fail(SONAR_E_INVALID, "n_cells=%d outside [0, max_frames * D = %lld]", n_cells,
                 static_cast<long long>(p->max_frames) * p->D);

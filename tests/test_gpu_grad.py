@@ -329,14 +329,15 @@ def _geometry_error(pos, true_pos):
     return float(np.sqrt(np.mean(n * n))), float(n.max())
 
 
-def test_cells_match_oracle(gpu, torch_mod):
+@pytest.mark.parametrize("mode", ["fd", "td", "cubic"])
+def test_cells_match_oracle(gpu, torch_mod, mode):
     """sonar_energyscape_cells: E at chosen cells (edges of the range included, one cell
     repeated, one outside the plan) and dL/dp for random weights, against the oracle's
     energyscape and its whole derivative chain with dE scattered onto those cells."""
     torch = torch_mod
     w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=37)
-    _say("case cells: M=32 N=4096 D=37 F=2 fd_fp32")
-    plan = _plan(gpu, w, "fd", max_frames=2)
+    _say(f"case cells {mode}: M=32 N=4096 D=37 F=2")
+    plan = _plan(gpu, w, mode, max_frames=2)
     x = torch.from_numpy(w.x).cuda()
     mf = plan.matched_filter(x)
     rng = np.random.default_rng(np.random.SeedSequence([4, 1, 2, 3]))
@@ -352,7 +353,7 @@ def test_cells_match_oracle(gpu, torch_mod):
     E_o = np.zeros(len(cells))
     E_scale = 0.0
     for f in range(2):
-        steps = _oracle_steps(w, f, plan, "fd")
+        steps = _oracle_steps(w, f, plan, mode)
         R, h, Q = steps[:3]
         Eo = O.envelope(steps[6], h, Q, R)
         E_scale = max(E_scale, float(np.max(np.abs(Eo))))
@@ -362,7 +363,7 @@ def test_cells_match_oracle(gpu, torch_mod):
                 E_o[i] = Eo[cd, cq]
                 dEf[cd, cq] += wts[i]
         G_b = O.envelope_vjp(steps[6], h, dEf, Q, R)
-        dpos_o += _oracle_back(w, plan, "fd", steps, G_b)[2]
+        dpos_o += _oracle_back(w, plan, mode, steps, G_b)[2]
     # E as the dense tests hold it: relative L2 over the cells, and every cell within 1e-5 of the
     # energyscape's largest value (a cell in the noise is a sum over the band whose terms cancel, so
     # its own relative error is larger)
