@@ -399,8 +399,10 @@ int sonar_tune_cache(const char* path);
  * (once; the bytes are added to SONAR_Q_WORKSPACE_BYTES), including the beam
  * window [max_frames][D][G'] that sonar_energyscape_backward fills.  Every FFT length
  * the plan accepts is supported: the P-point transforms of the adjoint run as P / L
- * phase transforms of L = min(P / 2, 16384) points.  The frequency-domain workspace
- * holds max_frames * D * P complex64 values (FP32 pairs) for those phase transforms.
+ * phase transforms of L = min(P / 2, 16384) points, through a scratch of at most
+ * 4 GiB (channels of P complex64 values, max_frames * D of them for frequency-domain
+ * plans and max_frames * M for time-domain ones, or as many as fit; the adjoint then
+ * takes them in chunks).
  */
 int sonar_plan_enable_gradients(sonar_plan plan);
 

@@ -435,27 +435,35 @@ hipError_t mfinv(const sonar_plan_s* p, const float2* V, int F, float* dx, hipSt
   SONAR_LOG_DISPATCH(p->logNF, launch_mfinv_t, p, V, F, dx, s)
 }
 
-// matched-filter adjoint of the time-domain path: dx from G_yhat over Z_P
+// matched-filter adjoint of the time-domain path: dx from G_yhat over Z_P (the phase transforms
+// of gscr_chans channels at a time through the scratch)
 hipError_t mfadj(const sonar_plan_s* p, const float2* gy, int F, float* dx, hipStream_t s) {
-  const int chans = F * p->M;
-  hipError_t e = phase_fft(p, gy, p->P, chans, p->P, 0, s);
-  if (e != hipSuccess) return e;
+  const long long chans = static_cast<long long>(F) * p->M;
   const int L = 1 << adj_logl(p);
-  hipLaunchKernelGGL(mfadj_mul_kernel, dim3(chans, (p->NF + 1 + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_cspec,
-                     p->d_tw, p->d_spec, p->NF, p->P / L, L);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (long long c0 = 0; c0 < chans; c0 += p->gscr_chans) {
+    const long long n = chans - c0 < p->gscr_chans ? chans - c0 : p->gscr_chans;
+    hipError_t e = phase_fft(p, gy + c0 * p->P, p->P, n, p->P, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mfadj_mul_kernel, dim3(static_cast<unsigned>(n), (p->NF + 1 + 255) / 256), dim3(256), 0, s,
+                       p->d_gscr, p->d_cspec, p->d_tw, p->d_spec + c0 * (p->NF + 1), p->NF, p->P / L, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   return mfinv(p, p->d_spec, F, dx, s);
 }
 
 // exact-phase beamformer: G_B, then dDl / dpos and G_Y / dx
 hipError_t vjp_fd(const sonar_plan_s* p, const float2* mf, const float2* gb, int F, float2* dyhat, float* dx,
                   double* dpos, hipStream_t s) {
-  hipError_t e = phase_fft(p, gb, p->G, static_cast<long long>(F) * p->D, p->G, p->n0 - p->hk, s);
-  if (e != hipSuccess) return e;
+  hipError_t e = hipSuccess;
+  const long long chans = static_cast<long long>(F) * p->D;
   const int L = 1 << adj_logl(p);
-  hipLaunchKernelGGL(gfd_band_kernel, dim3(F * p->D, (p->kb + 255) / 256), dim3(256), 0, s, p->d_gscr, p->d_tw,
-                     p->d_gband, p->NF, p->P, p->k_lo, p->kb, p->P / L, L);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  for (long long c0 = 0; c0 < chans; c0 += p->gscr_chans) {
+    const long long n = chans - c0 < p->gscr_chans ? chans - c0 : p->gscr_chans;
+    if ((e = phase_fft(p, gb + c0 * p->G, p->G, n, p->G, p->n0 - p->hk, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(gfd_band_kernel, dim3(static_cast<unsigned>(n), (p->kb + 255) / 256), dim3(256), 0, s, p->d_gscr,
+                       p->d_tw, p->d_gband + c0 * p->kb, p->NF, p->P, p->k_lo, p->kb, p->P / L, L);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (dpos) {
     int ms = 1;
     while (ms < p->M && ms < 64) ms *= 2;
@@ -841,7 +849,9 @@ hipError_t launch_energyscape_cells(const sonar_plan_s* p, const float2* mf, int
   // plan's transform scratch (P complex values per cell slot: S (K + M) floats must fit 2 P)
   int S = p->kb / 1024;
   S = S < 1 ? 1 : (S > 8 ? 8 : S);
-  while (S > 1 && static_cast<long long>(S) * (2 * p->K + p->M) > 2LL * p->P) --S;
+  const long long room = 2LL * p->gscr_chans * p->P;   // floats of scratch
+  while (S > 1 && static_cast<long long>(n) * S * (2 * p->K + p->M) > room) --S;
+  if (static_cast<long long>(n) * S * (2 * p->K + p->M) > room) return hipErrorInvalidValue;
   CellArgs a;
   a.Y = mf;
   a.cells = cells;

@@ -96,8 +96,9 @@ struct sonar_plan_s {
   unsigned short* d_mt_fir = nullptr;   // TD BF16: low-pass B fragments, [K-steps][hi, lo][64 lanes][8] BF16
   void* d_aux = nullptr;       // plan-build scratch
   float* d_gdl = nullptr;      // gradients (TD): dL/dDl, [max_frames][D][M]
-  float2* d_gscr = nullptr;    // gradients: even/odd spectra of G_yhat [max_frames][M][2][NF] (TD),
-                               // of G_b [max_frames][D][2][NF] (FD)
+  float2* d_gscr = nullptr;    // gradients: phase transforms of G_yhat (TD) or G_b (FD), gscr_chans
+                               // channels of P values at a time (at most GSCR_MAX_BYTES)
+  long long gscr_chans = 0;
   float2* d_gband = nullptr;   // gradients (FD): beam-spectrum gradient G_B, [max_frames][D][kb]
   float2* d_gspec = nullptr;   // gradients (FD): conj(C) G_Y on [0, NF], [max_frames][M][NF + 1]
   float2* d_gy = nullptr;      // gradients: matched-filter gradient for sonar_energyscape_backward
@@ -219,6 +220,8 @@ constexpr int MT_NWAVE_LARGE = 8;
 // global memory plus 2^MB_LOGN2-point transforms in LDS (k_mf_big.hip)
 constexpr int MB_LOGN2 = 14;
 constexpr int MB_MAX_R = 16;
+// gradient transform scratch: at most this many bytes (the adjoint runs its channels in chunks)
+constexpr long long GSCR_MAX_BYTES = 4LL << 30;
 constexpr int MT_MICS = 8;      // microphones staged per group with four planes (16 with two)
 // microphones staged per group: the staged bytes per group stay the same for both plane counts
 inline int mt_mics(const sonar_plan_s* p) { return mt_planes(p) == 2 ? 2 * MT_MICS : MT_MICS; }

@@ -1413,8 +1413,13 @@ int sonar_plan_enable_gradients(sonar_plan p) {
   if (p->grad_on) return SONAR_OK;
   const size_t mf = static_cast<size_t>(p->max_frames);
   size_t total = 0;
+  // transform scratch: every channel of a batch, or as many as GSCR_MAX_BYTES hold (the adjoint then
+  // runs its channels in chunks)
+  const long long all_chans = static_cast<long long>(mf) * (td ? p->M : p->D);
+  const long long cap_chans = std::max(1LL, GSCR_MAX_BYTES / (static_cast<long long>(p->P) * 8));
+  p->gscr_chans = std::min(all_chans, cap_chans);
   bool ok = dev_alloc(&p->d_gdl, mf * p->D * p->M, &total) == hipSuccess &&
-            dev_alloc(&p->d_gscr, mf * (td ? p->M : p->D) * 2 * static_cast<size_t>(p->NF), &total) == hipSuccess;
+            dev_alloc(&p->d_gscr, static_cast<size_t>(p->gscr_chans) * p->P, &total) == hipSuccess;
   if (ok && !td)
     ok = dev_alloc(&p->d_gband, mf * p->D * p->kb, &total) == hipSuccess &&
          dev_alloc(&p->d_gspec, mf * p->M * (static_cast<size_t>(p->NF) + 1), &total) == hipSuccess;
@@ -1474,6 +1479,12 @@ int sonar_energyscape_cells(sonar_plan p, const void* mf_in, const int32_t* cell
   if (n_cells < 0 || static_cast<long long>(n_cells) > static_cast<long long>(p->max_frames) * p->D)
     return fail(SONAR_E_INVALID, "n_cells=%d outside [0, max_frames * D = %lld]", n_cells,
                 static_cast<long long>(p->max_frames) * p->D);
+  if (!is_td(p)) {
+    const long long need = static_cast<long long>(n_cells) * (2 * p->K + p->M);   // floats, one range per cell
+    if (need > 2LL * p->gscr_chans * p->P)
+      return fail(SONAR_E_INVALID, "n_cells=%d needs more scratch than the plan's gradient workspace: pass fewer cells",
+                  n_cells);
+  }
   if (n_cells == 0) {
     if (dpos_out) {
       const hipError_t e = hipMemsetAsync(dpos_out, 0, sizeof(double) * 3 * p->M, stream);

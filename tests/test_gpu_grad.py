@@ -94,6 +94,29 @@ def test_vjp_long_fft_matches_oracle(gpu, torch_mod, mode, fft_len):
     _check_vjp(gpu, torch_mod, mode, n_dirs=11, fft_len=fft_len)
 
 
+def test_vjp_chunked_scratch_matches_per_frame(gpu, torch_mod):
+    """The adjoint's transform scratch holds at most 4 GiB (4096 channels of P = 131072): 2 frames
+    of 2100 directions run as two chunks in one call and as one chunk per frame in two calls; dx
+    agrees bit for bit and dL/dp is the sum of the per-frame ones (same FP64 reduction, other order)."""
+    torch = torch_mod
+    w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=2100)
+    _say("case vjp chunked scratch: M=32 N=4096 D=2100 F=2 P=131072 fd_fp32")
+    plan = _plan(gpu, w, "fd", max_frames=2, fft_len=131072)
+    x = torch.from_numpy(w.x).cuda()
+    mf = plan.matched_filter(x)
+    dE = torch.from_numpy(np.random.default_rng(np.random.SeedSequence([4, 2, 1, 0]))
+                          .standard_normal((2, plan.D, plan.Q)).astype(np.float32)).cuda()
+    _, dx, dpos = plan.vjp(mf, plan.beamform(mf), dE)
+    parts = [plan.vjp(mf[f:f + 1].contiguous(), plan.beamform(mf[f:f + 1].contiguous()), dE[f:f + 1].contiguous())
+             for f in range(2)]
+    torch.cuda.synchronize()
+    for f in range(2):
+        assert torch.equal(dx[f], parts[f][1][0]), f
+    err = rel_l2(dpos, parts[0][2] + parts[1][2])
+    _say(f"chunked vs per-frame: dx equal, dpos rel {err:.2e}")
+    assert err <= 1e-12
+
+
 def _check_vjp(gpu, torch_mod, mode, n_dirs, fft_len):
     torch = torch_mod
     w = synth.make_workload("c2", frames=2, n_samples=4096, n_dirs=n_dirs)
