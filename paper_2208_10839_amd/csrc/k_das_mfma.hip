@@ -85,7 +85,8 @@ __device__ __forceinline__ void mt_tile(
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale,
+    int nqt, int ntiles, int nx, int tpx, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
+    float fir_unscale,
     int block) {
   constexpr int MICS = NPL == 2 ? 2 * MT_MICS : MT_MICS;   // microphones staged per group
   extern __shared__ unsigned short sm[];    // NPL planes x MICS rows x wrow (re hi, re lo, im hi, im lo / re, im)
@@ -102,16 +103,27 @@ __device__ __forceinline__ void mt_tile(
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int rho = wv % RES;
-  // Workgroups are handed to the XCDs round-robin by index: XCD x = index % nx
-  // keeps the weights of its own tpx direction tiles in its L2 and runs them
-  // back to back on each staged window (frame f, range tile qt).
-  const int bx = block % nx;
-  int bid = block / nx;
-  const int tile = bx * tpx + bid % tpx;
-  if (tile >= ntiles) return;
-  bid /= tpx;
-  const int qt = bid % nqt;
-  const int f = bid / nqt;
+  // Workgroups are handed to the XCDs round-robin by index (XCD x = index % MT_XCDS), in one of two
+  // orders:
+  //  * window-major (nx = 0; single-term weights, whose fragments of all tiles fit every L2): XCD x
+  //    takes the windows (frame f, range tile qt) x, x + MT_XCDS, ... and runs every direction tile
+  //    of a window back to back, so each window is staged from HBM into one L2 once;
+  //  * tile-major (split weights, two or three times the fragments): XCD bx = index % nx keeps the
+  //    weights of its own tpx direction tiles in its L2 and runs them back to back on each window.
+  int tile, win;
+  if (nx == 0) {
+    const int jb = block / MT_XCDS;
+    tile = jb % ntiles;
+    win = block % MT_XCDS + MT_XCDS * (jb / ntiles);
+    if (win >= nwin) return;   // padding of the last round
+  } else {
+    const int bid = block / nx;
+    tile = (block % nx) * tpx + bid % tpx;
+    if (tile >= ntiles) return;
+    win = bid / tpx;
+  }
+  const int qt = win % nqt;
+  const int f = win / nqt;
   const int s0 = qt * qc * R;                // first window sample of the tile (a multiple of 4)
   const int s0a = s0 & ~7;                   // staged from here: 16-byte aligned rows
   // first sample of the wavefront, as an index into the staged rows
@@ -540,15 +552,17 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int gmax, int kcmax, int nmc, int wrow, int perm_off, float fir_unscale) {
-  mt_tile<NWAVE, NPL, F16, W1>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx,
+    int nqt, int ntiles, int nx, int tpx, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
+    float fir_unscale) {
+  mt_tile<NWAVE, NPL, F16, W1>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, nwin,
                            gmax, kcmax, nmc, wrow, perm_off, fir_unscale, static_cast<int>(blockIdx.x));
 }
 
 // Persistent launch over the items of a sensor-network batch (each item: one plan, its frames):
 // a work list of every item's tiles, item after item, each item's run padded to whole rounds of
-// MT_XCDS so that the XCD mapping of one-plan launches is kept (tile slot bx of every item on XCD
-// bx).  A fixed grid of workgroups (a few per CU) walks the list with a stride of its size.
+// MT_XCDS so that the XCD mapping of one-plan launches is kept (window x mod MT_XCDS of every item
+// on XCD x; the grid is a multiple of MT_XCDS).  A fixed grid of workgroups (a few per CU) walks
+// the list with a stride of its size.
 struct MtItem {
   const unsigned short* planes;
   const int4* gtab;
@@ -558,10 +572,10 @@ struct MtItem {
   const uint4* ftab;
   float* E;
   long long fstride;
-  int M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, gmax, kcmax, nmc, wrow, perm_off;
+  int M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, nwin, gmax, kcmax, nmc, wrow, perm_off;
   float fir_unscale;
   int work_begin;   // first work-list position of the item (a multiple of MT_XCDS)
-  int work_count;   // its tiles: frames x nqt x nx x tpx (positions up to the next item are padding)
+  int work_count;   // its positions (mt_grid_blocks), nwin = frames x nqt
 };
 struct MtWork {
   MtItem item[MT_MULTI_MAX_ITEMS];
@@ -578,13 +592,26 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const MtItem& it = work.item[i];
     if (w - it.work_begin >= it.work_count) continue;   // padding up to the next item (uniform)
     mt_tile<NWAVE, NPL, F16, W1>(it.planes, it.fstride, it.gtab, it.wtab, it.kcr, it.perm, it.ftab, it.E, it.M, it.D, it.Q,
-                             it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.nx, it.tpx, it.gmax, it.kcmax, it.nmc,
+                             it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.nx, it.tpx, it.nwin, it.gmax, it.kcmax, it.nmc,
                              it.wrow, it.perm_off, it.fir_unscale, w - it.work_begin);
     __syncthreads();   // the next tile's staging rewrites the LDS this tile's epilogue reads
   }
 }
 
 }  // namespace
+
+// workgroups of a launch over nwin windows and the order (nx = 0: window-major, for single-term
+// weights; else tile-major with tpx tiles per XCD)
+static long long mt_grid_blocks(const sonar_plan_s* p, int nwin, int* nx, int* tpx) {
+  if (mt_w1(p)) {
+    *nx = 0;
+    *tpx = 0;
+    return static_cast<long long>(MT_XCDS) * p->mt_ntiles * ((nwin + MT_XCDS - 1) / MT_XCDS);
+  }
+  *nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
+  *tpx = (p->mt_ntiles + *nx - 1) / *nx;
+  return static_cast<long long>(nwin) * *nx * *tpx;
+}
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
 // (|b| rows, their zero tail, and the split low-pass partial sums [nwave / 2][16][64] floats)
@@ -612,14 +639,14 @@ hipError_t set_mt_attr() {
 
 template <int NWAVE, int NPL, bool F16, bool W1>
 hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
-  const int nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
-  const int tpx = (p->mt_ntiles + nx - 1) / nx;
-  const long long nblk = static_cast<long long>(F) * p->mt_nqt * nx * tpx;
+  int nx, tpx;
+  const int nwin = F * p->mt_nqt;   // windows (frame, range tile)
+  const long long nblk = mt_grid_blocks(p, nwin, &nx, &tpx);
   hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL, F16, W1>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
                      mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, reinterpret_cast<const int4*>(p->d_mt_g),
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
-                     p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                     p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, nwin, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
                      static_cast<int>(mt_perm_offset(p)), p->mt_fir_unscale);
   return hipGetLastError();
 }
@@ -709,8 +736,8 @@ hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const flo
     it.qc = p->mt_qc;
     it.nqt = p->mt_nqt;
     it.ntiles = p->mt_ntiles;
-    it.nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
-    it.tpx = (p->mt_ntiles + it.nx - 1) / it.nx;
+    it.nwin = frames[i] * p->mt_nqt;
+    const long long blocks = mt_grid_blocks(p, it.nwin, &it.nx, &it.tpx);
     it.gmax = p->mt_gmax;
     it.kcmax = p->mt_kcmax;
     it.nmc = p->mt_nmc;
@@ -718,7 +745,7 @@ hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const flo
     it.perm_off = static_cast<int>(mt_perm_offset(p));
     it.fir_unscale = p->mt_fir_unscale;
     it.work_begin = pos;
-    it.work_count = frames[i] * p->mt_nqt * it.nx * it.tpx;
+    it.work_count = static_cast<int>(blocks);
     pos += (it.work_count + MT_XCDS - 1) / MT_XCDS * MT_XCDS;
     smem = std::max(smem, mt_smem_bytes(p));
   }
