@@ -146,7 +146,8 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
 template <int LOGNF>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
-    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound, int rows) {
+    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound, int rows,
+    long long chans) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -155,8 +156,12 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   __shared__ float2 lds[S::LDS_ELEMS];
   __shared__ float2 tw[TWLEN];
   const int tid = threadIdx.x;
-  const int par = blockIdx.x & 1;
-  const long long ch = blockIdx.x >> 1;
+  // workgroups 16 j + x and 16 j + 8 + x are the two parities of channel 8 j + x: both on XCD x
+  // (workgroups go to the XCDs round-robin), so the second reads the spectrum from that L2
+  const unsigned bi = blockIdx.x;
+  const int par = (bi >> 3) & 1;
+  const long long ch = static_cast<long long>(bi >> 4) * 8 + (bi & 7);
+  if (ch >= chans) return;
   load_tw<LOGNF>(tw, tw_g, tid, T);
   __syncthreads();
   const float2* tw_hi = tw;
@@ -280,9 +285,10 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
                      mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(2 * F * p->M), dim3(T), 0, s,
+  const long long chans = static_cast<long long>(F) * p->M;
+  hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(static_cast<unsigned>((chans + 7) / 8 * 16)), dim3(T), 0, s,
                      p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr, rows ? 1 : 0);
+                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr, rows ? 1 : 0, chans);
   return hipGetLastError();
 }
 
