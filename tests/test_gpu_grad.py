@@ -400,6 +400,31 @@ def test_cells_match_oracle(gpu, torch_mod, mode):
     assert errP <= TOL_GRAD
 
 
+def test_cells_errors(gpu, torch_mod):
+    """Status codes of sonar_energyscape_cells: modes without a cells reading, TD_NEAREST's position
+    derivative, more cells than the workspace holds."""
+    torch = torch_mod
+    w = synth.make_workload("c1", frames=1, n_dirs=7)
+    x = torch.from_numpy(w.x).cuda()
+    cells = torch.tensor([[0, 1, 2]], dtype=torch.int32, device="cuda")
+    one = torch.ones(1, dtype=torch.float32, device="cuda")
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, mode="td_bf16g")
+    with pytest.raises(gpu.SonarError) as ei:
+        plan.cells(plan.matched_filter(x), cells, one)
+    assert ei.value.status == gpu.SONAR_E_UNSUPPORTED
+    plan = gpu.Plan(w.mic_pos, w.chirp, w.dirs, w.x.shape[2], fs=w.fs, c=w.c, mode="td_nearest")
+    mf = plan.matched_filter(x)
+    E, _ = plan.cells(mf, cells, one, want_dpos=False)      # the energyscape cell alone is fine
+    assert np.isfinite(E.cpu().numpy()).all()
+    with pytest.raises(gpu.SonarError) as ei:
+        plan.cells(mf, cells, one)
+    assert ei.value.status == gpu.SONAR_E_UNSUPPORTED
+    many = cells.repeat(plan.D + 1, 1).contiguous()         # above max_frames * D = 7
+    with pytest.raises(gpu.SonarError) as ei:
+        plan.cells(mf, many, torch.ones(many.shape[0], dtype=torch.float32, device="cuda"), want_dpos=False)
+    assert ei.value.status == gpu.SONAR_E_INVALID
+
+
 def test_cells_match_dense_calibration(gpu, torch_mod):
     """The calibration workload (32 mics, 16384 samples, 1500 directions, 10 frames of 5
     reflectors): the cells path gives the dense path's loss and gradient."""
