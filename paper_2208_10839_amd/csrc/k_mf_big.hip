@@ -158,7 +158,7 @@ template <int R>
 __global__ __launch_bounds__(N2 / 16) void big_inv_rows(const float2* __restrict__ spec,
                                                         const float2* __restrict__ tw_g,
                                                         const float2* __restrict__ tw2_g,
-                                                        float2* __restrict__ scratch) {
+                                                        float2* __restrict__ scratch, long long chans) {
   using S = FftShape<LOGN2>;
   constexpr int NF = R * N2;
   constexpr int T = S::T;
@@ -166,9 +166,14 @@ __global__ __launch_bounds__(N2 / 16) void big_inv_rows(const float2* __restrict
   __shared__ float2 lds[S::LDS_ELEMS];
   __shared__ float2 tw[NHI + 64];
   const int tid = threadIdx.x;
-  const int k1 = blockIdx.x % R;
-  const int par = (blockIdx.x / R) & 1;
-  const long long ch = blockIdx.x / (2 * R);
+  // the 2R workgroups of channel 8 j + x (every k1, both parities: each reads a strided share of
+  // the channel's spectrum, together every line 2R times) are blocks 16 R j + 8 s + x, s < 2R:
+  // all on XCD x (workgroups go to the XCDs round-robin), so the lines come from that L2
+  const int s8 = (blockIdx.x / 8) % (2 * R);
+  const int k1 = s8 % R;
+  const int par = s8 / R;
+  const long long ch = static_cast<long long>(blockIdx.x / (16 * R)) * 8 + blockIdx.x % 8;
+  if (ch >= chans) return;
   for (int i = tid; i < NHI + 64; i += T) tw[i] = tw2_g[i];
   const BigTw twb = big_tw(tw_g, NF);
   const float2* in = spec + ch * (NF + 1);
@@ -283,7 +288,8 @@ __global__ __launch_bounds__(256) void big_inv_real(const float2* __restrict__ V
 
 template <int R>
 hipError_t inverse_real_t(const sonar_plan_s* p, const float2* V, int chans, float* out, hipStream_t s) {
-  hipLaunchKernelGGL((big_inv_rows<R>), dim3(chans * 2 * R), dim3(N2 / 16), 0, s, V, p->d_tw, p->d_tw2, p->d_big);
+  hipLaunchKernelGGL((big_inv_rows<R>), dim3((chans + 7) / 8 * 16 * R), dim3(N2 / 16), 0, s, V, p->d_tw, p->d_tw2,
+                     p->d_big, static_cast<long long>(chans));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((big_inv_real<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, V, p->d_tw, p->d_big, out, p->N,
@@ -309,8 +315,8 @@ hipError_t forward_t(const sonar_plan_s* p, const void* x, int F, float2* spec, 
 template <int R>
 hipError_t inverse_t(const sonar_plan_s* p, int F, float2* yext, hipStream_t s, bool rows) {
   const int chans = F * p->M;
-  hipLaunchKernelGGL((big_inv_rows<R>), dim3(chans * 2 * R), dim3(N2 / 16), 0, s, p->d_spec, p->d_tw, p->d_tw2,
-                     p->d_big);
+  hipLaunchKernelGGL((big_inv_rows<R>), dim3((chans + 7) / 8 * 16 * R), dim3(N2 / 16), 0, s, p->d_spec, p->d_tw,
+                     p->d_tw2, p->d_big, static_cast<long long>(chans));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((big_inv_radix<R>), dim3(N2 / 256, 2 * chans), dim3(256), 0, s, p->d_spec, p->d_tw, p->d_big,
