@@ -15,6 +15,8 @@ Beamformer paths (each with its own oracle reading and bar):
   fp32_td         time-domain linear-interpolation DAS, FP32 (oracle td, bar 1e-5)
   bf16_mfma_fd    frequency-domain exact-delay DAS, per-bin GEMM on BF16 MFMA (oracle fd, bar 1e-3)
   fp32_fd         frequency-domain DAS, per-bin GEMM on FP32 MFMA (oracle fd, bar 1e-5)
+  bf16x3_mfma_fd  the same GEMM on BF16 MFMA with split operands (hi*hi + hi*lo + lo*hi), the guaranteed-accuracy
+                  BF16 mode (oracle fd, bar 1e-3; errors near FP32)
   bf16_mfma_td    time-domain DAS as a dense product on BF16 MFMA, weights and samples split (td, 1e-3)
   bf16x2_mfma_td  the same with single-term BF16 samples: two products instead of three (td, 1e-3)
   f16_mfma_td     time-domain DAS on FP16 MFMA, delays on a 1/2048-sample grid (td, 3e-4)
@@ -65,6 +67,8 @@ PATHS = {
                      [CSRC + "k_fd.hip", CSRC + "fft_lds.hpp", CSRC + "plan.hpp"]),
     "fp32_fd": ("fd_fp32", "fd", 1e-5, "f32", "fd_gemm_kernel<fp32> + fd_ifft_env_kernel",
                 [CSRC + "k_fd.hip", CSRC + "fft_lds.hpp", CSRC + "plan.hpp"]),
+    "bf16x3_mfma_fd": ("fd_bf16x3", "fd", 1e-3, "bf16", "fd_gemm_kernel<bf16x3> + fd_ifft_env_kernel",
+                       [CSRC + "k_fd.hip", CSRC + "fft_lds.hpp", CSRC + "plan.hpp"]),
     "bf16_mfma_td": ("td_bf16", "td", 1e-3, "bf16", "das_mfma_env_kernel",
                      [CSRC + "k_das_mfma.hip", CSRC + "plan.hpp"]),
     "bf16x2_mfma_td": ("td_bf16x2", "td", 1e-3, "bf16", "das_mfma_env_kernel<single-term samples>",
