@@ -137,7 +137,7 @@ typedef struct {
   double band_lo_hz;         /* matched-filter band mask [lo, hi] in Hz;                    */
   double band_hi_hz;         /*   0, 0 disables the mask                                     */
   int32_t fft_len;           /* P: even, >= N + L - 1; 0 selects the smallest power of two  */
-                             /*   (this build transforms powers of two 32 .. 524288 only)    */
+                             /*   (the library transforms powers of two 32 .. 524288 only)   */
   int32_t bf_mode;           /* enum sonar_bf_mode                                            */
   int32_t sample_dtype;      /* enum sonar_dtype of x                                         */
   int32_t max_frames;        /* F_max >= 1: the workspace is sized for this batch            */

@@ -576,10 +576,10 @@ int sonar_plan_create(const sonar_plan_desc* desc, hipStream_t stream, sonar_pla
     delete p;
     return fail(SONAR_E_INVALID, "fft_len %d must be even and >= N + L - 1 = %lld", d.fft_len, need);
   } else if (!is_pow2(P) || P < 32) {
-    // a valid length (the definition only needs P even and >= N + L - 1) that the transforms of
-    // this build do not cover: they are radix-2^k
+    // a valid length (the definition only needs P even and >= N + L - 1) that the library's
+    // transforms do not cover: they are radix-2^k
     delete p;
-    return fail(SONAR_E_UNSUPPORTED, "fft_len %d: this build transforms powers of two >= 32 only", d.fft_len);
+    return fail(SONAR_E_UNSUPPORTED, "fft_len %d: the library transforms powers of two >= 32 only", d.fft_len);
   }
   if (P > 2LL * MB_MAX_R * (1 << MB_LOGN2)) {
     delete p;

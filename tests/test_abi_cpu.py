@@ -73,7 +73,7 @@ def _desc(**over):
     ("fft_len", 64, binding.SONAR_E_INVALID),         # below N + L - 1
     ("fft_len", 106, binding.SONAR_E_INVALID),        # even, but below N + L - 1
     ("fft_len", 108, binding.SONAR_E_UNSUPPORTED),    # valid (even, >= N + L - 1), not a power of two
-    ("fft_len", 120, binding.SONAR_E_UNSUPPORTED),    # valid: 2^3 3 5, radices this build does not have
+    ("fft_len", 120, binding.SONAR_E_UNSUPPORTED),    # valid: 2^3 3 5, radices the library does not have
     ("fft_len", 1048576, binding.SONAR_E_UNSUPPORTED),  # above 2 x 16 x 16384
     ("gate_begin", 50, binding.SONAR_E_INVALID),      # gate_end 0 -> n0 >= n1
     ("lpf_len", 4, binding.SONAR_E_INVALID),          # even, and no taps
