@@ -85,7 +85,7 @@ __device__ __forceinline__ void mt_tile(
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
+    int nqt, int ntiles, int tg, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
     float fir_unscale,
     int block) {
   constexpr int MICS = NPL == 2 ? 2 * MT_MICS : MT_MICS;   // microphones staged per group
@@ -103,24 +103,20 @@ __device__ __forceinline__ void mt_tile(
   const int lane = threadIdx.x & 63;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
   const int rho = wv % RES;
-  // Workgroups are handed to the XCDs round-robin by index (XCD x = index % MT_XCDS), in one of two
-  // orders:
-  //  * window-major (nx = 0; single-term weights, whose fragments of all tiles fit every L2): XCD x
-  //    takes the windows (frame f, range tile qt) x, x + MT_XCDS, ... and runs every direction tile
-  //    of a window back to back, so each window is staged from HBM into one L2 once;
-  //  * tile-major (split weights, two or three times the fragments): XCD bx = index % nx keeps the
-  //    weights of its own tpx direction tiles in its L2 and runs them back to back on each window.
+  // Workgroups are handed to the XCDs round-robin by index (XCD x = index % MT_XCDS).  The
+  // direction tiles are cut into tg groups (tg divides MT_XCDS) and XCD x serves group
+  // x / (MT_XCDS / tg) on the windows (frame f, range tile qt) congruent to x mod MT_XCDS / tg,
+  // running the group's tiles back to back on each window: each window is staged from HBM into
+  // tg L2s and each L2 holds the weight fragments of 1/tg of the tiles.  tg = 1 (window-major)
+  // where all the fragments fit one L2 (single-term weights), larger with split weights.
   int tile, win;
-  if (nx == 0) {
-    const int jb = block / MT_XCDS;
-    tile = jb % ntiles;
-    win = block % MT_XCDS + MT_XCDS * (jb / ntiles);
-    if (win >= nwin) return;   // padding of the last round
-  } else {
-    const int bid = block / nx;
-    tile = (block % nx) * tpx + bid % tpx;
-    if (tile >= ntiles) return;
-    win = bid / tpx;
+  {
+    const int xpg = MT_XCDS / tg;
+    const int ntg = (ntiles + tg - 1) / tg;
+    const int x = block % MT_XCDS, jb = block / MT_XCDS;
+    tile = (x / xpg) * ntg + jb % ntg;
+    win = x % xpg + xpg * (jb / ntg);
+    if (tile >= ntiles || win >= nwin) return;   // padding of the last round
   }
   const int qt = win % nqt;
   const int f = win / nqt;
@@ -552,9 +548,9 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const unsigned short* __restrict__ planes, long long fstride, const int4* __restrict__ gtab,
     const uint4* __restrict__ wtab, const int2* __restrict__ kcr, const int* __restrict__ perm,
     const uint4* __restrict__ ftab, float* __restrict__ E, int M, int D, int Q, int row, int R, int K, int qc,
-    int nqt, int ntiles, int nx, int tpx, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
+    int nqt, int ntiles, int tg, int nwin, int gmax, int kcmax, int nmc, int wrow, int perm_off,
     float fir_unscale) {
-  mt_tile<NWAVE, NPL, F16, W1>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, nwin,
+  mt_tile<NWAVE, NPL, F16, W1>(planes, fstride, gtab, wtab, kcr, perm, ftab, E, M, D, Q, row, R, K, qc, nqt, ntiles, tg, nwin,
                            gmax, kcmax, nmc, wrow, perm_off, fir_unscale, static_cast<int>(blockIdx.x));
 }
 
@@ -572,7 +568,7 @@ struct MtItem {
   const uint4* ftab;
   float* E;
   long long fstride;
-  int M, D, Q, row, R, K, qc, nqt, ntiles, nx, tpx, nwin, gmax, kcmax, nmc, wrow, perm_off;
+  int M, D, Q, row, R, K, qc, nqt, ntiles, tg, nwin, gmax, kcmax, nmc, wrow, perm_off;
   float fir_unscale;
   int work_begin;   // first work-list position of the item (a multiple of MT_XCDS)
   int work_count;   // its positions (mt_grid_blocks), nwin = frames x nqt
@@ -592,7 +588,7 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
     const MtItem& it = work.item[i];
     if (w - it.work_begin >= it.work_count) continue;   // padding up to the next item (uniform)
     mt_tile<NWAVE, NPL, F16, W1>(it.planes, it.fstride, it.gtab, it.wtab, it.kcr, it.perm, it.ftab, it.E, it.M, it.D, it.Q,
-                             it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.nx, it.tpx, it.nwin, it.gmax, it.kcmax, it.nmc,
+                             it.row, it.R, it.K, it.qc, it.nqt, it.ntiles, it.tg, it.nwin, it.gmax, it.kcmax, it.nmc,
                              it.wrow, it.perm_off, it.fir_unscale, w - it.work_begin);
     __syncthreads();   // the next tile's staging rewrites the LDS this tile's epilogue reads
   }
@@ -600,17 +596,15 @@ __global__ __launch_bounds__(NWAVE * 64) __attribute__((amdgpu_waves_per_eu(2, 2
 
 }  // namespace
 
-// workgroups of a launch over nwin windows and the order (nx = 0: window-major, for single-term
-// weights; else tile-major with tpx tiles per XCD)
-static long long mt_grid_blocks(const sonar_plan_s* p, int nwin, int* nx, int* tpx) {
-  if (mt_w1(p)) {
-    *nx = 0;
-    *tpx = 0;
-    return static_cast<long long>(MT_XCDS) * p->mt_ntiles * ((nwin + MT_XCDS - 1) / MT_XCDS);
-  }
-  *nx = p->mt_ntiles < MT_XCDS ? p->mt_ntiles : MT_XCDS;
-  *tpx = (p->mt_ntiles + *nx - 1) / *nx;
-  return static_cast<long long>(nwin) * *nx * *tpx;
+// tile groups of the workgroup order and the workgroups of a launch over nwin windows: one group
+// (window-major) for single-term weights, 2 for split weights on two planes, 8 (tile-major) for
+// four planes, as measured best at 32 x 16384 x 1500; at most the tile count (a power of two)
+static long long mt_grid_blocks(const sonar_plan_s* p, int nwin, int* tg) {
+  int g = mt_w1(p) ? 1 : (mt_planes(p) == 2 ? 2 : MT_XCDS);
+  while (g > 1 && g > p->mt_ntiles) g /= 2;
+  *tg = g;
+  const int xpg = MT_XCDS / g;
+  return static_cast<long long>(MT_XCDS) * ((p->mt_ntiles + g - 1) / g) * ((nwin + xpg - 1) / xpg);
 }
 
 // byte offset of the tile's slot -> direction table, after the staging and low-pass regions
@@ -639,14 +633,14 @@ hipError_t set_mt_attr() {
 
 template <int NWAVE, int NPL, bool F16, bool W1>
 hipError_t launch_mt(const sonar_plan_s* p, const unsigned short* planes, int F, float* E, hipStream_t s) {
-  int nx, tpx;
+  int tg;
   const int nwin = F * p->mt_nqt;   // windows (frame, range tile)
-  const long long nblk = mt_grid_blocks(p, nwin, &nx, &tpx);
+  const long long nblk = mt_grid_blocks(p, nwin, &tg);
   hipLaunchKernelGGL((das_mfma_env_kernel<NWAVE, NPL, F16, W1>), dim3(static_cast<unsigned>(nblk)), dim3(NWAVE * 64),
                      mt_smem_bytes(p), s, planes, 4 * p->mf_fstride, reinterpret_cast<const int4*>(p->d_mt_g),
                      reinterpret_cast<const uint4*>(p->d_mt_w), p->d_mt_kcr,
                      p->d_mt_perm, reinterpret_cast<const uint4*>(p->d_mt_fir), E, p->M, p->D, p->Q, p->row, p->R, p->K,
-                     p->mt_qc, p->mt_nqt, p->mt_ntiles, nx, tpx, nwin, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
+                     p->mt_qc, p->mt_nqt, p->mt_ntiles, tg, nwin, p->mt_gmax, p->mt_kcmax, p->mt_nmc, p->mt_wrow,
                      static_cast<int>(mt_perm_offset(p)), p->mt_fir_unscale);
   return hipGetLastError();
 }
@@ -737,7 +731,7 @@ hipError_t launch_das_mfma_env_multi(const sonar_plan_s* const* plans, const flo
     it.nqt = p->mt_nqt;
     it.ntiles = p->mt_ntiles;
     it.nwin = frames[i] * p->mt_nqt;
-    const long long blocks = mt_grid_blocks(p, it.nwin, &it.nx, &it.tpx);
+    const long long blocks = mt_grid_blocks(p, it.nwin, &it.tg);
     it.gmax = p->mt_gmax;
     it.kcmax = p->mt_kcmax;
     it.nmc = p->mt_nmc;
