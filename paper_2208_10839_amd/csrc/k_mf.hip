@@ -143,11 +143,17 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
 // Inverse transform of one output parity of one channel per workgroup:
 //   yhat[2a + par] = (1/P) (IDFT'_NF(Yhat[k] exp(2 pi i k par / P))[a] + Yhat[NF] (-1)^par)
 // written to the MF rows: element j of a row holds yhat[(origin + j) mod P].
-template <int LOGNF>
+// PLANES (0, 2 or 4 16-bit planes after the complex rows) and F16 (FP16 planes of 2^e yhat
+// instead of BF16) are compile-time, so each output format is its own kernel without the
+// other formats' live registers (the one kernel for all formats spilled at NF = 16384).
+template <int LOGNF, int PLANES, bool F16>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
-    long long fstride, int M, int row, int origin, int P, int planes, const float* __restrict__ fbound, int rows,
+    long long fstride, int M, int row, int origin, int P, const float* __restrict__ fbound, int rows,
     long long chans) {
+  static_assert(PLANES == 0 || PLANES == 2 || PLANES == 4, "no planes, two or four");
+  static_assert(!F16 || PLANES == 2, "FP16 samples come as two planes");
+  constexpr int planes = PLANES;
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -189,7 +195,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
                        static_cast<long long>(m) * planes * row;
   // TD_F16: FP16 planes of 2^e yhat (e from the frame's channel bounds), 2^-e / M in the frame header
   float sc = 0.f;
-  if (fbound) {
+  if constexpr (F16) {
     const int e = mf_f16_exponent(fbound, f, M);
     sc = ldexpf(1.0f, e);
     if (m == 0 && par == 0 && tid == 0)
@@ -200,22 +206,22 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const int n = 2 * S::out_index(tid, i) + par;
     const float2 y = make_float2((v[i].x + sgn * ny.x) * inv_p, (v[i].y + sgn * ny.y) * inv_p);
     unsigned short rh = 0, rl = 0, ih = 0, il = 0;
-    if (planes) {
-      rh = mf_plane_word(y.x, sc);
-      ih = mf_plane_word(y.y, sc);
-      if (planes == 4) {
+    if constexpr (planes != 0) {
+      rh = mf_plane_word(y.x, F16 ? sc : 0.f);
+      ih = mf_plane_word(y.y, F16 ? sc : 0.f);
+      if constexpr (planes == 4) {
         rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
         il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
       }
     }
     for (int j = (n - origin) & (P - 1); j < row; j += P) {
       if (rows) out[j] = y;
-      if (planes == 4) {
+      if constexpr (planes == 4) {
         pl[j] = rh;
         pl[row + j] = rl;
         pl[2 * row + j] = ih;
         pl[3 * row + j] = il;
-      } else if (planes == 2) {
+      } else if constexpr (planes == 2) {
         pl[j] = rh;
         pl[row + j] = ih;
       }
@@ -286,9 +292,25 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chans = static_cast<long long>(F) * p->M;
-  hipLaunchKernelGGL((mf_inv_kernel<LOGNF>), dim3(static_cast<unsigned>((chans + 7) / 8 * 16)), dim3(T), 0, s,
-                     p->d_spec, p->d_tw, yext, p->mf_fstride, p->M, p->row, static_cast<int>(p->origin), p->P,
-                     mt_planes(p), mt_f16(p) ? p->d_fbound : nullptr, rows ? 1 : 0, chans);
+  const dim3 grid(static_cast<unsigned>((chans + 7) / 8 * 16));
+  const int org = static_cast<int>(p->origin), rw = rows ? 1 : 0;
+  const int planes = mt_planes(p);
+  if (mt_f16(p)) {
+    if (planes != 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 2, true>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
+                       p->mf_fstride, p->M, p->row, org, p->P, p->d_fbound, rw, chans);
+  } else if (planes == 4) {
+    hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 4, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+  } else if (planes == 2) {
+    hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 2, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+  } else if (planes == 0) {
+    hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 0, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
