@@ -97,12 +97,15 @@ __device__ __forceinline__ void forward_mf(const TIn* __restrict__ x, int N,
 }
 
 // Forward transform and matched-filter product of one channel per workgroup;
-// writes the one-sided spectrum Yhat[0..NF] to spec[ch][0..NF] and, when bound is
-// given (TD_F16), (1/P) sum_k |Yhat[k]| to bound[ch] (the sample-scale bound).
+// writes the one-sided spectrum Yhat[k] for the band bins k in [k_lo, k_lo + kb) to
+// spec[ch][k] (C, hence Yhat, is zero at every other bin of [0, NF], which the inverse
+// takes as zero without reading) and, when bound is given (TD_F16), (1/P) sum_k |Yhat[k]|
+// to bound[ch] (the sample-scale bound; the bins outside the band add zeros).
 template <int LOGNF, typename TIn>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
     const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
-    const float2* __restrict__ tw_g, float2* __restrict__ spec, float* __restrict__ bound, float inv_p) {
+    const float2* __restrict__ tw_g, float2* __restrict__ spec, float* __restrict__ bound, float inv_p,
+    int k_lo, int kb) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -118,12 +121,17 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
   forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
   float2* out = spec + ch * (NF + 1);
   float acc = 0.f;
-  for (int k = tid; k < NF; k += T) {
+  // thread tid keeps bins k = tid mod T (its first one at or above k_lo), so each partial sum of
+  // the bound adds the same nonzero terms in the same order as over every bin
+  const int k_end = k_lo + kb;   // <= NF + 1
+  int k0 = tid;
+  if (k0 < k_lo) k0 += (k_lo - k0 + T - 1) / T * T;
+  for (int k = k0; k < (k_end < NF ? k_end : NF); k += T) {
     const float2 v = lds[padi(k)];
     out[k] = v;
     acc += sqrtf(v.x * v.x + v.y * v.y);
   }
-  if (tid == 0) {
+  if (tid == 0 && k_end > NF) {
     out[NF] = nyq;
     acc += sqrtf(nyq.x * nyq.x + nyq.y * nyq.y);
   }
@@ -150,7 +158,7 @@ template <int LOGNF, int PLANES, bool F16>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
     const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
     long long fstride, int M, int row, int origin, int P, const float* __restrict__ fbound, int rows,
-    long long chans) {
+    long long chans, int k_lo, int kb) {
   static_assert(PLANES == 0 || PLANES == 2 || PLANES == 4, "no planes, two or four");
   static_assert(!F16 || PLANES == 2, "FP16 samples come as two planes");
   constexpr int planes = PLANES;
@@ -179,10 +187,11 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int k = tid + r * (NF / 16);
-    v[r] = in[k];
+    // bins outside [k_lo, k_lo + kb) are zero (the forward kernel stores the band only)
+    v[r] = static_cast<unsigned>(k - k_lo) < static_cast<unsigned>(kb) ? in[k] : make_float2(0.f, 0.f);
     if (par) v[r] = cmul(v[r], cconj(cmul(twp_hi[k >> 6], twp_lo[k & 63])));   // exp(+2 pi i k / P)
   }
-  const float2 ny = in[NF];
+  const float2 ny = k_lo + kb > NF ? in[NF] : make_float2(0.f, 0.f);
   fft_lds<LOGNF, true>(v, lds, tw_hi, tw_lo, tid);
   const float inv_p = 1.0f / static_cast<float>(P);
   const float sgn = par ? -1.0f : 1.0f;
@@ -288,7 +297,7 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   constexpr int T = (1 << LOGNF) / 16;
   hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
                      static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec,
-                     mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P));
+                     mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P), p->k_lo, p->kb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chans = static_cast<long long>(F) * p->M;
@@ -298,16 +307,16 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   if (mt_f16(p)) {
     if (planes != 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 2, true>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
-                       p->mf_fstride, p->M, p->row, org, p->P, p->d_fbound, rw, chans);
+                       p->mf_fstride, p->M, p->row, org, p->P, p->d_fbound, rw, chans, p->k_lo, p->kb);
   } else if (planes == 4) {
     hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 4, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
-                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
   } else if (planes == 2) {
     hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 2, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
-                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
   } else if (planes == 0) {
     hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 0, false>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
-                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans);
+                       p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
   } else {
     return hipErrorInvalidValue;
   }
