@@ -48,11 +48,12 @@ __device__ __forceinline__ void load_tw(float2* tw, const float2* __restrict__ t
 }
 
 // Forward transform of one channel and the matched-filter product.  On return
-// lds holds Yhat[0..NF) (padded layout), *nyq holds Yhat[NF].
+// lds holds Yhat[k] (padded layout) for the band bins k in [k_lo, k_lo + kb), k < NF, and
+// *nyq holds Yhat[NF]; C is zero at every other bin, whose entries are left unspecified.
 template <int LOGNF, typename TIn>
 __device__ __forceinline__ void forward_mf(const TIn* __restrict__ x, int N,
                                            const float2* __restrict__ cspec, float2* lds,
-                                           const float2* tw, float2* nyq, int tid) {
+                                           const float2* tw, float2* nyq, int tid, int k_lo, int kb) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -76,8 +77,12 @@ __device__ __forceinline__ void forward_mf(const TIn* __restrict__ x, int N,
 #pragma unroll
   for (int i = 0; i < 16; ++i) lds[padi(S::out_index(tid, i))] = v[i];
   __syncthreads();
-  // split the packed transform into the real signal's spectrum and apply C
+  // split the packed transform into the real signal's spectrum and apply C, for the pairs
+  // (k, NF - k) with a bin in the band (bin 0 pairs with the Nyquist bin NF)
   for (int k = tid; k <= NF / 2; k += T) {
+    const bool in_k = static_cast<unsigned>(k - k_lo) < static_cast<unsigned>(kb);
+    const bool in_m = static_cast<unsigned>(NF - k - k_lo) < static_cast<unsigned>(kb);
+    if (!in_k && !in_m && k != 0) continue;
     const float2 A = lds[padi(k)];
     const float2 B = lds[padi((NF - k) & (NF - 1))];
     const float2 Ek = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));      // (A + conj B)/2
@@ -118,7 +123,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
   const long long ch = blockIdx.x;                       // f * M + m
   load_tw<LOGNF>(tw, tw_g, tid, T);
   __syncthreads();
-  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
+  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid, k_lo, kb);
   float2* out = spec + ch * (NF + 1);
   float acc = 0.f;
   // thread tid keeps bins k = tid mod T (its first one at or above k_lo), so each partial sum of
@@ -256,7 +261,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_band_kernel(
   const long long ch = blockIdx.x;                       // f * M + m
   load_tw<LOGNF>(tw, tw_g, tid, T);
   __syncthreads();
-  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid);
+  forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid, k_lo, kb);
   const long long f = ch / M;
   const int m = static_cast<int>(ch - f * M);
   float2* out = band + f * kb * M + m;
