@@ -248,7 +248,7 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
 template <int LOGNF, typename TIn>
 __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_band_kernel(
     const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
-    const float2* __restrict__ tw_g, float2* __restrict__ band, int M, int k_lo, int kb) {
+    const float2* __restrict__ tw_g, float2* __restrict__ band, int M, int F, int k_lo, int kb) {
   using S = FftShape<LOGNF>;
   constexpr int NF = S::NF;
   constexpr int T = S::T;
@@ -258,12 +258,18 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_band_kernel(
   __shared__ float2 tw[TWLEN];
   __shared__ float2 nyq;
   const int tid = threadIdx.x;
-  const long long ch = blockIdx.x;                       // f * M + m
+  // The M channels of a frame interleave in every stored bin row (8 M bytes), so all of them
+  // run on one XCD (workgroups go to the XCDs round-robin by index): workgroup 8 j + xc
+  // takes microphone j mod M of frame xc + 8 (j / M), and that L2 merges the rows before HBM.
+  const unsigned bi = blockIdx.x;
+  const long long jb = bi / MT_XCDS;
+  const int m = static_cast<int>(jb % M);
+  const long long f = static_cast<long long>(bi % MT_XCDS) + MT_XCDS * (jb / M);
+  if (f >= F) return;
+  const long long ch = f * M + m;
   load_tw<LOGNF>(tw, tw_g, tid, T);
   __syncthreads();
   forward_mf<LOGNF, TIn>(x + ch * N, N, cspec, lds, tw, &nyq, tid, k_lo, kb);
-  const long long f = ch / M;
-  const int m = static_cast<int>(ch - f * M);
   float2* out = band + f * kb * M + m;
   for (int j = tid; j < kb; j += T) {
     const int k = k_lo + j;
@@ -274,8 +280,9 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_band_kernel(
 template <int LOGNF, typename TIn>
 hipError_t launch_mf_band_t(const sonar_plan_s* p, const void* x, int F, float2* band, hipStream_t s) {
   constexpr int T = (1 << LOGNF) / 16;
-  hipLaunchKernelGGL((mf_fwd_band_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
-                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, band, p->M, p->k_lo, p->kb);
+  const unsigned blocks = static_cast<unsigned>(MT_XCDS * p->M * ((F + MT_XCDS - 1) / MT_XCDS));
+  hipLaunchKernelGGL((mf_fwd_band_kernel<LOGNF, TIn>), dim3(blocks), dim3(T), 0, s,
+                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, band, p->M, F, p->k_lo, p->kb);
   return hipGetLastError();
 }
 
