@@ -243,6 +243,120 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_inv_kernel(
   }
 }
 
+// Inverse transform of one output residue mod 4 of one channel per workgroup, with
+// H = NF / 2 point transforms (P = 4 H):
+//   yhat[4a + r] = (1/P) (IDFT'_H(V_r)[a] + Yhat[NF] (-1)^r),
+//   V_r[k0] = sum_{q = 0, 1} Yhat[k0 + q H] exp(2 pi i (k0 + q H) r / P),   k0 < H,
+// (exp(2 pi i k a / H) depends on k mod H only), so the four workgroups of a channel hold half
+// the LDS of one NF-point transform each and two of them share a CU.  Output formats as in
+// mf_inv_kernel; the H-point twiddle tables are built here the way the plan builds its own.
+template <int LOGH, int PLANES, bool F16>
+__global__ __launch_bounds__((1 << LOGH) / 16) void mf_inv4_kernel(
+    const float2* __restrict__ spec, const float2* __restrict__ tw_g, float2* __restrict__ yext,
+    long long fstride, int M, int row, int origin, int P, const float* __restrict__ fbound, int rows,
+    long long chans, int k_lo, int kb) {
+  static_assert(PLANES == 0 || PLANES == 2 || PLANES == 4, "no planes, two or four");
+  static_assert(!F16 || PLANES == 2, "FP16 samples come as two planes");
+  static_assert(LOGH >= 6, "H-point tables assume H >= 64");
+  constexpr int planes = PLANES;
+  using S = FftShape<LOGH>;
+  constexpr int H = S::NF;
+  constexpr int NF = 2 * H;
+  constexpr int T = S::T;
+  constexpr int NHI_H = H / 64;            // H-point table: exp(-2 pi i 64 t / H), exp(-2 pi i t / H)
+  constexpr int NHI = NF / 64;             // plan table: NF-point entries, then the P-point ones
+  constexpr int NHP = NF / 64 + 1;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[NHI_H + 64 + NHP + 64];
+  const int tid = threadIdx.x;
+  // workgroups 32 j + 8 r + x, r < 4, are the four residues of channel 8 j + x: all on XCD x
+  // (workgroups go to the XCDs round-robin), so three of them read the spectrum from that L2
+  const unsigned bi = blockIdx.x;
+  const int par = (bi >> 3) & 3;
+  const long long ch = static_cast<long long>(bi >> 5) * 8 + (bi & 7);
+  if (ch >= chans) return;
+  for (int i = tid; i < NHI_H + 64; i += T) {
+    const double num = i < NHI_H ? 64.0 * i : static_cast<double>(i - NHI_H);
+    double sn, cs;
+    sincospi(-2.0 * num / H, &sn, &cs);
+    tw[i] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+  }
+  for (int i = tid; i < NHP + 64; i += T) tw[NHI_H + 64 + i] = tw_g[NHI + 64 + i];
+  __syncthreads();
+  const float2* tw_hi = tw;
+  const float2* tw_lo = tw + NHI_H;
+  const float2* twp_hi = tw + NHI_H + 64;   // exp(-2 pi i 64 t / P), t <= NF / 64
+  const float2* twp_lo = twp_hi + NHP;      // exp(-2 pi i t / P), t < 64
+  const float2* in = spec + ch * (NF + 1);
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k0 = tid + r * (H / 16);
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int k = k0 + q * H;
+      // bins outside [k_lo, k_lo + kb) are zero (the forward kernel stores the band only)
+      if (static_cast<unsigned>(k - k_lo) < static_cast<unsigned>(kb)) {
+        float2 y = in[k];
+        if (par) {
+          int e = k * par;                  // < 3 NF = 1.5 P
+          if (e >= P) e -= P;
+          const bool neg = e >= NF;         // exp(2 pi i e / P) = -exp(2 pi i (e - NF) / P)
+          if (neg) e -= NF;
+          float2 w = cconj(cmul(twp_hi[e >> 6], twp_lo[e & 63]));
+          if (neg) w = make_float2(-w.x, -w.y);
+          y = cmul(y, w);
+        }
+        acc = cadd(acc, y);
+      }
+    }
+    v[r] = acc;
+  }
+  const float2 ny = k_lo + kb > NF ? in[NF] : make_float2(0.f, 0.f);
+  fft_lds<LOGH, true>(v, lds, tw_hi, tw_lo, tid);
+  const float inv_p = 1.0f / static_cast<float>(P);
+  const float sgn = (par & 1) ? -1.0f : 1.0f;
+  const long long f = ch / M;
+  const int m = static_cast<int>(ch - f * M);
+  float2* out = yext + f * fstride + static_cast<long long>(m) * row;
+  unsigned short* pl = reinterpret_cast<unsigned short*>(yext + f * fstride + static_cast<long long>(M) * row) +
+                       static_cast<long long>(m) * planes * row;
+  float sc = 0.f;
+  if constexpr (F16) {
+    const int e = mf_f16_exponent(fbound, f, M);
+    sc = ldexpf(1.0f, e);
+    if (m == 0 && par == 0 && tid == 0)
+      *reinterpret_cast<float*>(yext + f * fstride + mf_f16_header(M, row)) = ldexpf(1.0f / static_cast<float>(M), -e);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int n = 4 * S::out_index(tid, i) + par;
+    const float2 y = make_float2((v[i].x + sgn * ny.x) * inv_p, (v[i].y + sgn * ny.y) * inv_p);
+    unsigned short rh = 0, rl = 0, ih = 0, il = 0;
+    if constexpr (planes != 0) {
+      rh = mf_plane_word(y.x, F16 ? sc : 0.f);
+      ih = mf_plane_word(y.y, F16 ? sc : 0.f);
+      if constexpr (planes == 4) {
+        rl = bf16_rne(y.x - __uint_as_float(static_cast<unsigned>(rh) << 16));
+        il = bf16_rne(y.y - __uint_as_float(static_cast<unsigned>(ih) << 16));
+      }
+    }
+    for (int j = (n - origin) & (P - 1); j < row; j += P) {
+      if (rows) out[j] = y;
+      if constexpr (planes == 4) {
+        pl[j] = rh;
+        pl[row + j] = rl;
+        pl[2 * row + j] = ih;
+        pl[3 * row + j] = il;
+      } else if constexpr (planes == 2) {
+        pl[j] = rh;
+        pl[row + j] = ih;
+      }
+    }
+  }
+}
+
 // Forward transform and matched-filter product of one channel per workgroup;
 // writes the band bins [k_lo, k_lo + kb) bin-major: band[f][k'][m].
 template <int LOGNF, typename TIn>
@@ -313,9 +427,32 @@ hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* y
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chans = static_cast<long long>(F) * p->M;
-  const dim3 grid(static_cast<unsigned>((chans + 7) / 8 * 16));
   const int org = static_cast<int>(p->origin), rw = rows ? 1 : 0;
   const int planes = mt_planes(p);
+  if constexpr (LOGNF == 14) {
+    // NF = 16384: four residues mod 4 per channel with 8192-point transforms (two workgroups per
+    // CU, twice the workgroups of the two-parity split for small batches)
+    constexpr int T4 = (1 << (LOGNF - 1)) / 16;
+    const dim3 grid4(static_cast<unsigned>((chans + 7) / 8 * 32));
+    if (mt_f16(p)) {
+      if (planes != 2) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((mf_inv4_kernel<LOGNF - 1, 2, true>), grid4, dim3(T4), 0, s, p->d_spec, p->d_tw, yext,
+                         p->mf_fstride, p->M, p->row, org, p->P, p->d_fbound, rw, chans, p->k_lo, p->kb);
+    } else if (planes == 4) {
+      hipLaunchKernelGGL((mf_inv4_kernel<LOGNF - 1, 4, false>), grid4, dim3(T4), 0, s, p->d_spec, p->d_tw, yext,
+                         p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
+    } else if (planes == 2) {
+      hipLaunchKernelGGL((mf_inv4_kernel<LOGNF - 1, 2, false>), grid4, dim3(T4), 0, s, p->d_spec, p->d_tw, yext,
+                         p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
+    } else if (planes == 0) {
+      hipLaunchKernelGGL((mf_inv4_kernel<LOGNF - 1, 0, false>), grid4, dim3(T4), 0, s, p->d_spec, p->d_tw, yext,
+                         p->mf_fstride, p->M, p->row, org, p->P, nullptr, rw, chans, p->k_lo, p->kb);
+    } else {
+      return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+  const dim3 grid(static_cast<unsigned>((chans + 7) / 8 * 16));
   if (mt_f16(p)) {
     if (planes != 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL((mf_inv_kernel<LOGNF, 2, true>), grid, dim3(T), 0, s, p->d_spec, p->d_tw, yext,
