@@ -153,6 +153,82 @@ __global__ __launch_bounds__((1 << LOGNF) / 16) void mf_fwd_kernel(
   }
 }
 
+// Forward transform and matched-filter product of one channel split over two workgroups by
+// the parity s of the bin (NF = 2 H):
+//   Z[2k' + s] = DFT_H(u_s)[k'],   u_s[n] = (z[n] + (-1)^s z[n + H]) exp(-2 pi i s n / NF),
+// and the real split pairs bin k with NF - k, of the same parity, so each workgroup finishes its
+// bins alone; two such workgroups share a CU.  Writes the band bins of Yhat (as mf_fwd_kernel
+// does) straight from the split; no sample bound (TD_F16 keeps mf_fwd_kernel).
+template <int LOGH, typename TIn>
+__global__ __launch_bounds__((1 << LOGH) / 16) void mf_fwd2_kernel(
+    const TIn* __restrict__ x, int N, const float2* __restrict__ cspec,
+    const float2* __restrict__ tw_g, float2* __restrict__ spec, long long chans, int k_lo, int kb) {
+  static_assert(LOGH >= 6, "H-point tables assume H >= 64");
+  using S = FftShape<LOGH>;
+  constexpr int H = S::NF;
+  constexpr int NF = 2 * H;
+  constexpr int T = S::T;
+  constexpr int NHI_H = H / 64;            // H-point table, built here as the plan builds its own
+  constexpr int NHI = NF / 64;             // plan table: NF-point entries, then the P-point ones
+  constexpr int NHP = NF / 64 + 1;
+  constexpr int TWLEN = NHI_H + 64 + NHI + 64 + NHP + 64;
+  __shared__ float2 lds[S::LDS_ELEMS];
+  __shared__ float2 tw[TWLEN];
+  const int tid = threadIdx.x;
+  // workgroups 16 j + 8 s + x are the two parities of channel 8 j + x: both on XCD x
+  const unsigned bi = blockIdx.x;
+  const int sp = (bi >> 3) & 1;
+  const long long ch = static_cast<long long>(bi >> 4) * 8 + (bi & 7);
+  if (ch >= chans) return;
+  for (int i = tid; i < NHI_H + 64; i += T) {
+    const double num = i < NHI_H ? 64.0 * i : static_cast<double>(i - NHI_H);
+    double sn, cs;
+    sincospi(-2.0 * num / H, &sn, &cs);
+    tw[i] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+  }
+  for (int i = tid; i < NHI + 64 + NHP + 64; i += T) tw[NHI_H + 64 + i] = tw_g[i];
+  __syncthreads();
+  const float2* tw_hi = tw;                      // exp(-2 pi i 64 t / H)
+  const float2* tw_lo = tw + NHI_H;              // exp(-2 pi i t / H)
+  const float2* twn_hi = tw + NHI_H + 64;        // exp(-2 pi i 64 t / NF)
+  const float2* twn_lo = twn_hi + NHI;           // exp(-2 pi i t / NF)
+  const float2* twp_hi = twn_lo + 64;            // exp(-2 pi i 64 t / P)
+  const float2* twp_lo = twp_hi + NHP;           // exp(-2 pi i t / P)
+  const TIn* xc = x + ch * N;
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int n = tid + r * (H / 16);
+    const int i0 = 2 * n, i1 = 2 * (n + H);
+    const float2 a = make_float2(i0 < N ? to_f32<TIn>(xc[i0]) : 0.0f, i0 + 1 < N ? to_f32<TIn>(xc[i0 + 1]) : 0.0f);
+    const float2 b = make_float2(i1 < N ? to_f32<TIn>(xc[i1]) : 0.0f, i1 + 1 < N ? to_f32<TIn>(xc[i1 + 1]) : 0.0f);
+    v[r] = sp ? cmul(csub(a, b), cmul(twn_hi[n >> 6], twn_lo[n & 63])) : cadd(a, b);
+  }
+  fft_lds<LOGH, false>(v, lds, tw_hi, tw_lo, tid);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) lds[padi(S::out_index(tid, i))] = v[i];   // Z[2 k' + s] at k'
+  __syncthreads();
+  float2* out = spec + ch * (NF + 1);
+  for (int kq = tid; 2 * kq + sp <= NF / 2; kq += T) {
+    const int k = 2 * kq + sp;
+    const bool in_k = static_cast<unsigned>(k - k_lo) < static_cast<unsigned>(kb);
+    const bool in_m = static_cast<unsigned>(NF - k - k_lo) < static_cast<unsigned>(kb);
+    if (!in_k && !in_m) continue;           // (bin 0 pairs with the Nyquist bin NF)
+    const int km = (NF - k) & (NF - 1);     // same parity as k
+    const float2 A = lds[padi(kq)];
+    const float2 B = lds[padi((km - sp) >> 1)];
+    const float2 Ek = make_float2(0.5f * (A.x + B.x), 0.5f * (A.y - B.y));      // (A + conj B)/2
+    const float2 Ok = make_float2(0.5f * (A.y + B.y), -0.5f * (A.x - B.x));     // (A - conj B)/(2i)
+    const float2 wk = cmul(twp_hi[k >> 6], twp_lo[k & 63]);                     // exp(-2 pi i k / P)
+    const float2 wo = cmul(wk, Ok);
+    const float2 Xk = cadd(Ek, wo);
+    const float2 Xm = cconj(csub(Ek, wo));                                      // X[NF - k]
+    if (in_k) out[k] = cmul(Xk, cspec[k]);
+    if (in_m && k != NF / 2) out[NF - k] = cmul(Xm, cspec[NF - k]);
+  }
+}
+
 // Inverse transform of one output parity of one channel per workgroup:
 //   yhat[2a + par] = (1/P) (IDFT'_NF(Yhat[k] exp(2 pi i k par / P))[a] + Yhat[NF] (-1)^par)
 // written to the MF rows: element j of a row holds yhat[(origin + j) mod P].
@@ -421,9 +497,20 @@ hipError_t launch_mf_band_dt(const sonar_plan_s* p, const void* x, int F, float2
 template <int LOGNF, typename TIn>
 hipError_t launch_mf_td_t(const sonar_plan_s* p, const void* x, int F, float2* yext, hipStream_t s, bool rows) {
   constexpr int T = (1 << LOGNF) / 16;
-  hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
-                     static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec,
-                     mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P), p->k_lo, p->kb);
+  bool split = false;
+  if constexpr (LOGNF == 14) {
+    if (!mt_f16(p)) {   // two parities of 8192-point transforms per channel (two workgroups per CU)
+      const long long ch2 = static_cast<long long>(F) * p->M;
+      hipLaunchKernelGGL((mf_fwd2_kernel<LOGNF - 1, TIn>), dim3(static_cast<unsigned>((ch2 + 7) / 8 * 16)),
+                         dim3(T / 2), 0, s, static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec, ch2,
+                         p->k_lo, p->kb);
+      split = true;
+    }
+  }
+  if (!split)
+    hipLaunchKernelGGL((mf_fwd_kernel<LOGNF, TIn>), dim3(F * p->M), dim3(T), 0, s,
+                       static_cast<const TIn*>(x), p->N, p->d_cspec, p->d_tw, p->d_spec,
+                       mt_f16(p) ? p->d_fbound : nullptr, 1.0f / static_cast<float>(p->P), p->k_lo, p->kb);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long chans = static_cast<long long>(F) * p->M;
